@@ -1,0 +1,63 @@
+"""Measurement in FP64: probabilities, marginals, diagonal expectation values."""
+from __future__ import annotations
+
+import numpy as np
+
+from . import gates, sim
+
+
+def probs(psi: np.ndarray) -> np.ndarray:
+    """p_x = |psi_x|^2 over the full basis (Born rule)."""
+    return np.abs(psi) ** 2
+
+
+def marginal(psi: np.ndarray, D: int, n: int, qudits) -> np.ndarray:
+    """Marginal distribution of the listed qudits: p(y) = sum over all x whose
+    digits on ``qudits`` equal y of |psi_x|^2.  Bin index y = sum_i y_i D^(m-1-i)
+    in the listed order (what the paper's measure(index=...) returns as p)."""
+    qudits = list(qudits)
+    p = probs(psi).reshape((D,) * n)
+    others = [a for a in range(n) if a not in qudits]
+    s = p.sum(axis=tuple(others)) if others else p
+    # s has the measured axes in increasing qudit order; reorder to the listed order
+    order = sorted(qudits)
+    s = np.transpose(s, [order.index(q) for q in qudits])
+    return np.ascontiguousarray(s).reshape(-1)
+
+
+def sample_counts(p: np.ndarray, shots: int, seed: int) -> np.ndarray:
+    """Histogram of ``shots`` draws from p.  Parity unpinned (statistical only)."""
+    rng = np.random.default_rng(seed)
+    return np.bincount(rng.choice(len(p), size=shots, p=p / p.sum()), minlength=len(p))
+
+
+def z_diag(D: int) -> np.ndarray:
+    """Diagonal of the clock operator Z = diag(w^k)."""
+    w = gates.omega(D)
+    return np.array([w ** k for k in range(D)], dtype=np.complex128)
+
+
+def term_table(D: int, term) -> np.ndarray:
+    q, name = term
+    if name == "z":
+        return z_diag(D)
+    return np.asarray(name, dtype=np.complex128)
+
+
+def expect_diag(psi: np.ndarray, D: int, n: int, terms) -> complex:
+    """<O> = <psi| O |psi> for O = sum_t d_t(x_{q_t}) diagonal:
+    sum_x |psi_x|^2 sum_t d_t(x_{q_t})."""
+    dig = sim.digits_of(D, n, np.arange(D ** n))
+    f = np.zeros(D ** n, dtype=np.complex128)
+    for t in terms:
+        f += term_table(D, t)[dig[t[0]]]
+    return complex(np.sum(probs(psi) * f))
+
+
+def hermitian_part_diag(D: int, n: int, terms) -> np.ndarray:
+    """Diagonal of (O + O^dagger)/2, so that Re<psi|O|psi> = <psi|H_O|psi>."""
+    dig = sim.digits_of(D, n, np.arange(D ** n))
+    f = np.zeros(D ** n, dtype=np.float64)
+    for t in terms:
+        f += term_table(D, t).real[dig[t[0]]]
+    return f

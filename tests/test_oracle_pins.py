@@ -1,0 +1,325 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics:
+printed matrices, closed forms, invariants, textbook special cases and a
+brute-force second route.  CPU only."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import qf_inputs as qi
+from oracle import brute, gates, grad, measure, sim
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TOL = 1e-12
+
+
+def _eval_entry(expr, theta):
+    c, s = np.cos(theta / 2), np.sin(theta / 2)
+    env = {"c": c, "s": s, "i": 1j, "em": np.exp(-0.5j * theta), "ep": np.exp(0.5j * theta)}
+    return complex(eval(expr, {"__builtins__": {}}, env))
+
+
+def _eval_matrix(rows, theta=0.0):
+    return np.array([[_eval_entry(e, theta) for e in r] for r in rows])
+
+
+# ---------------------------------------------------------------- gate matrices
+
+def test_printed_rotation_matrices():
+    """The paper's printed D=2, D=3 and D=4 rotation matrices."""
+    fx = json.load(open(os.path.join(GOLDEN, "paper_rotation_matrices.json")))
+    for case in fx["cases"]:
+        for theta in (0.3, -1.7, 2.9, np.pi):
+            if case["gate"] == "rz":
+                got = gates.rz(case["D"], case["j"], theta)
+            else:
+                got = getattr(gates, case["gate"])(case["D"], case["j"], case["k"], theta)
+            want = _eval_matrix(case["matrix"], theta)
+            assert np.abs(got - want).max() < TOL, case["name"]
+    g = fx["generators_D2"]
+    assert np.allclose(gates.gm_sym(2, 0, 1), _eval_matrix(g["sx"]))
+    assert np.allclose(gates.gm_asym(2, 0, 1), _eval_matrix(g["sy"]))
+    assert np.allclose(gates.gm_diag(2, 1), _eval_matrix(g["sz"]))
+
+
+@pytest.mark.parametrize("D", range(2, 11))
+def test_rotation_closed_forms(D):
+    """The paper's general element formulas for R_x^{jk}, R_y^{jk} (two-level
+    rotation, identity elsewhere) and R_z^j (diagonal phases) versus the oracle's
+    eigendecomposition route."""
+    rng = np.random.default_rng(D)
+    for theta in rng.uniform(-np.pi, np.pi, size=3):
+        c, s = np.cos(theta / 2), np.sin(theta / 2)
+        for j in range(D):
+            for k in range(j + 1, D):
+                ex = np.eye(D, dtype=complex)
+                ex[j, j] = ex[k, k] = c
+                ex[j, k] = ex[k, j] = -1j * s
+                assert np.abs(gates.rx(D, j, k, theta) - ex).max() < TOL
+                ey = np.eye(D, dtype=complex)
+                ey[j, j] = ey[k, k] = c
+                ey[j, k] = -s
+                ey[k, j] = s
+                assert np.abs(gates.ry(D, j, k, theta) - ey).max() < TOL
+        for j in range(1, D):
+            # 1-indexed levels k = 1..j+1 carry the phase, exponent (-j) on k = j+1
+            want = np.ones(D, dtype=complex)
+            a = np.sqrt(2.0 / (j * (j + 1)))
+            for k1 in range(1, j + 2):
+                want[k1 - 1] = np.exp(-0.5j * theta * a * ((-j) if k1 == j + 1 else 1))
+            assert np.abs(gates.rz(D, j, theta) - np.diag(want)).max() < TOL
+
+
+@pytest.mark.parametrize("D", range(2, 11))
+def test_gell_mann_orthonormal(D):
+    """Generalized Gell-Mann matrices: Hermitian, traceless, Tr(S_a S_b) = 2 delta_ab,
+    D^2 - 1 of them (fixes the diagonal family's normalisation and support)."""
+    mats = []
+    for j in range(D):
+        for k in range(j + 1, D):
+            mats += [gates.gm_sym(D, j, k), gates.gm_asym(D, j, k)]
+    mats += [gates.gm_diag(D, j) for j in range(1, D)]
+    assert len(mats) == D * D - 1
+    G = np.array([[np.trace(a @ b) for b in mats] for a in mats])
+    assert np.abs(G - 2 * np.eye(len(mats))).max() < TOL
+    for m in mats:
+        assert abs(np.trace(m)) < TOL
+        assert np.abs(m - m.conj().T).max() < TOL
+
+
+@pytest.mark.parametrize("D", [2, 3, 4, 5, 7, 10])
+def test_fourier_shift_clock_identities(D):
+    H, X, Z = gates.fourier(D), gates.shift(D, 1), gates.clock(D, 1)
+    w = gates.omega(D)
+    I = np.eye(D)
+    # unitarity
+    for U in (H, X, Z):
+        assert np.abs(U.conj().T @ U - I).max() < TOL
+    # H|0> is the equal superposition of all D levels
+    assert np.allclose(H[:, 0], np.full(D, 1 / np.sqrt(D)))
+    # X^D = Z^D = I, Weyl relation Z X = w X Z
+    assert np.abs(np.linalg.matrix_power(X, D) - I).max() < TOL
+    assert np.abs(np.linalg.matrix_power(Z, D) - I).max() < TOL
+    assert np.abs(Z @ X - w * X @ Z).max() < TOL
+    # H^2 is the parity permutation |j> -> |-j mod D>, H^4 = I
+    P = np.zeros((D, D))
+    for j in range(D):
+        P[(-j) % D, j] = 1
+    assert np.abs(H @ H - P).max() < TOL
+    assert np.abs(np.linalg.matrix_power(H, 4) - I).max() < TOL
+    # shift by s acts as |x> -> |x+s>
+    for s in range(D):
+        Xs = gates.shift(D, s)
+        for x in range(D):
+            assert Xs[(x + s) % D, x] == 1
+
+
+@pytest.mark.parametrize("D", [2, 3, 5])
+def test_rotation_inverse_and_unitary(D):
+    for j in range(D):
+        for k in range(j + 1, D):
+            for f in (gates.rx, gates.ry):
+                R = f(D, j, k, 0.77)
+                assert np.abs(R @ f(D, j, k, -0.77) - np.eye(D)).max() < TOL
+                assert np.abs(R.conj().T @ R - np.eye(D)).max() < TOL
+
+
+# ------------------------------------------------------------ index and states
+
+def test_decimal_index_and_state_string():
+    D = 4
+    dig = sim.parse_state_string("0-1-3")
+    assert dig == [0, 1, 3]
+    assert sim.index_of(D, dig) == 0 * 16 + 1 * 4 + 3
+    psi = sim.basis_state(D, 3, dig)
+    assert psi[7] == 1 and np.count_nonzero(psi) == 1
+
+
+@pytest.mark.parametrize("D,n", [(3, 4), (2, 5), (5, 3)])
+def test_fourier_on_qudit0_is_most_significant(D, n):
+    c = qi.Circuit(D, n, [("h", 0)])
+    psi = sim.run(c)
+    nz = np.flatnonzero(np.abs(psi) > 1e-14)
+    assert list(nz) == [m * D ** (n - 1) for m in range(D)]
+    assert np.allclose(np.abs(psi[nz]), 1 / np.sqrt(D))
+
+
+@pytest.mark.parametrize("D,n", [(2, 6), (3, 5), (4, 4), (5, 3), (10, 3)])
+def test_ghz(D, n):
+    """H on qudit 0 then CSUM chain (0->1)...(n-2->n-1) gives (1/sqrt D) sum_j |j..j>."""
+    c = qi.Circuit(D, n, [("h", 0)] + qi.csum_chain(n))
+    psi = sim.run(c)
+    want = np.zeros(D ** n, dtype=complex)
+    for j in range(D):
+        want[sim.index_of(D, [j] * n)] = 1 / np.sqrt(D)
+    assert np.abs(psi - want).max() < TOL
+
+
+@pytest.mark.parametrize("D,n", [(3, 4), (4, 3)])
+def test_uniform_after_fourier_layer_and_chain(D, n):
+    """H on every qudit gives amplitude D^(-n/2) everywhere; a CSUM chain permutes
+    it, so the state stays uniform (first stage of the D=3, n=4 workload)."""
+    c = qi.Circuit(D, n, [("h", q) for q in range(n)] + qi.csum_chain(n))
+    psi = sim.run(c)
+    assert np.abs(psi - D ** (-n / 2)).max() < TOL
+
+
+def test_csum_on_basis_states():
+    D, n = 3, 2
+    for xc in range(D):
+        for xt in range(D):
+            psi = sim.apply_csum(sim.basis_state(D, n, [xc, xt]), D, n, 0, 1)
+            assert psi[sim.index_of(D, [xc, (xt + xc) % D])] == 1
+            psi = sim.apply_csum(sim.basis_state(D, n, [xc, xt]), D, n, 1, 0)
+            assert psi[sim.index_of(D, [(xc + xt) % D, xt])] == 1
+
+
+@pytest.mark.parametrize("D", [2, 3, 5])
+def test_permutation_orders(D):
+    n = 3
+    psi = qi.random_state(D, n, 11)
+    p = psi.copy()
+    for _ in range(D):
+        p = sim.apply_csum(p, D, n, 2, 0)
+    assert np.abs(p - psi).max() < TOL
+    p = psi.copy()
+    for _ in range(D):
+        p = sim.apply_shift(p, D, n, 1, 1)
+    assert np.abs(p - psi).max() < TOL
+    # shift via the digit map equals the shift matrix applied on the axis
+    assert np.abs(sim.apply_shift(psi, D, n, 1, 2) - sim.apply_1q(psi, D, n, 1, gates.shift(D, 2))).max() < TOL
+
+
+# ----------------------------------------------------------------- brute force
+
+@pytest.mark.parametrize("D,n,seed", [(2, 4, 0), (3, 4, 1), (4, 3, 2), (5, 3, 3), (3, 3, 4), (6, 2, 5)])
+def test_sim_matches_bruteforce_unitary(D, n, seed):
+    c = qi.random_circuit(D, n, 40, seed)
+    U = brute.circuit_unitary(c)
+    assert np.abs(U.conj().T @ U - np.eye(D ** n)).max() < 1e-10
+    psi0 = qi.random_state(D, n, seed + 100)
+    assert np.abs(sim.run(c, psi0) - U @ psi0).max() < 1e-12
+
+
+def test_config1_bruteforce():
+    c = qi.config1()
+    assert len(c.ops) == 29 and c.nparams == 16
+    U = brute.circuit_unitary(c)
+    assert np.abs(sim.run(c) - U[:, 0]).max() < 1e-12
+
+
+def test_swap_bruteforce():
+    D, n = 3, 3
+    psi = qi.random_state(D, n, 3)
+    U = brute.op_unitary(("swap", 0, 2), D, n, None)
+    assert np.abs(sim.apply_swap(psi, D, n, 0, 2) - U @ psi).max() < TOL
+
+
+# ------------------------------------------------------------------- invariants
+
+@pytest.mark.parametrize("D,n", [(3, 5), (5, 3)])
+def test_norm_and_unapply(D, n):
+    c = qi.random_circuit(D, n, 60, 9)
+    psi = sim.basis_state(D, n)
+    for op in c.ops:
+        psi = sim.apply_op(psi, D, n, op, c.theta)
+        assert abs(np.linalg.norm(psi) - 1) < 1e-12
+    for op in reversed(c.ops):
+        psi = sim.apply_inverse(psi, D, n, op, c.theta)
+    assert np.abs(psi - sim.basis_state(D, n)).max() < 1e-12
+
+
+# ------------------------------------------------------------------ algorithms
+
+@pytest.mark.parametrize("D", [2, 3, 4, 5])
+def test_deutsch_jozsa(D):
+    """Constant oracle: the register reads 0..0 with certainty.  Balanced oracle
+    (CSUM 2->3 with the target in the Fourier state of |D-1>): the phase kickback
+    w^{x_2} moves qudit 2 to level D-1, so p[0] = 0."""
+    psi0 = sim.basis_state(D, 4, [0, 0, 0, D - 1])
+    pc = measure.marginal(sim.run(qi.deutsch_jozsa_d(D, "constant"), psi0), D, 4, [0, 1, 2])
+    assert abs(pc[0] - 1) < TOL
+    pb = measure.marginal(sim.run(qi.deutsch_jozsa_d(D, "balanced"), psi0), D, 4, [0, 1, 2])
+    assert abs(pb[0]) < TOL
+    assert abs(pb[sim.index_of(D, [0, 0, D - 1])] - 1) < TOL
+
+
+def test_grover_qutrits():
+    """One Grover iteration on two qutrits marked |22>: the marked amplitude is
+    23/27, all others 5/27 (oracle I - 2|m><m|, diffusion 2|s><s| - I)."""
+    g = qi.grover_d3_n2_marker22()
+    D, n = g["dim"], g["n"]
+    s = sim.run(qi.Circuit(D, n, [("h", 0), ("h", 1)]))
+    m = sim.basis_state(D, n, list(g["marker"]))
+    oracle_u = np.eye(D ** n) - 2 * np.outer(m, m.conj())
+    diffusion = 2 * np.outer(s, s.conj()) - np.eye(D ** n)
+    c = qi.Circuit(D, n, [("u", 0, 2, oracle_u), ("u", 0, 2, diffusion)])
+    out = sim.run(c, s)
+    want = np.full(9, 5 / 27, dtype=complex)
+    want[8] = 23 / 27
+    assert np.abs(out - want).max() < TOL
+    assert abs(measure.probs(out)[8] - 529 / 729) < TOL
+
+
+# ------------------------------------------------------------------ measurement
+
+def test_marginals_product_state():
+    D, n = 3, 4
+    rng = np.random.default_rng(5)
+    singles = [qi.random_unitary(D, rng)[:, 0] for _ in range(n)]
+    psi = singles[0]
+    for v in singles[1:]:
+        psi = np.kron(psi, v)
+    for qs in ([0], [2], [1, 3], [3, 1], [0, 1, 2, 3], [2, 0, 3]):
+        want = np.array([1.0])
+        for q in qs:
+            want = np.kron(want, np.abs(singles[q]) ** 2)
+        assert np.abs(measure.marginal(psi, D, n, qs) - want).max() < TOL
+    assert abs(measure.probs(psi).sum() - 1) < TOL
+
+
+def test_expectation_special_cases():
+    D, n = 5, 3
+    w = gates.omega(D)
+    for digs in ([0, 0, 0], [3, 1, 4], [2, 2, 2]):
+        psi = sim.basis_state(D, n, digs)
+        assert abs(measure.expect_diag(psi, D, n, qi.z0_terms()) - w ** digs[0]) < TOL
+        want = sum(w ** d for d in digs)
+        assert abs(measure.expect_diag(psi, D, n, qi.zsum_terms(n)) - want) < TOL
+    # <Z> vanishes on the Fourier state of |0>
+    psi = sim.run(qi.Circuit(D, n, [("h", 0)]))
+    assert abs(measure.expect_diag(psi, D, n, qi.z0_terms())) < TOL
+
+
+# -------------------------------------------------------------------- gradients
+
+@pytest.mark.parametrize("D", [2, 3, 5, 10])
+def test_gradient_closed_form_single_qudit(D):
+    """R_y^{01}(theta)|0>, O = Z: Re<Z> = cos^2(t/2) + sin^2(t/2) cos(2 pi/D), so
+    dL/dtheta = -sin(theta) (1 - cos(2 pi / D)) / 2."""
+    for theta in (0.4, -2.1, 1.3):
+        c = qi.Circuit(D, 1, [("ry", 0, 0, 1, 0)], np.array([theta]))
+        L = grad.loss(c, qi.zsum_terms(1))
+        assert abs(L - (np.cos(theta / 2) ** 2 + np.sin(theta / 2) ** 2 * np.cos(2 * np.pi / D))) < TOL
+        g = grad.adjoint(c, qi.zsum_terms(1))
+        assert abs(g[0] + 0.5 * np.sin(theta) * (1 - np.cos(2 * np.pi / D))) < 1e-12
+
+
+@pytest.mark.parametrize("D,n,seed", [(3, 3, 1), (4, 2, 2), (5, 2, 3), (2, 4, 4)])
+def test_adjoint_matches_finite_differences(D, n, seed):
+    c = qi.random_circuit(D, n, 50, seed)
+    terms = qi.zsum_terms(n)
+    g = grad.adjoint(c, terms)
+    idx = np.arange(c.nparams)
+    fd = grad.finite_diff(c, terms, idx, h=1e-5)
+    assert np.abs(g - fd).max() <= 1e-8 * max(1.0, np.abs(fd).max())
+
+
+def test_adjoint_shared_parameter():
+    """A parameter used by two gates gets the sum of both contributions."""
+    D = 3
+    c = qi.Circuit(D, 2, [("rx", 0, 0, 1, 0), ("csum", 0, 1), ("ry", 1, 1, 2, 0)], np.array([0.9]))
+    g = grad.adjoint(c, qi.zsum_terms(2))
+    fd = grad.finite_diff(c, qi.zsum_terms(2), [0], h=1e-5)
+    assert abs(g[0] - fd[0]) < 1e-9
