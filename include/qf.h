@@ -1,0 +1,216 @@
+/*
+ * qf.h - C ABI of the MI355X (gfx950) qudit state-vector library.
+ *
+ * The library applies qudit gates to a dense complex state vector of D^n
+ * amplitudes, then computes measurement probabilities, diagonal expectation
+ * values and adjoint-method gradients.  The gate set and conventions follow
+ * Friedrich & Maziero, "QuForge: A Library for Qudits Simulation"
+ * (arXiv:2409.17716), Appendix "Matrix form of the quantum gates".
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Basis index (decimal representation, subsection "Generalized CNOT gate"):
+ *    for digits (x_0, ..., x_{n-1}), x = sum_k x_k D^(n-1-k).  Qudit 0 is the
+ *    most significant digit; the stride of qudit q is D^(n-1-q).
+ *  - Levels are 0-indexed (the paper programs {|j>}_{j=0}^{D-1}).
+ *  - Amplitudes are interleaved (re, im): complex64 = 2 x float, complex128 =
+ *    2 x double, exactly torch.complex64 / torch.complex128 memory.
+ *  - A state holds `batch` registers of D^n amplitudes back to back.
+ *  - Host matrices and tables are always complex FP64 (interleaved doubles);
+ *    the library casts them to the state's precision.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Every call
+ *    only enqueues work on it, except those documented as synchronising.
+ *
+ * Ownership: the caller owns every state, output and device matrix buffer.
+ * Host arrays are read before the call returns and may be freed right after.
+ * The library owns plan objects (freed by qf_plan_destroy) and stream-ordered
+ * temporary reduction buffers (allocated and freed on `stream`).
+ *
+ * Errors: argument validation is synchronous and enqueues nothing on failure.
+ * A failed HIP launch returns QF_EHIP.  Faults inside a kernel surface at the
+ * caller's next synchronisation.  No C++ exception crosses this ABI.
+ * qf_last_error() returns a thread-local message describing the last non-OK
+ * status of the calling thread.
+ *
+ * Limits: 2 <= dim <= 16; n >= 1; batch * dim^n < 2^32 amplitudes per call.
+ * Host D x D matrices of the per-gate calls travel as kernel arguments, so
+ * complex128 states accept dim <= 11 in qf_apply_1q.
+ */
+#ifndef QF_H
+#define QF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QF_OK = 0,
+    QF_EINVAL = -1,        /* bad argument: index out of range, NULL pointer, ...   */
+    QF_EDTYPE = -2,        /* unknown dtype or dtype mismatch                       */
+    QF_ERANGE = -3,        /* size beyond the documented limits                     */
+    QF_ENOMEM = -4,        /* device or host allocation failed                      */
+    QF_EHIP = -5,          /* a HIP runtime call failed                             */
+    QF_EUNSUPPORTED = -6   /* valid request this build does not implement           */
+} qf_status;
+
+typedef enum { QF_C64 = 0, QF_C128 = 1 } qf_dtype;
+
+/* A register (or a batch of registers) in device memory. */
+typedef struct qf_state {
+    void*   amps;    /* device pointer, batch * dim^n complex elements              */
+    int32_t n;       /* qudits per register                                          */
+    int32_t dim;     /* levels per qudit (D)                                         */
+    int64_t batch;   /* registers stored back to back                                */
+    int32_t dtype;   /* qf_dtype                                                     */
+} qf_state;
+
+/* ------------------------------------------------------------------------- */
+/* Per-gate entry points                                                     */
+/* ------------------------------------------------------------------------- */
+
+/* psi = |j_0 j_1 ... j_{n-1}> in every register (the paper's State('j0-j1-..'),
+ * section "Code style").  digits: host, batch*n values in [0, dim) (register b
+ * uses digits[b*n .. b*n+n-1]); NULL means |0...0> everywhere. */
+qf_status qf_state_init(const qf_state* s, const int32_t* digits, void* stream);
+
+/* One-qudit gate: psi[h, :, l] <- U psi[h, :, l] with the register viewed as
+ * [D^q][D][D^(n-1-q)] (a D x D matrix acting on qudit q, identity elsewhere;
+ * subsections "Fourier gate", "Generalized rotation gate", "Generalized
+ * phase-shift gate").  U: host, D*D complex FP64, row-major (U[a*D+b] is
+ * <a|U|b>).  q in [0, n).  The matrix need not be unitary. */
+qf_status qf_apply_1q(const qf_state* s, int32_t q, const double* U, void* stream);
+
+/* Controlled shift, a pure index permutation (subsections "Generalized NOT
+ * gate" and "Generalized CNOT gate"): |.. x_c .. x_t ..> ->
+ * |.. x_c .. (x_t + shift[x_c]) mod D ..>.  The generalized CNOT (CSUM) is
+ * shift[c] = c; the shift gate X_s is ctrl = -1 with shift[0] = s.
+ * shift: host, D entries (only shift[0] is read when ctrl = -1), any integers
+ * (reduced mod D).  ctrl != tgt, both in [0, n) (ctrl may be -1).
+ * Bit-exact: amplitudes are moved, never recomputed. */
+qf_status qf_apply_ctrl(const qf_state* s, int32_t ctrl, int32_t tgt,
+                        const int32_t* shift, void* stream);
+
+/* Diagonal gate on k qudits: psi_x <- phases[y] psi_x with
+ * y = sum_i x_{qudits[i]} D^(k-1-i) (clock/phase gate, R_z, controlled phase).
+ * qudits: host, k distinct indices in [0, n); phases: host, D^k complex FP64.
+ * Limit: D^k <= 256 (complex64) or 128 (complex128). */
+qf_status qf_apply_diag(const qf_state* s, int32_t k, const int32_t* qudits,
+                        const double* phases, void* stream);
+
+/* Custom dense gate on the k adjacent qudits q0..q0+k-1 (the paper's
+ * U(matrix, index), section "Grover's algorithm"): psi[h, :, l] <- B psi[h, :, l]
+ * with the register viewed as [D^q0][D^k][D^(n-q0-k)].
+ * B: DEVICE pointer, D^k x D^k row-major in the state's precision (complex64
+ * or complex128), caller-owned, read during the kernel.  complex64 blocks with
+ * D^k >= 32 run on FP32 matrix cores; others on vector ALUs.  D^k <= 1024. */
+qf_status qf_apply_fused(const qf_state* s, int32_t k, int32_t q0, const void* B,
+                         void* stream);
+
+/* Measurement probabilities (section "Code style": measure returns p).
+ * m = 0 and qudits = NULL: full distribution p_x = |psi_x|^2, out holds
+ * batch*D^n reals.  Otherwise the marginal of the listed qudits in the listed
+ * order, p(y) = sum_{x : x_qudits = y} |psi_x|^2 with y = sum_i y_i D^(m-1-i);
+ * out holds batch*D^m reals.  out: DEVICE, float for complex64 states, double
+ * for complex128.  Marginals accumulate in FP64 in a fixed order (bitwise
+ * reproducible run to run). */
+qf_status qf_probs(const qf_state* s, int32_t m, const int32_t* qudits, void* out,
+                   void* stream);
+
+/* Expectation of a diagonal observable that is a sum of one-qudit terms,
+ * <O> = sum_x |psi_x|^2 sum_t term_diag[t][x_{term_qudit[t]}]
+ * (e.g. Z_0 with Z = diag(w^k), or sum_i Z_i).  term_qudit: host, nterms
+ * indices in [0, n); term_diag: host, nterms*D complex FP64.
+ * out: DEVICE, batch complex128 values (2 doubles each), accumulated in FP64
+ * in a fixed order.  Limit: nterms*D <= 128. */
+qf_status qf_expect(const qf_state* s, int32_t nterms, const int32_t* term_qudit,
+                    const double* term_diag, double* out, void* stream);
+
+/* ------------------------------------------------------------------------- */
+/* Circuit programs (plans): fused forward and adjoint gradient              */
+/* ------------------------------------------------------------------------- */
+
+typedef enum {
+    QF_OP_H = 0,       /* Fourier gate on q0                                      */
+    QF_OP_X = 1,       /* shift x_q0 -> x_q0 + a mod D                             */
+    QF_OP_CLOCK = 2,   /* Z^a = diag(w^(a k)) on q0                                */
+    QF_OP_RX = 3,      /* exp(-i theta S_x^{jk} / 2) on q0                         */
+    QF_OP_RY = 4,      /* exp(-i theta S_y^{jk} / 2) on q0                         */
+    QF_OP_RZ = 5,      /* exp(-i theta S_z^{j} / 2) on q0, 1 <= j < D              */
+    QF_OP_CSUM = 6,    /* x_q1 -> x_q1 + x_q0 mod D  (q0 control, q1 target)       */
+    QF_OP_CSHIFT = 7,  /* x_q1 -> x_q1 + shifts[x_q0] mod D                        */
+    QF_OP_CZ = 8,      /* phase w^(x_q0 x_q1)                                      */
+    QF_OP_U = 9        /* dense D^k x D^k matrix `mat` on qudits q0..q0+k-1        */
+} qf_op_kind;
+
+typedef struct qf_op {
+    int32_t kind;        /* qf_op_kind                                              */
+    int32_t q0;          /* target of one-qudit gates; control of CSUM/CSHIFT/CZ;    */
+                         /* first qudit of U                                         */
+    int32_t q1;          /* target of CSUM/CSHIFT/CZ; k (qudit count) of U           */
+    int32_t j, k;        /* levels: RX/RY use j < k; RZ uses j; X and CLOCK use j as */
+                         /* the shift / exponent a                                   */
+    int32_t param;       /* rotation angle slot in theta, -1 for fixed gates         */
+    int32_t shifts[16];  /* CSHIFT table (first D entries used)                      */
+    const double* mat;   /* U: host D^k x D^k complex FP64, copied at plan creation  */
+} qf_op;
+
+typedef struct qf_plan qf_plan;
+
+/* Plan options.  Zero-initialised options select the defaults. */
+typedef struct qf_plan_opts {
+    int32_t fuse;         /* 0 = default (fused LDS stages), 1 = one kernel per gate */
+    int32_t tile_digits;  /* qudits per LDS tile; 0 = chosen from D and LDS size    */
+    int32_t ckpt_every;   /* adjoint: keep a state checkpoint every this many gates  */
+                          /* of the planned schedule; 0 = none                       */
+    int32_t reserved[5];
+} qf_plan_opts;
+
+/* Compile a circuit (ops applied in order) for registers of n qudits of
+ * dimension dim in precision dtype.  Fixed gates are built here; rotation
+ * matrices are rebuilt from theta on each qf_plan_forward / qf_adjoint_grad.
+ * Consecutive gates are grouped into stages that each make one pass over HBM.
+ * nparams: length of theta.  *out receives the plan. */
+qf_status qf_plan_create(int32_t dim, int32_t n, int32_t dtype, const qf_op* ops,
+                         int32_t nops, int32_t nparams, const qf_plan_opts* opts,
+                         qf_plan** out);
+
+/* Number of HBM passes (stages) of the plan's forward schedule. */
+int32_t qf_plan_num_stages(const qf_plan* plan);
+
+/* Apply the planned circuit in place to every register of s (shape must match
+ * the plan).  theta: host, nparams angles in radians. */
+qf_status qf_plan_forward(qf_plan* plan, const qf_state* s, const double* theta,
+                          void* stream);
+
+/* Adjoint-method gradient of L(theta) = Re <psi| O |psi> for O a sum of
+ * one-qudit diagonal terms (as in qf_expect), psi = circuit(theta) psi0
+ * (Jones & Gacon, arXiv:2009.02823; rotations R = exp(-i theta S / 2),
+ * subsection "Generalized rotation gate", give dL/dtheta = Im <lam|S|psi>).
+ * psi: in = the final state produced by qf_plan_forward; out = clobbered
+ * (un-applied back towards psi0).  lam: scratch state of the same shape.
+ * grad: host, batch*nparams doubles (register b writes grad[b*nparams ..]).
+ * Synchronises `stream` before returning. */
+qf_status qf_adjoint_grad(qf_plan* plan, const qf_state* psi, const qf_state* lam,
+                          const double* theta, int32_t nterms,
+                          const int32_t* term_qudit, const double* term_diag,
+                          double* grad, void* stream);
+
+void qf_plan_destroy(qf_plan* plan);
+
+/* ------------------------------------------------------------------------- */
+/* Misc                                                                      */
+/* ------------------------------------------------------------------------- */
+
+/* Thread-local message for the calling thread's last non-OK status. */
+const char* qf_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t qf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QF_H */

@@ -1,0 +1,315 @@
+"""Python binding of libqf.so, the MI355X (gfx950) qudit state-vector library.
+
+Every function named ``qf_*`` here marshals arguments for the C entry point of
+the same name in ``include/qf.h``; all computation runs in the HIP kernels of
+that library.  PyTorch supplies device memory and the current HIP stream.  If
+the shared library is missing, importing this package raises: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, List, Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libqf.so")
+
+QF_OK, QF_EINVAL, QF_EDTYPE, QF_ERANGE, QF_ENOMEM, QF_EHIP, QF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+QF_C64, QF_C128 = 0, 1
+(QF_OP_H, QF_OP_X, QF_OP_CLOCK, QF_OP_RX, QF_OP_RY, QF_OP_RZ, QF_OP_CSUM, QF_OP_CSHIFT, QF_OP_CZ,
+ QF_OP_U) = range(10)
+
+
+class QfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"qf status {status}: {msg}")
+        self.status = status
+
+
+class qf_state(ctypes.Structure):
+    _fields_ = [("amps", ctypes.c_void_p), ("n", ctypes.c_int32), ("dim", ctypes.c_int32),
+                ("batch", ctypes.c_int64), ("dtype", ctypes.c_int32)]
+
+
+class qf_op(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("q0", ctypes.c_int32), ("q1", ctypes.c_int32),
+                ("j", ctypes.c_int32), ("k", ctypes.c_int32), ("param", ctypes.c_int32),
+                ("shifts", ctypes.c_int32 * 16), ("mat", ctypes.POINTER(ctypes.c_double))]
+
+
+class qf_plan_opts(ctypes.Structure):
+    _fields_ = [("fuse", ctypes.c_int32), ("tile_digits", ctypes.c_int32), ("ckpt_every", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
+
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_PI32 = ctypes.POINTER(ctypes.c_int32)
+_PD = ctypes.POINTER(ctypes.c_double)
+_PS = ctypes.POINTER(qf_state)
+
+_SIGS = {
+    "qf_state_init": [_PS, _PI32, _P],
+    "qf_apply_1q": [_PS, _I32, _PD, _P],
+    "qf_apply_ctrl": [_PS, _I32, _I32, _PI32, _P],
+    "qf_apply_diag": [_PS, _I32, _PI32, _PD, _P],
+    "qf_apply_fused": [_PS, _I32, _I32, _P, _P],
+    "qf_probs": [_PS, _I32, _PI32, _P, _P],
+    "qf_expect": [_PS, _I32, _PI32, _PD, _PD, _P],
+    "qf_plan_create": [_I32, _I32, _I32, ctypes.POINTER(qf_op), _I32, _I32, ctypes.POINTER(qf_plan_opts),
+                       ctypes.POINTER(ctypes.c_void_p)],
+    "qf_plan_forward": [_P, _PS, _PD, _P],
+    "qf_adjoint_grad": [_P, _PS, _PS, _PD, _I32, _PI32, _PD, _PD, _P],
+}
+
+
+def _load() -> ctypes.CDLL:
+    # torch links its own libamdhip64 (soname libamdhip64.so.7).  Loading torch
+    # first lets libqf.so bind to that same HIP runtime by soname; loading
+    # libqf.so first would put a second HIP runtime in the process.
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2409_17716_amd.build` "
+                          "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, args in _SIGS.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int32
+    lib.qf_last_error.restype = ctypes.c_char_p
+    lib.qf_last_error.argtypes = []
+    lib.qf_version.restype = ctypes.c_int32
+    lib.qf_plan_num_stages.restype = ctypes.c_int32
+    lib.qf_plan_num_stages.argtypes = [_P]
+    lib.qf_plan_destroy.restype = None
+    lib.qf_plan_destroy.argtypes = [_P]
+    return lib
+
+
+lib = _load()
+
+
+def _check(st: int) -> None:
+    if st != QF_OK:
+        raise QfError(st, lib.qf_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None) -> int:
+    if stream is not None:
+        return int(stream)
+    return int(_torch().cuda.current_stream().cuda_stream)
+
+
+def _i32(a) -> ctypes.Array:
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+    return a, a.ctypes.data_as(_PI32)
+
+
+def _c128(a) -> tuple:
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.complex128)).view(np.float64)
+    return a, a.ctypes.data_as(_PD)
+
+
+def state_of(t, n: int, dim: int, batch: Optional[int] = None) -> qf_state:
+    """qf_state describing a torch complex64/complex128 CUDA tensor of batch*dim^n amplitudes."""
+    torch = _torch()
+    if not t.is_cuda:
+        raise QfError(QF_EINVAL, "state tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise QfError(QF_EINVAL, "state tensor must be contiguous")
+    if t.dtype == torch.complex64:
+        dt = QF_C64
+    elif t.dtype == torch.complex128:
+        dt = QF_C128
+    else:
+        raise QfError(QF_EDTYPE, f"unsupported dtype {t.dtype}")
+    N = dim ** n
+    b = t.numel() // N if batch is None else batch
+    if b * N != t.numel():
+        raise QfError(QF_EINVAL, f"tensor of {t.numel()} elements is not batch * {dim}^{n}")
+    return qf_state(t.data_ptr(), n, dim, b, dt)
+
+
+# ---------------------------------------------------------------------------
+# Per-gate entry points (same names as the C ABI).
+# ---------------------------------------------------------------------------
+
+def qf_state_init(t, n: int, dim: int, digits=None, stream=None) -> None:
+    s = state_of(t, n, dim)
+    if digits is None:
+        _check(lib.qf_state_init(ctypes.byref(s), None, _stream(stream)))
+    else:
+        arr, p = _i32(np.broadcast_to(np.asarray(digits), (s.batch, n)).reshape(-1))
+        _check(lib.qf_state_init(ctypes.byref(s), p, _stream(stream)))
+
+
+def qf_apply_1q(t, n: int, dim: int, q: int, U, stream=None) -> None:
+    s = state_of(t, n, dim)
+    arr, p = _c128(U)
+    _check(lib.qf_apply_1q(ctypes.byref(s), q, p, _stream(stream)))
+
+
+def qf_apply_ctrl(t, n: int, dim: int, ctrl: int, tgt: int, shift, stream=None) -> None:
+    s = state_of(t, n, dim)
+    arr, p = _i32(shift)
+    _check(lib.qf_apply_ctrl(ctypes.byref(s), ctrl, tgt, p, _stream(stream)))
+
+
+def qf_apply_diag(t, n: int, dim: int, qudits: Sequence[int], phases, stream=None) -> None:
+    s = state_of(t, n, dim)
+    qa, qp = _i32(qudits)
+    pa, pp = _c128(phases)
+    _check(lib.qf_apply_diag(ctypes.byref(s), len(qudits), qp, pp, _stream(stream)))
+
+
+def qf_apply_fused(t, n: int, dim: int, q0: int, k: int, B, stream=None) -> None:
+    """B: device tensor (K x K) in the state's precision."""
+    s = state_of(t, n, dim)
+    if not B.is_cuda or B.dtype != t.dtype or not B.is_contiguous():
+        raise QfError(QF_EINVAL, "B must be a contiguous device tensor of the state's dtype")
+    _check(lib.qf_apply_fused(ctypes.byref(s), k, q0, ctypes.c_void_p(B.data_ptr()), _stream(stream)))
+
+
+def qf_probs(t, n: int, dim: int, qudits: Optional[Sequence[int]] = None, out=None, stream=None):
+    torch = _torch()
+    s = state_of(t, n, dim)
+    rdt = torch.float32 if t.dtype == torch.complex64 else torch.float64
+    m = 0 if qudits is None else len(qudits)
+    size = s.batch * (dim ** (n if m == 0 else m))
+    if out is None:
+        out = torch.empty(size, dtype=rdt, device=t.device)
+    if qudits is None:
+        _check(lib.qf_probs(ctypes.byref(s), 0, None, ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    else:
+        qa, qp = _i32(qudits)
+        _check(lib.qf_probs(ctypes.byref(s), m, qp, ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def _terms_arrays(dim: int, terms) -> tuple:
+    """terms: list of (qudit, "z") or (qudit, table of dim complex values)."""
+    qs = [int(q) for q, _ in terms]
+    w = np.exp(2j * np.pi / dim)
+    tabs = []
+    for _, d in terms:
+        if isinstance(d, str):
+            if d != "z":
+                raise QfError(QF_EINVAL, f"unknown term {d}")
+            tabs.append(w ** np.arange(dim))
+        else:
+            tabs.append(np.asarray(d, dtype=np.complex128))
+    return qs, np.concatenate(tabs)
+
+
+def qf_expect(t, n: int, dim: int, terms, out=None, stream=None):
+    torch = _torch()
+    s = state_of(t, n, dim)
+    qs, tab = _terms_arrays(dim, terms)
+    qa, qp = _i32(qs)
+    ta, tp = _c128(tab)
+    if out is None:
+        out = torch.empty(2 * s.batch, dtype=torch.float64, device=t.device)
+    _check(lib.qf_expect(ctypes.byref(s), len(qs), qp, tp,
+                         ctypes.cast(ctypes.c_void_p(out.data_ptr()), _PD), _stream(stream)))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Plans.
+# ---------------------------------------------------------------------------
+
+_KIND = {"h": QF_OP_H, "x": QF_OP_X, "clock": QF_OP_CLOCK, "rx": QF_OP_RX, "ry": QF_OP_RY, "rz": QF_OP_RZ,
+         "csum": QF_OP_CSUM, "cshift": QF_OP_CSHIFT, "cz": QF_OP_CZ, "u": QF_OP_U}
+
+
+def ops_to_c(ops: Sequence[tuple]):
+    """Translate gate descriptors (see qf_inputs) into a qf_op array; returns the
+    array and the host matrices it points to (kept alive by the caller)."""
+    arr = (qf_op * max(1, len(ops)))()
+    keep = []
+    for i, op in enumerate(ops):
+        kind = op[0]
+        o = arr[i]
+        o.kind = _KIND[kind]
+        o.param = -1
+        if kind == "h":
+            o.q0 = op[1]
+        elif kind in ("x", "clock"):
+            o.q0, o.j = op[1], int(op[2])
+        elif kind in ("rx", "ry"):
+            o.q0, o.j, o.k, o.param = op[1], op[2], op[3], op[4]
+        elif kind == "rz":
+            o.q0, o.j, o.param = op[1], op[2], op[3]
+        elif kind in ("csum", "cz"):
+            o.q0, o.q1 = op[1], op[2]
+        elif kind == "cshift":
+            o.q0, o.q1 = op[1], op[2]
+            for c, v in enumerate(op[3]):
+                o.shifts[c] = int(v)
+        elif kind == "u":
+            o.q0, o.q1 = op[1], op[2]
+            m, p = _c128(op[3])
+            keep.append(m)
+            o.mat = p
+        else:
+            raise QfError(QF_EINVAL, f"unknown gate kind {kind}")
+    return arr, keep
+
+
+class Plan:
+    """A compiled circuit (qf_plan_create) for registers of n qudits of dimension dim."""
+
+    def __init__(self, dim: int, n: int, ops: Sequence[tuple], nparams: int, dtype: str = "c64",
+                 fuse: int = 0, tile_digits: int = 0, ckpt_every: int = 0):
+        self.dim, self.n, self.nparams = dim, n, nparams
+        self.dtype = QF_C64 if dtype == "c64" else QF_C128
+        arr, keep = ops_to_c(ops)
+        opts = qf_plan_opts(fuse, tile_digits, ckpt_every)
+        h = ctypes.c_void_p()
+        _check(lib.qf_plan_create(dim, n, self.dtype, arr, len(ops), nparams, ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def num_stages(self) -> int:
+        return lib.qf_plan_num_stages(self._h)
+
+    def forward(self, t, theta, stream=None) -> None:
+        s = state_of(t, self.n, self.dim)
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+        _check(lib.qf_plan_forward(self._h, ctypes.byref(s), th.ctypes.data_as(_PD), _stream(stream)))
+
+    def adjoint_grad(self, psi, lam, theta, terms, stream=None) -> np.ndarray:
+        s = state_of(psi, self.n, self.dim)
+        sl = state_of(lam, self.n, self.dim)
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+        qs, tab = _terms_arrays(self.dim, terms)
+        qa, qp = _i32(qs)
+        ta, tp = _c128(tab)
+        g = np.zeros(s.batch * self.nparams, dtype=np.float64)
+        _check(lib.qf_adjoint_grad(self._h, ctypes.byref(s), ctypes.byref(sl), th.ctypes.data_as(_PD), len(qs),
+                                   qp, tp, g.ctypes.data_as(_PD), _stream(stream)))
+        return g.reshape(s.batch, self.nparams) if s.batch > 1 else g
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and lib is not None:
+            lib.qf_plan_destroy(h)
+            self._h = None
+
+
+def plan_for(circuit, dtype: str = "c64", **kw) -> Plan:
+    return Plan(circuit.dim, circuit.n, circuit.ops, circuit.nparams, dtype, **kw)
+
+
+def new_state(n: int, dim: int, dtype: str = "c64", batch: int = 1, device="cuda"):
+    torch = _torch()
+    dt = torch.complex64 if dtype == "c64" else torch.complex128
+    return torch.empty(batch * dim ** n, dtype=dt, device=device)

@@ -1,0 +1,206 @@
+// C ABI of the per-gate entry points: argument validation (synchronous, before
+// any HIP call) and dispatch to the kernel launchers.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "qf_internal.h"
+
+namespace qf {
+
+static thread_local char g_err[512] = "";
+
+qf_status set_error(qf_status st, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+qf_status check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_error(QF_EHIP, "%s: launch failed: %s", what, hipGetErrorString(e));
+    return QF_OK;
+}
+
+qf_status make_view(const qf_state* s, StateView& v) {
+    QF_RETURN_IF(s == nullptr, QF_EINVAL, "state is NULL");
+    QF_RETURN_IF(s->amps == nullptr, QF_EINVAL, "state amplitudes pointer is NULL");
+    QF_RETURN_IF(s->dtype != QF_C64 && s->dtype != QF_C128, QF_EDTYPE, "unknown dtype %d", s->dtype);
+    QF_RETURN_IF(s->dim < 2 || s->dim > kMaxDim, QF_ERANGE, "dim %d outside 2..%d", s->dim, kMaxDim);
+    QF_RETURN_IF(s->n < 1, QF_EINVAL, "n = %d < 1", s->n);
+    QF_RETURN_IF(s->batch < 1, QF_EINVAL, "batch = %lld < 1", (long long)s->batch);
+    uint64_t N = 1;
+    for (int i = 0; i < s->n; ++i) {
+        N *= uint64_t(s->dim);
+        QF_RETURN_IF(N >= (1ull << 32), QF_ERANGE, "dim^n exceeds 2^32 amplitudes");
+    }
+    const uint64_t total = N * uint64_t(s->batch);
+    QF_RETURN_IF(total >= (1ull << 32), QF_ERANGE, "batch * dim^n = %llu exceeds 2^32 - 1",
+                 (unsigned long long)total);
+    v.amps = s->amps;
+    v.n = uint32_t(s->n);
+    v.D = uint32_t(s->dim);
+    v.N = uint32_t(N);
+    v.batch = uint32_t(s->batch);
+    v.total = uint32_t(total);
+    v.dtype = s->dtype;
+    return QF_OK;
+}
+
+static qf_status check_qudit(const StateView& v, int q, const char* what) {
+    QF_RETURN_IF(q < 0 || uint32_t(q) >= v.n, QF_EINVAL, "%s qudit %d outside [0, %u)", what, q, v.n);
+    return QF_OK;
+}
+
+static qf_status check_finite(const double* a, size_t cnt, const char* what) {
+    for (size_t i = 0; i < cnt; ++i)
+        QF_RETURN_IF(!std::isfinite(a[i]), QF_EINVAL, "%s contains a non-finite value at %zu", what, i);
+    return QF_OK;
+}
+
+// Combine one-qudit diagonal terms into per-qudit tables (terms on the same
+// qudit add up).  Returns the active qudits and a [active][D] complex table.
+qf_status combine_terms(const StateView& v, int32_t nterms, const int32_t* term_qudit, const double* term_diag,
+                        std::vector<int>& active, std::vector<double>& table) {
+    QF_RETURN_IF(nterms < 1, QF_EINVAL, "nterms = %d < 1", nterms);
+    QF_RETURN_IF(term_qudit == nullptr || term_diag == nullptr, QF_EINVAL, "term arrays are NULL");
+    QF_CHECK(check_finite(term_diag, size_t(nterms) * v.D * 2, "term_diag"));
+    std::vector<int> slot(v.n, -1);
+    active.clear();
+    table.clear();
+    for (int t = 0; t < nterms; ++t) {
+        QF_CHECK(check_qudit(v, term_qudit[t], "term"));
+        int q = term_qudit[t];
+        if (slot[q] < 0) {
+            slot[q] = int(active.size());
+            active.push_back(q);
+            table.resize(table.size() + 2 * v.D, 0.0);
+        }
+        for (uint32_t d = 0; d < v.D; ++d) {
+            table[2 * (slot[q] * v.D + d)] += term_diag[2 * (size_t(t) * v.D + d)];
+            table[2 * (slot[q] * v.D + d) + 1] += term_diag[2 * (size_t(t) * v.D + d) + 1];
+        }
+    }
+    QF_RETURN_IF(active.size() * v.D > 128 || active.size() > 32, QF_ERANGE,
+                 "observable spans %zu qudits x D=%u > 128 table entries", active.size(), v.D);
+    return QF_OK;
+}
+
+}  // namespace qf
+
+using namespace qf;
+
+extern "C" {
+
+const char* qf_last_error(void) { return g_err; }
+
+int32_t qf_version(void) { return 100; }
+
+qf_status qf_state_init(const qf_state* s, const int32_t* digits, void* stream) {
+    StateView v;
+    QF_CHECK(make_view(s, v));
+    std::vector<uint32_t> idx;
+    if (digits == nullptr) {
+        idx.push_back(0);
+    } else {
+        bool same = true;
+        for (uint32_t b = 0; b < v.batch; ++b) {
+            uint32_t x = 0;
+            for (uint32_t k = 0; k < v.n; ++k) {
+                const int32_t d = digits[size_t(b) * v.n + k];
+                QF_RETURN_IF(d < 0 || uint32_t(d) >= v.D, QF_EINVAL, "digit %d of register %u outside [0, %u)",
+                             d, b, v.D);
+                x = x * v.D + uint32_t(d);
+            }
+            if (!idx.empty() && idx[0] != x) same = false;
+            idx.push_back(x);
+        }
+        if (same) idx.resize(1);
+    }
+    return launch_init(v, idx, reinterpret_cast<hipStream_t>(stream));
+}
+
+qf_status qf_apply_1q(const qf_state* s, int32_t q, const double* U, void* stream) {
+    StateView v;
+    QF_CHECK(make_view(s, v));
+    QF_CHECK(check_qudit(v, q, "target"));
+    QF_RETURN_IF(U == nullptr, QF_EINVAL, "U is NULL");
+    QF_CHECK(check_finite(U, size_t(v.D) * v.D * 2, "U"));
+    return launch_apply_1q(v, q, U, reinterpret_cast<hipStream_t>(stream));
+}
+
+qf_status qf_apply_ctrl(const qf_state* s, int32_t ctrl, int32_t tgt, const int32_t* shift, void* stream) {
+    StateView v;
+    QF_CHECK(make_view(s, v));
+    QF_CHECK(check_qudit(v, tgt, "target"));
+    QF_RETURN_IF(ctrl != -1 && (ctrl < 0 || uint32_t(ctrl) >= v.n), QF_EINVAL, "control qudit %d outside [-1, %u)",
+                 ctrl, v.n);
+    QF_RETURN_IF(ctrl == tgt, QF_EINVAL, "control and target are both %d", ctrl);
+    QF_RETURN_IF(shift == nullptr, QF_EINVAL, "shift is NULL");
+    return launch_ctrl(v, ctrl, tgt, shift, reinterpret_cast<hipStream_t>(stream));
+}
+
+qf_status qf_apply_diag(const qf_state* s, int32_t k, const int32_t* qudits, const double* phases, void* stream) {
+    StateView v;
+    QF_CHECK(make_view(s, v));
+    QF_RETURN_IF(k < 1 || k > 8 || uint32_t(k) > v.n, QF_EINVAL, "k = %d outside [1, min(8, n)]", k);
+    QF_RETURN_IF(qudits == nullptr || phases == nullptr, QF_EINVAL, "qudits or phases is NULL");
+    for (int i = 0; i < k; ++i) {
+        QF_CHECK(check_qudit(v, qudits[i], "diagonal"));
+        for (int j = 0; j < i; ++j)
+            QF_RETURN_IF(qudits[i] == qudits[j], QF_EINVAL, "qudit %d listed twice", qudits[i]);
+    }
+    QF_CHECK(check_finite(phases, size_t(ipow(v.D, k)) * 2, "phases"));
+    return launch_diag(v, k, qudits, phases, reinterpret_cast<hipStream_t>(stream));
+}
+
+qf_status qf_apply_fused(const qf_state* s, int32_t k, int32_t q0, const void* B, void* stream) {
+    StateView v;
+    QF_CHECK(make_view(s, v));
+    QF_RETURN_IF(k < 1 || uint32_t(k) > v.n, QF_EINVAL, "k = %d outside [1, n]", k);
+    QF_RETURN_IF(q0 < 0 || uint32_t(q0 + k) > v.n, QF_EINVAL, "qudits %d..%d outside [0, %u)", q0, q0 + k - 1, v.n);
+    uint64_t K = 1;
+    for (int i = 0; i < k; ++i) K *= v.D;
+    QF_RETURN_IF(K > 1024, QF_ERANGE, "block size D^k = %llu > 1024", (unsigned long long)K);
+    QF_RETURN_IF(B == nullptr, QF_EINVAL, "B is NULL");
+    return launch_fused(v, k, q0, B, reinterpret_cast<hipStream_t>(stream));
+}
+
+qf_status qf_probs(const qf_state* s, int32_t m, const int32_t* qudits, void* out, void* stream) {
+    StateView v;
+    QF_CHECK(make_view(s, v));
+    QF_RETURN_IF(out == nullptr, QF_EINVAL, "out is NULL");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (m == 0) {
+        QF_RETURN_IF(qudits != nullptr, QF_EINVAL, "m = 0 requires qudits = NULL");
+        return launch_probs_full(v, out, st);
+    }
+    QF_RETURN_IF(m < 0 || uint32_t(m) > v.n || m > 32, QF_EINVAL, "m = %d outside [0, min(n, 32)]", m);
+    QF_RETURN_IF(qudits == nullptr, QF_EINVAL, "qudits is NULL");
+    bool identity = uint32_t(m) == v.n;
+    for (int i = 0; i < m; ++i) {
+        QF_CHECK(check_qudit(v, qudits[i], "measured"));
+        for (int j = 0; j < i; ++j)
+            QF_RETURN_IF(qudits[i] == qudits[j], QF_EINVAL, "qudit %d listed twice", qudits[i]);
+        identity = identity && qudits[i] == i;
+    }
+    if (identity) return launch_probs_full(v, out, st);
+    return launch_probs_marginal(v, m, qudits, out, st);
+}
+
+qf_status qf_expect(const qf_state* s, int32_t nterms, const int32_t* term_qudit, const double* term_diag,
+                    double* out, void* stream) {
+    StateView v;
+    QF_CHECK(make_view(s, v));
+    QF_RETURN_IF(out == nullptr, QF_EINVAL, "out is NULL");
+    std::vector<int> active;
+    std::vector<double> table;
+    QF_CHECK(combine_terms(v, nterms, term_qudit, term_diag, active, table));
+    return launch_expect(v, active, table, out, reinterpret_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

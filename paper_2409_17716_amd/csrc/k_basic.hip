@@ -1,0 +1,586 @@
+// Per-gate sweep kernels for gfx950: state init, one-qudit D x D mat-vec along
+// an axis, controlled-shift permutations, diagonal phases, probabilities and
+// diagonal expectation values.
+//
+// A register of n qudits is viewed, for a gate on qudit q, as [H][D][L] with
+// H = batch * D^q and L = D^(n-1-q) (the decimal index puts qudit 0 first).
+// A "fibre" is the D amplitudes psi[h, :, l].
+//  * L >= 64: one fibre per lane, lanes take consecutive l, so each of the D
+//    loads of a wavefront is one contiguous 64-element run (coalesced).
+//  * L <  64: a workgroup stages whole [D][L] rows (contiguous in HBM) through
+//    LDS with coalesced loads/stores and each lane processes one fibre from LDS.
+#include <type_traits>
+
+#include "qf_internal.h"
+
+namespace qf {
+namespace {
+
+constexpr int kBlock = 256;
+
+template <typename T, int D>
+struct MatArg {
+    cplx<T> m[D * D];
+};
+
+// ---------------------------------------------------------------------------
+// Fibre operations.
+// ---------------------------------------------------------------------------
+
+template <typename T, int D>
+struct OpMat {
+    MatArg<T, D> U;
+    __device__ bool skip(uint32_t) const { return false; }
+    __device__ void apply(cplx<T> (&v)[D], uint32_t) const {
+        cplx<T> w[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            cplx<T> acc = cmake<T>(0, 0);
+#pragma unroll
+            for (int b = 0; b < D; ++b) cmac(acc, U.m[a * D + b], v[b]);
+            w[a] = acc;
+        }
+#pragma unroll
+        for (int a = 0; a < D; ++a) v[a] = w[a];
+    }
+};
+
+// x_t -> x_t + shift[x_c] mod D; the control digit is read from the global
+// index of the fibre (any element of the fibre has the same x_c).
+template <typename T, int D>
+struct OpShift {
+    int32_t shift[D];  // already reduced to [0, D)
+    FastDiv strideC;   // x_c = (index / D^(n-1-c)) mod D
+    int32_t has_ctrl;
+    __device__ int amount(uint32_t gidx) const {
+        if (!has_ctrl) return shift[0];
+        const uint32_t c = strideC.div(gidx) % D;
+        int s = shift[0];
+#pragma unroll
+        for (int a = 1; a < D; ++a) s = (c == uint32_t(a)) ? shift[a] : s;
+        return s;
+    }
+    __device__ bool skip(uint32_t gidx) const { return amount(gidx) == 0; }
+    // v[b] <- v[(b - s) mod D] as a barrel of rotations by 1, 2, 4, ...: every
+    // register index is a compile-time constant, so nothing is spilled.
+    __device__ void apply(cplx<T> (&v)[D], uint32_t gidx) const {
+        const int s = amount(gidx);
+#pragma unroll
+        for (int bit = 1; bit < D; bit <<= 1) {
+            const bool on = (s & bit) != 0;
+            cplx<T> w[D];
+#pragma unroll
+            for (int b = 0; b < D; ++b) w[b] = v[(b - bit % D + D) % D];
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                v[b].re = on ? w[b].re : v[b].re;
+                v[b].im = on ? w[b].im : v[b].im;
+            }
+        }
+    }
+};
+
+template <typename T, int D, class Op>
+__global__ __launch_bounds__(kBlock) void k_axis_wide(cplx<T>* __restrict__ psi, uint32_t nfib,
+                                                      uint32_t L, FastDiv divL, Op op) {
+    const uint32_t f = blockIdx.x * kBlock + threadIdx.x;
+    if (f >= nfib) return;
+    const uint32_t h = divL.div(f);
+    const uint32_t l = f - h * L;
+    const uint32_t base = h * (uint32_t(D) * L) + l;
+    if (op.skip(base)) return;
+    cplx<T> v[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) v[d] = psi[base + uint32_t(d) * L];
+    op.apply(v, base);
+#pragma unroll
+    for (int d = 0; d < D; ++d) psi[base + uint32_t(d) * L] = v[d];
+}
+
+template <typename T, int D, class Op>
+__global__ __launch_bounds__(kBlock) void k_axis_narrow(cplx<T>* __restrict__ psi, uint32_t total,
+                                                        uint32_t L, uint32_t rows, Op op) {
+    __shared__ cplx<T> tile[kBlock * D];
+    const uint32_t E = rows * uint32_t(D) * L;  // <= kBlock * D
+    const uint32_t start = blockIdx.x * E;
+    const uint32_t cnt = min(E, total - start);
+    for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) tile[i] = psi[start + i];
+    __syncthreads();
+    const uint32_t nf = cnt / D;
+    if (threadIdx.x < nf) {
+        const uint32_t r = threadIdx.x / L;
+        const uint32_t l = threadIdx.x - r * L;
+        const uint32_t off = r * uint32_t(D) * L + l;
+        if (!op.skip(start + off)) {
+            cplx<T> v[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) v[d] = tile[off + uint32_t(d) * L];
+            op.apply(v, start + off);
+#pragma unroll
+            for (int d = 0; d < D; ++d) tile[off + uint32_t(d) * L] = v[d];
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) psi[start + i] = tile[i];
+}
+
+template <typename T, int D, class Op>
+qf_status run_axis(const StateView& s, int q, const Op& op, hipStream_t st, const char* what) {
+    auto* psi = reinterpret_cast<cplx<T>*>(s.amps);
+    const uint32_t L = ipow(D, s.n - 1 - q);
+    if (L >= 64) {
+        const uint32_t nfib = s.total / D;
+        const uint32_t grid = (nfib + kBlock - 1) / kBlock;
+        hipLaunchKernelGGL((k_axis_wide<T, D, Op>), dim3(grid), dim3(kBlock), 0, st, psi, nfib, L,
+                           FastDiv(L), op);
+    } else {
+        const uint32_t rows = (kBlock / L) > 0 ? kBlock / L : 1;
+        const uint32_t E = rows * D * L;
+        const uint32_t grid = (s.total + E - 1) / E;
+        hipLaunchKernelGGL((k_axis_narrow<T, D, Op>), dim3(grid), dim3(kBlock), 0, st, psi, s.total,
+                           L, rows, op);
+    }
+    return check_launch(what);
+}
+
+// ---------------------------------------------------------------------------
+// Compile-time dispatch on dtype and D.
+// ---------------------------------------------------------------------------
+
+template <class F>
+qf_status with_dim(uint32_t D, F&& f) {
+    switch (D) {
+        case 2: return f(std::integral_constant<int, 2>{});
+        case 3: return f(std::integral_constant<int, 3>{});
+        case 4: return f(std::integral_constant<int, 4>{});
+        case 5: return f(std::integral_constant<int, 5>{});
+        case 6: return f(std::integral_constant<int, 6>{});
+        case 7: return f(std::integral_constant<int, 7>{});
+        case 8: return f(std::integral_constant<int, 8>{});
+        case 9: return f(std::integral_constant<int, 9>{});
+        case 10: return f(std::integral_constant<int, 10>{});
+        case 11: return f(std::integral_constant<int, 11>{});
+        case 12: return f(std::integral_constant<int, 12>{});
+        case 13: return f(std::integral_constant<int, 13>{});
+        case 14: return f(std::integral_constant<int, 14>{});
+        case 15: return f(std::integral_constant<int, 15>{});
+        case 16: return f(std::integral_constant<int, 16>{});
+        default: return set_error(QF_EUNSUPPORTED, "dim %u outside 2..16", D);
+    }
+}
+
+template <class F>
+qf_status with_type(int dtype, F&& f) {
+    if (dtype == QF_C64) return f(float{});
+    if (dtype == QF_C128) return f(double{});
+    return set_error(QF_EDTYPE, "unknown dtype %d", dtype);
+}
+
+// ---------------------------------------------------------------------------
+// Init.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_init(cplx<T>* __restrict__ psi, uint32_t total, uint32_t N,
+                                                 FastDiv divN, const uint32_t* __restrict__ idx,
+                                                 uint32_t idx0) {
+    for (uint32_t x = blockIdx.x * kBlock + threadIdx.x; x < total; x += gridDim.x * kBlock) {
+        const uint32_t b = divN.div(x);
+        const uint32_t local = x - b * N;
+        const uint32_t target = idx ? idx[b] : idx0;
+        psi[x] = cmake<T>(local == target ? T(1) : T(0), T(0));
+    }
+}
+
+uint32_t grid_for(uint32_t total, uint32_t per_block, uint32_t cap = 1u << 20) {
+    uint32_t g = (total + per_block - 1) / per_block;
+    return g < 1 ? 1 : (g > cap ? cap : g);
+}
+
+// ---------------------------------------------------------------------------
+// Diagonal phases.
+// ---------------------------------------------------------------------------
+
+constexpr int kDiagBytes = 2048;
+
+template <typename T>
+struct DiagArg {
+    static constexpr int kMax = kDiagBytes / int(sizeof(cplx<T>));
+    FastDiv stride[8];
+    FastDiv divD;
+    uint32_t D;
+    uint32_t k;
+    uint32_t ntab;
+    cplx<T> table[kMax];
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_diag(cplx<T>* __restrict__ psi, uint32_t total,
+                                                 DiagArg<T> a) {
+    __shared__ cplx<T> tab[DiagArg<T>::kMax];
+    for (uint32_t i = threadIdx.x; i < a.ntab; i += kBlock) tab[i] = a.table[i];
+    __syncthreads();
+    for (uint32_t x = blockIdx.x * kBlock + threadIdx.x; x < total; x += gridDim.x * kBlock) {
+        uint32_t y = 0;
+        for (uint32_t i = 0; i < a.k; ++i) {
+            const uint32_t qv = a.stride[i].div(x);
+            y = y * a.D + (qv - a.divD.div(qv) * a.D);
+        }
+        psi[x] = cmul(psi[x], tab[y]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Probabilities.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_probs_full(const cplx<T>* __restrict__ psi, T* __restrict__ out,
+                                                       uint32_t total) {
+    for (uint32_t x = blockIdx.x * kBlock + threadIdx.x; x < total; x += gridDim.x * kBlock) {
+        const cplx<T> v = psi[x];
+        out[x] = v.re * v.re + v.im * v.im;
+    }
+}
+
+// Deterministic workgroup sum of one double per lane (fixed tree order).
+__device__ inline double block_sum(double v, double* sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+constexpr int kMaxMarg = 32;
+
+struct MargArg {
+    uint32_t N;           // D^n
+    uint32_t Z;           // elements per bin = D^(n-m)
+    uint32_t R;           // trailing contiguous run (digits below every measured qudit)
+    FastDiv divR;
+    FastDiv divD;
+    uint32_t D;
+    uint32_t m;           // measured qudits
+    uint32_t u;           // other (non-trailing, unmeasured) qudits
+    uint32_t bins;        // D^m
+    uint32_t chunk;       // elements of one bin summed by one workgroup
+    uint32_t chunks;      // workgroups per bin
+    uint32_t mstride[kMaxMarg];  // strides of measured qudits, listed order
+    uint32_t ostride[kMaxMarg];  // strides of the other qudits, most significant first
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_marg_partial(const cplx<T>* __restrict__ psi, MargArg a,
+                                                         double* __restrict__ partial) {
+    __shared__ double sh[kBlock];
+    const uint32_t c = blockIdx.x % a.chunks;
+    const uint32_t yb = blockIdx.x / a.chunks;
+    const uint32_t b = yb / a.bins;
+    const uint32_t y = yb - b * a.bins;
+    // base offset of bin y in register b
+    uint32_t base = b * a.N;
+    {
+        uint32_t yy = y;
+        for (int i = int(a.m) - 1; i >= 0; --i) {
+            const uint32_t q = a.divD.div(yy);
+            base += (yy - q * a.D) * a.mstride[i];
+            yy = q;
+        }
+    }
+    const uint32_t z0 = c * a.chunk;
+    const uint32_t z1 = min(a.Z, z0 + a.chunk);
+    double acc = 0.0;
+    for (uint32_t z = z0 + threadIdx.x; z < z1; z += kBlock) {
+        uint32_t zh = a.divR.div(z);
+        const uint32_t zl = z - zh * a.R;
+        uint32_t off = 0;
+        for (int j = int(a.u) - 1; j >= 0; --j) {
+            const uint32_t q = a.divD.div(zh);
+            off += (zh - q * a.D) * a.ostride[j];
+            zh = q;
+        }
+        const cplx<T> v = psi[base + off + zl];
+        acc += double(v.re) * double(v.re) + double(v.im) * double(v.im);
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+template <typename T>
+__global__ void k_marg_final(const double* __restrict__ partial, uint32_t chunks, uint32_t nbins,
+                             T* __restrict__ out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nbins) return;
+    double s = 0.0;
+    for (uint32_t c = 0; c < chunks; ++c) s += partial[i * chunks + c];
+    out[i] = T(s);
+}
+
+// ---------------------------------------------------------------------------
+// Diagonal expectation values and the Hermitian part of a diagonal observable.
+// ---------------------------------------------------------------------------
+
+constexpr int kMaxActive = 32;
+constexpr int kMaxTable = 128;
+
+struct ObsArg {
+    uint32_t nact;
+    uint32_t D;
+    FastDiv divD;
+    FastDiv stride[kMaxActive];
+    double table[2 * kMaxTable];  // [active][D] complex, interleaved
+};
+
+__device__ inline void obs_value(const ObsArg& a, const double* tab, uint32_t x, double& fr, double& fi) {
+    fr = 0.0;
+    fi = 0.0;
+    for (uint32_t t = 0; t < a.nact; ++t) {
+        const uint32_t qv = a.stride[t].div(x);
+        const uint32_t d = qv - a.divD.div(qv) * a.D;
+        fr += tab[2 * (t * a.D + d)];
+        fi += tab[2 * (t * a.D + d) + 1];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_expect_partial(const cplx<T>* __restrict__ psi, uint32_t N,
+                                                           uint32_t chunk, uint32_t nblk, ObsArg a,
+                                                           double* __restrict__ partial) {
+    __shared__ double tab[2 * kMaxTable];
+    __shared__ double sh[kBlock];
+    for (uint32_t i = threadIdx.x; i < 2 * a.nact * a.D; i += kBlock) tab[i] = a.table[i];
+    __syncthreads();
+    const uint32_t b = blockIdx.x / nblk;
+    const uint32_t blk = blockIdx.x - b * nblk;
+    const uint32_t x0 = blk * chunk;
+    const uint32_t x1 = min(N, x0 + chunk);
+    const cplx<T>* reg = psi + size_t(b) * N;
+    double ar = 0.0, ai = 0.0;
+    for (uint32_t x = x0 + threadIdx.x; x < x1; x += kBlock) {
+        const cplx<T> v = reg[x];
+        const double p = double(v.re) * double(v.re) + double(v.im) * double(v.im);
+        double fr, fi;
+        obs_value(a, tab, x, fr, fi);
+        ar += p * fr;
+        ai += p * fi;
+    }
+    const double sr = block_sum(ar, sh);
+    const double si = block_sum(ai, sh);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = sr;
+        partial[2 * blockIdx.x + 1] = si;
+    }
+}
+
+__global__ void k_expect_final(const double* __restrict__ partial, uint32_t nblk, uint32_t batch,
+                               double* __restrict__ out) {
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    double sr = 0.0, si = 0.0;
+    for (uint32_t c = 0; c < nblk; ++c) {
+        sr += partial[2 * (b * nblk + c)];
+        si += partial[2 * (b * nblk + c) + 1];
+    }
+    out[2 * b] = sr;
+    out[2 * b + 1] = si;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_diag_observable(const cplx<T>* __restrict__ psi,
+                                                            cplx<T>* __restrict__ lam, uint32_t total,
+                                                            FastDiv divN, uint32_t N, ObsArg a) {
+    __shared__ double tab[2 * kMaxTable];
+    for (uint32_t i = threadIdx.x; i < 2 * a.nact * a.D; i += kBlock) tab[i] = a.table[i];
+    __syncthreads();
+    for (uint32_t x = blockIdx.x * kBlock + threadIdx.x; x < total; x += gridDim.x * kBlock) {
+        const uint32_t local = x - divN.div(x) * N;
+        double fr, fi;
+        obs_value(a, tab, local, fr, fi);
+        const cplx<T> v = psi[x];
+        lam[x] = cmake<T>(T(fr) * v.re, T(fr) * v.im);
+    }
+}
+
+ObsArg make_obs(const StateView& s, const std::vector<int>& active, const std::vector<double>& table,
+                bool real_only) {
+    ObsArg a{};
+    a.nact = uint32_t(active.size());
+    a.D = s.D;
+    a.divD.init(s.D);
+    for (size_t t = 0; t < active.size(); ++t) a.stride[t].init(ipow(s.D, s.n - 1 - active[t]));
+    for (size_t i = 0; i < active.size() * s.D; ++i) {
+        a.table[2 * i] = real_only ? table[i] : table[2 * i];
+        a.table[2 * i + 1] = real_only ? 0.0 : table[2 * i + 1];
+    }
+    return a;
+}
+
+}  // namespace
+
+// ===========================================================================
+// Launchers.
+// ===========================================================================
+
+qf_status launch_init(const StateView& s, const std::vector<uint32_t>& index, hipStream_t st) {
+    return with_type(s.dtype, [&](auto tag) -> qf_status {
+        using T = decltype(tag);
+        uint32_t* didx = nullptr;
+        uint32_t idx0 = index.empty() ? 0u : index[0];
+        if (index.size() > 1) {
+            QF_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&didx), index.size() * sizeof(uint32_t), st));
+            QF_HIP_CHECK(hipMemcpyAsync(didx, index.data(), index.size() * sizeof(uint32_t),
+                                        hipMemcpyHostToDevice, st));
+        }
+        hipLaunchKernelGGL(k_init<T>, dim3(grid_for(s.total, kBlock * 4)), dim3(kBlock), 0, st,
+                           reinterpret_cast<cplx<T>*>(s.amps), s.total, s.N, FastDiv(s.N), didx, idx0);
+        qf_status r = check_launch("k_init");
+        if (didx) QF_HIP_CHECK(hipFreeAsync(didx, st));
+        return r;
+    });
+}
+
+qf_status launch_apply_1q(const StateView& s, int q, const double* U, hipStream_t st) {
+    return with_type(s.dtype, [&](auto tag) -> qf_status {
+        using T = decltype(tag);
+        return with_dim(s.D, [&](auto dtag) -> qf_status {
+            constexpr int D = decltype(dtag)::value;
+            if constexpr (sizeof(MatArg<T, D>) > 2048) {
+                return set_error(QF_ERANGE, "dim %d too large for a complex128 kernel-argument matrix", D);
+            } else {
+                OpMat<T, D> op;
+                for (int i = 0; i < D * D; ++i) op.U.m[i] = cmake<T>(T(U[2 * i]), T(U[2 * i + 1]));
+                return run_axis<T, D>(s, q, op, st, "qf_apply_1q");
+            }
+        });
+    });
+}
+
+qf_status launch_ctrl(const StateView& s, int ctrl, int tgt, const int32_t* shift, hipStream_t st) {
+    return with_type(s.dtype, [&](auto tag) -> qf_status {
+        using T = decltype(tag);
+        return with_dim(s.D, [&](auto dtag) -> qf_status {
+            constexpr int D = decltype(dtag)::value;
+            OpShift<T, D> op;
+            const int nsh = ctrl < 0 ? 1 : D;
+            for (int i = 0; i < D; ++i) {
+                const int v = i < nsh ? shift[i] : 0;
+                op.shift[i] = ((v % D) + D) % D;
+            }
+            op.has_ctrl = ctrl >= 0;
+            op.strideC = FastDiv(ctrl >= 0 ? ipow(D, s.n - 1 - ctrl) : 1u);
+            return run_axis<T, D>(s, tgt, op, st, "qf_apply_ctrl");
+        });
+    });
+}
+
+qf_status launch_diag(const StateView& s, int k, const int32_t* qudits, const double* phases,
+                      hipStream_t st) {
+    return with_type(s.dtype, [&](auto tag) -> qf_status {
+        using T = decltype(tag);
+        DiagArg<T> a{};
+        a.D = s.D;
+        a.k = uint32_t(k);
+        a.ntab = ipow(s.D, k);
+        if (a.ntab > uint32_t(DiagArg<T>::kMax))
+            return set_error(QF_ERANGE, "D^k = %u exceeds %d table entries", a.ntab, DiagArg<T>::kMax);
+        a.divD.init(s.D);
+        for (int i = 0; i < k; ++i) a.stride[i].init(ipow(s.D, s.n - 1 - qudits[i]));
+        for (uint32_t i = 0; i < a.ntab; ++i) a.table[i] = cmake<T>(T(phases[2 * i]), T(phases[2 * i + 1]));
+        hipLaunchKernelGGL(k_diag<T>, dim3(grid_for(s.total, kBlock * 4)), dim3(kBlock), 0, st,
+                           reinterpret_cast<cplx<T>*>(s.amps), s.total, a);
+        return check_launch("qf_apply_diag");
+    });
+}
+
+qf_status launch_probs_full(const StateView& s, void* out, hipStream_t st) {
+    return with_type(s.dtype, [&](auto tag) -> qf_status {
+        using T = decltype(tag);
+        hipLaunchKernelGGL(k_probs_full<T>, dim3(grid_for(s.total, kBlock * 4)), dim3(kBlock), 0, st,
+                           reinterpret_cast<const cplx<T>*>(s.amps), reinterpret_cast<T*>(out), s.total);
+        return check_launch("qf_probs");
+    });
+}
+
+qf_status launch_probs_marginal(const StateView& s, int m, const int32_t* qudits, void* out,
+                                hipStream_t st) {
+    MargArg a{};
+    a.N = s.N;
+    a.D = s.D;
+    a.divD.init(s.D);
+    a.m = uint32_t(m);
+    a.bins = ipow(s.D, m);
+    a.Z = ipow(s.D, s.n - m);
+    int maxp = -1;
+    std::vector<bool> meas(s.n, false);
+    for (int i = 0; i < m; ++i) {
+        meas[qudits[i]] = true;
+        maxp = qudits[i] > maxp ? qudits[i] : maxp;
+        a.mstride[i] = ipow(s.D, s.n - 1 - qudits[i]);
+    }
+    const uint32_t r = s.n - 1 - uint32_t(maxp);
+    a.R = ipow(s.D, r);
+    a.divR.init(a.R);
+    uint32_t u = 0;
+    for (int p = 0; p < maxp; ++p)
+        if (!meas[p]) a.ostride[u++] = ipow(s.D, s.n - 1 - p);
+    a.u = u;
+    a.chunk = kBlock * 16;
+    a.chunks = (a.Z + a.chunk - 1) / a.chunk;
+    const uint64_t nblocks = uint64_t(a.chunks) * a.bins * s.batch;
+    if (nblocks >= (1ull << 31)) return set_error(QF_ERANGE, "marginal grid too large");
+    return with_type(s.dtype, [&](auto tag) -> qf_status {
+        using T = decltype(tag);
+        double* partial = nullptr;
+        QF_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&partial), nblocks * sizeof(double), st));
+        hipLaunchKernelGGL(k_marg_partial<T>, dim3(uint32_t(nblocks)), dim3(kBlock), 0, st,
+                           reinterpret_cast<const cplx<T>*>(s.amps), a, partial);
+        qf_status r1 = check_launch("qf_probs marginal");
+        const uint32_t nb = a.bins * s.batch;
+        hipLaunchKernelGGL(k_marg_final<T>, dim3((nb + 255) / 256), dim3(256), 0, st, partial, a.chunks, nb,
+                           reinterpret_cast<T*>(out));
+        qf_status r2 = check_launch("qf_probs marginal final");
+        QF_HIP_CHECK(hipFreeAsync(partial, st));
+        return r1 != QF_OK ? r1 : r2;
+    });
+}
+
+qf_status launch_expect(const StateView& s, const std::vector<int>& active, const std::vector<double>& table,
+                        double* out, hipStream_t st) {
+    ObsArg a = make_obs(s, active, table, false);
+    const uint32_t chunk = kBlock * 16;
+    const uint32_t nblk = (s.N + chunk - 1) / chunk;
+    const uint64_t nblocks = uint64_t(nblk) * s.batch;
+    if (nblocks >= (1ull << 31)) return set_error(QF_ERANGE, "expectation grid too large");
+    return with_type(s.dtype, [&](auto tag) -> qf_status {
+        using T = decltype(tag);
+        double* partial = nullptr;
+        QF_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&partial), nblocks * 2 * sizeof(double), st));
+        hipLaunchKernelGGL(k_expect_partial<T>, dim3(uint32_t(nblocks)), dim3(kBlock), 0, st,
+                           reinterpret_cast<const cplx<T>*>(s.amps), s.N, chunk, nblk, a, partial);
+        qf_status r1 = check_launch("qf_expect");
+        hipLaunchKernelGGL(k_expect_final, dim3((s.batch + 255) / 256), dim3(256), 0, st, partial, nblk,
+                           s.batch, out);
+        qf_status r2 = check_launch("qf_expect final");
+        QF_HIP_CHECK(hipFreeAsync(partial, st));
+        return r1 != QF_OK ? r1 : r2;
+    });
+}
+
+qf_status launch_diag_observable(const StateView& s, void* lam_amps, const std::vector<int>& active,
+                                 const std::vector<double>& table_re, hipStream_t st) {
+    ObsArg a = make_obs(s, active, table_re, true);
+    return with_type(s.dtype, [&](auto tag) -> qf_status {
+        using T = decltype(tag);
+        hipLaunchKernelGGL(k_diag_observable<T>, dim3(grid_for(s.total, kBlock * 4)), dim3(kBlock), 0, st,
+                           reinterpret_cast<const cplx<T>*>(s.amps), reinterpret_cast<cplx<T>*>(lam_amps),
+                           s.total, FastDiv(s.N), s.N, a);
+        return check_launch("diag observable");
+    });
+}
+
+}  // namespace qf

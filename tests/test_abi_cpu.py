@@ -1,0 +1,100 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/qf.h, and rejects bad arguments before touching HIP."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import qf_inputs as qi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qf.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(qf_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def qf():
+    import paper_2409_17716_amd as qf
+    return qf
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ["qf_state_init", "qf_apply_1q", "qf_apply_ctrl", "qf_apply_diag", "qf_apply_fused", "qf_probs",
+              "qf_expect", "qf_adjoint_grad"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(qf):
+    for name in _declared():
+        assert hasattr(qf.lib, name), name
+
+
+def test_version(qf):
+    assert qf.lib.qf_version() >= 100
+
+
+def _fake_state(qf, n=3, dim=3, batch=1, dtype=0):
+    return qf.qf_state(0x1000, n, dim, batch, dtype)
+
+
+def test_validation_errors_before_any_hip_call(qf):
+    lib = qf.lib
+    U = np.eye(3, dtype=np.complex128).view(np.float64)
+    pU = U.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    s = _fake_state(qf)
+    assert lib.qf_apply_1q(ctypes.byref(s), 3, pU, None) == qf.QF_EINVAL
+    assert b"outside" in lib.qf_last_error()
+    assert lib.qf_apply_1q(ctypes.byref(s), -1, pU, None) == qf.QF_EINVAL
+    assert lib.qf_apply_1q(None, 0, pU, None) == qf.QF_EINVAL
+    assert lib.qf_apply_1q(ctypes.byref(s), 0, None, None) == qf.QF_EINVAL
+    bad = np.array(U)
+    bad[0] = np.nan
+    assert lib.qf_apply_1q(ctypes.byref(s), 0, bad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                           None) == qf.QF_EINVAL
+    s_null = qf.qf_state(0, 3, 3, 1, 0)
+    assert lib.qf_apply_1q(ctypes.byref(s_null), 0, pU, None) == qf.QF_EINVAL
+    s_dt = qf.qf_state(0x1000, 3, 3, 1, 7)
+    assert lib.qf_apply_1q(ctypes.byref(s_dt), 0, pU, None) == qf.QF_EDTYPE
+    s_dim = qf.qf_state(0x1000, 3, 17, 1, 0)
+    assert lib.qf_apply_1q(ctypes.byref(s_dim), 0, pU, None) == qf.QF_ERANGE
+    s_big = qf.qf_state(0x1000, 21, 3, 1, 0)  # 3^21 > 2^32
+    assert lib.qf_apply_1q(ctypes.byref(s_big), 0, pU, None) == qf.QF_ERANGE
+    s_bat = qf.qf_state(0x1000, 20, 3, 2, 0)  # 2 * 3^20 > 2^32
+    assert lib.qf_apply_1q(ctypes.byref(s_bat), 0, pU, None) == qf.QF_ERANGE
+    sh = (ctypes.c_int32 * 3)(0, 1, 2)
+    assert lib.qf_apply_ctrl(ctypes.byref(s), 1, 1, sh, None) == qf.QF_EINVAL
+    assert lib.qf_apply_ctrl(ctypes.byref(s), 5, 1, sh, None) == qf.QF_EINVAL
+    assert lib.qf_apply_ctrl(ctypes.byref(s), 0, 1, None, None) == qf.QF_EINVAL
+    qs = (ctypes.c_int32 * 2)(1, 1)
+    ph = (ctypes.c_double * 18)()
+    assert lib.qf_apply_diag(ctypes.byref(s), 2, qs, ph, None) == qf.QF_EINVAL
+    assert lib.qf_apply_fused(ctypes.byref(s), 2, 2, ctypes.c_void_p(0x2000), None) == qf.QF_EINVAL
+    s10 = qf.qf_state(0x1000, 4, 10, 1, 0)
+    assert lib.qf_apply_fused(ctypes.byref(s10), 4, 0, ctypes.c_void_p(0x2000), None) == qf.QF_ERANGE
+    assert lib.qf_probs(ctypes.byref(s), 0, None, None, None) == qf.QF_EINVAL
+    mq = (ctypes.c_int32 * 2)(0, 0)
+    assert lib.qf_probs(ctypes.byref(s), 2, mq, ctypes.c_void_p(0x3000), None) == qf.QF_EINVAL
+    tq = (ctypes.c_int32 * 1)(4)
+    td = (ctypes.c_double * 6)()
+    out = (ctypes.c_double * 2)()
+    assert lib.qf_expect(ctypes.byref(s), 1, tq, td, out, None) == qf.QF_EINVAL
+    dg = (ctypes.c_int32 * 3)(0, 3, 0)
+    assert lib.qf_state_init(ctypes.byref(s), dg, None) == qf.QF_EINVAL
+
+
+def test_plan_validation_and_schedule(qf):
+    # plans without custom matrices allocate nothing on the device
+    c = qi.config2(n=6, layers=2)
+    p = qf.plan_for(c, fuse=1)
+    assert p.num_stages == len(c.ops)
+    for bad in ([("rx", 0, 1, 1, 0)], [("rz", 0, 0, 0)], [("csum", 1, 1)], [("h", 9)], [("rx", 0, 0, 1, 5)]):
+        with pytest.raises(qf.QfError):
+            qf.Plan(3, 4, bad, 1)

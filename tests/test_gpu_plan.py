@@ -1,0 +1,111 @@
+"""GPU parity of planned circuits (forward) and of the adjoint gradient against the
+FP64 oracle: full states at small sizes, the five workloads at reduced size, and
+gradients against the oracle adjoint and central finite differences."""
+import numpy as np
+import pytest
+
+import qf_inputs as qi
+from oracle import grad, measure, sim
+from tests.gpu_helpers import TOL, maxabs, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qf():
+    import paper_2409_17716_amd as qf
+    return qf
+
+
+def run_gpu(qf, c, dtype, fuse=0, psi0=None, **kw):
+    p = qf.plan_for(c, dtype, fuse=fuse, **kw)
+    if psi0 is None:
+        t = qf.new_state(c.n, c.dim, dtype)
+        qf.qf_state_init(t, c.n, c.dim, None)
+    else:
+        t = to_dev(psi0, dtype)
+    p.forward(t, c.theta)
+    return p, t
+
+
+CIRCUITS = [
+    ("config1", lambda: qi.config1(), "c128"),
+    ("config2_small", lambda: qi.config2(n=7, layers=3), "c64"),
+    ("config3_small", lambda: qi.config3(n=5, layers=2), "c64"),
+    ("config5_small", lambda: qi.config5(n=4, layers=2), "c64"),
+    ("random_d3", lambda: qi.random_circuit(3, 6, 120, 1), "c128"),
+    ("random_d4", lambda: qi.random_circuit(4, 5, 120, 2), "c64"),
+    ("random_d7", lambda: qi.random_circuit(7, 3, 80, 3), "c128"),
+]
+
+
+@pytest.mark.parametrize("name,make,dt", CIRCUITS, ids=[c[0] for c in CIRCUITS])
+@pytest.mark.parametrize("fuse", [0, 1])
+def test_plan_forward_matches_oracle(qf, name, make, dt, fuse):
+    c = make()
+    _, t = run_gpu(qf, c, dt, fuse=fuse)
+    want = sim.run(c)
+    assert maxabs(to_np(t), want) <= TOL[dt], name
+
+
+def test_config1_outputs(qf):
+    """D=3, n=4, complex128: state and basis probabilities within 1e-12."""
+    c = qi.config1()
+    _, t = run_gpu(qf, c, "c128")
+    want = sim.run(c)
+    assert maxabs(to_np(t), want) <= 1e-12
+    p = to_np(qf.qf_probs(t, c.n, c.dim))
+    assert maxabs(p, measure.probs(want)) <= 1e-12
+
+
+def test_plan_batch_of_registers(qf):
+    c = qi.config2(n=5, layers=2)
+    psi = qi.random_state(3, 5, 2, batch=4)
+    p = qf.plan_for(c, "c64")
+    t = to_dev(psi.reshape(-1), "c64")
+    p.forward(t, c.theta)
+    got = to_np(t).reshape(4, -1)
+    for b in range(4):
+        assert maxabs(got[b], sim.run(c, psi[b])) <= 2e-5
+
+
+ADJ = [
+    ("random_d3_c128", lambda: qi.random_circuit(3, 4, 80, 11), "c128", 1e-9),
+    ("random_d5_c128", lambda: qi.random_circuit(5, 3, 60, 12), "c128", 1e-9),
+    ("config3_small", lambda: qi.config3(n=5, layers=2), "c64", 1e-4),
+    ("config2_small", lambda: qi.config2(n=6, layers=2), "c64", 1e-4),
+    ("config5_small", lambda: qi.config5(n=3, layers=2), "c64", 1e-4),
+]
+
+
+def _grad_close(g, ref, rel, dtype="c64"):
+    """|g - ref| <= rel * max(|ref|, floor).  The floor covers entries whose exact
+    value is (near) zero: with a complex64 state the per-amplitude rounding error
+    (about 1e-6 after a few hundred gates) bounds the absolute gradient error at
+    about 1e-2 * rel * max|ref|; complex128 keeps 1e-3."""
+    floor = (1e-2 if dtype == "c64" else 1e-3) * np.abs(ref).max()
+    return np.all(np.abs(g - ref) <= rel * np.maximum(np.abs(ref), floor))
+
+
+@pytest.mark.parametrize("name,make,dt,rel", ADJ, ids=[a[0] for a in ADJ])
+def test_adjoint_matches_oracle_adjoint(qf, name, make, dt, rel):
+    c = make()
+    terms = qi.zsum_terms(c.n)
+    p, t = run_gpu(qf, c, dt)
+    lam = qf.new_state(c.n, c.dim, dt)
+    g = p.adjoint_grad(t, lam, c.theta, terms)
+    ref = grad.adjoint(c, terms)
+    assert _grad_close(g, ref, rel, dt), (np.abs(g - ref).max(), np.abs(ref).max())
+
+
+def test_adjoint_vs_finite_differences(qf):
+    """config-3 structure at n=5: GPU adjoint vs FP64 central differences
+    (h = 1e-6) on 16 parameters, relative error <= 1e-4."""
+    c = qi.config3(n=5, layers=2)
+    terms = qi.zsum_terms(c.n)
+    p, t = run_gpu(qf, c, "c64")
+    lam = qf.new_state(c.n, c.dim, "c64")
+    g = p.adjoint_grad(t, lam, c.theta, terms)
+    idx = qi.config3_fd_params(c, 16)
+    fd = grad.finite_diff(c, terms, idx, h=1e-6)
+    assert _grad_close(g[idx], fd, 1e-4), np.abs(g[idx] - fd).max()
