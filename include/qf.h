@@ -160,11 +160,19 @@ typedef struct qf_plan qf_plan;
 
 /* Plan options.  Zero-initialised options select the defaults. */
 typedef struct qf_plan_opts {
-    int32_t fuse;         /* 0 = default (fused LDS stages), 1 = one kernel per gate */
-    int32_t tile_digits;  /* qudits per LDS tile; 0 = chosen from D and LDS size    */
-    int32_t ckpt_every;   /* adjoint: keep a state checkpoint every this many gates  */
-                          /* of the planned schedule; 0 = none                       */
-    int32_t reserved[5];
+    int32_t fuse;         /* 0 = fused LDS stages (default); 1 = one kernel per gate; */
+                          /* 2 = one kernel per run of one-qudit gates on a qudit     */
+    int32_t tile_digits;  /* qudits per LDS tile of the forward stages; 0 = chosen    */
+                          /* from D and the LDS budget                                */
+    int32_t low_digits;   /* least significant qudits always in the tile (contiguous */
+                          /* HBM runs); 0 = chosen from D                             */
+    int32_t ckpt_every;   /* keep a state checkpoint every this many gates of the    */
+                          /* circuit for the adjoint; 0 = none                        */
+    int32_t adj_tile_digits; /* qudits per tile of the adjoint stages; 0 = chosen     */
+    int32_t stage_kernel; /* forward stages: 0 = register rounds (default), 1 = one   */
+                          /* LDS sweep per op                                          */
+    int32_t group_digits; /* register rounds: qudits per lane group; 0 = chosen from D */
+    int32_t reserved[1];
 } qf_plan_opts;
 
 /* Compile a circuit (ops applied in order) for registers of n qudits of
@@ -176,8 +184,28 @@ qf_status qf_plan_create(int32_t dim, int32_t n, int32_t dtype, const qf_op* ops
                          int32_t nops, int32_t nparams, const qf_plan_opts* opts,
                          qf_plan** out);
 
-/* Number of HBM passes (stages) of the plan's forward schedule. */
+/* Number of kernel passes over the state in the plan's forward schedule. */
 int32_t qf_plan_num_stages(const qf_plan* plan);
+
+/* Number of kernel passes of the plan's adjoint (reverse) schedule. */
+int32_t qf_plan_num_adjoint_stages(const qf_plan* plan);
+
+/* Per-kernel timing of a plan's launches, measured with HIP events recorded
+ * around every pass on the launch stream while profiling is enabled. */
+typedef struct qf_kernel_stat {
+    char    name[32];     /* kernel family: "stage", "stage_adj", "fused", ...     */
+    int64_t launches;
+    double  total_ms;     /* summed event-to-event durations                       */
+    double  bytes;        /* summed algorithmic HBM bytes (each pass reads and     */
+                          /* writes its state(s) once)                             */
+} qf_kernel_stat;
+
+/* enable != 0 starts recording (and clears earlier records). */
+qf_status qf_plan_set_profiling(qf_plan* plan, int32_t enable);
+
+/* Waits for the recorded events, writes up to cap per-family sums to out and
+ * the number of families to *count, then clears the records. */
+qf_status qf_plan_read_profile(qf_plan* plan, qf_kernel_stat* out, int32_t cap, int32_t* count);
 
 /* Apply the planned circuit in place to every register of s (shape must match
  * the plan).  theta: host, nparams angles in radians. */

@@ -41,8 +41,14 @@ class qf_op(ctypes.Structure):
 
 
 class qf_plan_opts(ctypes.Structure):
-    _fields_ = [("fuse", ctypes.c_int32), ("tile_digits", ctypes.c_int32), ("ckpt_every", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+    _fields_ = [("fuse", ctypes.c_int32), ("tile_digits", ctypes.c_int32), ("low_digits", ctypes.c_int32),
+                ("ckpt_every", ctypes.c_int32), ("adj_tile_digits", ctypes.c_int32), ("stage_kernel", ctypes.c_int32),
+                ("group_digits", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+
+
+class qf_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p
@@ -63,6 +69,8 @@ _SIGS = {
                        ctypes.POINTER(ctypes.c_void_p)],
     "qf_plan_forward": [_P, _PS, _PD, _P],
     "qf_adjoint_grad": [_P, _PS, _PS, _PD, _I32, _PI32, _PD, _PD, _P],
+    "qf_plan_set_profiling": [_P, _I32],
+    "qf_plan_read_profile": [_P, ctypes.POINTER(qf_kernel_stat), _I32, _PI32],
 }
 
 
@@ -82,8 +90,9 @@ def _load() -> ctypes.CDLL:
     lib.qf_last_error.restype = ctypes.c_char_p
     lib.qf_last_error.argtypes = []
     lib.qf_version.restype = ctypes.c_int32
-    lib.qf_plan_num_stages.restype = ctypes.c_int32
-    lib.qf_plan_num_stages.argtypes = [_P]
+    for name in ("qf_plan_num_stages", "qf_plan_num_adjoint_stages"):
+        getattr(lib, name).restype = ctypes.c_int32
+        getattr(lib, name).argtypes = [_P]
     lib.qf_plan_destroy.restype = None
     lib.qf_plan_destroy.argtypes = [_P]
     return lib
@@ -268,11 +277,12 @@ class Plan:
     """A compiled circuit (qf_plan_create) for registers of n qudits of dimension dim."""
 
     def __init__(self, dim: int, n: int, ops: Sequence[tuple], nparams: int, dtype: str = "c64",
-                 fuse: int = 0, tile_digits: int = 0, ckpt_every: int = 0):
+                 fuse: int = 0, tile_digits: int = 0, low_digits: int = 0, ckpt_every: int = 0,
+                 adj_tile_digits: int = 0, stage_kernel: int = 0, group_digits: int = 0):
         self.dim, self.n, self.nparams = dim, n, nparams
         self.dtype = QF_C64 if dtype == "c64" else QF_C128
         arr, keep = ops_to_c(ops)
-        opts = qf_plan_opts(fuse, tile_digits, ckpt_every)
+        opts = qf_plan_opts(fuse, tile_digits, low_digits, ckpt_every, adj_tile_digits, stage_kernel, group_digits)
         h = ctypes.c_void_p()
         _check(lib.qf_plan_create(dim, n, self.dtype, arr, len(ops), nparams, ctypes.byref(opts), ctypes.byref(h)))
         self._h = h
@@ -280,6 +290,21 @@ class Plan:
     @property
     def num_stages(self) -> int:
         return lib.qf_plan_num_stages(self._h)
+
+    @property
+    def num_adjoint_stages(self) -> int:
+        return lib.qf_plan_num_adjoint_stages(self._h)
+
+    def set_profiling(self, enable: bool) -> None:
+        _check(lib.qf_plan_set_profiling(self._h, 1 if enable else 0))
+
+    def read_profile(self) -> dict:
+        """{family: (launches, total_ms, bytes)} of the launches recorded since
+        profiling was enabled or last read (waits for their events)."""
+        arr = (qf_kernel_stat * 16)()
+        cnt = ctypes.c_int32()
+        _check(lib.qf_plan_read_profile(self._h, arr, 16, ctypes.byref(cnt)))
+        return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms, arr[i].bytes) for i in range(cnt.value)}
 
     def forward(self, t, theta, stream=None) -> None:
         s = state_of(t, self.n, self.dim)

@@ -22,9 +22,9 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libqf.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
-HIP_FLAGS = ["-x", "hip", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-munsafe-fp-atomics", "-Rpass-analysis=kernel-resource-usage"]
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-Wno-unused-result",
+          "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+HIP_FLAGS = ["-x", "hip", "-Rpass-analysis=kernel-resource-usage"]
 
 
 def _compile(src: str, verbose: bool) -> tuple[str, str]:

@@ -116,22 +116,35 @@ __global__ __launch_bounds__(kFB) void k_adj_axis(cplx<T>* __restrict__ psi, cpl
     }
 }
 
-// out[b][slot][e] = sum over the workgroups of register b, in order.
-__global__ void k_adj_reduce(const double* __restrict__ partial, uint32_t blocks_per_reg, uint32_t E,
-                             uint32_t batch, uint32_t nslots, uint32_t slot, double* __restrict__ out) {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= batch * E) return;
-    const uint32_t b = t / E;
-    const uint32_t e = t - b * E;
+// out[b][slot][e] = sum over the workgroups of register b: one workgroup per
+// (b, e); lanes take workgroups k = lane, lane + 256, ..., then a fixed tree.
+__global__ __launch_bounds__(256) void k_adj_reduce(const double* __restrict__ partial, uint32_t blocks_per_reg,
+                                                    uint32_t E, uint32_t nslots, uint32_t slot,
+                                                    double* __restrict__ out) {
+    __shared__ double sh[2][256];
+    const uint32_t b = blockIdx.x / E;
+    const uint32_t e = blockIdx.x - b * E;
     double sr = 0.0, si = 0.0;
-    for (uint32_t k = 0; k < blocks_per_reg; ++k) {
+    for (uint32_t k = threadIdx.x; k < blocks_per_reg; k += 256) {
         const double* p = partial + (size_t(b) * blocks_per_reg + k) * E * 2;
         sr += p[2 * e];
         si += p[2 * e + 1];
     }
-    double* o = out + ((size_t(b) * nslots + slot) * E + e) * 2;
-    o[0] = sr;
-    o[1] = si;
+    sh[0][threadIdx.x] = sr;
+    sh[1][threadIdx.x] = si;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double* o = out + ((size_t(b) * nslots + slot) * E + e) * 2;
+        o[0] = sh[0][0];
+        o[1] = sh[1][0];
+    }
 }
 
 template <class F>
@@ -182,9 +195,8 @@ qf_status launch_adj_axis(const StateView& s, void* lam, int q, const double* W,
                                bpr, s.N, L, FastDiv(L), w, partial);
             QF_CHECK(check_launch("adjoint axis"));
             const uint32_t E = D * D;
-            const uint32_t nt = s.batch * E;
-            hipLaunchKernelGGL(k_adj_reduce, dim3((nt + 255) / 256), dim3(256), 0, st, partial, bpr, E, s.batch,
-                               nslots, slot, mout);
+            hipLaunchKernelGGL(k_adj_reduce, dim3(s.batch * E), dim3(256), 0, st, partial, bpr, E, nslots, slot,
+                               mout);
             return check_launch("adjoint reduce");
         }
     };

@@ -311,14 +311,16 @@ __global__ __launch_bounds__(kBlock) void k_marg_partial(const cplx<T>* __restri
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
+// One workgroup per bin: lanes sum chunks c = lane, lane + 256, ..., then a fixed tree.
 template <typename T>
-__global__ void k_marg_final(const double* __restrict__ partial, uint32_t chunks, uint32_t nbins,
-                             T* __restrict__ out) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nbins) return;
+__global__ __launch_bounds__(kBlock) void k_marg_final(const double* __restrict__ partial, uint32_t chunks,
+                                                       T* __restrict__ out) {
+    __shared__ double sh[kBlock];
+    const uint32_t i = blockIdx.x;
     double s = 0.0;
-    for (uint32_t c = 0; c < chunks; ++c) s += partial[i * chunks + c];
-    out[i] = T(s);
+    for (uint32_t c = threadIdx.x; c < chunks; c += kBlock) s += partial[size_t(i) * chunks + c];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) out[i] = T(s);
 }
 
 // ---------------------------------------------------------------------------
@@ -377,17 +379,22 @@ __global__ __launch_bounds__(kBlock) void k_expect_partial(const cplx<T>* __rest
     }
 }
 
-__global__ void k_expect_final(const double* __restrict__ partial, uint32_t nblk, uint32_t batch,
-                               double* __restrict__ out) {
-    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= batch) return;
+// One workgroup per register: lanes sum partials c = lane, lane + 256, ..., then a fixed tree.
+__global__ __launch_bounds__(kBlock) void k_expect_final(const double* __restrict__ partial, uint32_t nblk,
+                                                         double* __restrict__ out) {
+    __shared__ double sh[kBlock];
+    const uint32_t b = blockIdx.x;
     double sr = 0.0, si = 0.0;
-    for (uint32_t c = 0; c < nblk; ++c) {
-        sr += partial[2 * (b * nblk + c)];
-        si += partial[2 * (b * nblk + c) + 1];
+    for (uint32_t c = threadIdx.x; c < nblk; c += kBlock) {
+        sr += partial[2 * (size_t(b) * nblk + c)];
+        si += partial[2 * (size_t(b) * nblk + c) + 1];
     }
-    out[2 * b] = sr;
-    out[2 * b + 1] = si;
+    sr = block_sum(sr, sh);
+    si = block_sum(si, sh);
+    if (threadIdx.x == 0) {
+        out[2 * b] = sr;
+        out[2 * b + 1] = si;
+    }
 }
 
 template <typename T>
@@ -541,7 +548,7 @@ qf_status launch_probs_marginal(const StateView& s, int m, const int32_t* qudits
                            reinterpret_cast<const cplx<T>*>(s.amps), a, partial);
         qf_status r1 = check_launch("qf_probs marginal");
         const uint32_t nb = a.bins * s.batch;
-        hipLaunchKernelGGL(k_marg_final<T>, dim3((nb + 255) / 256), dim3(256), 0, st, partial, a.chunks, nb,
+        hipLaunchKernelGGL(k_marg_final<T>, dim3(nb), dim3(kBlock), 0, st, partial, a.chunks,
                            reinterpret_cast<T*>(out));
         qf_status r2 = check_launch("qf_probs marginal final");
         QF_HIP_CHECK(hipFreeAsync(partial, st));
@@ -563,8 +570,7 @@ qf_status launch_expect(const StateView& s, const std::vector<int>& active, cons
         hipLaunchKernelGGL(k_expect_partial<T>, dim3(uint32_t(nblocks)), dim3(kBlock), 0, st,
                            reinterpret_cast<const cplx<T>*>(s.amps), s.N, chunk, nblk, a, partial);
         qf_status r1 = check_launch("qf_expect");
-        hipLaunchKernelGGL(k_expect_final, dim3((s.batch + 255) / 256), dim3(256), 0, st, partial, nblk,
-                           s.batch, out);
+        hipLaunchKernelGGL(k_expect_final, dim3(s.batch), dim3(kBlock), 0, st, partial, nblk, out);
         qf_status r2 = check_launch("qf_expect final");
         QF_HIP_CHECK(hipFreeAsync(partial, st));
         return r1 != QF_OK ? r1 : r2;

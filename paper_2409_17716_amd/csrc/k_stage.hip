@@ -1,0 +1,640 @@
+// Fused LDS stages: one HBM pass applies every gate of a stage to a tile of k
+// qudits held in LDS.
+//
+// Load/store: tile element e lives at base + offhi[e / R] + e % R; consecutive
+// lanes take consecutive e, so each wavefront reads contiguous runs of R = D^r
+// amplitudes (r low qudits are always in the tile).
+//
+// Ops (read from a device array; every lane reads the same op, so the loads are
+// scalar):
+//   SOP_U      dense D x D matrix on one tile qudit: each lane takes whole fibres
+//              (D amplitudes at LDS stride D^(k-1-dim)) into registers.
+//   SOP_SHIFT  x_t -> x_t + shifts[x_c] mod D on a tile qudit t; the control
+//              digit comes from the fibre's global index, so the control may be
+//              any qudit, inside or outside the tile.  Pure data movement.
+//   SOP_PHASE  product of two-qudit diagonal factors table[x_a * D + x_b]; the
+//              digits come from the global index, so a and b may be any qudits.
+#include <type_traits>
+
+#include "qf_internal.h"
+
+namespace qf {
+namespace {
+
+constexpr int kSB = 256;
+
+template <int D>
+__device__ inline uint32_t tile_base(const StageGeom& g, uint32_t blk) {
+    const uint32_t b = blk / g.ntiles;
+    uint32_t t = blk - b * g.ntiles;
+    uint32_t base = b * g.N;
+    for (int j = int(g.nout) - 1; j >= 0; --j) {
+        const uint32_t q = t / D;
+        base += (t - q * D) * g.out_stride[j];
+        t = q;
+    }
+    return base;
+}
+
+template <int D>
+__device__ inline void build_offhi(const StageGeom& g, uint32_t* offhi) {
+    const int nh = int(g.k - g.r);
+    for (uint32_t h = threadIdx.x; h < g.nhi; h += kSB) {
+        uint32_t hh = h, off = 0;
+        for (int i = nh - 1; i >= 0; --i) {
+            const uint32_t q = hh / D;
+            off += (hh - q * D) * g.hi_stride[i];
+            hh = q;
+        }
+        offhi[h] = off;
+    }
+}
+
+__device__ inline uint32_t global_index(const StageGeom& g, const uint32_t* offhi, uint32_t base, uint32_t e) {
+    const uint32_t eh = g.divR.div(e);
+    return base + offhi[eh] + (e - eh * g.R);
+}
+
+// Loads and stores go in batches of kIO per lane so that kIO global accesses
+// per lane are in flight before the first one is waited on.
+constexpr int kIO = 8;
+
+template <typename T>
+__device__ inline void tile_load(const cplx<T>* __restrict__ psi, cplx<T>* tile, const StageGeom& g,
+                                 const uint32_t* offhi, uint32_t base) {
+    uint32_t e0 = threadIdx.x;
+    for (; e0 + (kIO - 1) * kSB < g.TE; e0 += kSB * kIO) {
+        cplx<T> t[kIO];
+#pragma unroll
+        for (int j = 0; j < kIO; ++j) t[j] = psi[global_index(g, offhi, base, e0 + uint32_t(j) * kSB)];
+#pragma unroll
+        for (int j = 0; j < kIO; ++j) tile[e0 + uint32_t(j) * kSB] = t[j];
+    }
+    for (; e0 < g.TE; e0 += kSB) tile[e0] = psi[global_index(g, offhi, base, e0)];
+}
+
+template <typename T>
+__device__ inline void tile_store(cplx<T>* __restrict__ psi, const cplx<T>* tile, const StageGeom& g,
+                                  const uint32_t* offhi, uint32_t base) {
+    uint32_t e0 = threadIdx.x;
+    for (; e0 + (kIO - 1) * kSB < g.TE; e0 += kSB * kIO) {
+        cplx<T> t[kIO];
+#pragma unroll
+        for (int j = 0; j < kIO; ++j) t[j] = tile[e0 + uint32_t(j) * kSB];
+#pragma unroll
+        for (int j = 0; j < kIO; ++j) psi[global_index(g, offhi, base, e0 + uint32_t(j) * kSB)] = t[j];
+    }
+    for (; e0 < g.TE; e0 += kSB) psi[global_index(g, offhi, base, e0)] = tile[e0];
+}
+
+template <typename T, int D>
+__device__ inline void matvec(const cplx<T>* __restrict__ M, bool real, const cplx<T> (&v)[D], cplx<T> (&w)[D]) {
+    if (real) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            T re = 0, im = 0;
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                const T m = M[a * D + b].re;
+                re = fma(m, v[b].re, re);
+                im = fma(m, v[b].im, im);
+            }
+            w[a] = cmake<T>(re, im);
+        }
+    } else {
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            cplx<T> acc = cmake<T>(0, 0);
+#pragma unroll
+            for (int b = 0; b < D; ++b) cmac(acc, M[a * D + b], v[b]);
+            w[a] = acc;
+        }
+    }
+}
+
+template <typename T, int D>
+__device__ inline void op_u(cplx<T>* tile, const StageGeom& g, const StageOp& op, const cplx<T>* __restrict__ M) {
+    const uint32_t nf = g.TE / D;
+    const uint32_t ls = op.ls;
+    const bool real = op.real != 0;
+    for (uint32_t f = threadIdx.x; f < nf; f += kSB) {
+        const uint32_t hi = op.divls.div(f);
+        const uint32_t lb = hi * (uint32_t(D) * ls) + (f - hi * ls);
+        cplx<T> v[D], w[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) v[d] = tile[lb + uint32_t(d) * ls];
+        matvec<T, D>(M, real, v, w);
+#pragma unroll
+        for (int d = 0; d < D; ++d) tile[lb + uint32_t(d) * ls] = w[d];
+    }
+}
+
+template <int D>
+__device__ inline int shift_amount(const StageOp& op, uint32_t gidx) {
+    if (!op.has_ctrl) return op.shifts[0];
+    const uint32_t xc = op.ctrl_stride.div(gidx) % D;
+    int s = op.shifts[0];
+#pragma unroll
+    for (int a = 1; a < D; ++a) s = (xc == uint32_t(a)) ? op.shifts[a] : s;
+    return s;
+}
+
+// v[b] <- v[(b - s) mod D] as a barrel of rotations by 1, 2, 4, ...: every
+// register index is a compile-time constant, so nothing is spilled.
+template <typename T, int D>
+__device__ inline void shift_fibre(cplx<T>* tile, uint32_t lb, uint32_t ls, int s) {
+    cplx<T> v[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) v[d] = tile[lb + uint32_t(d) * ls];
+#pragma unroll
+    for (int bit = 1; bit < D; bit <<= 1) {
+        const bool on = (s & bit) != 0;
+        cplx<T> w[D];
+#pragma unroll
+        for (int b = 0; b < D; ++b) w[b] = v[(b - bit % D + D) % D];
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            v[b].re = on ? w[b].re : v[b].re;
+            v[b].im = on ? w[b].im : v[b].im;
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) tile[lb + uint32_t(d) * ls] = v[d];
+}
+
+template <int D>
+__device__ inline uint32_t fibre_lb(const StageOp& op, uint32_t f) {
+    const uint32_t hi = op.divls.div(f);
+    return hi * (uint32_t(D) * op.ls) + (f - hi * op.ls);
+}
+
+template <typename T, int D>
+__device__ inline cplx<T> phase_of(const StageOp& op, const cplx<T>* __restrict__ M, uint32_t gidx) {
+    cplx<T> ph = cmake<T>(1, 0);
+    for (int p = 0; p < op.npairs; ++p) {
+        const uint32_t xa = op.pa[p].div(gidx) % D;
+        const uint32_t xb = op.pb[p].div(gidx) % D;
+        ph = cmul(ph, M[op.ptab[p] + xa * D + xb]);
+    }
+    return ph;
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(kSB) void k_stage(cplx<T>* __restrict__ psi, StageGeom g,
+                                               const StageOp* __restrict__ ops, int nops,
+                                               const cplx<T>* __restrict__ mats) {
+    extern __shared__ unsigned char smem[];
+    cplx<T>* tile = reinterpret_cast<cplx<T>*>(smem);
+    __shared__ uint32_t offhi[kMaxHi];
+    const uint32_t base = tile_base<D>(g, blockIdx.x);
+    build_offhi<D>(g, offhi);
+    __syncthreads();
+    tile_load(psi, tile, g, offhi, base);
+    __syncthreads();
+    for (int oi = 0; oi < nops; ++oi) {
+        const StageOp& op = ops[oi];
+        if (op.type == SOP_U) {
+            op_u<T, D>(tile, g, op, mats + op.mat);
+        } else if (op.type == SOP_SHIFT) {
+            const uint32_t nf = g.TE / D;
+            for (uint32_t f = threadIdx.x; f < nf; f += kSB) {
+                const uint32_t lb = fibre_lb<D>(op, f);
+                const int s = shift_amount<D>(op, global_index(g, offhi, base, lb));
+                if (s != 0) shift_fibre<T, D>(tile, lb, op.ls, s);
+            }
+        } else {
+            for (uint32_t e = threadIdx.x; e < g.TE; e += kSB)
+                tile[e] = cmul(tile[e], phase_of<T, D>(op, mats, global_index(g, offhi, base, e)));
+        }
+        __syncthreads();
+    }
+    tile_store(psi, tile, g, offhi, base);
+}
+
+// Reverse stage on psi and lam.  Before a U with slot >= 0, lane (entry, part)
+// sums psi_f[a] conj(lam_f[c]) over the fibres f = part, part + P, ... and the
+// parts are then added in a fixed order.
+template <typename T, int D>
+__global__ __launch_bounds__(kSB) void k_stage_adj(cplx<T>* __restrict__ psi, cplx<T>* __restrict__ lam,
+                                                   StageGeom g, const StageOp* __restrict__ ops, int nops,
+                                                   const cplx<T>* __restrict__ mats, double* __restrict__ partial) {
+    extern __shared__ unsigned char smem[];
+    cplx<T>* tp = reinterpret_cast<cplx<T>*>(smem);
+    cplx<T>* tl = tp + g.TE;
+    __shared__ uint32_t offhi[kMaxHi];
+    __shared__ double red[2][kSB];
+    constexpr int E = D * D;
+    constexpr int P = kSB / E;
+    const uint32_t nblocks = gridDim.x;
+    const uint32_t base = tile_base<D>(g, blockIdx.x);
+    build_offhi<D>(g, offhi);
+    __syncthreads();
+    tile_load(psi, tp, g, offhi, base);
+    tile_load(lam, tl, g, offhi, base);
+    __syncthreads();
+    const uint32_t nf = g.TE / D;
+    for (int oi = 0; oi < nops; ++oi) {
+        const StageOp& op = ops[oi];
+        if (op.type == SOP_U) {
+            if (op.slot >= 0) {
+                const int e = threadIdx.x % E;
+                const int part = threadIdx.x / E;
+                double ar = 0.0, ai = 0.0;
+                if (part < P) {
+                    const uint32_t a = uint32_t(e / D), c = uint32_t(e % D);
+                    for (uint32_t f = part; f < nf; f += P) {
+                        const uint32_t lb = fibre_lb<D>(op, f);
+                        const cplx<T> x = tp[lb + a * op.ls];
+                        const cplx<T> y = tl[lb + c * op.ls];
+                        ar += double(x.re) * double(y.re) + double(x.im) * double(y.im);
+                        ai += double(x.im) * double(y.re) - double(x.re) * double(y.im);
+                    }
+                }
+                red[0][threadIdx.x] = ar;
+                red[1][threadIdx.x] = ai;
+                __syncthreads();
+                if (int(threadIdx.x) < E) {
+                    double sr = 0.0, si = 0.0;
+                    for (int p = 0; p < P; ++p) {
+                        sr += red[0][p * E + threadIdx.x];
+                        si += red[1][p * E + threadIdx.x];
+                    }
+                    double* o = partial + ((size_t(op.slot) * nblocks + blockIdx.x) * E + threadIdx.x) * 2;
+                    o[0] = sr;
+                    o[1] = si;
+                }
+                __syncthreads();
+            }
+            op_u<T, D>(tp, g, op, mats + op.mat);
+            op_u<T, D>(tl, g, op, mats + op.mat);
+        } else if (op.type == SOP_SHIFT) {
+            for (uint32_t f = threadIdx.x; f < nf; f += kSB) {
+                const uint32_t lb = fibre_lb<D>(op, f);
+                const int s = shift_amount<D>(op, global_index(g, offhi, base, lb));
+                if (s != 0) {
+                    shift_fibre<T, D>(tp, lb, op.ls, s);
+                    shift_fibre<T, D>(tl, lb, op.ls, s);
+                }
+            }
+        } else {
+            for (uint32_t e = threadIdx.x; e < g.TE; e += kSB) {
+                const cplx<T> ph = phase_of<T, D>(op, mats, global_index(g, offhi, base, e));
+                tp[e] = cmul(tp[e], ph);
+                tl[e] = cmul(tl[e], ph);
+            }
+        }
+        __syncthreads();
+    }
+    tile_store(psi, tp, g, offhi, base);
+    tile_store(lam, tl, g, offhi, base);
+}
+
+// One workgroup per (register, slot, entry): lanes sum the tiles
+// i = lane, lane + 256, ... of the register, then a fixed tree.
+__global__ __launch_bounds__(kSB) void k_stage_mreduce(const double* __restrict__ partial, uint32_t nslots,
+                                                       uint32_t ntiles, uint32_t batch, uint32_t E,
+                                                       double* __restrict__ mout, uint32_t nslots_total,
+                                                       uint32_t slot0) {
+    __shared__ double red[2][kSB];
+    const uint32_t e = blockIdx.x % E;
+    const uint32_t bj = blockIdx.x / E;
+    const uint32_t b = bj / nslots;
+    const uint32_t j = bj - b * nslots;
+    const uint32_t nblocks = ntiles * batch;
+    double ar = 0.0, ai = 0.0;
+    for (uint32_t i = threadIdx.x; i < ntiles; i += kSB) {
+        const double* p = partial + ((size_t(j) * nblocks + b * ntiles + i) * E + e) * 2;
+        ar += p[0];
+        ai += p[1];
+    }
+    red[0][threadIdx.x] = ar;
+    red[1][threadIdx.x] = ai;
+    __syncthreads();
+    for (int w = kSB / 2; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double* o = mout + ((size_t(b) * nslots_total + slot0 + j) * E + e) * 2;
+        o[0] = red[0][0];
+        o[1] = red[1][0];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Register rounds.  Register index i of a lane's sub-tile has digits
+// (i_0, ..., i_{M-1}) (i_0 most significant); digit j belongs to the round's
+// j-th group qudit.  All register indices are compile-time constants.
+// ---------------------------------------------------------------------------
+
+constexpr int cpow(int b, int e) { return e == 0 ? 1 : b * cpow(b, e - 1); }
+
+template <int D, int M, int J>
+__device__ constexpr int rdigit(int i) {
+    return (i / cpow(D, M - 1 - J)) % D;
+}
+
+template <typename T, int D, int M, int J>
+__device__ inline void r_u(cplx<T> (&v)[cpow(D, M)], const cplx<T>* __restrict__ U, bool real) {
+    constexpr int SJ = cpow(D, M - 1 - J);
+    constexpr int NF = cpow(D, M - 1);
+#pragma unroll
+    for (int c = 0; c < NF; ++c) {
+        const int b0 = (c / SJ) * SJ * D + (c % SJ);
+        cplx<T> x[D], y[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) x[d] = v[b0 + d * SJ];
+        matvec<T, D>(U, real, x, y);
+#pragma unroll
+        for (int d = 0; d < D; ++d) v[b0 + d * SJ] = y[d];
+    }
+}
+
+// rotate x[b] <- x[(b - s) mod D] (barrel of compile-time rotations)
+template <typename T, int D>
+__device__ inline void rotate(cplx<T> (&x)[D], int s) {
+#pragma unroll
+    for (int bit = 1; bit < D; bit <<= 1) {
+        const bool on = (s & bit) != 0;
+        cplx<T> w[D];
+#pragma unroll
+        for (int b = 0; b < D; ++b) w[b] = x[(b - bit % D + D) % D];
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            x[b].re = on ? w[b].re : x[b].re;
+            x[b].im = on ? w[b].im : x[b].im;
+        }
+    }
+}
+
+template <typename T, int D, int M, int J, int CJ>
+__device__ inline void r_shift(cplx<T> (&v)[cpow(D, M)], const StageOp& op, int s_thread) {
+    constexpr int SJ = cpow(D, M - 1 - J);
+    constexpr int NF = cpow(D, M - 1);
+#pragma unroll
+    for (int c = 0; c < NF; ++c) {
+        const int b0 = (c / SJ) * SJ * D + (c % SJ);
+        int s;
+        if constexpr (CJ >= 0) {
+            s = op.shifts[rdigit<D, M, CJ>(b0)];
+        } else {
+            s = s_thread;
+        }
+        cplx<T> x[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) x[d] = v[b0 + d * SJ];
+        rotate<T, D>(x, s);
+#pragma unroll
+        for (int d = 0; d < D; ++d) v[b0 + d * SJ] = x[d];
+    }
+}
+
+// CZ factors multiply amplitude x by w^e(x) with e(x) = sum over factors of
+// x_a x_b.  Within a lane's sub-tile the digits outside the group are
+// constant, so e is a quadratic form in the group digits d_j:
+//   e = e0 + sum_j lin_j d_j + sum_{j<l} quad_jl d_j d_l,
+// whose coefficients are accumulated once per sub-tile.
+template <typename T, int D, int M>
+__device__ inline void r_phase(cplx<T> (&v)[cpow(D, M)], const StageOp& op, const cplx<T>* __restrict__ mats,
+                               uint32_t gidx0) {
+    constexpr int DM = cpow(D, M);
+    int e0 = 0;
+    int lin[M];
+    int quad[M][M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        lin[j] = 0;
+#pragma unroll
+        for (int l = 0; l < M; ++l) quad[j][l] = 0;
+    }
+    for (int p = 0; p < op.npairs; ++p) {
+        const int ag = op.agpos[p], bg = op.bgpos[p];
+        const int ca = ag < 0 ? int(op.pa[p].div(gidx0) % D) : 0;
+        const int cb = bg < 0 ? int(op.pb[p].div(gidx0) % D) : 0;
+        if (ag < 0 && bg < 0) e0 += ca * cb;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            lin[j] += (ag == j && bg < 0) ? cb : 0;
+            lin[j] += (bg == j && ag < 0) ? ca : 0;
+#pragma unroll
+            for (int l = 0; l < M; ++l) quad[j][l] += ((ag == j && bg == l) || (ag == l && bg == j)) ? 1 : 0;
+        }
+    }
+    const cplx<T>* W = mats + op.wtab;
+#pragma unroll
+    for (int i = 0; i < DM; ++i) {
+        int e = e0;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const int dj = (i / cpow(D, M - 1 - j)) % D;
+            e += lin[j] * dj;
+#pragma unroll
+            for (int l = j + 1; l < M; ++l) e += quad[j][l] * dj * ((i / cpow(D, M - 1 - l)) % D);
+        }
+        v[i] = cmul(v[i], W[e % D]);
+    }
+}
+
+template <typename T, int D, int M, int J>
+__device__ inline void r_shift_dispatch(cplx<T> (&v)[cpow(D, M)], const StageOp& op, int s_thread) {
+    switch (op.ctrl_gpos) {
+        case 0: if constexpr (M > 0 && J != 0) r_shift<T, D, M, J, 0>(v, op, s_thread); break;
+        case 1: if constexpr (M > 1 && J != 1) r_shift<T, D, M, J, 1>(v, op, s_thread); break;
+        case 2: if constexpr (M > 2 && J != 2) r_shift<T, D, M, J, 2>(v, op, s_thread); break;
+        case 3: if constexpr (M > 3 && J != 3) r_shift<T, D, M, J, 3>(v, op, s_thread); break;
+        case 4: if constexpr (M > 4 && J != 4) r_shift<T, D, M, J, 4>(v, op, s_thread); break;
+        default: r_shift<T, D, M, J, -1>(v, op, s_thread); break;
+    }
+}
+
+template <typename T, int D, int M>
+__device__ inline void r_apply(cplx<T> (&v)[cpow(D, M)], const StageOp& op, const cplx<T>* __restrict__ mats,
+                               uint32_t gidx0) {
+    if (op.type == SOP_U) {
+        const cplx<T>* U = mats + op.mat;
+        const bool real = op.real != 0;
+        switch (op.gpos) {
+            case 0: r_u<T, D, M, 0>(v, U, real); break;
+            case 1: if constexpr (M > 1) r_u<T, D, M, 1>(v, U, real); break;
+            case 2: if constexpr (M > 2) r_u<T, D, M, 2>(v, U, real); break;
+            case 3: if constexpr (M > 3) r_u<T, D, M, 3>(v, U, real); break;
+            case 4: if constexpr (M > 4) r_u<T, D, M, 4>(v, U, real); break;
+        }
+    } else if (op.type == SOP_SHIFT) {
+        int s_thread = op.shifts[0];
+        if (op.has_ctrl && op.ctrl_gpos < 0) {
+            const uint32_t xc = op.ctrl_stride.div(gidx0) % D;
+#pragma unroll
+            for (int a = 1; a < D; ++a) s_thread = (xc == uint32_t(a)) ? op.shifts[a] : s_thread;
+        }
+        switch (op.gpos) {
+            case 0: r_shift_dispatch<T, D, M, 0>(v, op, s_thread); break;
+            case 1: if constexpr (M > 1) r_shift_dispatch<T, D, M, 1>(v, op, s_thread); break;
+            case 2: if constexpr (M > 2) r_shift_dispatch<T, D, M, 2>(v, op, s_thread); break;
+            case 3: if constexpr (M > 3) r_shift_dispatch<T, D, M, 3>(v, op, s_thread); break;
+            case 4: if constexpr (M > 4) r_shift_dispatch<T, D, M, 4>(v, op, s_thread); break;
+        }
+    } else {
+        r_phase<T, D, M>(v, op, mats, gidx0);
+    }
+}
+
+// LDS offset of register i of a sub-tile relative to the sub-tile's first element.
+template <int D, int M>
+__device__ inline uint32_t sub_offset(int i, const uint32_t* gls) {
+    uint32_t o = 0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) o += uint32_t((i / cpow(D, M - 1 - j)) % D) * gls[j];
+    return o;
+}
+
+template <typename T, int D, int M>
+__global__ __launch_bounds__(kSB) void k_stage_rounds(cplx<T>* __restrict__ psi, StageGeom g,
+                                                      const RoundDesc* __restrict__ rounds, int nrounds,
+                                                      const StageOp* __restrict__ ops,
+                                                      const cplx<T>* __restrict__ mats) {
+    constexpr int DM = cpow(D, M);
+    extern __shared__ unsigned char smem[];
+    cplx<T>* tile = reinterpret_cast<cplx<T>*>(smem);
+    __shared__ uint32_t offhi[kMaxHi];
+    const uint32_t base = tile_base<D>(g, blockIdx.x);
+    build_offhi<D>(g, offhi);
+    __syncthreads();
+    tile_load(psi, tile, g, offhi, base);
+    __syncthreads();
+    const uint32_t nsub = g.TE / DM;
+    for (int ri = 0; ri < nrounds; ++ri) {
+        const RoundDesc& rd = rounds[ri];
+        for (uint32_t u = threadIdx.x; u < nsub; u += kSB) {
+            uint32_t tb = 0, uu = u;
+            for (int j = rd.nother - 1; j >= 0; --j) {
+                const uint32_t q = uu / D;
+                tb += (uu - q * D) * rd.ols[j];
+                uu = q;
+            }
+            cplx<T> v[DM];
+#pragma unroll
+            for (int i = 0; i < DM; ++i) v[i] = tile[tb + sub_offset<D, M>(i, rd.gls)];
+            const uint32_t gidx0 = global_index(g, offhi, base, tb);
+            for (int oi = rd.op0; oi < rd.op0 + rd.nops; ++oi) r_apply<T, D, M>(v, ops[oi], mats, gidx0);
+#pragma unroll
+            for (int i = 0; i < DM; ++i) tile[tb + sub_offset<D, M>(i, rd.gls)] = v[i];
+        }
+        __syncthreads();
+    }
+    tile_store(psi, tile, g, offhi, base);
+}
+
+template <class F>
+qf_status with_dim_s(uint32_t D, F&& f) {
+    switch (D) {
+        case 2: return f(std::integral_constant<int, 2>{});
+        case 3: return f(std::integral_constant<int, 3>{});
+        case 4: return f(std::integral_constant<int, 4>{});
+        case 5: return f(std::integral_constant<int, 5>{});
+        case 6: return f(std::integral_constant<int, 6>{});
+        case 7: return f(std::integral_constant<int, 7>{});
+        case 8: return f(std::integral_constant<int, 8>{});
+        case 9: return f(std::integral_constant<int, 9>{});
+        case 10: return f(std::integral_constant<int, 10>{});
+        case 11: return f(std::integral_constant<int, 11>{});
+        case 12: return f(std::integral_constant<int, 12>{});
+        case 13: return f(std::integral_constant<int, 13>{});
+        case 14: return f(std::integral_constant<int, 14>{});
+        case 15: return f(std::integral_constant<int, 15>{});
+        case 16: return f(std::integral_constant<int, 16>{});
+        default: return set_error(QF_EUNSUPPORTED, "dim %u outside 2..16", D);
+    }
+}
+
+}  // namespace
+
+size_t stage_lds_bytes(const StageGeom& g, int dtype, bool adjoint) {
+    const size_t esz = dtype == QF_C64 ? 8 : 16;
+    return size_t(g.TE) * esz * (adjoint ? 2 : 1);
+}
+
+qf_status launch_stage(const StateView& s, const StageGeom& g, const StageOp* dops, int nops, const void* dmats,
+                       hipStream_t st) {
+    const uint32_t grid = g.ntiles * s.batch;
+    const size_t lds = stage_lds_bytes(g, s.dtype, false);
+    return with_dim_s(s.D, [&](auto dtag) -> qf_status {
+        constexpr int D = decltype(dtag)::value;
+        if (s.dtype == QF_C64)
+            hipLaunchKernelGGL((k_stage<float, D>), dim3(grid), dim3(kSB), lds, st,
+                               reinterpret_cast<cplx<float>*>(s.amps), g, dops, nops,
+                               reinterpret_cast<const cplx<float>*>(dmats));
+        else
+            hipLaunchKernelGGL((k_stage<double, D>), dim3(grid), dim3(kSB), lds, st,
+                               reinterpret_cast<cplx<double>*>(s.amps), g, dops, nops,
+                               reinterpret_cast<const cplx<double>*>(dmats));
+        return check_launch("stage");
+    });
+}
+
+// Register group sizes compiled per D (D^M <= 32 amplitudes per lane).
+int max_group_size(uint32_t D) { return D == 2 ? 5 : D == 3 ? 3 : D <= 5 ? 2 : 1; }
+
+template <typename T, int D, int M>
+static qf_status launch_rounds_m(const StateView& s, const StageGeom& g, const RoundDesc* drounds, int nrounds,
+                                 const StageOp* dops, const void* dmats, hipStream_t st) {
+    const uint32_t grid = g.ntiles * s.batch;
+    const size_t lds = stage_lds_bytes(g, s.dtype, false);
+    hipLaunchKernelGGL((k_stage_rounds<T, D, M>), dim3(grid), dim3(kSB), lds, st, reinterpret_cast<cplx<T>*>(s.amps),
+                       g, drounds, nrounds, dops, reinterpret_cast<const cplx<T>*>(dmats));
+    return check_launch("stage rounds");
+}
+
+qf_status launch_stage_rounds(const StateView& s, int M, const StageGeom& g, const RoundDesc* drounds, int nrounds,
+                              const StageOp* dops, const void* dmats, hipStream_t st) {
+    return with_dim_s(s.D, [&](auto dtag) -> qf_status {
+        constexpr int D = decltype(dtag)::value;
+        auto go = [&](auto tag) -> qf_status {
+            using T = decltype(tag);
+            switch (M) {
+                case 1: return launch_rounds_m<T, D, 1>(s, g, drounds, nrounds, dops, dmats, st);
+                case 2: if constexpr (D <= 5) return launch_rounds_m<T, D, 2>(s, g, drounds, nrounds, dops, dmats, st);
+                        break;
+                case 3: if constexpr (D <= 3) return launch_rounds_m<T, D, 3>(s, g, drounds, nrounds, dops, dmats, st);
+                        break;
+                case 4: if constexpr (D <= 2) return launch_rounds_m<T, D, 4>(s, g, drounds, nrounds, dops, dmats, st);
+                        break;
+                case 5: if constexpr (D <= 2) return launch_rounds_m<T, D, 5>(s, g, drounds, nrounds, dops, dmats, st);
+                        break;
+            }
+            return set_error(QF_EUNSUPPORTED, "register group of %d qudits for D = %d", M, D);
+        };
+        return s.dtype == QF_C64 ? go(float{}) : go(double{});
+    });
+}
+
+qf_status launch_stage_adj(const StateView& s, void* lam, const StageGeom& g, const StageOp* dops, int nops,
+                           const void* dmats, double* partial, hipStream_t st) {
+    const uint32_t grid = g.ntiles * s.batch;
+    const size_t lds = stage_lds_bytes(g, s.dtype, true);
+    return with_dim_s(s.D, [&](auto dtag) -> qf_status {
+        constexpr int D = decltype(dtag)::value;
+        if (s.dtype == QF_C64)
+            hipLaunchKernelGGL((k_stage_adj<float, D>), dim3(grid), dim3(kSB), lds, st,
+                               reinterpret_cast<cplx<float>*>(s.amps), reinterpret_cast<cplx<float>*>(lam), g, dops,
+                               nops, reinterpret_cast<const cplx<float>*>(dmats), partial);
+        else
+            hipLaunchKernelGGL((k_stage_adj<double, D>), dim3(grid), dim3(kSB), lds, st,
+                               reinterpret_cast<cplx<double>*>(s.amps), reinterpret_cast<cplx<double>*>(lam), g, dops,
+                               nops, reinterpret_cast<const cplx<double>*>(dmats), partial);
+        return check_launch("stage adjoint");
+    });
+}
+
+qf_status launch_stage_mreduce(const double* partial, uint32_t nslots, uint32_t ntiles, uint32_t batch, uint32_t E,
+                               double* mout, uint32_t nslots_total, uint32_t slot0, hipStream_t st) {
+    if (nslots == 0) return QF_OK;
+    hipLaunchKernelGGL(k_stage_mreduce, dim3(batch * nslots * E), dim3(kSB), 0, st, partial, nslots, ntiles, batch,
+                       E, mout, nslots_total, slot0);
+    return check_launch("stage M reduce");
+}
+
+}  // namespace qf

@@ -68,6 +68,12 @@ static bool is_1q(int kind) {
 }
 static bool is_rot(int kind) { return kind == QF_OP_RX || kind == QF_OP_RY || kind == QF_OP_RZ; }
 
+static qf_status check_finite_theta(const double* theta, int nparams) {
+    for (int i = 0; i < nparams; ++i)
+        QF_RETURN_IF(!std::isfinite(theta[i]), QF_EINVAL, "theta[%d] is not finite", i);
+    return QF_OK;
+}
+
 static Mat gate_matrix(const qf_op& g, int D, const double* theta) {
     const double pi = 3.14159265358979323846;
     Mat m = identity(D);
@@ -129,35 +135,120 @@ static Mat generator(const qf_op& g, int D) {
     return m;
 }
 
+// ---------------------------------------------------------------------------
+// Per-gate schedule (opts.fuse = 1: one kernel per gate; 2: one kernel per run
+// of one-qudit gates on a qudit).
+// ---------------------------------------------------------------------------
+
 enum StepType { ST_AXIS, ST_CTRL, ST_DIAG, ST_FUSED };
 
 struct Step {
     StepType type;
-    int q = 0;             // AXIS target; CTRL target; FUSED q0; DIAG first qudit
-    int q2 = -1;           // CTRL control; DIAG second qudit
-    int k = 1;             // FUSED qudit count
+    int q = 0;               // AXIS target; CTRL target; FUSED q0; DIAG first qudit
+    int q2 = -1;             // CTRL control; DIAG second qudit
+    int k = 1;               // FUSED qudit count
     std::vector<int> gates;  // gate indices folded into this step, in order
     bool has_param = false;
-    int slot = -1;         // adjoint M slot
+    int slot = -1;           // adjoint M slot
+};
+
+// ---------------------------------------------------------------------------
+// Stage schedule (opts.fuse = 0).
+// ---------------------------------------------------------------------------
+
+struct GRef {
+    int gi;
+    bool inv;
+};
+
+// A stage op before its matrices exist.
+struct HOp {
+    int type;                // SOP_U / SOP_SHIFT / SOP_PHASE
+    int q = -1;              // U, SHIFT: tile qudit acted on
+    int ctrl = -1;           // SHIFT: control qudit or -1
+    std::vector<GRef> g;     // U: fused run in application order; SHIFT: one gate; PHASE: factors
+    int slot = -1;           // adjoint: stage-local M slot
+    int gslot = -1;          // adjoint: plan-wide M slot
+};
+
+struct Pass {
+    bool tile = true;
+    std::vector<int> T;      // tile qudits, ascending
+    StageGeom geom{};
+    std::vector<HOp> ops;
+    int nslots = 0, slot0 = 0;
+    int op_off = 0, nops = 0;
+    size_t mat_off = 0, nmat = 0;  // complex elements
+    GRef fused{-1, false};   // !tile: the dense block gate
+    int seg = 0;             // checkpoint segment
+    int round_off = 0, nrounds = 0;  // register rounds (forward); nrounds = 0: op-by-op kernel
+};
+
+struct PassList {
+    std::vector<Pass> passes;
+    std::vector<StageOp> hops;
+    std::vector<RoundDesc> hrounds;
+    RoundDesc* drounds = nullptr;
+    size_t nmats = 0;
+    int nslots = 0;
+    StageOp* dops = nullptr;
+    void* dmats = nullptr;
+    void* hmats = nullptr;
+    hipEvent_t copied = nullptr, done = nullptr;
+    bool copied_valid = false, done_valid = false;
+    void release() {
+        if (drounds) (void)hipFree(drounds);
+        drounds = nullptr;
+        if (dops) (void)hipFree(dops);
+        if (dmats) (void)hipFree(dmats);
+        if (hmats) (void)hipHostFree(hmats);
+        if (copied) (void)hipEventDestroy(copied);
+        if (done) (void)hipEventDestroy(done);
+        dops = nullptr;
+        dmats = hmats = nullptr;
+        copied = done = nullptr;
+    }
+};
+
+struct ProfRec {
+    int family;
+    double bytes;
+    hipEvent_t a, b;
 };
 
 }  // namespace qf
 
 struct qf_plan {
     int D = 0, n = 0, dtype = 0, nparams = 0;
+    int group = 1;                    // register-round group size
     qf_plan_opts opts{};
     std::vector<qf::Gate> gates;
-    std::vector<qf::Step> steps;
-    int nslots = 0;
+    std::vector<qf::Step> steps;      // fuse = 1, 2
+    int nslots = 0;                   // fuse = 1, 2
+    qf::PassList fwd, rev;            // fuse = 0
+    std::vector<int> seg_end;         // gate index where each checkpoint segment ends
+    void* ckpt = nullptr;             // (nseg - 1) saved states
+    size_t ckpt_bytes = 0;
+    bool profiling = false;
+    std::vector<qf::ProfRec> prof;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
     ~qf_plan() {
         for (auto& g : gates) {
             if (g.dmat) (void)hipFree(g.dmat);
             if (g.dmat_adj) (void)hipFree(g.dmat_adj);
         }
+        fwd.release();
+        rev.release();
+        if (ckpt) (void)hipFree(ckpt);
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     }
 };
 
 namespace qf {
+
+static const char* kFamilies[] = {"stage", "stage_adj", "fused", "axis", "ctrl", "diag", "adj_axis", "checkpoint"};
+enum Family { F_STAGE, F_STAGE_ADJ, F_FUSED, F_AXIS, F_CTRL, F_DIAG, F_ADJ_AXIS, F_CKPT, F_COUNT };
 
 static qf_status validate_op(const qf_op& o, int D, int n, int nparams) {
     auto qok = [&](int q) { return q >= 0 && q < n; };
@@ -199,10 +290,33 @@ static qf_status validate_op(const qf_op& o, int D, int n, int nparams) {
     return QF_OK;
 }
 
-// Schedule: one-qudit gates accumulate per qudit (gates on different qudits
-// commute) and are flushed as one D x D step right before the next
-// multi-qudit gate that touches the qudit, or at the end.
-static void build_schedule(qf_plan* p) {
+static void to_interleaved(const Mat& m, std::vector<double>& out) {
+    out.resize(m.size() * 2);
+    for (size_t i = 0; i < m.size(); ++i) {
+        out[2 * i] = m[i].real();
+        out[2 * i + 1] = m[i].imag();
+    }
+}
+
+static int shift_of(const qf_op& o, int c, int D) {
+    int v = 0;
+    if (o.kind == QF_OP_X) v = (c == 0) ? o.j : 0;
+    if (o.kind == QF_OP_CSUM) v = c;
+    if (o.kind == QF_OP_CSHIFT) v = o.shifts[c];
+    return ((v % D) + D) % D;
+}
+
+static void cz_table(int D, bool inverse, Mat& out) {
+    const double pi = 3.14159265358979323846;
+    out.assign(size_t(D) * D, cd(0, 0));
+    for (int a = 0; a < D; ++a)
+        for (int b = 0; b < D; ++b)
+            out[size_t(a) * D + b] = std::polar(1.0, 2 * pi * double((a * b) % D) / D * (inverse ? -1.0 : 1.0));
+}
+
+// ---- per-gate schedule ----
+
+static void build_steps(qf_plan* p) {
     std::vector<std::vector<int>> pending(p->n);
     auto flush = [&](int q) {
         if (pending[q].empty()) return;
@@ -214,12 +328,12 @@ static void build_schedule(qf_plan* p) {
         p->steps.push_back(s);
         pending[q].clear();
     };
-    const bool fuse = p->opts.fuse != 1;
+    const bool per_gate = p->opts.fuse == 1;
     for (int gi = 0; gi < int(p->gates.size()); ++gi) {
         const qf_op& o = p->gates[gi].op;
         if (is_1q(o.kind)) {
             pending[o.q0].push_back(gi);
-            if (!fuse) flush(o.q0);
+            if (per_gate) flush(o.q0);
             continue;
         }
         Step s;
@@ -261,61 +375,36 @@ static void build_schedule(qf_plan* p) {
         if (s.type == ST_AXIS && s.has_param) s.slot = p->nslots++;
 }
 
-static void to_interleaved(const Mat& m, std::vector<double>& out) {
-    out.resize(m.size() * 2);
-    for (size_t i = 0; i < m.size(); ++i) {
-        out[2 * i] = m[i].real();
-        out[2 * i + 1] = m[i].imag();
-    }
-}
-
 static Mat step_matrix(const qf_plan* p, const Step& s, const double* theta) {
     Mat U = identity(p->D);
     for (int gi : s.gates) U = matmul(gate_matrix(p->gates[gi].op, p->D, theta), U, p->D);
     return U;
 }
 
-static void ctrl_shifts(const qf_plan* p, const Step& s, bool inverse, int32_t* sh) {
-    const qf_op& o = p->gates[s.gates[0]].op;
-    const int D = p->D;
-    for (int c = 0; c < D; ++c) {
-        int v = 0;
-        if (o.kind == QF_OP_X) v = (c == 0) ? o.j : 0;
-        if (o.kind == QF_OP_CSUM) v = c;
-        if (o.kind == QF_OP_CSHIFT) v = o.shifts[c];
-        v = ((v % D) + D) % D;
-        sh[c] = inverse ? (D - v) % D : v;
-    }
-}
-
-static void cz_table(int D, bool inverse, std::vector<double>& out) {
-    const double pi = 3.14159265358979323846;
-    out.resize(size_t(D) * D * 2);
-    for (int a = 0; a < D; ++a)
-        for (int b = 0; b < D; ++b) {
-            const double ang = 2 * pi * double((a * b) % D) / D * (inverse ? -1.0 : 1.0);
-            out[2 * (a * D + b)] = std::cos(ang);
-            out[2 * (a * D + b) + 1] = std::sin(ang);
-        }
-}
-
 static qf_status run_step(const qf_plan* p, const Step& s, const StateView& v, const double* theta, bool inverse,
                           hipStream_t st) {
-    std::vector<double> buf;
     switch (s.type) {
         case ST_AXIS: {
             Mat U = step_matrix(p, s, theta);
             if (inverse) U = dagger(U, p->D);
+            std::vector<double> buf;
             to_interleaved(U, buf);
             return launch_apply_1q(v, s.q, buf.data(), st);
         }
         case ST_CTRL: {
             int32_t sh[kMaxDim];
-            ctrl_shifts(p, s, inverse, sh);
+            const qf_op& o = p->gates[s.gates[0]].op;
+            for (int c = 0; c < p->D; ++c) {
+                const int v0 = shift_of(o, c, p->D);
+                sh[c] = inverse ? (p->D - v0) % p->D : v0;
+            }
             return launch_ctrl(v, s.q2, s.q, sh, st);
         }
         case ST_DIAG: {
-            cz_table(p->D, inverse, buf);
+            Mat t;
+            cz_table(p->D, inverse, t);
+            std::vector<double> buf;
+            to_interleaved(t, buf);
             const int32_t qs[2] = {s.q, s.q2};
             return launch_diag(v, 2, qs, buf.data(), st);
         }
@@ -327,6 +416,478 @@ static qf_status run_step(const qf_plan* p, const Step& s, const StateView& v, c
     return QF_OK;
 }
 
+// ---- stage planning ----
+
+struct Touch {
+    int q;
+    bool diag;  // the gate is block diagonal in this qudit's basis
+};
+
+static void touches(const qf_op& o, std::vector<Touch>& t) {
+    t.clear();
+    switch (o.kind) {
+        case QF_OP_H:
+        case QF_OP_RX:
+        case QF_OP_RY:
+        case QF_OP_X:
+            t.push_back({o.q0, false});
+            break;
+        case QF_OP_CLOCK:
+        case QF_OP_RZ:
+            t.push_back({o.q0, true});
+            break;
+        case QF_OP_CSUM:
+        case QF_OP_CSHIFT:
+            t.push_back({o.q0, true});
+            t.push_back({o.q1, false});
+            break;
+        case QF_OP_CZ:
+            t.push_back({o.q0, true});
+            t.push_back({o.q1, true});
+            break;
+        case QF_OP_U:
+            for (int q = o.q0; q < o.q0 + o.q1; ++q) t.push_back({q, false});
+            break;
+    }
+}
+
+// Qudit that must be inside the tile (-1: none; CZ acts on any digits).
+static int local_need(const qf_op& o) {
+    if (is_1q(o.kind) || o.kind == QF_OP_X) return o.q0;
+    if (o.kind == QF_OP_CSUM || o.kind == QF_OP_CSHIFT) return o.q1;
+    return -1;
+}
+
+// Default register group size per D (best of a sweep on MI355X, complex64,
+// at the default tile size).
+static int default_group(int D, int dtype) {
+    (void)dtype;
+    return std::min(max_group_size(uint32_t(D)), D == 2 ? 4 : D <= 4 ? 2 : 1);
+}
+
+static void tile_shape(int D, int n, int dtype, int tile_opt, int low_opt, bool adjoint, int& k, int& r) {
+    const size_t esz = dtype == QF_C64 ? 8 : 16;
+    // Default tile: at most 32 KB of forward amplitudes (measured best for
+    // D = 3, 5 on MI355X: several workgroups per CU overlap their load, compute
+    // and store phases); the adjoint holds psi and lam tiles in 56 KB.
+    const size_t budget = (adjoint ? 56 * 1024 : 32 * 1024);
+    if (tile_opt > 0) {
+        k = tile_opt;
+    } else {
+        k = 1;
+        while (size_t(ipow(D, k + 1)) * esz * (adjoint ? 2 : 1) <= budget && k + 1 <= n) ++k;
+    }
+    if (k >= n) {
+        k = n;
+        r = n;
+        return;
+    }
+    if (low_opt > 0) {
+        r = low_opt;
+    } else {
+        r = 1;
+        while (size_t(ipow(D, r)) * esz < 256 && r + 1 < k) ++r;
+    }
+    if (r >= k) r = k - 1;
+    while (ipow(D, k - r) > uint32_t(kMaxHi)) ++r;
+}
+
+static void make_geom(int D, int n, int k, int r, const std::vector<int>& T, StageGeom& g) {
+    g = StageGeom{};
+    g.k = k;
+    g.r = r;
+    g.TE = ipow(D, k);
+    g.R = ipow(D, r);
+    g.nhi = ipow(D, k - r);
+    g.ntiles = ipow(D, n - k);
+    g.N = ipow(D, n);
+    g.nout = n - k;
+    g.divR.init(g.R);
+    std::vector<bool> in(n, false);
+    for (int q : T) in[q] = true;
+    int h = 0;
+    for (int q : T)
+        if (q < n - r) g.hi_stride[h++] = ipow(D, n - 1 - q);
+    int o = 0;
+    for (int q = 0; q < n; ++q)
+        if (!in[q]) g.out_stride[o++] = ipow(D, n - 1 - q);
+}
+
+// Greedy stage builder over a gate sequence.  Each pass picks a tile (the low
+// r qudits plus the qudits the earliest remaining gates need), then takes, in
+// order, every remaining gate whose target is in the tile and that commutes
+// with every gate left behind so far (two gates commute when every qudit they
+// share is one on which both act block-diagonally).
+static void plan_passes(const qf_plan* p, const std::vector<GRef>& seq, int k, int r, int seg, PassList& out) {
+    const int n = p->n;
+    const int m = int(seq.size());
+    std::vector<char> done(m, 0);
+    int remaining = m, first = 0;
+    std::vector<Touch> tv;
+    while (remaining > 0) {
+        while (done[first]) ++first;
+        const qf_op& o0 = p->gates[seq[first].gi].op;
+        if (o0.kind == QF_OP_U) {
+            Pass pf;
+            pf.tile = false;
+            pf.fused = seq[first];
+            pf.seg = seg;
+            done[first] = 1;
+            --remaining;
+            out.passes.push_back(pf);
+            continue;
+        }
+        std::vector<char> inT(n, 0);
+        int cnt = 0;
+        for (int q = n - r; q < n; ++q) inT[q] = 1, ++cnt;
+        for (int i = first; i < m && cnt < k; ++i) {
+            if (done[i]) continue;
+            const int q = local_need(p->gates[seq[i].gi].op);
+            if (q >= 0 && !inT[q]) inT[q] = 1, ++cnt;
+        }
+        for (int q = n - r - 1; q >= 0 && cnt < k; --q)
+            if (!inT[q]) inT[q] = 1, ++cnt;
+        Pass ps;
+        ps.seg = seg;
+        for (int q = 0; q < n; ++q)
+            if (inT[q]) ps.T.push_back(q);
+        make_geom(p->D, n, k, r, ps.T, ps.geom);
+        std::vector<char> bFull(n, 0), bDiag(n, 0);
+        std::vector<std::vector<GRef>> pending(n);
+        auto flush = [&](int q) {
+            if (pending[q].empty()) return;
+            HOp h;
+            h.type = SOP_U;
+            h.q = q;
+            h.g = pending[q];
+            ps.ops.push_back(h);
+            pending[q].clear();
+        };
+        for (int i = first; i < m; ++i) {
+            if (done[i]) continue;
+            const qf_op& o = p->gates[seq[i].gi].op;
+            touches(o, tv);
+            bool conflict = false;
+            for (const Touch& t : tv) conflict = conflict || bFull[t.q] || (!t.diag && bDiag[t.q]);
+            const int need = local_need(o);
+            const bool local = o.kind != QF_OP_U && (need < 0 || inT[need]);
+            if (!conflict && local) {
+                done[i] = 1;
+                --remaining;
+                if (is_1q(o.kind)) {
+                    pending[o.q0].push_back(seq[i]);
+                    continue;
+                }
+                for (const Touch& t : tv) flush(t.q);
+                if (o.kind == QF_OP_CZ) {
+                    if (!ps.ops.empty() && ps.ops.back().type == SOP_PHASE && int(ps.ops.back().g.size()) < kMaxPairs) {
+                        ps.ops.back().g.push_back(seq[i]);
+                    } else {
+                        HOp h;
+                        h.type = SOP_PHASE;
+                        h.g = {seq[i]};
+                        ps.ops.push_back(h);
+                    }
+                } else {
+                    HOp h;
+                    h.type = SOP_SHIFT;
+                    h.q = (o.kind == QF_OP_X) ? o.q0 : o.q1;
+                    h.ctrl = (o.kind == QF_OP_X) ? -1 : o.q0;
+                    h.g = {seq[i]};
+                    ps.ops.push_back(h);
+                }
+            } else {
+                for (const Touch& t : tv) (t.diag ? bDiag : bFull)[t.q] = 1;
+            }
+        }
+        for (int q = 0; q < n; ++q) flush(q);
+        out.passes.push_back(ps);
+    }
+}
+
+static Mat group_matrix(const qf_plan* p, const std::vector<GRef>& g, const double* theta) {
+    Mat U = identity(p->D);
+    for (const GRef& r : g) {
+        Mat G = gate_matrix(p->gates[r.gi].op, p->D, theta);
+        if (r.inv) G = dagger(G, p->D);
+        U = matmul(G, U, p->D);
+    }
+    return U;
+}
+
+// Register rounds of a forward tile pass: consecutive ops are grouped while the
+// qudits they act on (targets of U and SHIFT) fit in a group of M tile qudits;
+// the group is padded with the most significant unused tile qudits.
+static void build_rounds(const qf_plan* p, Pass& ps, PassList& L, const std::vector<int>& dim_of, size_t& moff) {
+    const int D = p->D;
+    const int k = int(ps.geom.k);
+    const int M = p->group;
+    ps.nrounds = 0;
+    ps.round_off = int(L.hrounds.size());
+    if (k < M || ps.ops.empty()) return;
+    auto target_dim = [&](const HOp& h) { return h.type == SOP_PHASE ? -1 : dim_of[h.q]; };
+    size_t i = 0;
+    while (i < ps.ops.size()) {
+        std::vector<int> grp;
+        size_t j = i;
+        for (; j < ps.ops.size(); ++j) {
+            const int d = target_dim(ps.ops[j]);
+            if (d < 0 || std::find(grp.begin(), grp.end(), d) != grp.end()) continue;
+            if (int(grp.size()) == M) break;
+            grp.push_back(d);
+        }
+        for (int d = 0; int(grp.size()) < M && d < k; ++d)
+            if (std::find(grp.begin(), grp.end(), d) == grp.end()) grp.push_back(d);
+        std::sort(grp.begin(), grp.end());
+        RoundDesc rd{};
+        rd.op0 = int(i);
+        rd.nops = int(j - i);
+        for (int g = 0; g < M; ++g) rd.gls[g] = ipow(D, k - 1 - grp[g]);
+        rd.nother = k - M;
+        int o = 0;
+        for (int d = 0; d < k; ++d)
+            if (std::find(grp.begin(), grp.end(), d) == grp.end()) rd.ols[o++] = ipow(D, k - 1 - d);
+        auto gpos_of_qudit = [&](int q) -> int {
+            if (q < 0 || dim_of[q] < 0) return -1;
+            auto it = std::find(grp.begin(), grp.end(), dim_of[q]);
+            return it == grp.end() ? -1 : int(it - grp.begin());
+        };
+        for (size_t oi = i; oi < j; ++oi) {
+            const HOp& h = ps.ops[oi];
+            StageOp& so = L.hops[ps.op_off + oi];
+            so.gpos = h.type == SOP_PHASE ? -1 : gpos_of_qudit(h.q);
+            so.ctrl_gpos = h.type == SOP_SHIFT ? gpos_of_qudit(h.ctrl) : -1;
+            if (h.type == SOP_PHASE) {
+                for (size_t pi = 0; pi < h.g.size(); ++pi) {
+                    const qf_op& g = p->gates[h.g[pi].gi].op;
+                    so.agpos[pi] = gpos_of_qudit(g.q0);
+                    so.bgpos[pi] = gpos_of_qudit(g.q1);
+                }
+                so.wtab = int(moff);
+                moff += size_t(D);
+            }
+        }
+        L.hrounds.push_back(rd);
+        ++ps.nrounds;
+        i = j;
+    }
+}
+
+// Static part of the stage ops; matrix offsets; M slots (for adjoint lists).
+static void finalize_passes(const qf_plan* p, PassList& L, bool adjoint) {
+    const int D = p->D, n = p->n;
+    L.hops.clear();
+    L.hrounds.clear();
+    L.nmats = 0;
+    L.nslots = 0;
+    for (Pass& ps : L.passes) {
+        if (!ps.tile) continue;
+        ps.op_off = int(L.hops.size());
+        ps.mat_off = L.nmats;
+        ps.nslots = 0;
+        ps.slot0 = L.nslots;
+        size_t moff = 0;
+        std::vector<int> dim_of(n, -1);
+        for (size_t i = 0; i < ps.T.size(); ++i) dim_of[ps.T[i]] = int(i);
+        const int k = int(ps.geom.k);
+        for (HOp& h : ps.ops) {
+            StageOp so{};
+            so.type = h.type;
+            so.slot = -1;
+            if (h.type == SOP_U || h.type == SOP_SHIFT) {
+                so.dim = dim_of[h.q];
+                so.ls = ipow(D, k - 1 - so.dim);
+                so.divls.init(so.ls);
+            }
+            if (h.type == SOP_U) {
+                so.mat = int(moff);
+                moff += size_t(D) * D;
+                bool real = true, rot = false;
+                for (const GRef& r : h.g) {
+                    const int kind = p->gates[r.gi].op.kind;
+                    real = real && kind == QF_OP_RY;
+                    rot = rot || is_rot(kind);
+                }
+                so.real = real;
+                if (adjoint && rot) {
+                    h.slot = ps.nslots++;
+                    h.gslot = L.nslots++;
+                    so.slot = h.slot;
+                }
+            } else if (h.type == SOP_SHIFT) {
+                const GRef& r = h.g[0];
+                const qf_op& o = p->gates[r.gi].op;
+                so.has_ctrl = h.ctrl >= 0;
+                so.ctrl_stride.init(h.ctrl >= 0 ? ipow(D, n - 1 - h.ctrl) : 1u);
+                for (int c = 0; c < D; ++c) {
+                    const int v = shift_of(o, c, D);
+                    so.shifts[c] = r.inv ? (D - v) % D : v;
+                }
+            } else {
+                so.npairs = int(h.g.size());
+                for (size_t j = 0; j < h.g.size(); ++j) {
+                    const qf_op& o = p->gates[h.g[j].gi].op;
+                    so.pa[j].init(ipow(D, n - 1 - o.q0));
+                    so.pb[j].init(ipow(D, n - 1 - o.q1));
+                    so.ptab[j] = int(moff);
+                    moff += size_t(D) * D;
+                }
+            }
+            L.hops.push_back(so);
+        }
+        ps.nops = int(ps.ops.size());
+        if (!adjoint) build_rounds(p, ps, L, dim_of, moff);
+        ps.nmat = moff;
+        L.nmats += moff;
+    }
+}
+
+static qf_status upload_ops(const qf_plan* p, PassList& L) {
+    const size_t esz = p->dtype == QF_C64 ? 8 : 16;
+    if (!L.hops.empty()) {
+        QF_HIP_CHECK(hipMalloc(reinterpret_cast<void**>(&L.dops), L.hops.size() * sizeof(StageOp)));
+        QF_HIP_CHECK(hipMemcpy(L.dops, L.hops.data(), L.hops.size() * sizeof(StageOp), hipMemcpyHostToDevice));
+    }
+    if (!L.hrounds.empty()) {
+        QF_HIP_CHECK(hipMalloc(reinterpret_cast<void**>(&L.drounds), L.hrounds.size() * sizeof(RoundDesc)));
+        QF_HIP_CHECK(hipMemcpy(L.drounds, L.hrounds.data(), L.hrounds.size() * sizeof(RoundDesc),
+                               hipMemcpyHostToDevice));
+    }
+    const size_t mb = std::max<size_t>(L.nmats, 1) * esz;
+    QF_HIP_CHECK(hipMalloc(&L.dmats, mb));
+    QF_HIP_CHECK(hipHostMalloc(&L.hmats, mb, hipHostMallocDefault));
+    QF_HIP_CHECK(hipEventCreateWithFlags(&L.copied, hipEventDisableTiming));
+    QF_HIP_CHECK(hipEventCreateWithFlags(&L.done, hipEventDisableTiming));
+    return QF_OK;
+}
+
+template <typename T>
+static void put_mat(void* base, size_t off, const Mat& m) {
+    cplx<T>* d = reinterpret_cast<cplx<T>*>(base) + off;
+    for (size_t i = 0; i < m.size(); ++i) d[i] = cmake<T>(T(m[i].real()), T(m[i].imag()));
+}
+
+// Build every stage matrix from theta into the pinned staging buffer and copy it
+// to the device on `st`.
+static qf_status upload_mats(const qf_plan* p, PassList& L, const double* theta, hipStream_t st) {
+    if (L.dmats == nullptr) QF_CHECK(upload_ops(p, L));
+    if (L.copied_valid) QF_HIP_CHECK(hipEventSynchronize(L.copied));
+    const int D = p->D;
+    for (const Pass& ps : L.passes) {
+        if (!ps.tile) continue;
+        for (size_t i = 0; i < ps.ops.size(); ++i) {
+            const HOp& h = ps.ops[i];
+            const StageOp& so = L.hops[ps.op_off + i];
+            if (h.type == SOP_U) {
+                const Mat U = group_matrix(p, h.g, theta);
+                if (p->dtype == QF_C64)
+                    put_mat<float>(L.hmats, ps.mat_off + so.mat, U);
+                else
+                    put_mat<double>(L.hmats, ps.mat_off + so.mat, U);
+            } else if (h.type == SOP_PHASE) {
+                for (size_t j = 0; j < h.g.size(); ++j) {
+                    Mat t;
+                    cz_table(D, h.g[j].inv, t);
+                    if (p->dtype == QF_C64)
+                        put_mat<float>(L.hmats, ps.mat_off + so.ptab[j], t);
+                    else
+                        put_mat<double>(L.hmats, ps.mat_off + so.ptab[j], t);
+                }
+                if (ps.nrounds > 0) {
+                    // w^e for the summed exponent e of the op's CZ factors (all of one direction)
+                    const double pi = 3.14159265358979323846;
+                    const double sgn = h.g[0].inv ? -1.0 : 1.0;
+                    Mat w(static_cast<size_t>(D));
+                    for (int e = 0; e < D; ++e) w[e] = std::polar(1.0, sgn * 2 * pi * e / D);
+                    if (p->dtype == QF_C64)
+                        put_mat<float>(L.hmats, ps.mat_off + so.wtab, w);
+                    else
+                        put_mat<double>(L.hmats, ps.mat_off + so.wtab, w);
+                }
+            }
+        }
+    }
+    if (L.done_valid) QF_HIP_CHECK(hipStreamWaitEvent(st, L.done, 0));
+    const size_t esz = p->dtype == QF_C64 ? 8 : 16;
+    if (L.nmats) QF_HIP_CHECK(hipMemcpyAsync(L.dmats, L.hmats, L.nmats * esz, hipMemcpyHostToDevice, st));
+    QF_HIP_CHECK(hipEventRecord(L.copied, st));
+    L.copied_valid = true;
+    return QF_OK;
+}
+
+// ---- profiling ----
+
+static qf_status prof_begin(qf_plan* p, hipStream_t st, hipEvent_t* a) {
+    *a = nullptr;
+    if (!p->profiling) return QF_OK;
+    if (p->ev_used + 2 > p->ev_pool.size()) {
+        for (int i = 0; i < 64; ++i) {
+            hipEvent_t e;
+            QF_HIP_CHECK(hipEventCreate(&e));
+            p->ev_pool.push_back(e);
+        }
+    }
+    *a = p->ev_pool[p->ev_used++];
+    QF_HIP_CHECK(hipEventRecord(*a, st));
+    return QF_OK;
+}
+
+static qf_status prof_end(qf_plan* p, hipStream_t st, hipEvent_t a, int family, double bytes) {
+    if (!p->profiling || a == nullptr) return QF_OK;
+    hipEvent_t b = p->ev_pool[p->ev_used++];
+    QF_HIP_CHECK(hipEventRecord(b, st));
+    p->prof.push_back({family, bytes, a, b});
+    return QF_OK;
+}
+
+// ---- checkpoints ----
+
+static size_t state_bytes(const StateView& v) { return size_t(v.total) * (v.dtype == QF_C64 ? 8 : 16); }
+
+static qf_status ensure_ckpt(qf_plan* p, const StateView& v) {
+    const size_t nsave = p->seg_end.size() > 1 ? p->seg_end.size() - 1 : 0;
+    const size_t need = nsave * state_bytes(v);
+    if (need <= p->ckpt_bytes) return QF_OK;
+    if (p->ckpt) QF_HIP_CHECK(hipFree(p->ckpt));
+    p->ckpt = nullptr;
+    p->ckpt_bytes = 0;
+    if (hipMalloc(&p->ckpt, need) != hipSuccess) {
+        (void)hipGetLastError();
+        p->ckpt = nullptr;
+        return set_error(QF_ENOMEM, "checkpoint allocation of %zu bytes failed", need);
+    }
+    p->ckpt_bytes = need;
+    return QF_OK;
+}
+
+static qf_status run_tile_pass(qf_plan* p, const PassList& L, const Pass& ps, const StateView& v, void* lam,
+                               double* partial, hipStream_t st) {
+    const size_t esz = p->dtype == QF_C64 ? 8 : 16;
+    const void* mats = reinterpret_cast<const unsigned char*>(L.dmats) + ps.mat_off * esz;
+    hipEvent_t a;
+    QF_CHECK(prof_begin(p, st, &a));
+    if (lam == nullptr) {
+        if (ps.nrounds > 0 && p->opts.stage_kernel == 0)
+            QF_CHECK(launch_stage_rounds(v, p->group, ps.geom, L.drounds + ps.round_off, ps.nrounds,
+                                         L.dops + ps.op_off, mats, st));
+        else
+            QF_CHECK(launch_stage(v, ps.geom, L.dops + ps.op_off, ps.nops, mats, st));
+        QF_CHECK(prof_end(p, st, a, F_STAGE, 2.0 * state_bytes(v)));
+    } else {
+        QF_CHECK(launch_stage_adj(v, lam, ps.geom, L.dops + ps.op_off, ps.nops, mats, partial, st));
+        QF_CHECK(prof_end(p, st, a, F_STAGE_ADJ, 4.0 * state_bytes(v)));
+    }
+    return QF_OK;
+}
+
+static qf_status run_fused_pass(qf_plan* p, const Pass& ps, const StateView& v, hipStream_t st) {
+    const Gate& g = p->gates[ps.fused.gi];
+    hipEvent_t a;
+    QF_CHECK(prof_begin(p, st, &a));
+    QF_CHECK(launch_fused(v, g.op.q1, g.op.q0, ps.fused.inv ? g.dmat_adj : g.dmat, st));
+    return prof_end(p, st, a, F_FUSED, 2.0 * state_bytes(v));
+}
+
 static qf_status check_plan_state(const qf_plan* p, const qf_state* s, StateView& v) {
     QF_RETURN_IF(p == nullptr, QF_EINVAL, "plan is NULL");
     QF_CHECK(make_view(s, v));
@@ -334,6 +895,29 @@ static qf_status check_plan_state(const qf_plan* p, const qf_state* s, StateView
                  "state (dim %u, n %u, dtype %d) does not match the plan (dim %d, n %d, dtype %d)", v.D, v.n, v.dtype,
                  p->D, p->n, p->dtype);
     return QF_OK;
+}
+
+// Gradient contributions of one fused run of one-qudit gates from its M:
+// dL/dtheta_i += Im Tr(V_i S_i V_i^dagger M), V_i = product of the run's gates
+// after gate i (forward order), M = sum_f psi_f lam_f^dagger after the run.
+static void add_group_grad(const qf_plan* p, const std::vector<int>& fwd_gates, const double* theta,
+                           const double* M, double* grad) {
+    const int D = p->D;
+    const int m = int(fwd_gates.size());
+    std::vector<Mat> suffix(m + 1);
+    suffix[m] = identity(D);
+    for (int i = m - 1; i >= 0; --i)
+        suffix[i] = matmul(suffix[i + 1], gate_matrix(p->gates[fwd_gates[i]].op, D, theta), D);
+    for (int i = 0; i < m; ++i) {
+        const qf_op& o = p->gates[fwd_gates[i]].op;
+        if (!is_rot(o.kind)) continue;
+        const Mat& V = suffix[i + 1];
+        const Mat A = matmul(matmul(V, generator(o, D), D), dagger(V, D), D);
+        cd tr(0, 0);
+        for (int r = 0; r < D; ++r)
+            for (int c = 0; c < D; ++c) tr += A[size_t(r) * D + c] * cd(M[2 * (c * D + r)], M[2 * (c * D + r) + 1]);
+        grad[o.param] += tr.imag();
+    }
 }
 
 }  // namespace qf
@@ -347,10 +931,15 @@ qf_status qf_plan_create(int32_t dim, int32_t n, int32_t dtype, const qf_op* ops
     QF_RETURN_IF(out == nullptr, QF_EINVAL, "out is NULL");
     *out = nullptr;
     QF_RETURN_IF(dim < 2 || dim > kMaxDim, QF_ERANGE, "dim %d outside 2..%d", dim, kMaxDim);
-    QF_RETURN_IF(n < 1, QF_EINVAL, "n = %d < 1", n);
+    QF_RETURN_IF(n < 1 || n > 32, QF_EINVAL, "n = %d outside 1..32", n);
     QF_RETURN_IF(dtype != QF_C64 && dtype != QF_C128, QF_EDTYPE, "unknown dtype %d", dtype);
     QF_RETURN_IF(nops < 0 || (nops > 0 && ops == nullptr), QF_EINVAL, "bad op list");
     QF_RETURN_IF(nparams < 0, QF_EINVAL, "nparams < 0");
+    {
+        uint64_t N = 1;
+        for (int i = 0; i < n; ++i) N *= uint64_t(dim);
+        QF_RETURN_IF(N >= (1ull << 32), QF_ERANGE, "dim^n exceeds 2^32 amplitudes");
+    }
     for (int i = 0; i < nops; ++i) {
         qf_status st = validate_op(ops[i], dim, n, nparams);
         if (st != QF_OK) return set_error(st, "op %d: %s", i, qf_last_error());
@@ -362,6 +951,15 @@ qf_status qf_plan_create(int32_t dim, int32_t n, int32_t dtype, const qf_op* ops
     p->dtype = dtype;
     p->nparams = nparams;
     if (opts) p->opts = *opts;
+    QF_RETURN_IF(p->opts.fuse < 0 || p->opts.fuse > 2, QF_EINVAL, "fuse = %d outside 0..2", p->opts.fuse);
+    QF_RETURN_IF(p->opts.group_digits < 0 || p->opts.group_digits > max_group_size(uint32_t(dim)), QF_EINVAL,
+                 "group_digits = %d outside 0..%d for dim %d", p->opts.group_digits, max_group_size(uint32_t(dim)),
+                 dim);
+    p->group = p->opts.group_digits > 0 ? p->opts.group_digits : default_group(dim, dtype);
+    QF_RETURN_IF(p->opts.tile_digits < 0 || p->opts.tile_digits > kMaxTileDims || p->opts.adj_tile_digits < 0 ||
+                     p->opts.adj_tile_digits > kMaxTileDims || p->opts.low_digits < 0 || p->opts.ckpt_every < 0 ||
+                     p->opts.stage_kernel < 0 || p->opts.stage_kernel > 1,
+                 QF_EINVAL, "bad tile / checkpoint options");
     p->gates.resize(nops);
     for (int i = 0; i < nops; ++i) {
         Gate& g = p->gates[i];
@@ -380,13 +978,17 @@ qf_status qf_plan_create(int32_t dim, int32_t n, int32_t dtype, const qf_op* ops
                     if (dtype == QF_C64) {
                         float* fa = reinterpret_cast<float*>(a.data()) + 2 * (r * K + c);
                         float* fb = reinterpret_cast<float*>(b.data()) + 2 * (r * K + c);
-                        fa[0] = float(x.real()); fa[1] = float(x.imag());
-                        fb[0] = float(y.real()); fb[1] = float(y.imag());
+                        fa[0] = float(x.real());
+                        fa[1] = float(x.imag());
+                        fb[0] = float(y.real());
+                        fb[1] = float(y.imag());
                     } else {
                         double* da = reinterpret_cast<double*>(a.data()) + 2 * (r * K + c);
                         double* db = reinterpret_cast<double*>(b.data()) + 2 * (r * K + c);
-                        da[0] = x.real(); da[1] = x.imag();
-                        db[0] = y.real(); db[1] = y.imag();
+                        da[0] = x.real();
+                        da[1] = x.imag();
+                        db[0] = y.real();
+                        db[1] = y.imag();
                     }
                 }
             QF_HIP_CHECK(hipMalloc(&g.dmat, a.size()));
@@ -395,19 +997,92 @@ qf_status qf_plan_create(int32_t dim, int32_t n, int32_t dtype, const qf_op* ops
             QF_HIP_CHECK(hipMemcpy(g.dmat_adj, b.data(), b.size(), hipMemcpyHostToDevice));
         }
     }
-    build_schedule(p.get());
+    // checkpoint segments: [0, e0), [e0, e1), ...
+    const int every = p->opts.ckpt_every;
+    for (int e = every; every > 0 && e < nops; e += every) p->seg_end.push_back(e);
+    p->seg_end.push_back(nops);
+    if (p->opts.fuse != 0) {
+        build_steps(p.get());
+    } else if (nops > 0) {
+        int k, r, ka, ra;
+        tile_shape(dim, n, dtype, p->opts.tile_digits, p->opts.low_digits, false, k, r);
+        tile_shape(dim, n, dtype, p->opts.adj_tile_digits, p->opts.low_digits, true, ka, ra);
+        const size_t esz = dtype == QF_C64 ? 8 : 16;
+        // gfx950 has 160 KB of LDS per workgroup
+        QF_RETURN_IF(size_t(ipow(dim, k)) * esz + 4096 > 160 * 1024 ||
+                         2 * size_t(ipow(dim, ka)) * esz + 8192 > 160 * 1024,
+                     QF_ERANGE, "tile of %d (adjoint %d) qudits exceeds the 160 KB LDS of a workgroup", k, ka);
+        int start = 0;
+        for (size_t sgi = 0; sgi < p->seg_end.size(); ++sgi) {
+            std::vector<GRef> seq;
+            for (int i = start; i < p->seg_end[sgi]; ++i) seq.push_back({i, false});
+            plan_passes(p.get(), seq, k, r, int(sgi), p->fwd);
+            start = p->seg_end[sgi];
+        }
+        for (int sgi = int(p->seg_end.size()) - 1; sgi >= 0; --sgi) {
+            const int lo = sgi == 0 ? 0 : p->seg_end[sgi - 1];
+            std::vector<GRef> seq;
+            for (int i = p->seg_end[sgi] - 1; i >= lo; --i) seq.push_back({i, true});
+            plan_passes(p.get(), seq, ka, ra, sgi, p->rev);
+        }
+        finalize_passes(p.get(), p->fwd, false);
+        finalize_passes(p.get(), p->rev, true);
+    }
     *out = p.release();
     return QF_OK;
 }
 
-int32_t qf_plan_num_stages(const qf_plan* plan) { return plan ? int32_t(plan->steps.size()) : -1; }
+int32_t qf_plan_num_stages(const qf_plan* plan) {
+    if (!plan) return -1;
+    return plan->opts.fuse != 0 ? int32_t(plan->steps.size()) : int32_t(plan->fwd.passes.size());
+}
+
+int32_t qf_plan_num_adjoint_stages(const qf_plan* plan) {
+    if (!plan) return -1;
+    return plan->opts.fuse != 0 ? int32_t(plan->steps.size()) : int32_t(plan->rev.passes.size());
+}
 
 qf_status qf_plan_forward(qf_plan* plan, const qf_state* s, const double* theta, void* stream) {
     StateView v;
     QF_CHECK(check_plan_state(plan, s, v));
     QF_RETURN_IF(plan->nparams > 0 && theta == nullptr, QF_EINVAL, "theta is NULL");
+    QF_CHECK(check_finite_theta(theta, plan->nparams));
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    for (const Step& step : plan->steps) QF_CHECK(run_step(plan, step, v, theta, false, st));
+    if (plan->opts.fuse != 0) {
+        for (const Step& step : plan->steps) {
+            hipEvent_t a;
+            QF_CHECK(prof_begin(plan, st, &a));
+            QF_CHECK(run_step(plan, step, v, theta, false, st));
+            const int fam = step.type == ST_AXIS ? F_AXIS
+                            : step.type == ST_CTRL ? F_CTRL
+                            : step.type == ST_DIAG ? F_DIAG
+                                                   : F_FUSED;
+            QF_CHECK(prof_end(plan, st, a, fam, 2.0 * state_bytes(v)));
+        }
+        return QF_OK;
+    }
+    if (plan->fwd.passes.empty()) return QF_OK;
+    const bool save = plan->seg_end.size() > 1;
+    if (save) QF_CHECK(ensure_ckpt(plan, v));
+    QF_CHECK(upload_mats(plan, plan->fwd, theta, st));
+    const size_t sb = state_bytes(v);
+    for (size_t i = 0; i < plan->fwd.passes.size(); ++i) {
+        const Pass& ps = plan->fwd.passes[i];
+        if (ps.tile)
+            QF_CHECK(run_tile_pass(plan, plan->fwd, ps, v, nullptr, nullptr, st));
+        else
+            QF_CHECK(run_fused_pass(plan, ps, v, st));
+        const bool seg_end = i + 1 == plan->fwd.passes.size() || plan->fwd.passes[i + 1].seg != ps.seg;
+        if (save && seg_end && size_t(ps.seg) + 1 < plan->seg_end.size()) {
+            hipEvent_t a;
+            QF_CHECK(prof_begin(plan, st, &a));
+            QF_HIP_CHECK(hipMemcpyAsync(reinterpret_cast<unsigned char*>(plan->ckpt) + size_t(ps.seg) * sb, v.amps,
+                                        sb, hipMemcpyDeviceToDevice, st));
+            QF_CHECK(prof_end(plan, st, a, F_CKPT, 2.0 * sb));
+        }
+    }
+    QF_HIP_CHECK(hipEventRecord(plan->fwd.done, st));
+    plan->fwd.done_valid = true;
     return QF_OK;
 }
 
@@ -421,6 +1096,7 @@ qf_status qf_adjoint_grad(qf_plan* plan, const qf_state* psi, const qf_state* la
     QF_RETURN_IF(psi->amps == lam->amps, QF_EINVAL, "psi and lam must not alias");
     QF_RETURN_IF(grad == nullptr, QF_EINVAL, "grad is NULL");
     QF_RETURN_IF(plan->nparams > 0 && theta == nullptr, QF_EINVAL, "theta is NULL");
+    QF_CHECK(check_finite_theta(theta, plan->nparams));
     std::vector<int> active;
     std::vector<double> table;
     QF_CHECK(combine_terms(v, nterms, term_qudit, term_diag, active, table));
@@ -429,31 +1105,74 @@ qf_status qf_adjoint_grad(qf_plan* plan, const qf_state* psi, const qf_state* la
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const int D = plan->D;
     const size_t E = size_t(D) * D;
+    const bool staged = plan->opts.fuse == 0;
+    const int nslots = staged ? plan->rev.nslots : plan->nslots;
+    QF_RETURN_IF(staged && plan->seg_end.size() > 1 && (plan->ckpt == nullptr || !plan->fwd.done_valid), QF_EINVAL,
+                 "checkpointed plan: run qf_plan_forward on this state first");
 
     // lam = H_O psi with H_O the Hermitian part of O
     QF_CHECK(launch_diag_observable(v, lam->amps, active, table_re, st));
 
+    size_t pdoubles = 1;
+    if (staged) {
+        for (const Pass& ps : plan->rev.passes)
+            if (ps.tile) pdoubles = std::max(pdoubles, size_t(ps.nslots) * ps.geom.ntiles * v.batch * E * 2);
+    } else {
+        pdoubles = std::max<size_t>(adj_axis_partial_doubles(v), 1);
+    }
     double* partial = nullptr;
     double* mdev = nullptr;
-    const size_t mcount = size_t(v.batch) * std::max(plan->nslots, 1) * E * 2;
-    QF_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&partial),
-                                std::max<size_t>(adj_axis_partial_doubles(v), 1) * sizeof(double), st));
+    const size_t mcount = size_t(v.batch) * std::max(nslots, 1) * E * 2;
+    QF_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&partial), pdoubles * sizeof(double), st));
     QF_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&mdev), mcount * sizeof(double), st));
     qf_status rs = QF_OK;
-    for (int si = int(plan->steps.size()) - 1; si >= 0 && rs == QF_OK; --si) {
-        const Step& s = plan->steps[si];
-        if (s.type == ST_AXIS && s.has_param) {
-            Mat W = dagger(step_matrix(plan, s, theta), D);
-            std::vector<double> buf;
-            to_interleaved(W, buf);
-            rs = launch_adj_axis(v, lam->amps, s.q, buf.data(), partial, mdev, plan->nslots, s.slot, st);
-        } else {
-            rs = run_step(plan, s, v, theta, true, st);
-            if (rs == QF_OK) rs = run_step(plan, s, vl, theta, true, st);
+    if (staged) {
+        rs = upload_mats(plan, plan->rev, theta, st);
+        const size_t sb = state_bytes(v);
+        for (size_t i = 0; i < plan->rev.passes.size() && rs == QF_OK; ++i) {
+            const Pass& ps = plan->rev.passes[i];
+            // re-anchor psi at the start of each reverse segment but the last one
+            const bool seg_start = i == 0 || plan->rev.passes[i - 1].seg != ps.seg;
+            if (seg_start && size_t(ps.seg) + 1 < plan->seg_end.size()) {
+                hipError_t e = hipMemcpyAsync(v.amps, reinterpret_cast<unsigned char*>(plan->ckpt) + size_t(ps.seg) * sb,
+                                              sb, hipMemcpyDeviceToDevice, st);
+                if (e != hipSuccess) rs = set_error(QF_EHIP, "checkpoint restore failed: %s", hipGetErrorString(e));
+            }
+            if (rs != QF_OK) break;
+            if (ps.tile) {
+                rs = run_tile_pass(plan, plan->rev, ps, v, lam->amps, partial, st);
+                if (rs == QF_OK)
+                    rs = launch_stage_mreduce(partial, ps.nslots, ps.geom.ntiles, v.batch, uint32_t(E), mdev,
+                                              uint32_t(plan->rev.nslots), uint32_t(ps.slot0), st);
+            } else {
+                rs = run_fused_pass(plan, ps, v, st);
+                if (rs == QF_OK) rs = run_fused_pass(plan, ps, vl, st);
+            }
+        }
+        if (rs == QF_OK) {
+            hipError_t e = hipEventRecord(plan->rev.done, st);
+            if (e == hipSuccess) plan->rev.done_valid = true;
+        }
+    } else {
+        for (int si = int(plan->steps.size()) - 1; si >= 0 && rs == QF_OK; --si) {
+            const Step& s = plan->steps[si];
+            if (s.type == ST_AXIS && s.has_param) {
+                Mat W = dagger(step_matrix(plan, s, theta), D);
+                std::vector<double> buf;
+                to_interleaved(W, buf);
+                hipEvent_t a;
+                rs = prof_begin(plan, st, &a);
+                if (rs == QF_OK)
+                    rs = launch_adj_axis(v, lam->amps, s.q, buf.data(), partial, mdev, plan->nslots, s.slot, st);
+                if (rs == QF_OK) rs = prof_end(plan, st, a, F_ADJ_AXIS, 4.0 * state_bytes(v));
+            } else {
+                rs = run_step(plan, s, v, theta, true, st);
+                if (rs == QF_OK) rs = run_step(plan, s, vl, theta, true, st);
+            }
         }
     }
     std::vector<double> mhost(mcount);
-    if (rs == QF_OK && plan->nslots > 0) {
+    if (rs == QF_OK && nslots > 0) {
         hipError_t e = hipMemcpyAsync(mhost.data(), mdev, mcount * sizeof(double), hipMemcpyDeviceToHost, st);
         if (e != hipSuccess) rs = set_error(QF_EHIP, "copy of M matrices failed: %s", hipGetErrorString(e));
     }
@@ -463,30 +1182,62 @@ qf_status qf_adjoint_grad(qf_plan* plan, const qf_state* psi, const qf_state* la
     if (rs != QF_OK) return rs;
     QF_RETURN_IF(e != hipSuccess, QF_EHIP, "stream synchronisation failed: %s", hipGetErrorString(e));
 
-    // dL/dtheta_i = Im Tr(V_i S_i V_i^dagger M) with V_i the product of the
-    // step's gates after gate i and M = sum_f psi_f lam_f^dagger after the step.
     std::memset(grad, 0, sizeof(double) * size_t(v.batch) * plan->nparams);
-    for (const Step& s : plan->steps) {
-        if (!(s.type == ST_AXIS && s.has_param)) continue;
-        const int m = int(s.gates.size());
-        std::vector<Mat> suffix(m + 1);
-        suffix[m] = identity(D);
-        for (int i = m - 1; i >= 0; --i)
-            suffix[i] = matmul(suffix[i + 1], gate_matrix(plan->gates[s.gates[i]].op, D, theta), D);
-        for (int i = 0; i < m; ++i) {
-            const qf_op& o = plan->gates[s.gates[i]].op;
-            if (!is_rot(o.kind)) continue;
-            const Mat& V = suffix[i + 1];
-            const Mat A = matmul(matmul(V, generator(o, D), D), dagger(V, D), D);
-            for (uint32_t b = 0; b < v.batch; ++b) {
-                const double* M = mhost.data() + ((size_t(b) * plan->nslots + s.slot) * E) * 2;
-                cd tr(0, 0);
-                for (int r = 0; r < D; ++r)
-                    for (int c = 0; c < D; ++c) tr += A[size_t(r) * D + c] * cd(M[2 * (c * D + r)], M[2 * (c * D + r) + 1]);
-                grad[size_t(b) * plan->nparams + o.param] += tr.imag();
-            }
+    for (uint32_t b = 0; b < v.batch; ++b) {
+        double* gb = grad + size_t(b) * plan->nparams;
+        if (staged) {
+            for (const Pass& ps : plan->rev.passes)
+                for (const HOp& h : ps.ops) {
+                    if (h.gslot < 0) continue;
+                    std::vector<int> fwd_gates;
+                    for (auto it = h.g.rbegin(); it != h.g.rend(); ++it) fwd_gates.push_back(it->gi);
+                    add_group_grad(plan, fwd_gates, theta, mhost.data() + ((size_t(b) * nslots + h.gslot) * E) * 2,
+                                   gb);
+                }
+        } else {
+            for (const Step& s : plan->steps)
+                if (s.type == ST_AXIS && s.has_param)
+                    add_group_grad(plan, s.gates, theta, mhost.data() + ((size_t(b) * nslots + s.slot) * E) * 2, gb);
         }
     }
+    return QF_OK;
+}
+
+qf_status qf_plan_set_profiling(qf_plan* plan, int32_t enable) {
+    QF_RETURN_IF(plan == nullptr, QF_EINVAL, "plan is NULL");
+    plan->profiling = enable != 0;
+    plan->prof.clear();
+    plan->ev_used = 0;
+    return QF_OK;
+}
+
+qf_status qf_plan_read_profile(qf_plan* plan, qf_kernel_stat* out, int32_t cap, int32_t* count) {
+    QF_RETURN_IF(plan == nullptr || count == nullptr, QF_EINVAL, "plan or count is NULL");
+    double ms[F_COUNT] = {0}, bytes[F_COUNT] = {0};
+    int64_t launches[F_COUNT] = {0};
+    for (const ProfRec& r : plan->prof) {
+        QF_HIP_CHECK(hipEventSynchronize(r.b));
+        float t = 0.f;
+        QF_HIP_CHECK(hipEventElapsedTime(&t, r.a, r.b));
+        ms[r.family] += t;
+        bytes[r.family] += r.bytes;
+        launches[r.family] += 1;
+    }
+    int c = 0;
+    for (int f = 0; f < F_COUNT; ++f) {
+        if (launches[f] == 0) continue;
+        if (out && c < cap) {
+            std::memset(out[c].name, 0, sizeof(out[c].name));
+            std::strncpy(out[c].name, kFamilies[f], sizeof(out[c].name) - 1);
+            out[c].launches = launches[f];
+            out[c].total_ms = ms[f];
+            out[c].bytes = bytes[f];
+        }
+        ++c;
+    }
+    *count = c;
+    plan->prof.clear();
+    plan->ev_used = 0;
     return QF_OK;
 }
 

@@ -49,3 +49,85 @@ qf_status launch_diag_observable(const StateView& psi, void* lam_amps, const std
 qf_status launch_fused(const StateView& s, int k, int q0, const void* B, hipStream_t st);
 
 }  // namespace qf
+
+namespace qf {
+
+// ---- fused LDS stages (k_stage.hip) ----
+//
+// A stage keeps a tile of k qudits of one register in LDS: the r least
+// significant qudits (a contiguous run of R = D^r amplitudes in HBM) plus k - r
+// further qudits.  The other n - k qudits are fixed per tile.  The tile's local
+// index e has the tile qudits in increasing qudit order (most significant
+// first); the global index of local element e is
+//   base(tile) + offhi[e / R] + e % R.
+constexpr int kMaxTileDims = 16;
+constexpr int kMaxOuter = 32;
+constexpr int kMaxHi = 1024;  // D^(k-r) entries of the offhi table
+constexpr int kMaxPairs = 8;
+
+struct StageGeom {
+    uint32_t k, r;       // tile qudits, low (contiguous) qudits
+    uint32_t TE;         // D^k tile elements
+    uint32_t R;          // D^r
+    uint32_t nhi;        // D^(k-r)
+    uint32_t ntiles;     // D^(n-k) tiles per register
+    uint32_t N;          // D^n
+    uint32_t nout;       // n - k
+    FastDiv divR;
+    uint32_t hi_stride[kMaxTileDims];  // global strides of the high tile qudits, most significant first
+    uint32_t out_stride[kMaxOuter];    // global strides of the outer qudits, most significant first
+};
+
+enum StageOpType : int32_t { SOP_U = 0, SOP_SHIFT = 1, SOP_PHASE = 2 };
+
+// Register rounds of a forward stage: each lane holds a sub-tile of D^M
+// amplitudes (every combination of the M group qudits) in registers and applies
+// the round's ops [op0, op0 + nops) to it; the group position of each op's
+// qudits is stored in the op (gpos, ctrl_gpos, agpos/bgpos).
+constexpr int kMaxGroup = 5;
+struct RoundDesc {
+    int32_t op0, nops;
+    uint32_t gls[kMaxGroup];        // LDS strides of the group qudits, register digit 0 first
+    int32_t nother;                 // k - M
+    uint32_t ols[kMaxTileDims];     // LDS strides of the other tile qudits, most significant first
+};
+
+struct StageOp {
+    int32_t type;
+    int32_t dim;          // local tile dimension (U, SHIFT)
+    uint32_t ls;          // LDS stride of dim, D^(k-1-dim)
+    FastDiv divls;
+    int32_t has_ctrl;     // SHIFT: 1 if controlled
+    FastDiv ctrl_stride;  // SHIFT: global stride of the control qudit
+    int32_t shifts[16];   // SHIFT: x_t -> x_t + shifts[x_c] (already in [0, D))
+    int32_t mat;          // U: offset (complex elements) of the D x D matrix
+    int32_t real;         // U: all imaginary parts are zero
+    int32_t slot;         // adjoint: M slot of this U inside the stage, -1 = none
+    int32_t npairs;       // PHASE: number of two-qudit diagonal factors
+    FastDiv pa[kMaxPairs], pb[kMaxPairs];  // PHASE: global strides of the two qudits
+    int32_t ptab[kMaxPairs];               // PHASE: offset of each D x D table (complex)
+    // register-round form (forward stages)
+    int32_t gpos;         // U, SHIFT: group position of the target
+    int32_t ctrl_gpos;    // SHIFT: group position of the control, -1 = not in the group
+    int32_t agpos[kMaxPairs], bgpos[kMaxPairs];  // PHASE: group positions, -1 = not in the group
+    int32_t wtab;         // PHASE: offset of the D-entry table w^e (e = sum of x_a x_b mod D)
+};
+
+qf_status launch_stage(const StateView& s, const StageGeom& g, const StageOp* dops, int nops, const void* dmats,
+                       hipStream_t st);
+// Register-round form with groups of M qudits (1 <= M <= max_group_size(D)).
+int max_group_size(uint32_t D);
+qf_status launch_stage_rounds(const StateView& s, int M, const StageGeom& g, const RoundDesc* drounds, int nrounds,
+                              const StageOp* dops, const void* dmats, hipStream_t st);
+// Reverse stage: applies the (already inverted) ops to psi and lam; before each
+// U with slot >= 0 it accumulates M = sum_f psi_f lam_f^dagger over the tile
+// into partial[(slot * nblocks + block) * D*D] (complex FP64).
+qf_status launch_stage_adj(const StateView& s, void* lam, const StageGeom& g, const StageOp* dops, int nops,
+                           const void* dmats, double* partial, hipStream_t st);
+// mout[(b * nslots_total + slot0 + j) * E] = sum over the tiles of register b of
+// partial[j], for j < nslots (fixed order).
+qf_status launch_stage_mreduce(const double* partial, uint32_t nslots, uint32_t ntiles, uint32_t batch, uint32_t E,
+                               double* mout, uint32_t nslots_total, uint32_t slot0, hipStream_t st);
+size_t stage_lds_bytes(const StageGeom& g, int dtype, bool adjoint);
+
+}  // namespace qf

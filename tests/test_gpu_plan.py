@@ -40,12 +40,44 @@ CIRCUITS = [
 
 
 @pytest.mark.parametrize("name,make,dt", CIRCUITS, ids=[c[0] for c in CIRCUITS])
-@pytest.mark.parametrize("fuse", [0, 1])
-def test_plan_forward_matches_oracle(qf, name, make, dt, fuse):
+@pytest.mark.parametrize("fuse,kernel", [(0, 0), (0, 1), (1, 0), (2, 0)])
+def test_plan_forward_matches_oracle(qf, name, make, dt, fuse, kernel):
     c = make()
-    _, t = run_gpu(qf, c, dt, fuse=fuse)
+    _, t = run_gpu(qf, c, dt, fuse=fuse, stage_kernel=kernel)
     want = sim.run(c)
     assert maxabs(to_np(t), want) <= TOL[dt], name
+
+
+TILES = [(3, 1), (3, 2), (4, 2), (5, 3), (2, 1)]
+
+
+@pytest.mark.parametrize("tile,low", TILES)
+@pytest.mark.parametrize("kernel,group", [(0, 0), (0, 1), (0, 9), (1, 0)])
+def test_stage_tiles_small(qf, tile, low, kernel, group):
+    """Small tiles force many passes, controls outside the tile and deferred gates;
+    kernel 0 = register rounds (group 9 = the largest group compiled for D),
+    1 = one LDS sweep per op."""
+    for c, dt in ((qi.config2(n=7, layers=3), "c64"), (qi.random_circuit(3, 6, 150, 21), "c128"),
+                  (qi.config3(n=5, layers=2), "c64"), (qi.random_circuit(4, 5, 150, 22), "c64"),
+                  (qi.random_circuit(2, 9, 200, 23), "c64"), (qi.random_circuit(7, 4, 100, 24), "c64")):
+        gmax = {2: 5, 3: 3, 4: 2, 5: 2}.get(c.dim, 1)
+        p, t = run_gpu(qf, c, dt, tile_digits=min(tile, c.n), low_digits=low, stage_kernel=kernel,
+                       group_digits=min(group, gmax))
+        assert p.num_stages >= 1
+        assert maxabs(to_np(t), sim.run(c)) <= TOL[dt], (c.name, tile, low)
+
+
+def test_stage_batch_and_reuse(qf):
+    """One plan applied to a batch of registers, twice with different angles."""
+    c = qi.config2(n=6, layers=2)
+    p = qf.plan_for(c, "c64")
+    psi = qi.random_state(3, 6, 5, batch=3)
+    for theta in (c.theta, -0.5 * c.theta):
+        t = to_dev(psi.reshape(-1), "c64")
+        p.forward(t, theta)
+        got = to_np(t).reshape(3, -1)
+        for b in range(3):
+            assert maxabs(got[b], sim.run(c, psi[b], theta=theta)) <= 2e-5
 
 
 def test_config1_outputs(qf):
@@ -88,14 +120,41 @@ def _grad_close(g, ref, rel, dtype="c64"):
 
 
 @pytest.mark.parametrize("name,make,dt,rel", ADJ, ids=[a[0] for a in ADJ])
-def test_adjoint_matches_oracle_adjoint(qf, name, make, dt, rel):
+@pytest.mark.parametrize("fuse", [0, 2])
+def test_adjoint_matches_oracle_adjoint(qf, name, make, dt, rel, fuse):
     c = make()
     terms = qi.zsum_terms(c.n)
-    p, t = run_gpu(qf, c, dt)
+    p, t = run_gpu(qf, c, dt, fuse=fuse)
     lam = qf.new_state(c.n, c.dim, dt)
     g = p.adjoint_grad(t, lam, c.theta, terms)
     ref = grad.adjoint(c, terms)
     assert _grad_close(g, ref, rel, dt), (np.abs(g - ref).max(), np.abs(ref).max())
+
+
+@pytest.mark.parametrize("tile,ckpt", [(3, 0), (4, 40), (0, 100), (3, 37)])
+def test_adjoint_stage_tiles_and_checkpoints(qf, tile, ckpt):
+    c = qi.config2(n=6, layers=3)
+    terms = qi.zsum_terms(c.n)
+    p, t = run_gpu(qf, c, "c64", adj_tile_digits=tile, ckpt_every=ckpt)
+    lam = qf.new_state(c.n, c.dim, "c64")
+    g = p.adjoint_grad(t, lam, c.theta, terms)
+    ref = grad.adjoint(c, terms)
+    assert _grad_close(g, ref, 1e-4, "c64"), (np.abs(g - ref).max(), np.abs(ref).max())
+
+
+def test_adjoint_batch(qf):
+    c = qi.config3(n=4, layers=2)
+    terms = qi.zsum_terms(c.n)
+    psi = qi.random_state(5, 4, 3, batch=2)
+    p = qf.plan_for(c, "c128")
+    t = to_dev(psi.reshape(-1), "c128")
+    p.forward(t, c.theta)
+    lam = qf.new_state(c.n, c.dim, "c128", batch=2)
+    g = p.adjoint_grad(t, lam, c.theta, terms)
+    for b in range(2):
+        psi_f = sim.run(c, psi[b])
+        ref = grad.adjoint(c, terms, psi_final=psi_f)
+        assert _grad_close(g[b], ref, 1e-9, "c128")
 
 
 def test_adjoint_vs_finite_differences(qf):
