@@ -161,7 +161,10 @@ typedef struct qf_plan qf_plan;
 /* Plan options.  Zero-initialised options select the defaults. */
 typedef struct qf_plan_opts {
     int32_t fuse;         /* 0 = fused LDS stages (default); 1 = one kernel per gate; */
-                          /* 2 = one kernel per run of one-qudit gates on a qudit     */
+                          /* 2 = one kernel per run of one-qudit gates on a qudit;    */
+                          /* 3 = stages, with the one-qudit runs of qudit pairs       */
+                          /* (2i, 2i+1) applied as dense D^2 x D^2 blocks (matrix    */
+                          /* cores for complex64 when D^2 >= 32)                      */
     int32_t tile_digits;  /* qudits per LDS tile of the forward stages; 0 = chosen    */
                           /* from D and the LDS budget                                */
     int32_t low_digits;   /* least significant qudits always in the tile (contiguous */
@@ -224,6 +227,17 @@ qf_status qf_adjoint_grad(qf_plan* plan, const qf_state* psi, const qf_state* la
                           const double* theta, int32_t nterms,
                           const int32_t* term_qudit, const double* term_diag,
                           double* grad, void* stream);
+
+/* Autotuner: times candidate schedules of this plan's circuit on the caller's
+ * state s (stage tiles of the default size +-1 qudit with every register group
+ * size, the one-sweep-per-op stage kernel, two-qudit dense blocks, per-qudit
+ * runs), each as two forward passes timed with HIP events on `stream`, then
+ * rebuilds the plan with the fastest options (written to *chosen if not NULL).
+ * The winner is cached per (D, n, dtype, batch, gate structure) for the life of
+ * the process.  s is overwritten (it holds the result of a forward pass).
+ * Synchronises `stream`. */
+qf_status qf_plan_autotune(qf_plan* plan, const qf_state* s, const double* theta,
+                           qf_plan_opts* chosen, void* stream);
 
 void qf_plan_destroy(qf_plan* plan);
 

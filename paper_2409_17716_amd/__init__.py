@@ -70,6 +70,7 @@ _SIGS = {
     "qf_plan_forward": [_P, _PS, _PD, _P],
     "qf_adjoint_grad": [_P, _PS, _PS, _PD, _I32, _PI32, _PD, _PD, _P],
     "qf_plan_set_profiling": [_P, _I32],
+    "qf_plan_autotune": [_P, _PS, _PD, ctypes.POINTER(qf_plan_opts), _P],
     "qf_plan_read_profile": [_P, ctypes.POINTER(qf_kernel_stat), _I32, _PI32],
 }
 
@@ -80,7 +81,7 @@ def _load() -> ctypes.CDLL:
     # libqf.so first would put a second HIP runtime in the process.
     import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2409_17716_amd.build` "
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2409_17716_amd/build.py` "
                           "(there is no CPU fallback)")
     lib = ctypes.CDLL(LIB_PATH)
     for name, args in _SIGS.items():
@@ -294,6 +295,15 @@ class Plan:
     @property
     def num_adjoint_stages(self) -> int:
         return lib.qf_plan_num_adjoint_stages(self._h)
+
+    def autotune(self, t, theta, stream=None) -> dict:
+        """qf_plan_autotune on state t (overwritten); returns the chosen options."""
+        s = state_of(t, self.n, self.dim)
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+        o = qf_plan_opts()
+        _check(lib.qf_plan_autotune(self._h, ctypes.byref(s), th.ctypes.data_as(_PD), ctypes.byref(o),
+                                    _stream(stream)))
+        return {f: getattr(o, f) for f, _ in qf_plan_opts._fields_ if f != "reserved"}
 
     def set_profiling(self, enable: bool) -> None:
         _check(lib.qf_plan_set_profiling(self._h, 1 if enable else 0))

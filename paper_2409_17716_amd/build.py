@@ -1,6 +1,6 @@
 """Build libqf.so (HIP kernels for gfx950 + the C ABI) in-tree with hipcc.
 
-    python -m paper_2409_17716_amd.build [--jobs N] [--verbose]
+    python paper_2409_17716_amd/build.py [--jobs N] [--verbose]
 
 Every HIP source is compiled for gfx950 only, with packed-FP32 instruction
 selection disabled.  Kernels that use scratch (register spills) are reported.

@@ -88,9 +88,190 @@ __global__ __launch_bounds__(kBlock) void k_fused_valu(cplx<T>* __restrict__ psi
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP32 matrix-core path (complex64, K >= 32).  Y = B X with
+//   Y_re = B_re X_re - B_im X_im,  Y_im = B_re X_im + B_im X_re
+// on v_mfma_f32_16x16x4f32 (A: 16 x 4, B: 4 x 16, C: 16 x 16).  Lane l of a
+// wavefront supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
+// C[4 (l / 16) + r][l % 16] in accumulator register r.
+//
+// A workgroup owns NTM = 64 fibres.  X is staged in LDS as separate real and
+// imaginary planes of Kp = ceil16(K) rows (rows >= K are zero), each row padded
+// to 68 floats so that the four rows a wavefront reads per step fall in
+// different banks.  B fragments are read from global memory (the K x K block
+// stays in L2).  Wave w computes row blocks w, w + 4, ... against all four
+// 16-fibre column blocks.  A real B (every imaginary part zero) skips the two
+// products with B_im.
+// ---------------------------------------------------------------------------
+
+constexpr int NTM = 64;
+constexpr int RS = NTM + 4;  // LDS row stride (floats)
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(kBlock) void k_fused_mfma(cplx<float>* __restrict__ psi,
+                                                       const cplx<float>* __restrict__ B, FusedGeom g,
+                                                       uint32_t Kp, int real) {
+    extern __shared__ unsigned char smem[];
+    float* xr = reinterpret_cast<float*>(smem);
+    float* xi = xr + size_t(Kp) * RS;
+    const uint32_t f0 = blockIdx.x * NTM;
+    const uint32_t nt = min(uint32_t(NTM), g.nfib - f0);
+    // stage X (zero rows >= K and columns >= nt)
+    for (uint32_t e = threadIdx.x; e < Kp * NTM; e += kBlock) {
+        const uint32_t b = e / NTM;
+        const uint32_t i = e - b * NTM;
+        cplx<float> v = cmake<float>(0.f, 0.f);
+        if (b < g.K && i < nt) v = psi[fibre_base(g, f0 + i) + b * g.L];
+        xr[b * RS + i] = v.re;
+        xi[b * RS + i] = v.im;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int lr = lane & 15;  // A row / B column / C column inside a block
+    const int lk = lane >> 4;  // A column / B row inside a k step; C row group
+    const uint32_t nrb = Kp / 16;
+    for (uint32_t rb = wave; rb < nrb; rb += kBlock / 64) {
+        f32x4 cr[4], ci[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            cr[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+            ci[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+        const uint32_t arow = rb * 16 + lr;
+        for (uint32_t k0 = 0; k0 < Kp; k0 += 4) {
+            const uint32_t acol = k0 + lk;
+            cplx<float> a = cmake<float>(0.f, 0.f);
+            if (arow < g.K && acol < g.K) a = B[arow * g.K + acol];
+            const float* xrr = xr + (k0 + lk) * RS + lr;
+            const float* xir = xi + (k0 + lk) * RS + lr;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float br = xrr[j * 16];
+                const float bi = xir[j * 16];
+                cr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.re, br, cr[j], 0, 0, 0);
+                ci[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.re, bi, ci[j], 0, 0, 0);
+                if (!real) {
+                    cr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.im, bi, cr[j], 0, 0, 0);
+                    ci[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.im, br, ci[j], 0, 0, 0);
+                }
+            }
+        }
+        // write back rows rb*16 + 4*lk + r of the four column blocks
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t col = uint32_t(j * 16 + lr);
+            if (col >= nt) continue;
+            const uint32_t base = fibre_base(g, f0 + col);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint32_t row = rb * 16 + uint32_t(4 * lk + r);
+                if (row < g.K) psi[base + row * g.L] = cmake<float>(cr[j][r], ci[j][r]);
+            }
+        }
+    }
+}
+
+// Persistent variant for Kp = 16 * NRB <= 128: wave w owns row blocks w and
+// w + 4 and keeps their B fragments for every k step in registers, then loops
+// over fibre tiles (grid-stride), so B is read once per workgroup.
+template <int NRB>
+__global__ __launch_bounds__(kBlock) void k_fused_mfma_regs(cplx<float>* __restrict__ psi,
+                                                            const cplx<float>* __restrict__ B, FusedGeom g,
+                                                            int real) {
+    constexpr int Kp = 16 * NRB;
+    constexpr int KS = Kp / 4;
+    constexpr int RPW = (NRB + 3) / 4;  // row blocks per wave
+    extern __shared__ unsigned char smem[];
+    float* xr = reinterpret_cast<float*>(smem);
+    float* xi = xr + size_t(Kp) * RS;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int lr = lane & 15;
+    const int lk = lane >> 4;
+    float are[RPW][KS], aim[RPW][KS];
+#pragma unroll
+    for (int q = 0; q < RPW; ++q) {
+        const uint32_t arow = uint32_t((wave + 4 * q) * 16 + lr);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const uint32_t acol = uint32_t(ks * 4 + lk);
+            cplx<float> a = cmake<float>(0.f, 0.f);
+            if (wave + 4 * q < NRB && arow < g.K && acol < g.K) a = B[arow * g.K + acol];
+            are[q][ks] = a.re;
+            aim[q][ks] = a.im;
+        }
+    }
+    const uint32_t ntiles = (g.nfib + NTM - 1) / NTM;
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t f0 = tile * NTM;
+        const uint32_t nt = min(uint32_t(NTM), g.nfib - f0);
+        __syncthreads();
+        for (uint32_t e = threadIdx.x; e < uint32_t(Kp * NTM); e += kBlock) {
+            const uint32_t b = e / NTM;
+            const uint32_t i = e - b * NTM;
+            cplx<float> v = cmake<float>(0.f, 0.f);
+            if (b < g.K && i < nt) v = psi[fibre_base(g, f0 + i) + b * g.L];
+            xr[b * RS + i] = v.re;
+            xi[b * RS + i] = v.im;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) {
+            const int rb = wave + 4 * q;
+            if (rb >= NRB) continue;
+            f32x4 cr[4], ci[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                cr[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+                ci[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const float* xrr = xr + (ks * 4 + lk) * RS + lr;
+                const float* xir = xi + (ks * 4 + lk) * RS + lr;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float br = xrr[j * 16];
+                    const float bi = xir[j * 16];
+                    cr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(are[q][ks], br, cr[j], 0, 0, 0);
+                    ci[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(are[q][ks], bi, ci[j], 0, 0, 0);
+                    if (!real) {
+                        cr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(-aim[q][ks], bi, cr[j], 0, 0, 0);
+                        ci[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(aim[q][ks], br, ci[j], 0, 0, 0);
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t col = uint32_t(j * 16 + lr);
+                if (col >= nt) continue;
+                const uint32_t base = fibre_base(g, f0 + col);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const uint32_t row = uint32_t(rb * 16 + 4 * lk + r);
+                    if (row < g.K) psi[base + row * g.L] = cmake<float>(cr[j][r], ci[j][r]);
+                }
+            }
+        }
+    }
+}
+
+template <int NRB>
+qf_status launch_mfma_regs(const StateView& s, const FusedGeom& g, const void* B, bool real, hipStream_t st) {
+    const size_t lds = size_t(2) * (16 * NRB) * RS * sizeof(float);
+    const uint32_t ntiles = (g.nfib + NTM - 1) / NTM;
+    const uint32_t grid = ntiles < 2048 ? ntiles : 2048;
+    hipLaunchKernelGGL(k_fused_mfma_regs<NRB>, dim3(grid), dim3(kBlock), lds, st,
+                       reinterpret_cast<cplx<float>*>(s.amps), reinterpret_cast<const cplx<float>*>(B), g,
+                       real ? 1 : 0);
+    return check_launch("qf_apply_fused (matrix cores, persistent)");
+}
+
 }  // namespace
 
-qf_status launch_fused(const StateView& s, int k, int q0, const void* B, hipStream_t st) {
+qf_status launch_fused(const StateView& s, int k, int q0, const void* B, hipStream_t st, bool real) {
     const uint32_t K = ipow(s.D, k);
     FusedGeom g{};
     g.K = K;
@@ -103,6 +284,25 @@ qf_status launch_fused(const StateView& s, int k, int q0, const void* B, hipStre
     g.divL.init(g.L);
     g.divK.init(K);
     g.divNT.init(nt);
+    if (s.dtype == QF_C64 && K >= 32 && K <= 128) {
+        switch ((K + 15) / 16) {
+            case 2: return launch_mfma_regs<2>(s, g, B, real, st);
+            case 3: return launch_mfma_regs<3>(s, g, B, real, st);
+            case 4: return launch_mfma_regs<4>(s, g, B, real, st);
+            case 5: return launch_mfma_regs<5>(s, g, B, real, st);
+            case 6: return launch_mfma_regs<6>(s, g, B, real, st);
+            case 7: return launch_mfma_regs<7>(s, g, B, real, st);
+            case 8: return launch_mfma_regs<8>(s, g, B, real, st);
+        }
+    }
+    if (s.dtype == QF_C64 && K >= 32 && K <= 256) {
+        const uint32_t Kp = (K + 15) / 16 * 16;
+        const size_t lds = size_t(2) * Kp * RS * sizeof(float);
+        const uint32_t grid = (g.nfib + NTM - 1) / NTM;
+        hipLaunchKernelGGL(k_fused_mfma, dim3(grid), dim3(kBlock), lds, st, reinterpret_cast<cplx<float>*>(s.amps),
+                           reinterpret_cast<const cplx<float>*>(B), g, Kp, real ? 1 : 0);
+        return check_launch("qf_apply_fused (matrix cores)");
+    }
     const uint32_t grid = (g.nfib + nt - 1) / nt;
     const size_t lds = size_t(K) * nt * esz;
     if (s.dtype == QF_C64) {

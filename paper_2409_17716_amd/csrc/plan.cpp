@@ -61,6 +61,15 @@ struct Gate {
     Mat mat;           // QF_OP_U: D^k x D^k
     void* dmat = nullptr;
     void* dmat_adj = nullptr;
+    bool real = false; // QF_OP_U: every imaginary part is zero
+};
+
+// A two-qudit dense block made of the one-qudit runs of qudits q0 and q0 + 1
+// (pair mode, forward only): U_run0 (x) U_run1, rebuilt from theta per call.
+struct Synth {
+    qf_op op;                 // kind QF_OP_U on q0, q0 + 1
+    std::vector<int> run0, run1;
+    bool real = false;
 };
 
 static bool is_1q(int kind) {
@@ -223,6 +232,7 @@ struct qf_plan {
     int group = 1;                    // register-round group size
     qf_plan_opts opts{};
     std::vector<qf::Gate> gates;
+    std::vector<qf::Synth> synth;     // fuse = 3
     std::vector<qf::Step> steps;      // fuse = 1, 2
     int nslots = 0;                   // fuse = 1, 2
     qf::PassList fwd, rev;            // fuse = 0
@@ -233,6 +243,31 @@ struct qf_plan {
     std::vector<qf::ProfRec> prof;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
+    qf_plan() = default;
+    qf_plan(const qf_plan&) = delete;
+    qf_plan& operator=(const qf_plan&) = delete;
+    // Exchanges everything, including the ownership of device buffers and events.
+    void swap_with(qf_plan& o) {
+        std::swap(D, o.D);
+        std::swap(n, o.n);
+        std::swap(dtype, o.dtype);
+        std::swap(nparams, o.nparams);
+        std::swap(group, o.group);
+        std::swap(opts, o.opts);
+        gates.swap(o.gates);
+        synth.swap(o.synth);
+        steps.swap(o.steps);
+        std::swap(nslots, o.nslots);
+        std::swap(fwd, o.fwd);
+        std::swap(rev, o.rev);
+        seg_end.swap(o.seg_end);
+        std::swap(ckpt, o.ckpt);
+        std::swap(ckpt_bytes, o.ckpt_bytes);
+        std::swap(profiling, o.profiling);
+        prof.swap(o.prof);
+        ev_pool.swap(o.ev_pool);
+        std::swap(ev_used, o.ev_used);
+    }
     ~qf_plan() {
         for (auto& g : gates) {
             if (g.dmat) (void)hipFree(g.dmat);
@@ -246,6 +281,9 @@ struct qf_plan {
 };
 
 namespace qf {
+
+// fuse 0 (LDS stages) and 3 (stages + two-qudit blocks) use pass lists.
+static bool staged(const qf_plan* p) { return p->opts.fuse == 0 || p->opts.fuse == 3; }
 
 static const char* kFamilies[] = {"stage", "stage_adj", "fused", "axis", "ctrl", "diag", "adj_axis", "checkpoint"};
 enum Family { F_STAGE, F_STAGE_ADJ, F_FUSED, F_AXIS, F_CTRL, F_DIAG, F_ADJ_AXIS, F_CKPT, F_COUNT };
@@ -451,6 +489,56 @@ static void touches(const qf_op& o, std::vector<Touch>& t) {
     }
 }
 
+static const qf_op& op_of(const qf_plan* p, const GRef& r) {
+    const int ng = int(p->gates.size());
+    return r.gi < ng ? p->gates[r.gi].op : p->synth[r.gi - ng].op;
+}
+
+// Pair mode: one-qudit runs of qudits (2i, 2i+1) are collected and emitted as
+// one dense two-qudit block right before the next gate that touches either
+// qudit (the runs commute with every gate in between).  An odd last qudit keeps
+// its one-qudit gates.
+static void pair_fuse(qf_plan* p, int lo, int hi, std::vector<GRef>& seq) {
+    const int n = p->n, ng = int(p->gates.size());
+    std::vector<std::vector<int>> pending(n);
+    auto flush_pair = [&](int pr) {
+        const int a = 2 * pr, b = 2 * pr + 1;
+        if (b >= n) {
+            for (int gi : pending[a]) seq.push_back({gi, false});
+            pending[a].clear();
+            return;
+        }
+        if (pending[a].empty() && pending[b].empty()) return;
+        Synth sy;
+        sy.op = qf_op{};
+        sy.op.kind = QF_OP_U;
+        sy.op.q0 = a;
+        sy.op.q1 = 2;
+        sy.op.param = -1;
+        sy.run0 = pending[a];
+        sy.run1 = pending[b];
+        sy.real = true;
+        for (int gi : sy.run0) sy.real = sy.real && p->gates[gi].op.kind == QF_OP_RY;
+        for (int gi : sy.run1) sy.real = sy.real && p->gates[gi].op.kind == QF_OP_RY;
+        p->synth.push_back(sy);
+        seq.push_back({ng + int(p->synth.size()) - 1, false});
+        pending[a].clear();
+        pending[b].clear();
+    };
+    std::vector<Touch> tv;
+    for (int gi = lo; gi < hi; ++gi) {
+        const qf_op& o = p->gates[gi].op;
+        if (is_1q(o.kind)) {
+            pending[o.q0].push_back(gi);
+            continue;
+        }
+        touches(o, tv);
+        for (const Touch& t : tv) flush_pair(t.q / 2);
+        seq.push_back({gi, false});
+    }
+    for (int pr = 0; 2 * pr < n; ++pr) flush_pair(pr);
+}
+
 // Qudit that must be inside the tile (-1: none; CZ acts on any digits).
 static int local_need(const qf_op& o) {
     if (is_1q(o.kind) || o.kind == QF_OP_X) return o.q0;
@@ -526,7 +614,7 @@ static void plan_passes(const qf_plan* p, const std::vector<GRef>& seq, int k, i
     std::vector<Touch> tv;
     while (remaining > 0) {
         while (done[first]) ++first;
-        const qf_op& o0 = p->gates[seq[first].gi].op;
+        const qf_op& o0 = op_of(p, seq[first]);
         if (o0.kind == QF_OP_U) {
             Pass pf;
             pf.tile = false;
@@ -542,7 +630,7 @@ static void plan_passes(const qf_plan* p, const std::vector<GRef>& seq, int k, i
         for (int q = n - r; q < n; ++q) inT[q] = 1, ++cnt;
         for (int i = first; i < m && cnt < k; ++i) {
             if (done[i]) continue;
-            const int q = local_need(p->gates[seq[i].gi].op);
+            const int q = local_need(op_of(p, seq[i]));
             if (q >= 0 && !inT[q]) inT[q] = 1, ++cnt;
         }
         for (int q = n - r - 1; q >= 0 && cnt < k; --q)
@@ -565,7 +653,7 @@ static void plan_passes(const qf_plan* p, const std::vector<GRef>& seq, int k, i
         };
         for (int i = first; i < m; ++i) {
             if (done[i]) continue;
-            const qf_op& o = p->gates[seq[i].gi].op;
+            const qf_op& o = op_of(p, seq[i]);
             touches(o, tv);
             bool conflict = false;
             for (const Touch& t : tv) conflict = conflict || bFull[t.q] || (!t.diag && bDiag[t.q]);
@@ -680,8 +768,16 @@ static void finalize_passes(const qf_plan* p, PassList& L, bool adjoint) {
     L.hrounds.clear();
     L.nmats = 0;
     L.nslots = 0;
+    const int ng = int(p->gates.size());
     for (Pass& ps : L.passes) {
-        if (!ps.tile) continue;
+        if (!ps.tile) {
+            if (ps.fused.gi >= ng) {  // synthetic pair block: its D^2 x D^2 matrix lives in the pass mats
+                ps.mat_off = L.nmats;
+                ps.nmat = size_t(D) * D * D * D;
+                L.nmats += ps.nmat;
+            }
+            continue;
+        }
         ps.op_off = int(L.hops.size());
         ps.mat_off = L.nmats;
         ps.nslots = 0;
@@ -773,8 +869,28 @@ static qf_status upload_mats(const qf_plan* p, PassList& L, const double* theta,
     if (L.dmats == nullptr) QF_CHECK(upload_ops(p, L));
     if (L.copied_valid) QF_HIP_CHECK(hipEventSynchronize(L.copied));
     const int D = p->D;
+    const int ng = int(p->gates.size());
     for (const Pass& ps : L.passes) {
-        if (!ps.tile) continue;
+        if (!ps.tile) {
+            if (ps.fused.gi >= ng) {
+                const Synth& sy = p->synth[ps.fused.gi - ng];
+                Mat A = identity(D), B = identity(D);
+                for (int gi : sy.run0) A = matmul(gate_matrix(p->gates[gi].op, D, theta), A, D);
+                for (int gi : sy.run1) B = matmul(gate_matrix(p->gates[gi].op, D, theta), B, D);
+                const int K = D * D;
+                Mat Kr(size_t(K) * K);
+                for (int a0 = 0; a0 < D; ++a0)
+                    for (int b0 = 0; b0 < D; ++b0)
+                        for (int a1 = 0; a1 < D; ++a1)
+                            for (int b1 = 0; b1 < D; ++b1)
+                                Kr[size_t(a0 * D + b0) * K + (a1 * D + b1)] = A[a0 * D + a1] * B[b0 * D + b1];
+                if (p->dtype == QF_C64)
+                    put_mat<float>(L.hmats, ps.mat_off, Kr);
+                else
+                    put_mat<double>(L.hmats, ps.mat_off, Kr);
+            }
+            continue;
+        }
         for (size_t i = 0; i < ps.ops.size(); ++i) {
             const HOp& h = ps.ops[i];
             const StageOp& so = L.hops[ps.op_off + i];
@@ -880,11 +996,19 @@ static qf_status run_tile_pass(qf_plan* p, const PassList& L, const Pass& ps, co
     return QF_OK;
 }
 
-static qf_status run_fused_pass(qf_plan* p, const Pass& ps, const StateView& v, hipStream_t st) {
-    const Gate& g = p->gates[ps.fused.gi];
+static qf_status run_fused_pass(qf_plan* p, const PassList& L, const Pass& ps, const StateView& v, hipStream_t st) {
+    const int ng = int(p->gates.size());
     hipEvent_t a;
     QF_CHECK(prof_begin(p, st, &a));
-    QF_CHECK(launch_fused(v, g.op.q1, g.op.q0, ps.fused.inv ? g.dmat_adj : g.dmat, st));
+    if (ps.fused.gi >= ng) {
+        const Synth& sy = p->synth[ps.fused.gi - ng];
+        const size_t esz = p->dtype == QF_C64 ? 8 : 16;
+        const void* m = reinterpret_cast<const unsigned char*>(L.dmats) + ps.mat_off * esz;
+        QF_CHECK(launch_fused(v, 2, sy.op.q0, m, st, sy.real));
+    } else {
+        const Gate& g = p->gates[ps.fused.gi];
+        QF_CHECK(launch_fused(v, g.op.q1, g.op.q0, ps.fused.inv ? g.dmat_adj : g.dmat, st, g.real));
+    }
     return prof_end(p, st, a, F_FUSED, 2.0 * state_bytes(v));
 }
 
@@ -951,7 +1075,7 @@ qf_status qf_plan_create(int32_t dim, int32_t n, int32_t dtype, const qf_op* ops
     p->dtype = dtype;
     p->nparams = nparams;
     if (opts) p->opts = *opts;
-    QF_RETURN_IF(p->opts.fuse < 0 || p->opts.fuse > 2, QF_EINVAL, "fuse = %d outside 0..2", p->opts.fuse);
+    QF_RETURN_IF(p->opts.fuse < 0 || p->opts.fuse > 3, QF_EINVAL, "fuse = %d outside 0..3", p->opts.fuse);
     QF_RETURN_IF(p->opts.group_digits < 0 || p->opts.group_digits > max_group_size(uint32_t(dim)), QF_EINVAL,
                  "group_digits = %d outside 0..%d for dim %d", p->opts.group_digits, max_group_size(uint32_t(dim)),
                  dim);
@@ -968,7 +1092,11 @@ qf_status qf_plan_create(int32_t dim, int32_t n, int32_t dtype, const qf_op* ops
         if (ops[i].kind == QF_OP_U) {
             const size_t K = ipow(dim, ops[i].q1);
             g.mat.resize(K * K);
-            for (size_t e = 0; e < K * K; ++e) g.mat[e] = cd(ops[i].mat[2 * e], ops[i].mat[2 * e + 1]);
+            g.real = true;
+            for (size_t e = 0; e < K * K; ++e) {
+                g.mat[e] = cd(ops[i].mat[2 * e], ops[i].mat[2 * e + 1]);
+                g.real = g.real && ops[i].mat[2 * e + 1] == 0.0;
+            }
             const size_t esz = dtype == QF_C64 ? 8 : 16;
             std::vector<unsigned char> a(K * K * esz), b(K * K * esz);
             for (size_t r = 0; r < K; ++r)
@@ -1001,7 +1129,7 @@ qf_status qf_plan_create(int32_t dim, int32_t n, int32_t dtype, const qf_op* ops
     const int every = p->opts.ckpt_every;
     for (int e = every; every > 0 && e < nops; e += every) p->seg_end.push_back(e);
     p->seg_end.push_back(nops);
-    if (p->opts.fuse != 0) {
+    if (!staged(p.get())) {
         build_steps(p.get());
     } else if (nops > 0) {
         int k, r, ka, ra;
@@ -1015,7 +1143,10 @@ qf_status qf_plan_create(int32_t dim, int32_t n, int32_t dtype, const qf_op* ops
         int start = 0;
         for (size_t sgi = 0; sgi < p->seg_end.size(); ++sgi) {
             std::vector<GRef> seq;
-            for (int i = start; i < p->seg_end[sgi]; ++i) seq.push_back({i, false});
+            if (p->opts.fuse == 3)
+                pair_fuse(p.get(), start, p->seg_end[sgi], seq);
+            else
+                for (int i = start; i < p->seg_end[sgi]; ++i) seq.push_back({i, false});
             plan_passes(p.get(), seq, k, r, int(sgi), p->fwd);
             start = p->seg_end[sgi];
         }
@@ -1034,12 +1165,12 @@ qf_status qf_plan_create(int32_t dim, int32_t n, int32_t dtype, const qf_op* ops
 
 int32_t qf_plan_num_stages(const qf_plan* plan) {
     if (!plan) return -1;
-    return plan->opts.fuse != 0 ? int32_t(plan->steps.size()) : int32_t(plan->fwd.passes.size());
+    return !staged(plan) ? int32_t(plan->steps.size()) : int32_t(plan->fwd.passes.size());
 }
 
 int32_t qf_plan_num_adjoint_stages(const qf_plan* plan) {
     if (!plan) return -1;
-    return plan->opts.fuse != 0 ? int32_t(plan->steps.size()) : int32_t(plan->rev.passes.size());
+    return !staged(plan) ? int32_t(plan->steps.size()) : int32_t(plan->rev.passes.size());
 }
 
 qf_status qf_plan_forward(qf_plan* plan, const qf_state* s, const double* theta, void* stream) {
@@ -1048,7 +1179,7 @@ qf_status qf_plan_forward(qf_plan* plan, const qf_state* s, const double* theta,
     QF_RETURN_IF(plan->nparams > 0 && theta == nullptr, QF_EINVAL, "theta is NULL");
     QF_CHECK(check_finite_theta(theta, plan->nparams));
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    if (plan->opts.fuse != 0) {
+    if (!staged(plan)) {
         for (const Step& step : plan->steps) {
             hipEvent_t a;
             QF_CHECK(prof_begin(plan, st, &a));
@@ -1071,7 +1202,7 @@ qf_status qf_plan_forward(qf_plan* plan, const qf_state* s, const double* theta,
         if (ps.tile)
             QF_CHECK(run_tile_pass(plan, plan->fwd, ps, v, nullptr, nullptr, st));
         else
-            QF_CHECK(run_fused_pass(plan, ps, v, st));
+            QF_CHECK(run_fused_pass(plan, plan->fwd, ps, v, st));
         const bool seg_end = i + 1 == plan->fwd.passes.size() || plan->fwd.passes[i + 1].seg != ps.seg;
         if (save && seg_end && size_t(ps.seg) + 1 < plan->seg_end.size()) {
             hipEvent_t a;
@@ -1105,16 +1236,16 @@ qf_status qf_adjoint_grad(qf_plan* plan, const qf_state* psi, const qf_state* la
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const int D = plan->D;
     const size_t E = size_t(D) * D;
-    const bool staged = plan->opts.fuse == 0;
-    const int nslots = staged ? plan->rev.nslots : plan->nslots;
-    QF_RETURN_IF(staged && plan->seg_end.size() > 1 && (plan->ckpt == nullptr || !plan->fwd.done_valid), QF_EINVAL,
+    const bool stg = staged(plan);
+    const int nslots = stg ? plan->rev.nslots : plan->nslots;
+    QF_RETURN_IF(stg && plan->seg_end.size() > 1 && (plan->ckpt == nullptr || !plan->fwd.done_valid), QF_EINVAL,
                  "checkpointed plan: run qf_plan_forward on this state first");
 
     // lam = H_O psi with H_O the Hermitian part of O
     QF_CHECK(launch_diag_observable(v, lam->amps, active, table_re, st));
 
     size_t pdoubles = 1;
-    if (staged) {
+    if (stg) {
         for (const Pass& ps : plan->rev.passes)
             if (ps.tile) pdoubles = std::max(pdoubles, size_t(ps.nslots) * ps.geom.ntiles * v.batch * E * 2);
     } else {
@@ -1126,7 +1257,7 @@ qf_status qf_adjoint_grad(qf_plan* plan, const qf_state* psi, const qf_state* la
     QF_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&partial), pdoubles * sizeof(double), st));
     QF_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&mdev), mcount * sizeof(double), st));
     qf_status rs = QF_OK;
-    if (staged) {
+    if (stg) {
         rs = upload_mats(plan, plan->rev, theta, st);
         const size_t sb = state_bytes(v);
         for (size_t i = 0; i < plan->rev.passes.size() && rs == QF_OK; ++i) {
@@ -1145,8 +1276,8 @@ qf_status qf_adjoint_grad(qf_plan* plan, const qf_state* psi, const qf_state* la
                     rs = launch_stage_mreduce(partial, ps.nslots, ps.geom.ntiles, v.batch, uint32_t(E), mdev,
                                               uint32_t(plan->rev.nslots), uint32_t(ps.slot0), st);
             } else {
-                rs = run_fused_pass(plan, ps, v, st);
-                if (rs == QF_OK) rs = run_fused_pass(plan, ps, vl, st);
+                rs = run_fused_pass(plan, plan->rev, ps, v, st);
+                if (rs == QF_OK) rs = run_fused_pass(plan, plan->rev, ps, vl, st);
             }
         }
         if (rs == QF_OK) {
@@ -1185,7 +1316,7 @@ qf_status qf_adjoint_grad(qf_plan* plan, const qf_state* psi, const qf_state* la
     std::memset(grad, 0, sizeof(double) * size_t(v.batch) * plan->nparams);
     for (uint32_t b = 0; b < v.batch; ++b) {
         double* gb = grad + size_t(b) * plan->nparams;
-        if (staged) {
+        if (stg) {
             for (const Pass& ps : plan->rev.passes)
                 for (const HOp& h : ps.ops) {
                     if (h.gslot < 0) continue;
@@ -1242,5 +1373,142 @@ qf_status qf_plan_read_profile(qf_plan* plan, qf_kernel_stat* out, int32_t cap, 
 }
 
 void qf_plan_destroy(qf_plan* plan) { delete plan; }
+
+}  // extern "C"
+
+namespace qf {
+
+// Reconstructs the op list a plan was created from (matrices of custom gates
+// as interleaved FP64).
+static void plan_ops(const qf_plan* p, std::vector<qf_op>& ops, std::vector<std::vector<double>>& mats) {
+    ops.clear();
+    mats.clear();
+    mats.reserve(p->gates.size());
+    for (const Gate& g : p->gates) {
+        qf_op o = g.op;
+        if (o.kind == QF_OP_U) {
+            mats.emplace_back();
+            to_interleaved(g.mat, mats.back());
+            o.mat = mats.back().data();
+        }
+        ops.push_back(o);
+    }
+}
+
+static uint64_t plan_key(const qf_plan* p, uint32_t batch) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) {
+        h ^= v;
+        h *= 1099511628211ull;
+    };
+    mix(uint64_t(p->D));
+    mix(uint64_t(p->n));
+    mix(uint64_t(p->dtype));
+    mix(uint64_t(batch));
+    mix(uint64_t(p->opts.ckpt_every));
+    for (const Gate& g : p->gates) {
+        mix(uint64_t(g.op.kind));
+        mix(uint64_t(uint32_t(g.op.q0)) | (uint64_t(uint32_t(g.op.q1)) << 32));
+        mix(uint64_t(uint32_t(g.op.j)) | (uint64_t(uint32_t(g.op.k)) << 32));
+    }
+    return h;
+}
+
+struct TuneCache {
+    std::vector<std::pair<uint64_t, qf_plan_opts>> entries;
+};
+static TuneCache g_tune;
+
+}  // namespace qf
+
+extern "C" {
+
+qf_status qf_plan_autotune(qf_plan* plan, const qf_state* s, const double* theta, qf_plan_opts* chosen,
+                           void* stream) {
+    StateView v;
+    QF_CHECK(check_plan_state(plan, s, v));
+    QF_RETURN_IF(plan->nparams > 0 && theta == nullptr, QF_EINVAL, "theta is NULL");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const uint64_t key = plan_key(plan, v.batch);
+    std::vector<qf_op> ops;
+    std::vector<std::vector<double>> mats;
+    plan_ops(plan, ops, mats);
+    qf_plan_opts best = plan->opts;
+    bool cached = false;
+    for (const auto& e : g_tune.entries)
+        if (e.first == key) {
+            best = e.second;
+            cached = true;
+        }
+    if (!cached) {
+        // candidates: stage plans over tile sizes and register groups, pair blocks,
+        // and the per-gate-run schedule
+        std::vector<qf_plan_opts> cand;
+        int k0, r0;
+        tile_shape(plan->D, plan->n, plan->dtype, 0, 0, false, k0, r0);
+        const int gmax = max_group_size(uint32_t(plan->D));
+        for (int dk = -1; dk <= 1; ++dk) {
+            const int k = k0 + dk;
+            if (k < 1 || k > plan->n) continue;
+            for (int g = 1; g <= gmax; ++g) {
+                qf_plan_opts o = plan->opts;
+                o.fuse = 0;
+                o.tile_digits = k;
+                o.group_digits = g;
+                o.stage_kernel = 0;
+                cand.push_back(o);
+            }
+            qf_plan_opts o = plan->opts;
+            o.fuse = 0;
+            o.tile_digits = k;
+            o.stage_kernel = 1;
+            cand.push_back(o);
+        }
+        if (plan->D * plan->D >= 16) {
+            qf_plan_opts o = plan->opts;
+            o.fuse = 3;
+            o.tile_digits = 0;
+            o.group_digits = 0;
+            cand.push_back(o);
+        }
+        {
+            qf_plan_opts o = plan->opts;
+            o.fuse = 2;
+            cand.push_back(o);
+        }
+        hipEvent_t e0, e1;
+        QF_HIP_CHECK(hipEventCreate(&e0));
+        QF_HIP_CHECK(hipEventCreate(&e1));
+        float best_ms = 1e30f;
+        for (const qf_plan_opts& o : cand) {
+            qf_plan* tp = nullptr;
+            if (qf_plan_create(plan->D, plan->n, plan->dtype, ops.data(), int32_t(ops.size()), plan->nparams, &o,
+                               &tp) != QF_OK)
+                continue;  // e.g. a tile beyond the LDS size
+            qf_status rs = qf_plan_forward(tp, s, theta, stream);
+            if (rs == QF_OK) rs = hipEventRecord(e0, st) == hipSuccess ? QF_OK : QF_EHIP;
+            for (int rep = 0; rep < 2 && rs == QF_OK; ++rep) rs = qf_plan_forward(tp, s, theta, stream);
+            if (rs == QF_OK) rs = hipEventRecord(e1, st) == hipSuccess ? QF_OK : QF_EHIP;
+            float ms = 0.f;
+            if (rs == QF_OK && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
+                ms < best_ms) {
+                best_ms = ms;
+                best = o;
+            }
+            qf_plan_destroy(tp);
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        QF_RETURN_IF(best_ms >= 1e30f, QF_EHIP, "no autotuning candidate ran");
+        g_tune.entries.push_back({key, best});
+    }
+    // rebuild this plan with the chosen options
+    qf_plan* np = nullptr;
+    QF_CHECK(qf_plan_create(plan->D, plan->n, plan->dtype, ops.data(), int32_t(ops.size()), plan->nparams, &best, &np));
+    plan->swap_with(*np);
+    qf_plan_destroy(np);
+    if (chosen) *chosen = best;
+    return QF_OK;
+}
 
 }  // extern "C"

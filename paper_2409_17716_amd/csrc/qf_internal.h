@@ -46,7 +46,8 @@ qf_status launch_diag_observable(const StateView& psi, void* lam_amps, const std
                                  const std::vector<double>& table_re, hipStream_t st);
 
 // ---- fused dense blocks (k_fused.hip) ----
-qf_status launch_fused(const StateView& s, int k, int q0, const void* B, hipStream_t st);
+// real: every imaginary part of B is zero (halves the matrix-core products).
+qf_status launch_fused(const StateView& s, int k, int q0, const void* B, hipStream_t st, bool real = false);
 
 }  // namespace qf
 

@@ -120,6 +120,25 @@ def test_apply_fused(qf, D, n, k, dt):
         assert maxabs(to_np(t), want) <= tol, (q0,)
 
 
+@pytest.mark.parametrize("D,n,k", [(2, 8, 5), (4, 5, 3), (3, 6, 4), (10, 4, 2), (5, 4, 3), (2, 9, 8), (10, 3, 2)])
+def test_apply_fused_matrix_cores(qf, D, n, k):
+    """complex64 blocks with D^k >= 32 run on the FP32 matrix cores (v_mfma_f32_16x16x4f32,
+    rows padded to a multiple of 16); every admissible position, so both the
+    L = 1 (contiguous fibres) and the strided staging paths are covered."""
+    rng = np.random.default_rng(100 * D + k)
+    psi = qi.random_state(D, n, 17, batch=2).reshape(-1)
+    K = D ** k
+    for q0 in range(n - k + 1):
+        B = qi.random_unitary(K, rng)
+        Bt = to_dev(B.reshape(-1), "c64").reshape(K, K)
+        t = to_dev(psi, "c64")
+        qf.qf_apply_fused(t, n, D, q0, k, Bt)
+        Bq = B.astype(np.complex64).astype(np.complex128)
+        want = np.concatenate([sim.apply_matrix(r, D, n, list(range(q0, q0 + k)), Bq)
+                               for r in rounded(psi, "c64").reshape(2, -1)])
+        assert maxabs(to_np(t), want) <= 2e-5, (q0, maxabs(to_np(t), want))
+
+
 def test_grover_fused_block(qf):
     """One Grover iteration on two qutrits via two custom 9x9 blocks: marked
     amplitude 23/27, the others 5/27."""

@@ -40,7 +40,7 @@ CIRCUITS = [
 
 
 @pytest.mark.parametrize("name,make,dt", CIRCUITS, ids=[c[0] for c in CIRCUITS])
-@pytest.mark.parametrize("fuse,kernel", [(0, 0), (0, 1), (1, 0), (2, 0)])
+@pytest.mark.parametrize("fuse,kernel", [(0, 0), (0, 1), (1, 0), (2, 0), (3, 0)])
 def test_plan_forward_matches_oracle(qf, name, make, dt, fuse, kernel):
     c = make()
     _, t = run_gpu(qf, c, dt, fuse=fuse, stage_kernel=kernel)
@@ -120,7 +120,7 @@ def _grad_close(g, ref, rel, dtype="c64"):
 
 
 @pytest.mark.parametrize("name,make,dt,rel", ADJ, ids=[a[0] for a in ADJ])
-@pytest.mark.parametrize("fuse", [0, 2])
+@pytest.mark.parametrize("fuse", [0, 2, 3])
 def test_adjoint_matches_oracle_adjoint(qf, name, make, dt, rel, fuse):
     c = make()
     terms = qi.zsum_terms(c.n)
@@ -168,3 +168,28 @@ def test_adjoint_vs_finite_differences(qf):
     idx = qi.config3_fd_params(c, 16)
     fd = grad.finite_diff(c, terms, idx, h=1e-6)
     assert _grad_close(g[idx], fd, 1e-4), np.abs(g[idx] - fd).max()
+
+
+def test_pair_blocks_on_matrix_cores(qf):
+    """Pair mode on D=10 (100 x 100 real blocks on the matrix cores) and D=7
+    (49 x 49 complex blocks), against the oracle."""
+    for c in (qi.config5(n=4, layers=3), qi.config5(n=5, layers=2), qi.random_circuit(7, 4, 120, 31)):
+        p, t = run_gpu(qf, c, "c64", fuse=3)
+        assert maxabs(to_np(t), sim.run(c)) <= 2e-5, c.name
+
+
+def test_autotune_keeps_parity(qf):
+    c = qi.config2(n=7, layers=3)
+    p = qf.plan_for(c, "c64")
+    scratch = qf.new_state(c.n, c.dim, "c64")
+    qf.qf_state_init(scratch, c.n, c.dim, None)
+    chosen = p.autotune(scratch, c.theta)
+    assert chosen["fuse"] in (0, 2, 3)
+    t = qf.new_state(c.n, c.dim, "c64")
+    qf.qf_state_init(t, c.n, c.dim, None)
+    p.forward(t, c.theta)
+    assert maxabs(to_np(t), sim.run(c)) <= 2e-5
+    lam = qf.new_state(c.n, c.dim, "c64")
+    g = p.adjoint_grad(t, lam, c.theta, qi.zsum_terms(c.n))
+    ref = grad.adjoint(c, qi.zsum_terms(c.n))
+    assert _grad_close(g, ref, 1e-4, "c64")
