@@ -151,7 +151,8 @@ typedef struct qf_op {
     int32_t q1;          /* target of CSUM/CSHIFT/CZ; k (qudit count) of U           */
     int32_t j, k;        /* levels: RX/RY use j < k; RZ uses j; X and CLOCK use j as */
                          /* the shift / exponent a                                   */
-    int32_t param;       /* rotation angle slot in theta, -1 for fixed gates         */
+    int32_t param;       /* rotation angle slot in theta, -1 for fixed gates; a     */
+                         /* CLOCK with param >= 0 takes its exponent a from theta    */
     int32_t shifts[16];  /* CSHIFT table (first D entries used)                      */
     const double* mat;   /* U: host D^k x D^k complex FP64, copied at plan creation  */
 } qf_op;
@@ -227,6 +228,31 @@ qf_status qf_adjoint_grad(qf_plan* plan, const qf_state* psi, const qf_state* la
                           const double* theta, int32_t nterms,
                           const int32_t* term_qudit, const double* term_diag,
                           double* grad, void* stream);
+
+/* ---- device-parameter (bound) mode: graph-capturable steps ----
+ * qf_plan_bind allocates, once, everything a forward + adjoint step needs for
+ * states of up to `batch` registers: per-register gate matrices, reduction
+ * scratch, gradient work buffers and checkpoints.  Afterwards
+ * qf_plan_forward_dev and qf_adjoint_grad_dev build every matrix on the device
+ * from a DEVICE array of angles and neither allocate, copy from the host nor
+ * synchronise, so a whole training step can be captured in a HIP graph and
+ * replayed with new angles written into the same device array.  Needs a stage
+ * plan (fuse = 0).  Synchronous; re-binding frees the previous workspaces. */
+qf_status qf_plan_bind(qf_plan* plan, int64_t batch);
+
+/* Forward pass with angles theta (DEVICE, FP64): register b uses
+ * theta[b * theta_stride .. + nparams]; theta_stride = 0 shares one set. */
+qf_status qf_plan_forward_dev(qf_plan* plan, const qf_state* s, const double* theta,
+                              int64_t theta_stride, void* stream);
+
+/* Adjoint gradient as qf_adjoint_grad, all on the device: grad (DEVICE,
+ * batch*nparams doubles), and, if loss is not NULL, <O> per register (DEVICE,
+ * batch complex values, 2 doubles each) taken before the reverse walk.
+ * Per-parameter sums run in a fixed order (bitwise reproducible). */
+qf_status qf_adjoint_grad_dev(qf_plan* plan, const qf_state* psi, const qf_state* lam,
+                              const double* theta, int64_t theta_stride, int32_t nterms,
+                              const int32_t* term_qudit, const double* term_diag,
+                              double* grad, double* loss, void* stream);
 
 /* Autotuner: times candidate schedules of this plan's circuit on the caller's
  * state s (stage tiles of the default size +-1 qudit with every register group

@@ -71,6 +71,9 @@ _SIGS = {
     "qf_adjoint_grad": [_P, _PS, _PS, _PD, _I32, _PI32, _PD, _PD, _P],
     "qf_plan_set_profiling": [_P, _I32],
     "qf_plan_autotune": [_P, _PS, _PD, ctypes.POINTER(qf_plan_opts), _P],
+    "qf_plan_bind": [_P, ctypes.c_int64],
+    "qf_plan_forward_dev": [_P, _PS, _P, ctypes.c_int64, _P],
+    "qf_adjoint_grad_dev": [_P, _PS, _PS, _P, ctypes.c_int64, _I32, _PI32, _PD, _P, _P, _P],
     "qf_plan_read_profile": [_P, ctypes.POINTER(qf_kernel_stat), _I32, _PI32],
 }
 
@@ -236,8 +239,8 @@ def qf_expect(t, n: int, dim: int, terms, out=None, stream=None):
 # Plans.
 # ---------------------------------------------------------------------------
 
-_KIND = {"h": QF_OP_H, "x": QF_OP_X, "clock": QF_OP_CLOCK, "rx": QF_OP_RX, "ry": QF_OP_RY, "rz": QF_OP_RZ,
-         "csum": QF_OP_CSUM, "cshift": QF_OP_CSHIFT, "cz": QF_OP_CZ, "u": QF_OP_U}
+_KIND = {"h": QF_OP_H, "x": QF_OP_X, "clock": QF_OP_CLOCK, "clockp": QF_OP_CLOCK, "rx": QF_OP_RX, "ry": QF_OP_RY,
+         "rz": QF_OP_RZ, "csum": QF_OP_CSUM, "cshift": QF_OP_CSHIFT, "cz": QF_OP_CZ, "u": QF_OP_U}
 
 
 def ops_to_c(ops: Sequence[tuple]):
@@ -254,6 +257,8 @@ def ops_to_c(ops: Sequence[tuple]):
             o.q0 = op[1]
         elif kind in ("x", "clock"):
             o.q0, o.j = op[1], int(op[2])
+        elif kind == "clockp":  # clock gate whose exponent is theta[op[2]]
+            o.q0, o.param = op[1], int(op[2])
         elif kind in ("rx", "ry"):
             o.q0, o.j, o.k, o.param = op[1], op[2], op[3], op[4]
         elif kind == "rz":
@@ -304,6 +309,29 @@ class Plan:
         _check(lib.qf_plan_autotune(self._h, ctypes.byref(s), th.ctypes.data_as(_PD), ctypes.byref(o),
                                     _stream(stream)))
         return {f: getattr(o, f) for f, _ in qf_plan_opts._fields_ if f != "reserved"}
+
+    # ---- device-parameter mode (graph-capturable) ----
+    def bind(self, batch: int) -> None:
+        _check(lib.qf_plan_bind(self._h, int(batch)))
+        self.bound = int(batch)
+
+    def forward_dev(self, t, theta_dev, theta_stride: int, stream=None) -> None:
+        s = state_of(t, self.n, self.dim)
+        _check(lib.qf_plan_forward_dev(self._h, ctypes.byref(s), ctypes.c_void_p(theta_dev.data_ptr()),
+                                       int(theta_stride), _stream(stream)))
+
+    def adjoint_grad_dev(self, psi, lam, theta_dev, theta_stride: int, terms, grad_dev, loss_dev=None,
+                         stream=None) -> None:
+        s = state_of(psi, self.n, self.dim)
+        sl = state_of(lam, self.n, self.dim)
+        qs, tab = _terms_arrays(self.dim, terms)
+        self._keep = (_i32(qs), _c128(tab))
+        (qa, qp), (ta, tp) = self._keep
+        _check(lib.qf_adjoint_grad_dev(self._h, ctypes.byref(s), ctypes.byref(sl),
+                                       ctypes.c_void_p(theta_dev.data_ptr()), int(theta_stride), len(qs), qp, tp,
+                                       ctypes.c_void_p(grad_dev.data_ptr()),
+                                       ctypes.c_void_p(loss_dev.data_ptr()) if loss_dev is not None else None,
+                                       _stream(stream)))
 
     def set_profiling(self, enable: bool) -> None:
         _check(lib.qf_plan_set_profiling(self._h, 1 if enable else 0))

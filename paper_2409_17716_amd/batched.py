@@ -1,0 +1,178 @@
+"""Ragged batches of variational circuits on one GPU.
+
+Circuits are grouped by (D, n, gate layout); every group becomes one bound
+stage plan over a batch of registers, with each register's angles (and clock
+exponents) in a device array.  One training step (init, forward, <O> and the
+adjoint gradient of every circuit) is then a fixed sequence of kernel launches
+with no host work, captured once in a HIP graph and replayed per step; new
+angles are written into the device arrays between replays.
+
+``plain_step`` runs the same circuits one at a time through the ordinary
+per-circuit path (host-built matrices, host gradient) for comparison.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Callable, Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import Plan, new_state, qf_state_init
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def default_terms(n: int):
+    """sum_i Z_i (the loss Re<sum_i Z_i>)."""
+    return [(q, "z") for q in range(n)]
+
+
+def _layout(c) -> Tuple:
+    """Gate layout of a circuit with angles and clock exponents abstracted."""
+    key = []
+    for op in c.ops:
+        if op[0] == "clock":
+            key.append(("clock", op[1]))
+        elif op[0] in ("rx", "ry", "rz"):
+            key.append(op[:-1] + (op[-1],))
+        elif op[0] == "u":
+            key.append(("u", op[1], op[2], np.asarray(op[3]).tobytes()))
+        else:
+            key.append(op)
+    return (c.dim, c.n, tuple(key))
+
+
+@dataclass
+class _Group:
+    idx: List[int]
+    dim: int
+    n: int
+    nrot: int                      # rotation angles per circuit
+    nclock: int                    # clock exponents per circuit (stored after the angles)
+    plan: Plan = None
+    theta: object = None           # device float64 [batch, nrot + nclock]
+    psi: object = None
+    lam: object = None
+    grad: object = None            # device float64 [batch, nrot + nclock]
+    loss: object = None            # device float64 [batch, 2]
+    terms: list = field(default_factory=list)
+
+
+class RaggedBatch:
+    """A ragged batch of circuits (uneven n and D) stepped as one HIP graph."""
+
+    def __init__(self, circuits: Sequence, dtype: str = "c64",
+                 terms: Callable[[int], list] = default_terms):
+        torch = _torch()
+        self.circuits = list(circuits)
+        self.dtype = dtype
+        groups: Dict[Tuple, List[int]] = {}
+        for i, c in enumerate(self.circuits):
+            groups.setdefault(_layout(c), []).append(i)
+        self.groups: List[_Group] = []
+        for key, idx in sorted(groups.items(), key=lambda kv: (kv[0][0], kv[0][1])):
+            c0 = self.circuits[idx[0]]
+            ops, nclock = [], 0
+            for op in c0.ops:
+                if op[0] == "clock":
+                    ops.append(("clockp", op[1], c0.nparams + nclock))
+                    nclock += 1
+                else:
+                    ops.append(op)
+            P = c0.nparams + nclock
+            g = _Group(idx=idx, dim=c0.dim, n=c0.n, nrot=c0.nparams, nclock=nclock)
+            g.plan = Plan(c0.dim, c0.n, ops, P, dtype)
+            g.plan.bind(len(idx))
+            th = np.zeros((len(idx), P))
+            for r, ci in enumerate(idx):
+                c = self.circuits[ci]
+                th[r, :c.nparams] = c.theta
+                th[r, c.nparams:] = [op[2] for op in c.ops if op[0] == "clock"]
+            g.theta = torch.tensor(th, dtype=torch.float64, device="cuda")
+            g.psi = new_state(g.n, g.dim, dtype, batch=len(idx))
+            g.lam = new_state(g.n, g.dim, dtype, batch=len(idx))
+            g.grad = torch.zeros((len(idx), P), dtype=torch.float64, device="cuda")
+            g.loss = torch.zeros((len(idx), 2), dtype=torch.float64, device="cuda")
+            g.terms = terms(g.n)
+            self.groups.append(g)
+        self.graph = None
+
+    @property
+    def amplitudes(self) -> int:
+        return sum(c.dim ** c.n for c in self.circuits)
+
+    def step(self) -> None:
+        """Enqueue one training step of every circuit on the current stream."""
+        for g in self.groups:
+            P = g.nrot + g.nclock
+            qf_state_init(g.psi, g.n, g.dim, None)
+            g.plan.forward_dev(g.psi, g.theta, P)
+            g.plan.adjoint_grad_dev(g.psi, g.lam, g.theta, P, g.terms, g.grad, g.loss)
+
+    def capture(self) -> None:
+        """Capture step() in a HIP graph (after one eager warm-up step)."""
+        torch = _torch()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.step()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.step()
+        torch.cuda.synchronize()
+
+    def replay(self) -> None:
+        self.graph.replay()
+
+    def set_angles(self, i: int, theta: np.ndarray) -> None:
+        """Write new rotation angles of circuit i into its group's device array."""
+        torch = _torch()
+        for g in self.groups:
+            if i in g.idx:
+                r = g.idx.index(i)
+                g.theta[r, :g.nrot].copy_(torch.as_tensor(theta, dtype=torch.float64))
+                return
+        raise KeyError(i)
+
+    def gradients(self) -> List[np.ndarray]:
+        out: List[Optional[np.ndarray]] = [None] * len(self.circuits)
+        for g in self.groups:
+            gr = g.grad.cpu().numpy()
+            for r, ci in enumerate(g.idx):
+                out[ci] = gr[r, :g.nrot].copy()
+        return out
+
+    def losses(self) -> np.ndarray:
+        out = np.zeros(len(self.circuits))
+        for g in self.groups:
+            lv = g.loss.cpu().numpy()
+            for r, ci in enumerate(g.idx):
+                out[ci] = lv[r, 0]
+        return out
+
+
+class PlainLoop:
+    """The same circuits one at a time through the per-circuit path: a plan per
+    circuit, host-built matrices, and the host-side gradient of qf_adjoint_grad."""
+
+    def __init__(self, circuits: Sequence, dtype: str = "c64",
+                 terms: Callable[[int], list] = default_terms):
+        from . import plan_for
+        self.circuits = list(circuits)
+        self.plans = [plan_for(c, dtype) for c in self.circuits]
+        self.psi = [new_state(c.n, c.dim, dtype) for c in self.circuits]
+        self.lam = [new_state(c.n, c.dim, dtype) for c in self.circuits]
+        self.terms = [terms(c.n) for c in self.circuits]
+        self.grads: List[np.ndarray] = []
+
+    def step(self) -> None:
+        self.grads = []
+        for c, p, psi, lam, t in zip(self.circuits, self.plans, self.psi, self.lam, self.terms):
+            qf_state_init(psi, c.n, c.dim, None)
+            p.forward(psi, c.theta)
+            self.grads.append(p.adjoint_grad(psi, lam, c.theta, t))

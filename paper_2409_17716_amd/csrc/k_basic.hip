@@ -556,6 +556,29 @@ qf_status launch_probs_marginal(const StateView& s, int m, const int32_t* qudits
     });
 }
 
+size_t expect_ws_doubles(const StateView& s) {
+    const uint32_t chunk = kBlock * 16;
+    const uint32_t nblk = (s.N + chunk - 1) / chunk;
+    return size_t(nblk) * s.batch * 2;
+}
+
+qf_status launch_expect_ws(const StateView& s, const std::vector<int>& active, const std::vector<double>& table,
+                           double* out, double* partial, hipStream_t st) {
+    ObsArg a = make_obs(s, active, table, false);
+    const uint32_t chunk = kBlock * 16;
+    const uint32_t nblk = (s.N + chunk - 1) / chunk;
+    const uint64_t nblocks = uint64_t(nblk) * s.batch;
+    if (nblocks >= (1ull << 31)) return set_error(QF_ERANGE, "expectation grid too large");
+    return with_type(s.dtype, [&](auto tag) -> qf_status {
+        using T = decltype(tag);
+        hipLaunchKernelGGL(k_expect_partial<T>, dim3(uint32_t(nblocks)), dim3(kBlock), 0, st,
+                           reinterpret_cast<const cplx<T>*>(s.amps), s.N, chunk, nblk, a, partial);
+        QF_CHECK(check_launch("qf_expect"));
+        hipLaunchKernelGGL(k_expect_final, dim3(s.batch), dim3(kBlock), 0, st, partial, nblk, out);
+        return check_launch("qf_expect final");
+    });
+}
+
 qf_status launch_expect(const StateView& s, const std::vector<int>& active, const std::vector<double>& table,
                         double* out, hipStream_t st) {
     ObsArg a = make_obs(s, active, table, false);

@@ -182,7 +182,8 @@ __device__ inline cplx<T> phase_of(const StageOp& op, const cplx<T>* __restrict_
 template <typename T, int D>
 __global__ __launch_bounds__(kSB) void k_stage(cplx<T>* __restrict__ psi, StageGeom g,
                                                const StageOp* __restrict__ ops, int nops,
-                                               const cplx<T>* __restrict__ mats) {
+                                               const cplx<T>* __restrict__ mats, size_t mat_stride) {
+    mats += size_t(blockIdx.x / g.ntiles) * mat_stride;  // per-register matrices (stride 0: shared)
     extern __shared__ unsigned char smem[];
     cplx<T>* tile = reinterpret_cast<cplx<T>*>(smem);
     __shared__ uint32_t offhi[kMaxHi];
@@ -217,7 +218,9 @@ __global__ __launch_bounds__(kSB) void k_stage(cplx<T>* __restrict__ psi, StageG
 template <typename T, int D>
 __global__ __launch_bounds__(kSB) void k_stage_adj(cplx<T>* __restrict__ psi, cplx<T>* __restrict__ lam,
                                                    StageGeom g, const StageOp* __restrict__ ops, int nops,
-                                                   const cplx<T>* __restrict__ mats, double* __restrict__ partial) {
+                                                   const cplx<T>* __restrict__ mats, size_t mat_stride,
+                                                   double* __restrict__ partial) {
+    mats += size_t(blockIdx.x / g.ntiles) * mat_stride;
     extern __shared__ unsigned char smem[];
     cplx<T>* tp = reinterpret_cast<cplx<T>*>(smem);
     cplx<T>* tl = tp + g.TE;
@@ -495,7 +498,8 @@ template <typename T, int D, int M>
 __global__ __launch_bounds__(kSB) void k_stage_rounds(cplx<T>* __restrict__ psi, StageGeom g,
                                                       const RoundDesc* __restrict__ rounds, int nrounds,
                                                       const StageOp* __restrict__ ops,
-                                                      const cplx<T>* __restrict__ mats) {
+                                                      const cplx<T>* __restrict__ mats, size_t mat_stride) {
+    mats += size_t(blockIdx.x / g.ntiles) * mat_stride;
     constexpr int DM = cpow(D, M);
     extern __shared__ unsigned char smem[];
     cplx<T>* tile = reinterpret_cast<cplx<T>*>(smem);
@@ -558,7 +562,7 @@ size_t stage_lds_bytes(const StageGeom& g, int dtype, bool adjoint) {
 }
 
 qf_status launch_stage(const StateView& s, const StageGeom& g, const StageOp* dops, int nops, const void* dmats,
-                       hipStream_t st) {
+                       hipStream_t st, size_t mat_stride) {
     const uint32_t grid = g.ntiles * s.batch;
     const size_t lds = stage_lds_bytes(g, s.dtype, false);
     return with_dim_s(s.D, [&](auto dtag) -> qf_status {
@@ -566,11 +570,11 @@ qf_status launch_stage(const StateView& s, const StageGeom& g, const StageOp* do
         if (s.dtype == QF_C64)
             hipLaunchKernelGGL((k_stage<float, D>), dim3(grid), dim3(kSB), lds, st,
                                reinterpret_cast<cplx<float>*>(s.amps), g, dops, nops,
-                               reinterpret_cast<const cplx<float>*>(dmats));
+                               reinterpret_cast<const cplx<float>*>(dmats), mat_stride);
         else
             hipLaunchKernelGGL((k_stage<double, D>), dim3(grid), dim3(kSB), lds, st,
                                reinterpret_cast<cplx<double>*>(s.amps), g, dops, nops,
-                               reinterpret_cast<const cplx<double>*>(dmats));
+                               reinterpret_cast<const cplx<double>*>(dmats), mat_stride);
         return check_launch("stage");
     });
 }
@@ -580,29 +584,29 @@ int max_group_size(uint32_t D) { return D == 2 ? 5 : D == 3 ? 3 : D <= 5 ? 2 : 1
 
 template <typename T, int D, int M>
 static qf_status launch_rounds_m(const StateView& s, const StageGeom& g, const RoundDesc* drounds, int nrounds,
-                                 const StageOp* dops, const void* dmats, hipStream_t st) {
+                                 const StageOp* dops, const void* dmats, size_t mat_stride, hipStream_t st) {
     const uint32_t grid = g.ntiles * s.batch;
     const size_t lds = stage_lds_bytes(g, s.dtype, false);
     hipLaunchKernelGGL((k_stage_rounds<T, D, M>), dim3(grid), dim3(kSB), lds, st, reinterpret_cast<cplx<T>*>(s.amps),
-                       g, drounds, nrounds, dops, reinterpret_cast<const cplx<T>*>(dmats));
+                       g, drounds, nrounds, dops, reinterpret_cast<const cplx<T>*>(dmats), mat_stride);
     return check_launch("stage rounds");
 }
 
 qf_status launch_stage_rounds(const StateView& s, int M, const StageGeom& g, const RoundDesc* drounds, int nrounds,
-                              const StageOp* dops, const void* dmats, hipStream_t st) {
+                              const StageOp* dops, const void* dmats, hipStream_t st, size_t mat_stride) {
     return with_dim_s(s.D, [&](auto dtag) -> qf_status {
         constexpr int D = decltype(dtag)::value;
         auto go = [&](auto tag) -> qf_status {
             using T = decltype(tag);
             switch (M) {
-                case 1: return launch_rounds_m<T, D, 1>(s, g, drounds, nrounds, dops, dmats, st);
-                case 2: if constexpr (D <= 5) return launch_rounds_m<T, D, 2>(s, g, drounds, nrounds, dops, dmats, st);
+                case 1: return launch_rounds_m<T, D, 1>(s, g, drounds, nrounds, dops, dmats, mat_stride, st);
+                case 2: if constexpr (D <= 5) return launch_rounds_m<T, D, 2>(s, g, drounds, nrounds, dops, dmats, mat_stride, st);
                         break;
-                case 3: if constexpr (D <= 3) return launch_rounds_m<T, D, 3>(s, g, drounds, nrounds, dops, dmats, st);
+                case 3: if constexpr (D <= 3) return launch_rounds_m<T, D, 3>(s, g, drounds, nrounds, dops, dmats, mat_stride, st);
                         break;
-                case 4: if constexpr (D <= 2) return launch_rounds_m<T, D, 4>(s, g, drounds, nrounds, dops, dmats, st);
+                case 4: if constexpr (D <= 2) return launch_rounds_m<T, D, 4>(s, g, drounds, nrounds, dops, dmats, mat_stride, st);
                         break;
-                case 5: if constexpr (D <= 2) return launch_rounds_m<T, D, 5>(s, g, drounds, nrounds, dops, dmats, st);
+                case 5: if constexpr (D <= 2) return launch_rounds_m<T, D, 5>(s, g, drounds, nrounds, dops, dmats, mat_stride, st);
                         break;
             }
             return set_error(QF_EUNSUPPORTED, "register group of %d qudits for D = %d", M, D);
@@ -612,7 +616,7 @@ qf_status launch_stage_rounds(const StateView& s, int M, const StageGeom& g, con
 }
 
 qf_status launch_stage_adj(const StateView& s, void* lam, const StageGeom& g, const StageOp* dops, int nops,
-                           const void* dmats, double* partial, hipStream_t st) {
+                           const void* dmats, double* partial, hipStream_t st, size_t mat_stride) {
     const uint32_t grid = g.ntiles * s.batch;
     const size_t lds = stage_lds_bytes(g, s.dtype, true);
     return with_dim_s(s.D, [&](auto dtag) -> qf_status {
@@ -620,11 +624,11 @@ qf_status launch_stage_adj(const StateView& s, void* lam, const StageGeom& g, co
         if (s.dtype == QF_C64)
             hipLaunchKernelGGL((k_stage_adj<float, D>), dim3(grid), dim3(kSB), lds, st,
                                reinterpret_cast<cplx<float>*>(s.amps), reinterpret_cast<cplx<float>*>(lam), g, dops,
-                               nops, reinterpret_cast<const cplx<float>*>(dmats), partial);
+                               nops, reinterpret_cast<const cplx<float>*>(dmats), mat_stride, partial);
         else
             hipLaunchKernelGGL((k_stage_adj<double, D>), dim3(grid), dim3(kSB), lds, st,
                                reinterpret_cast<cplx<double>*>(s.amps), reinterpret_cast<cplx<double>*>(lam), g, dops,
-                               nops, reinterpret_cast<const cplx<double>*>(dmats), partial);
+                               nops, reinterpret_cast<const cplx<double>*>(dmats), mat_stride, partial);
         return check_launch("stage adjoint");
     });
 }

@@ -94,7 +94,12 @@ static Mat gate_matrix(const qf_op& g, int D, const double* theta) {
             break;
         }
         case QF_OP_CLOCK:
-            for (int r = 0; r < D; ++r) m[size_t(r) * D + r] = std::polar(1.0, 2 * pi * double(((g.j % D + D) % D) * r % D) / D);
+            if (g.param >= 0) {  // exponent a = theta[param] (any real value)
+                for (int r = 0; r < D; ++r) m[size_t(r) * D + r] = std::polar(1.0, 2 * pi * theta[g.param] * r / D);
+            } else {
+                for (int r = 0; r < D; ++r)
+                    m[size_t(r) * D + r] = std::polar(1.0, 2 * pi * double(((g.j % D + D) % D) * r % D) / D);
+            }
             break;
         case QF_OP_RX: {
             const double t = theta[g.param];
@@ -198,6 +203,9 @@ struct PassList {
     std::vector<StageOp> hops;
     std::vector<RoundDesc> hrounds;
     RoundDesc* drounds = nullptr;
+    std::vector<DevGroup> hgroups;   // bound mode: matrices built on the device
+    DevGroup* dgroups = nullptr;
+    void* dmats_b = nullptr;         // bound mode: batch x nmats matrices
     size_t nmats = 0;
     int nslots = 0;
     StageOp* dops = nullptr;
@@ -205,7 +213,14 @@ struct PassList {
     void* hmats = nullptr;
     hipEvent_t copied = nullptr, done = nullptr;
     bool copied_valid = false, done_valid = false;
+    void release_bound() {
+        if (dgroups) (void)hipFree(dgroups);
+        if (dmats_b) (void)hipFree(dmats_b);
+        dgroups = nullptr;
+        dmats_b = nullptr;
+    }
     void release() {
+        release_bound();
         if (drounds) (void)hipFree(drounds);
         drounds = nullptr;
         if (dops) (void)hipFree(dops);
@@ -243,6 +258,32 @@ struct qf_plan {
     std::vector<qf::ProfRec> prof;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
+    // bound (device-parameter) mode
+    uint32_t bound = 0;
+    std::vector<qf::DevGate> hgates;
+    qf::DevGate* dgates = nullptr;
+    std::vector<qf::DevGradGroup> hgg;
+    qf::DevGradGroup* dgg = nullptr;
+    int32_t* d_poff = nullptr;
+    int32_t* d_plist = nullptr;
+    int ncontrib = 0;
+    double* w_partial = nullptr;
+    double* w_m = nullptr;
+    double* w_contrib = nullptr;
+    double* w_expect = nullptr;
+    void release_bound() {
+        for (void* q : {static_cast<void*>(dgates), static_cast<void*>(dgg), static_cast<void*>(d_poff),
+                        static_cast<void*>(d_plist), static_cast<void*>(w_partial), static_cast<void*>(w_m),
+                        static_cast<void*>(w_contrib), static_cast<void*>(w_expect)})
+            if (q) (void)hipFree(q);
+        dgates = nullptr;
+        dgg = nullptr;
+        d_poff = d_plist = nullptr;
+        w_partial = w_m = w_contrib = w_expect = nullptr;
+        fwd.release_bound();
+        rev.release_bound();
+        bound = 0;
+    }
     qf_plan() = default;
     qf_plan(const qf_plan&) = delete;
     qf_plan& operator=(const qf_plan&) = delete;
@@ -267,8 +308,21 @@ struct qf_plan {
         prof.swap(o.prof);
         ev_pool.swap(o.ev_pool);
         std::swap(ev_used, o.ev_used);
+        std::swap(bound, o.bound);
+        hgates.swap(o.hgates);
+        std::swap(dgates, o.dgates);
+        hgg.swap(o.hgg);
+        std::swap(dgg, o.dgg);
+        std::swap(d_poff, o.d_poff);
+        std::swap(d_plist, o.d_plist);
+        std::swap(ncontrib, o.ncontrib);
+        std::swap(w_partial, o.w_partial);
+        std::swap(w_m, o.w_m);
+        std::swap(w_contrib, o.w_contrib);
+        std::swap(w_expect, o.w_expect);
     }
     ~qf_plan() {
+        release_bound();
         for (auto& g : gates) {
             if (g.dmat) (void)hipFree(g.dmat);
             if (g.dmat_adj) (void)hipFree(g.dmat_adj);
@@ -297,6 +351,8 @@ static qf_status validate_op(const qf_op& o, int D, int n, int nparams) {
         case QF_OP_X:
         case QF_OP_CLOCK:
             QF_RETURN_IF(!qok(o.q0), QF_EINVAL, "qudit %d outside [0, %d)", o.q0, n);
+            QF_RETURN_IF(o.kind == QF_OP_CLOCK && o.param >= nparams, QF_EINVAL, "param %d outside [0, %d)", o.param,
+                         nparams);
             break;
         case QF_OP_RX:
         case QF_OP_RY:
@@ -1509,6 +1565,218 @@ qf_status qf_plan_autotune(qf_plan* plan, const qf_state* s, const double* theta
     qf_plan_destroy(np);
     if (chosen) *chosen = best;
     return QF_OK;
+}
+
+}  // extern "C"
+
+namespace qf {
+
+static DevGate dev_gate(const qf_op& o) { return DevGate{o.kind, o.j, o.k, o.param}; }
+
+static void bound_groups(qf_plan* p, PassList& L) {
+    L.hgroups.clear();
+    for (const Pass& ps : L.passes) {
+        if (!ps.tile) continue;
+        for (size_t i = 0; i < ps.ops.size(); ++i) {
+            const HOp& h = ps.ops[i];
+            const StageOp& so = L.hops[ps.op_off + i];
+            if (h.type == SOP_U) {
+                DevGroup g{DG_U, uint32_t(ps.mat_off + so.mat), int32_t(p->hgates.size()), int32_t(h.g.size()),
+                           h.g[0].inv ? 1 : 0};
+                for (const GRef& r : h.g) p->hgates.push_back(dev_gate(op_of(p, r)));
+                L.hgroups.push_back(g);
+            } else if (h.type == SOP_PHASE) {
+                for (size_t j = 0; j < h.g.size(); ++j)
+                    L.hgroups.push_back(DevGroup{DG_CZ, uint32_t(ps.mat_off + so.ptab[j]), 0, 0, h.g[j].inv ? 1 : 0});
+                if (ps.nrounds > 0)
+                    L.hgroups.push_back(DevGroup{DG_W, uint32_t(ps.mat_off + so.wtab), 0, 0, h.g[0].inv ? 1 : 0});
+            }
+        }
+    }
+}
+
+template <typename X>
+static qf_status dev_upload(X** dst, const std::vector<X>& src) {
+    if (src.empty()) return QF_OK;
+    QF_HIP_CHECK(hipMalloc(reinterpret_cast<void**>(dst), src.size() * sizeof(X)));
+    QF_HIP_CHECK(hipMemcpy(*dst, src.data(), src.size() * sizeof(X), hipMemcpyHostToDevice));
+    return QF_OK;
+}
+
+static qf_status dev_alloc(void** dst, size_t bytes) {
+    if (hipMalloc(dst, std::max<size_t>(bytes, 16)) != hipSuccess) {
+        (void)hipGetLastError();
+        *dst = nullptr;
+        return set_error(QF_ENOMEM, "device allocation of %zu bytes failed", bytes);
+    }
+    return QF_OK;
+}
+
+static qf_status check_bound(const qf_plan* p, const StateView& v, int64_t theta_stride) {
+    QF_RETURN_IF(p->bound == 0, QF_EINVAL, "plan is not bound: call qf_plan_bind first");
+    QF_RETURN_IF(v.batch > p->bound, QF_ERANGE, "state batch %u exceeds the bound batch %u", v.batch, p->bound);
+    QF_RETURN_IF(theta_stride != 0 && theta_stride < p->nparams, QF_EINVAL,
+                 "theta_stride %lld must be 0 or >= nparams %d", (long long)theta_stride, p->nparams);
+    return QF_OK;
+}
+
+}  // namespace qf
+
+extern "C" {
+
+qf_status qf_plan_bind(qf_plan* plan, int64_t batch) {
+    QF_RETURN_IF(plan == nullptr, QF_EINVAL, "plan is NULL");
+    QF_RETURN_IF(batch < 1 || batch >= (int64_t(1) << 31), QF_EINVAL, "batch %lld out of range", (long long)batch);
+    QF_RETURN_IF(plan->opts.fuse != 0, QF_EUNSUPPORTED, "device-parameter mode needs a stage plan (fuse = 0)");
+    plan->release_bound();
+    const uint64_t N = ipow(plan->D, plan->n);
+    QF_RETURN_IF(N * uint64_t(batch) >= (1ull << 32), QF_ERANGE, "batch * D^n exceeds 2^32 amplitudes");
+    const int D = plan->D;
+    const size_t E = size_t(D) * D;
+    const size_t esz = plan->dtype == QF_C64 ? 8 : 16;
+    plan->hgates.clear();
+    bound_groups(plan, plan->fwd);
+    bound_groups(plan, plan->rev);
+    // gradient runs and contribution slots
+    plan->hgg.clear();
+    std::vector<std::pair<int, int>> contrib;  // (param, slot)
+    int nc = 0;
+    for (const Pass& ps : plan->rev.passes)
+        for (const HOp& h : ps.ops) {
+            if (h.gslot < 0) continue;
+            DevGradGroup g{h.gslot, int32_t(plan->hgates.size()), int32_t(h.g.size()), nc};
+            for (auto it = h.g.rbegin(); it != h.g.rend(); ++it) plan->hgates.push_back(dev_gate(op_of(plan, *it)));
+            for (int i = int(h.g.size()) - 1; i >= 0; --i) {  // the kernel walks the run backwards
+                const qf_op& o = op_of(plan, h.g[h.g.size() - 1 - i]);
+                if (is_rot(o.kind)) contrib.push_back({o.param, nc++});
+            }
+            plan->hgg.push_back(g);
+        }
+    plan->ncontrib = nc;
+    std::vector<int32_t> poff(plan->nparams + 1, 0), plist(nc);
+    for (auto& c : contrib) poff[c.first + 1]++;
+    for (int i = 0; i < plan->nparams; ++i) poff[i + 1] += poff[i];
+    {
+        std::vector<int32_t> fill(poff.begin(), poff.end() - 1);
+        for (auto& c : contrib) plist[fill[c.first]++] = c.second;
+    }
+    qf_status rs = QF_OK;
+    auto step = [&](qf_status r) {
+        if (rs == QF_OK) rs = r;
+    };
+    step(dev_upload(&plan->dgates, plan->hgates));
+    step(dev_upload(&plan->fwd.dgroups, plan->fwd.hgroups));
+    step(dev_upload(&plan->rev.dgroups, plan->rev.hgroups));
+    step(dev_upload(&plan->dgg, plan->hgg));
+    step(dev_upload(&plan->d_poff, poff));
+    if (nc > 0) step(dev_upload(&plan->d_plist, plist));
+    if (rs == QF_OK && plan->fwd.dmats == nullptr) step(upload_ops(plan, plan->fwd));
+    if (rs == QF_OK && plan->rev.dmats == nullptr) step(upload_ops(plan, plan->rev));
+    step(dev_alloc(&plan->fwd.dmats_b, std::max<size_t>(plan->fwd.nmats, 1) * esz * size_t(batch)));
+    step(dev_alloc(&plan->rev.dmats_b, std::max<size_t>(plan->rev.nmats, 1) * esz * size_t(batch)));
+    size_t pd = 1;
+    for (const Pass& ps : plan->rev.passes)
+        if (ps.tile) pd = std::max(pd, size_t(ps.nslots) * ps.geom.ntiles * size_t(batch) * E * 2);
+    step(dev_alloc(reinterpret_cast<void**>(&plan->w_partial), pd * sizeof(double)));
+    step(dev_alloc(reinterpret_cast<void**>(&plan->w_m),
+                   size_t(batch) * std::max(plan->rev.nslots, 1) * E * 2 * sizeof(double)));
+    step(dev_alloc(reinterpret_cast<void**>(&plan->w_contrib), size_t(batch) * std::max(nc, 1) * sizeof(double)));
+    StateView v{};
+    v.n = plan->n;
+    v.D = D;
+    v.N = uint32_t(N);
+    v.batch = uint32_t(batch);
+    v.total = uint32_t(N * uint64_t(batch));
+    v.dtype = plan->dtype;
+    step(dev_alloc(reinterpret_cast<void**>(&plan->w_expect), expect_ws_doubles(v) * sizeof(double)));
+    if (rs == QF_OK && plan->seg_end.size() > 1) step(ensure_ckpt(plan, v));
+    if (rs != QF_OK) {
+        plan->release_bound();
+        return rs;
+    }
+    plan->bound = uint32_t(batch);
+    return QF_OK;
+}
+
+qf_status qf_plan_forward_dev(qf_plan* plan, const qf_state* s, const double* theta, int64_t theta_stride,
+                              void* stream) {
+    StateView v;
+    QF_CHECK(check_plan_state(plan, s, v));
+    QF_CHECK(check_bound(plan, v, theta_stride));
+    QF_RETURN_IF(plan->nparams > 0 && theta == nullptr, QF_EINVAL, "theta is NULL");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    PassList& L = plan->fwd;
+    const size_t esz = plan->dtype == QF_C64 ? 8 : 16;
+    QF_CHECK(launch_build_mats(plan->D, plan->dtype, L.dgroups, int(L.hgroups.size()), plan->dgates, theta,
+                               theta_stride, v.batch, L.dmats_b, L.nmats, st));
+    const size_t sb = state_bytes(v);
+    for (size_t i = 0; i < L.passes.size(); ++i) {
+        const Pass& ps = L.passes[i];
+        if (ps.tile) {
+            const void* mats = reinterpret_cast<const unsigned char*>(L.dmats_b) + ps.mat_off * esz;
+            if (ps.nrounds > 0 && plan->opts.stage_kernel == 0)
+                QF_CHECK(launch_stage_rounds(v, plan->group, ps.geom, L.drounds + ps.round_off, ps.nrounds,
+                                             L.dops + ps.op_off, mats, st, L.nmats));
+            else
+                QF_CHECK(launch_stage(v, ps.geom, L.dops + ps.op_off, ps.nops, mats, st, L.nmats));
+        } else {
+            const Gate& g = plan->gates[ps.fused.gi];
+            QF_CHECK(launch_fused(v, g.op.q1, g.op.q0, g.dmat, st, g.real));
+        }
+        const bool seg_end = i + 1 == L.passes.size() || L.passes[i + 1].seg != ps.seg;
+        if (plan->seg_end.size() > 1 && seg_end && size_t(ps.seg) + 1 < plan->seg_end.size())
+            QF_HIP_CHECK(hipMemcpyAsync(reinterpret_cast<unsigned char*>(plan->ckpt) + size_t(ps.seg) * sb, v.amps,
+                                        sb, hipMemcpyDeviceToDevice, st));
+    }
+    return QF_OK;
+}
+
+qf_status qf_adjoint_grad_dev(qf_plan* plan, const qf_state* psi, const qf_state* lam, const double* theta,
+                              int64_t theta_stride, int32_t nterms, const int32_t* term_qudit,
+                              const double* term_diag, double* grad, double* loss, void* stream) {
+    StateView v, vl;
+    QF_CHECK(check_plan_state(plan, psi, v));
+    QF_CHECK(check_plan_state(plan, lam, vl));
+    QF_CHECK(check_bound(plan, v, theta_stride));
+    QF_RETURN_IF(vl.batch != v.batch, QF_EINVAL, "psi and lam batch differ");
+    QF_RETURN_IF(psi->amps == lam->amps, QF_EINVAL, "psi and lam must not alias");
+    QF_RETURN_IF(grad == nullptr && plan->nparams > 0, QF_EINVAL, "grad is NULL");
+    QF_RETURN_IF(plan->nparams > 0 && theta == nullptr, QF_EINVAL, "theta is NULL");
+    std::vector<int> active;
+    std::vector<double> table;
+    QF_CHECK(combine_terms(v, nterms, term_qudit, term_diag, active, table));
+    std::vector<double> table_re(active.size() * v.D);
+    for (size_t i = 0; i < table_re.size(); ++i) table_re[i] = table[2 * i];
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int D = plan->D;
+    const size_t E = size_t(D) * D;
+    const size_t esz = plan->dtype == QF_C64 ? 8 : 16;
+    if (loss) QF_CHECK(launch_expect_ws(v, active, table, loss, plan->w_expect, st));
+    QF_CHECK(launch_diag_observable(v, lam->amps, active, table_re, st));
+    PassList& L = plan->rev;
+    QF_CHECK(launch_build_mats(plan->D, plan->dtype, L.dgroups, int(L.hgroups.size()), plan->dgates, theta,
+                               theta_stride, v.batch, L.dmats_b, L.nmats, st));
+    const size_t sb = state_bytes(v);
+    for (size_t i = 0; i < L.passes.size(); ++i) {
+        const Pass& ps = L.passes[i];
+        const bool seg_start = i == 0 || L.passes[i - 1].seg != ps.seg;
+        if (seg_start && size_t(ps.seg) + 1 < plan->seg_end.size())
+            QF_HIP_CHECK(hipMemcpyAsync(v.amps, reinterpret_cast<unsigned char*>(plan->ckpt) + size_t(ps.seg) * sb, sb,
+                                        hipMemcpyDeviceToDevice, st));
+        if (ps.tile) {
+            const void* mats = reinterpret_cast<const unsigned char*>(L.dmats_b) + ps.mat_off * esz;
+            QF_CHECK(launch_stage_adj(v, lam->amps, ps.geom, L.dops + ps.op_off, ps.nops, mats, plan->w_partial, st,
+                                      L.nmats));
+            QF_CHECK(launch_stage_mreduce(plan->w_partial, ps.nslots, ps.geom.ntiles, v.batch, uint32_t(E), plan->w_m,
+                                          uint32_t(L.nslots), uint32_t(ps.slot0), st));
+        } else {
+            const Gate& g = plan->gates[ps.fused.gi];
+            QF_CHECK(launch_fused(v, g.op.q1, g.op.q0, g.dmat_adj, st, g.real));
+            QF_CHECK(launch_fused(vl, g.op.q1, g.op.q0, g.dmat_adj, st, g.real));
+        }
+    }
+    return launch_grad(D, plan->dgg, int(plan->hgg.size()), plan->dgates, theta, theta_stride, plan->w_m, L.nslots,
+                       v.batch, plan->w_contrib, plan->ncontrib, plan->d_poff, plan->d_plist, plan->nparams, grad, st);
 }
 
 }  // extern "C"

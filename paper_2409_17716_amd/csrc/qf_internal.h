@@ -40,6 +40,10 @@ qf_status launch_probs_marginal(const StateView& s, int m, const int32_t* qudits
 // table: per active qudit D complex values (combined terms), active: qudit list
 qf_status launch_expect(const StateView& s, const std::vector<int>& active,
                         const std::vector<double>& table, double* out, hipStream_t st);
+// Same with a caller workspace of expect_ws_doubles(s) doubles (no allocation).
+size_t expect_ws_doubles(const StateView& s);
+qf_status launch_expect_ws(const StateView& s, const std::vector<int>& active, const std::vector<double>& table,
+                           double* out, double* ws, hipStream_t st);
 // Elementwise lam = f(x) * psi with f(x) = sum over active qudits of the real
 // table value (the Hermitian part of a diagonal observable).
 qf_status launch_diag_observable(const StateView& psi, void* lam_amps, const std::vector<int>& active,
@@ -114,21 +118,54 @@ struct StageOp {
     int32_t wtab;         // PHASE: offset of the D-entry table w^e (e = sum of x_a x_b mod D)
 };
 
+// mat_stride: complex elements between the matrices of consecutive registers
+// (0: every register uses the same matrices).
 qf_status launch_stage(const StateView& s, const StageGeom& g, const StageOp* dops, int nops, const void* dmats,
-                       hipStream_t st);
+                       hipStream_t st, size_t mat_stride = 0);
 // Register-round form with groups of M qudits (1 <= M <= max_group_size(D)).
 int max_group_size(uint32_t D);
 qf_status launch_stage_rounds(const StateView& s, int M, const StageGeom& g, const RoundDesc* drounds, int nrounds,
-                              const StageOp* dops, const void* dmats, hipStream_t st);
+                              const StageOp* dops, const void* dmats, hipStream_t st, size_t mat_stride = 0);
 // Reverse stage: applies the (already inverted) ops to psi and lam; before each
 // U with slot >= 0 it accumulates M = sum_f psi_f lam_f^dagger over the tile
 // into partial[(slot * nblocks + block) * D*D] (complex FP64).
 qf_status launch_stage_adj(const StateView& s, void* lam, const StageGeom& g, const StageOp* dops, int nops,
-                           const void* dmats, double* partial, hipStream_t st);
+                           const void* dmats, double* partial, hipStream_t st, size_t mat_stride = 0);
 // mout[(b * nslots_total + slot0 + j) * E] = sum over the tiles of register b of
 // partial[j], for j < nslots (fixed order).
 qf_status launch_stage_mreduce(const double* partial, uint32_t nslots, uint32_t ntiles, uint32_t batch, uint32_t E,
                                double* mout, uint32_t nslots_total, uint32_t slot0, hipStream_t st);
 size_t stage_lds_bytes(const StageGeom& g, int dtype, bool adjoint);
+
+}  // namespace qf
+
+namespace qf {
+
+// ---- device-side parameters (k_params.hip) ----
+// A forward-order gate of a fused run (kinds: QF_OP_H, CLOCK, RX, RY, RZ).
+struct DevGate {
+    int32_t kind, j, k, param;
+};
+// One matrix a register needs: a fused run product, a CZ table or a w^e table.
+enum DevGroupType : int32_t { DG_U = 0, DG_CZ = 1, DG_W = 2 };
+struct DevGroup {
+    int32_t type;
+    uint32_t mat_off;  // complex elements from the start of a register's matrices
+    int32_t g0, ng;    // DG_U: gates [g0, g0 + ng) of the gate list, application order
+    int32_t inv;       // DG_U: every gate is applied as its inverse; DG_CZ / DG_W: conjugated
+};
+// A fused run that owns an adjoint M slot; its gates in forward order.
+struct DevGradGroup {
+    int32_t gslot;
+    int32_t g0, ng;    // forward-order gates in the gate list
+    int32_t c0;        // first contribution slot (one per rotation of the run)
+};
+
+qf_status launch_build_mats(int D, int dtype, const DevGroup* groups, int ngroups, const DevGate* gates,
+                            const double* theta, int64_t theta_stride, uint32_t batch, void* mats, size_t mat_stride,
+                            hipStream_t st);
+qf_status launch_grad(int D, const DevGradGroup* gg, int ngg, const DevGate* gates, const double* theta,
+                      int64_t theta_stride, const double* M, int nslots, uint32_t batch, double* contrib, int ncontrib,
+                      const int32_t* p_off, const int32_t* p_list, int nparams, double* grad, hipStream_t st);
 
 }  // namespace qf
