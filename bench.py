@@ -40,6 +40,7 @@ def _args():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the ragged-batch measurement")
     ap.add_argument("--pmc-workload", action="store_true",
                     help="run only the counter workload: two plain copies of the state size, then one step")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -111,6 +112,45 @@ def write_traffic(fetch_dir: str, write_dir: str) -> None:
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec))
+
+
+def batched_measurement(steps: int) -> dict:
+    """Ragged batch of 1024 circuits (768 qutrit, n ~ U{6..10}; 256 ququart,
+    n ~ U{5..8}; depth-6 ansatz, own angles): init + forward + <sum Z_i> + adjoint
+    gradient of every circuit, as one HIP graph replay per step, against the same
+    circuits looped one at a time through the per-circuit path."""
+    import numpy as np
+    import torch
+
+    import qf_inputs as qi
+    from paper_2409_17716_amd.batched import PlainLoop, RaggedBatch
+    circ = qi.config4()
+    rb = RaggedBatch(circ)
+    rb.capture()
+    for _ in range(2):
+        rb.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rb.replay()
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / steps
+    pl = PlainLoop(circ)
+    pl.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pl.step()
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    gb = rb.gradients()
+    rel = max(float(np.abs(gb[i] - pl.grads[i]).max() / max(1e-12, np.abs(pl.grads[i]).max()))
+              for i in range(len(circ)))
+    return {"workload": "1024 circuits: 768 qutrit (n ~ U{6..10}) + 256 ququart (n ~ U{5..8}), depth-6 ansatz, "
+                        "complex64; forward + Re<sum Z_i> + adjoint gradient per circuit",
+            "circuits": len(circ), "amplitudes": int(sum(c.dim ** c.n for c in circ)), "groups": len(rb.groups),
+            "batched_ms_per_step": round(tb * 1e3, 3), "batched_circuits_per_s": len(circ) / tb,
+            "plain_ms_per_step": round(tp * 1e3, 2), "plain_circuits_per_s": len(circ) / tp,
+            "speedup": tp / tb, "max_rel_grad_diff_vs_plain": rel}
 
 
 def cpu_baseline(c, seconds: float) -> dict:
@@ -219,6 +259,8 @@ def main() -> int:
         "roofline": roofline,
         "z0": [float(ev[0]), float(ev[1])],
     }
+    if not a.no_batched:
+        out["batched"] = batched_measurement(max(1, a.steps // 2))
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, a.cpu_seconds)
     print(json.dumps(out), flush=True)

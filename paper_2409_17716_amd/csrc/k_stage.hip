@@ -23,6 +23,13 @@ namespace {
 
 constexpr int kSB = 256;
 
+// Workgroup barrier for LDS data only: waits for this wave's LDS operations
+// (lgkmcnt) and meets the other waves, without the fence of __syncthreads that
+// would also wait for every outstanding global load (the pipelined kernel keeps
+// the next tile's loads in flight across these barriers).  The memory clobber
+// keeps the compiler from moving memory accesses across it.
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 template <int D>
 __device__ inline uint32_t tile_base(const StageGeom& g, uint32_t blk) {
     const uint32_t b = blk / g.ntiles;
@@ -59,32 +66,63 @@ __device__ inline uint32_t global_index(const StageGeom& g, const uint32_t* offh
 // per lane are in flight before the first one is waited on.
 constexpr int kIO = 8;
 
+// Tile I/O by runs: the tile is nhi runs of R contiguous amplitudes (run h
+// starts at base + offhi[h] in HBM and at h * R in LDS).  A lane keeps one
+// offset o inside a run and walks runs, so no per-element division is needed:
+// with R < 256 the lanes form G = 256 / R groups of R (group gr takes runs
+// gr, gr + G, ...); otherwise every lane strides through each run by 256.
+template <typename T, bool LOAD>
+__device__ inline void tile_io(cplx<T>* __restrict__ psi, cplx<T>* tile, const StageGeom& g, const uint32_t* offhi,
+                               uint32_t base) {
+    if (g.R < kSB) {
+        const uint32_t G = kSB / g.R;
+        const uint32_t gr = threadIdx.x / g.R;
+        const uint32_t o = threadIdx.x - gr * g.R;
+        if (gr >= G) return;
+        uint32_t h = gr;
+        for (; h + (kIO - 1) * G < g.nhi; h += G * kIO) {
+            cplx<T> t[kIO];
+            if (LOAD) {
+#pragma unroll
+                for (int j = 0; j < kIO; ++j) t[j] = psi[base + offhi[h + j * G] + o];
+#pragma unroll
+                for (int j = 0; j < kIO; ++j) tile[(h + j * G) * g.R + o] = t[j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < kIO; ++j) t[j] = tile[(h + j * G) * g.R + o];
+#pragma unroll
+                for (int j = 0; j < kIO; ++j) psi[base + offhi[h + j * G] + o] = t[j];
+            }
+        }
+        for (; h < g.nhi; h += G) {
+            if (LOAD)
+                tile[h * g.R + o] = psi[base + offhi[h] + o];
+            else
+                psi[base + offhi[h] + o] = tile[h * g.R + o];
+        }
+    } else {
+        for (uint32_t h = 0; h < g.nhi; ++h) {
+            const uint32_t gb = base + offhi[h];
+            for (uint32_t o = threadIdx.x; o < g.R; o += kSB) {
+                if (LOAD)
+                    tile[h * g.R + o] = psi[gb + o];
+                else
+                    psi[gb + o] = tile[h * g.R + o];
+            }
+        }
+    }
+}
+
 template <typename T>
 __device__ inline void tile_load(const cplx<T>* __restrict__ psi, cplx<T>* tile, const StageGeom& g,
                                  const uint32_t* offhi, uint32_t base) {
-    uint32_t e0 = threadIdx.x;
-    for (; e0 + (kIO - 1) * kSB < g.TE; e0 += kSB * kIO) {
-        cplx<T> t[kIO];
-#pragma unroll
-        for (int j = 0; j < kIO; ++j) t[j] = psi[global_index(g, offhi, base, e0 + uint32_t(j) * kSB)];
-#pragma unroll
-        for (int j = 0; j < kIO; ++j) tile[e0 + uint32_t(j) * kSB] = t[j];
-    }
-    for (; e0 < g.TE; e0 += kSB) tile[e0] = psi[global_index(g, offhi, base, e0)];
+    tile_io<T, true>(const_cast<cplx<T>*>(psi), tile, g, offhi, base);
 }
 
 template <typename T>
 __device__ inline void tile_store(cplx<T>* __restrict__ psi, const cplx<T>* tile, const StageGeom& g,
                                   const uint32_t* offhi, uint32_t base) {
-    uint32_t e0 = threadIdx.x;
-    for (; e0 + (kIO - 1) * kSB < g.TE; e0 += kSB * kIO) {
-        cplx<T> t[kIO];
-#pragma unroll
-        for (int j = 0; j < kIO; ++j) t[j] = tile[e0 + uint32_t(j) * kSB];
-#pragma unroll
-        for (int j = 0; j < kIO; ++j) psi[global_index(g, offhi, base, e0 + uint32_t(j) * kSB)] = t[j];
-    }
-    for (; e0 < g.TE; e0 += kSB) psi[global_index(g, offhi, base, e0)] = tile[e0];
+    tile_io<T, false>(psi, const_cast<cplx<T>*>(tile), g, offhi, base);
 }
 
 template <typename T, int D>
@@ -532,6 +570,177 @@ __global__ __launch_bounds__(kSB) void k_stage_rounds(cplx<T>* __restrict__ psi,
     tile_store(psi, tile, g, offhi, base);
 }
 
+// Pipelined persistent variant: a workgroup walks tiles blockIdx.x,
+// blockIdx.x + gridDim.x, ...; the global loads of the next tile are issued into
+// registers before the current tile's rounds run from LDS, so their latency
+// overlaps the compute and the stores.  Runs are shorter than the workgroup
+// (R < 256): lane (gr, o) handles offset o of runs gr, gr + G, ... (at most
+// MAXE of them).
+template <int MAXE>
+struct RunPlan {
+    uint32_t G, gr, o, cnt;
+};
+
+template <typename T, int MAXE>
+__device__ inline void pipe_prefetch(const cplx<T>* __restrict__ psi, const StageGeom& g, const uint32_t* offhi,
+                                     uint32_t base, const RunPlan<MAXE>& rp, cplx<T> (&buf)[MAXE]) {
+#pragma unroll
+    for (int j = 0; j < MAXE; ++j)
+        if (uint32_t(j) < rp.cnt) buf[j] = psi[base + offhi[rp.gr + uint32_t(j) * rp.G] + rp.o];
+}
+
+template <typename T, int D, int M, int MAXE>
+__global__ __launch_bounds__(kSB) void k_stage_pipe(cplx<T>* __restrict__ psi, StageGeom g,
+                                                    const RoundDesc* __restrict__ rounds, int nrounds,
+                                                    const StageOp* __restrict__ ops,
+                                                    const cplx<T>* __restrict__ mats0, size_t mat_stride,
+                                                    uint32_t total) {
+    constexpr int DM = cpow(D, M);
+    extern __shared__ unsigned char smem[];
+    cplx<T>* tile = reinterpret_cast<cplx<T>*>(smem);
+    __shared__ uint32_t offhi[kMaxHi];
+    build_offhi<D>(g, offhi);
+    RunPlan<MAXE> rp;
+    rp.G = kSB / g.R;
+    rp.gr = threadIdx.x / g.R;
+    rp.o = threadIdx.x - rp.gr * g.R;
+    rp.cnt = rp.gr < rp.G && rp.gr < g.nhi ? (g.nhi - rp.gr + rp.G - 1) / rp.G : 0;
+    __syncthreads();
+    cplx<T> buf[MAXE];
+    uint32_t t = blockIdx.x;
+    if (t < total) pipe_prefetch<T, MAXE>(psi, g, offhi, tile_base<D>(g, t), rp, buf);
+    const uint32_t nsub = g.TE / DM;
+    for (; t < total; t += gridDim.x) {
+        const uint32_t base = tile_base<D>(g, t);
+        const cplx<T>* mats = mats0 + size_t(t / g.ntiles) * mat_stride;
+        lds_barrier();  // the previous tile's stores have read LDS
+#pragma unroll
+        for (int j = 0; j < MAXE; ++j)
+            if (uint32_t(j) < rp.cnt) tile[(rp.gr + uint32_t(j) * rp.G) * g.R + rp.o] = buf[j];
+        lds_barrier();
+        const uint32_t nxt = t + gridDim.x;
+        if (nxt < total) pipe_prefetch<T, MAXE>(psi, g, offhi, tile_base<D>(g, nxt), rp, buf);
+        for (int ri = 0; ri < nrounds; ++ri) {
+            const RoundDesc& rd = rounds[ri];
+            for (uint32_t u = threadIdx.x; u < nsub; u += kSB) {
+                uint32_t tb = 0, uu = u;
+                for (int j = rd.nother - 1; j >= 0; --j) {
+                    const uint32_t q = uu / D;
+                    tb += (uu - q * D) * rd.ols[j];
+                    uu = q;
+                }
+                cplx<T> v[DM];
+#pragma unroll
+                for (int i = 0; i < DM; ++i) v[i] = tile[tb + sub_offset<D, M>(i, rd.gls)];
+                const uint32_t gidx0 = global_index(g, offhi, base, tb);
+                for (int oi = rd.op0; oi < rd.op0 + rd.nops; ++oi) r_apply<T, D, M>(v, ops[oi], mats, gidx0);
+#pragma unroll
+                for (int i = 0; i < DM; ++i) tile[tb + sub_offset<D, M>(i, rd.gls)] = v[i];
+            }
+            lds_barrier();
+        }
+        // store this tile
+        if (rp.gr < rp.G)
+            for (uint32_t h = rp.gr; h < g.nhi; h += rp.G) psi[base + offhi[h] + rp.o] = tile[h * g.R + rp.o];
+    }
+}
+
+// M = sum over the tile's fibres along the op's qudit of psi_f lam_f^dagger,
+// from the LDS tiles, into partial[(slot * nblocks + block) * D*D] (complex
+// FP64).  Lane (entry, part) sums fibres part, part + P, ...; the parts are
+// then added in a fixed order.
+template <typename T, int D>
+__device__ inline void tile_m(const cplx<T>* tp, const cplx<T>* tl, const StageGeom& g, const StageOp& op,
+                              double (*red)[kSB], double* __restrict__ partial) {
+    constexpr int E = D * D;
+    constexpr int P = kSB / E;
+    const uint32_t nf = g.TE / D;
+    const int e = threadIdx.x % E;
+    const int part = threadIdx.x / E;
+    double ar = 0.0, ai = 0.0;
+    if (part < P) {
+        const uint32_t a = uint32_t(e / D), c = uint32_t(e % D);
+        for (uint32_t f = part; f < nf; f += P) {
+            const uint32_t lb = fibre_lb<D>(op, f);
+            const cplx<T> x = tp[lb + a * op.ls];
+            const cplx<T> y = tl[lb + c * op.ls];
+            ar += double(x.re) * double(y.re) + double(x.im) * double(y.im);
+            ai += double(x.im) * double(y.re) - double(x.re) * double(y.im);
+        }
+    }
+    red[0][threadIdx.x] = ar;
+    red[1][threadIdx.x] = ai;
+    __syncthreads();
+    if (int(threadIdx.x) < E) {
+        double sr = 0.0, si = 0.0;
+        for (int q = 0; q < P; ++q) {
+            sr += red[0][q * E + threadIdx.x];
+            si += red[1][q * E + threadIdx.x];
+        }
+        double* o = partial + ((size_t(op.slot) * gridDim.x + blockIdx.x) * E + threadIdx.x) * 2;
+        o[0] = sr;
+        o[1] = si;
+    }
+    __syncthreads();
+}
+
+// Reverse stage in register rounds on psi and lam.  A U that owns an M slot
+// always opens its round, so its M is taken from the LDS tiles before the
+// round's ops run in registers.
+template <typename T, int D, int M>
+__global__ __launch_bounds__(kSB) void k_stage_adj_rounds(cplx<T>* __restrict__ psi, cplx<T>* __restrict__ lam,
+                                                          StageGeom g, const RoundDesc* __restrict__ rounds,
+                                                          int nrounds, const StageOp* __restrict__ ops,
+                                                          const cplx<T>* __restrict__ mats, size_t mat_stride,
+                                                          double* __restrict__ partial) {
+    constexpr int DM = cpow(D, M);
+    mats += size_t(blockIdx.x / g.ntiles) * mat_stride;
+    extern __shared__ unsigned char smem[];
+    cplx<T>* tp = reinterpret_cast<cplx<T>*>(smem);
+    cplx<T>* tl = tp + g.TE;
+    __shared__ uint32_t offhi[kMaxHi];
+    __shared__ double red[2][kSB];
+    const uint32_t base = tile_base<D>(g, blockIdx.x);
+    build_offhi<D>(g, offhi);
+    __syncthreads();
+    tile_load(psi, tp, g, offhi, base);
+    tile_load(lam, tl, g, offhi, base);
+    __syncthreads();
+    const uint32_t nsub = g.TE / DM;
+    for (int ri = 0; ri < nrounds; ++ri) {
+        const RoundDesc& rd = rounds[ri];
+        const StageOp& op0 = ops[rd.op0];
+        if (op0.type == SOP_U && op0.slot >= 0) tile_m<T, D>(tp, tl, g, op0, red, partial);
+        for (uint32_t u = threadIdx.x; u < nsub; u += kSB) {
+            uint32_t tb = 0, uu = u;
+            for (int j = rd.nother - 1; j >= 0; --j) {
+                const uint32_t q = uu / D;
+                tb += (uu - q * D) * rd.ols[j];
+                uu = q;
+            }
+            cplx<T> vp[DM], vl[DM];
+#pragma unroll
+            for (int i = 0; i < DM; ++i) {
+                vp[i] = tp[tb + sub_offset<D, M>(i, rd.gls)];
+                vl[i] = tl[tb + sub_offset<D, M>(i, rd.gls)];
+            }
+            const uint32_t gidx0 = global_index(g, offhi, base, tb);
+            for (int oi = rd.op0; oi < rd.op0 + rd.nops; ++oi) {
+                r_apply<T, D, M>(vp, ops[oi], mats, gidx0);
+                r_apply<T, D, M>(vl, ops[oi], mats, gidx0);
+            }
+#pragma unroll
+            for (int i = 0; i < DM; ++i) {
+                tp[tb + sub_offset<D, M>(i, rd.gls)] = vp[i];
+                tl[tb + sub_offset<D, M>(i, rd.gls)] = vl[i];
+            }
+        }
+        __syncthreads();
+    }
+    tile_store(psi, tp, g, offhi, base);
+    tile_store(lam, tl, g, offhi, base);
+}
+
 template <class F>
 qf_status with_dim_s(uint32_t D, F&& f) {
     switch (D) {
@@ -592,6 +801,61 @@ static qf_status launch_rounds_m(const StateView& s, const StageGeom& g, const R
     return check_launch("stage rounds");
 }
 
+template <typename T, int D, int M>
+static qf_status launch_pipe_m(const StateView& s, const StageGeom& g, const RoundDesc* drounds, int nrounds,
+                               const StageOp* dops, const void* dmats, size_t mat_stride, int wgs_per_cu,
+                               hipStream_t st) {
+    const uint32_t total = g.ntiles * s.batch;
+    const uint32_t cap = 256u * uint32_t(wgs_per_cu);
+    const uint32_t grid = total < cap ? total : cap;
+    const size_t lds = stage_lds_bytes(g, s.dtype, false);
+    const uint32_t G = kSB / g.R;
+    const uint32_t per = (g.nhi + G - 1) / G;
+    if (per <= 8)
+        hipLaunchKernelGGL((k_stage_pipe<T, D, M, 8>), dim3(grid), dim3(kSB), lds, st,
+                           reinterpret_cast<cplx<T>*>(s.amps), g, drounds, nrounds, dops,
+                           reinterpret_cast<const cplx<T>*>(dmats), mat_stride, total);
+    else if (per <= 16)
+        hipLaunchKernelGGL((k_stage_pipe<T, D, M, 16>), dim3(grid), dim3(kSB), lds, st,
+                           reinterpret_cast<cplx<T>*>(s.amps), g, drounds, nrounds, dops,
+                           reinterpret_cast<const cplx<T>*>(dmats), mat_stride, total);
+    else
+        hipLaunchKernelGGL((k_stage_pipe<T, D, M, 32>), dim3(grid), dim3(kSB), lds, st,
+                           reinterpret_cast<cplx<T>*>(s.amps), g, drounds, nrounds, dops,
+                           reinterpret_cast<const cplx<T>*>(dmats), mat_stride, total);
+    return check_launch("stage (pipelined)");
+}
+
+bool stage_pipe_ok(const StageGeom& g) {
+    if (g.R >= uint32_t(kSB)) return false;
+    const uint32_t G = kSB / g.R;
+    return (g.nhi + G - 1) / G <= 32;
+}
+
+qf_status launch_stage_pipe(const StateView& s, int M, const StageGeom& g, const RoundDesc* drounds, int nrounds,
+                            const StageOp* dops, const void* dmats, int wgs_per_cu, hipStream_t st,
+                            size_t mat_stride) {
+    return with_dim_s(s.D, [&](auto dtag) -> qf_status {
+        constexpr int D = decltype(dtag)::value;
+        auto go = [&](auto tag) -> qf_status {
+            using T = decltype(tag);
+            switch (M) {
+                case 1: return launch_pipe_m<T, D, 1>(s, g, drounds, nrounds, dops, dmats, mat_stride, wgs_per_cu, st);
+                case 2:
+                    if constexpr (D <= 5)
+                        return launch_pipe_m<T, D, 2>(s, g, drounds, nrounds, dops, dmats, mat_stride, wgs_per_cu, st);
+                    break;
+                case 3:
+                    if constexpr (D <= 3)
+                        return launch_pipe_m<T, D, 3>(s, g, drounds, nrounds, dops, dmats, mat_stride, wgs_per_cu, st);
+                    break;
+            }
+            return set_error(QF_EUNSUPPORTED, "pipelined stage with a group of %d qudits for D = %d", M, D);
+        };
+        return s.dtype == QF_C64 ? go(float{}) : go(double{});
+    });
+}
+
 qf_status launch_stage_rounds(const StateView& s, int M, const StageGeom& g, const RoundDesc* drounds, int nrounds,
                               const StageOp* dops, const void* dmats, hipStream_t st, size_t mat_stride) {
     return with_dim_s(s.D, [&](auto dtag) -> qf_status {
@@ -610,6 +874,41 @@ qf_status launch_stage_rounds(const StateView& s, int M, const StageGeom& g, con
                         break;
             }
             return set_error(QF_EUNSUPPORTED, "register group of %d qudits for D = %d", M, D);
+        };
+        return s.dtype == QF_C64 ? go(float{}) : go(double{});
+    });
+}
+
+template <typename T, int D, int M>
+static qf_status launch_adj_rounds_m(const StateView& s, void* lam, const StageGeom& g, const RoundDesc* drounds,
+                                     int nrounds, const StageOp* dops, const void* dmats, double* partial,
+                                     size_t mat_stride, hipStream_t st) {
+    const uint32_t grid = g.ntiles * s.batch;
+    const size_t lds = stage_lds_bytes(g, s.dtype, true);
+    hipLaunchKernelGGL((k_stage_adj_rounds<T, D, M>), dim3(grid), dim3(kSB), lds, st,
+                       reinterpret_cast<cplx<T>*>(s.amps), reinterpret_cast<cplx<T>*>(lam), g, drounds, nrounds, dops,
+                       reinterpret_cast<const cplx<T>*>(dmats), mat_stride, partial);
+    return check_launch("stage adjoint rounds");
+}
+
+qf_status launch_stage_adj_rounds(const StateView& s, void* lam, int M, const StageGeom& g, const RoundDesc* drounds,
+                                  int nrounds, const StageOp* dops, const void* dmats, double* partial, hipStream_t st,
+                                  size_t mat_stride) {
+    return with_dim_s(s.D, [&](auto dtag) -> qf_status {
+        constexpr int D = decltype(dtag)::value;
+        auto go = [&](auto tag) -> qf_status {
+            using T = decltype(tag);
+            switch (M) {
+                case 1:
+                    return launch_adj_rounds_m<T, D, 1>(s, lam, g, drounds, nrounds, dops, dmats, partial, mat_stride,
+                                                        st);
+                case 2:
+                    if constexpr (D <= 5)
+                        return launch_adj_rounds_m<T, D, 2>(s, lam, g, drounds, nrounds, dops, dmats, partial,
+                                                            mat_stride, st);
+                    break;
+            }
+            return set_error(QF_EUNSUPPORTED, "adjoint register group of %d qudits for D = %d", M, D);
         };
         return s.dtype == QF_C64 ? go(float{}) : go(double{});
     });

@@ -762,10 +762,11 @@ static Mat group_matrix(const qf_plan* p, const std::vector<GRef>& g, const doub
 // Register rounds of a forward tile pass: consecutive ops are grouped while the
 // qudits they act on (targets of U and SHIFT) fit in a group of M tile qudits;
 // the group is padded with the most significant unused tile qudits.
-static void build_rounds(const qf_plan* p, Pass& ps, PassList& L, const std::vector<int>& dim_of, size_t& moff) {
+static void build_rounds(const qf_plan* p, Pass& ps, PassList& L, const std::vector<int>& dim_of, size_t& moff,
+                         bool adjoint) {
     const int D = p->D;
     const int k = int(ps.geom.k);
-    const int M = p->group;
+    const int M = adjoint ? std::min(p->group, 2) : p->group;
     ps.nrounds = 0;
     ps.round_off = int(L.hrounds.size());
     if (k < M || ps.ops.empty()) return;
@@ -775,6 +776,8 @@ static void build_rounds(const qf_plan* p, Pass& ps, PassList& L, const std::vec
         std::vector<int> grp;
         size_t j = i;
         for (; j < ps.ops.size(); ++j) {
+            // adjoint: a U that owns an M slot opens its own round
+            if (adjoint && j > i && ps.ops[j].type == SOP_U && L.hops[ps.op_off + j].slot >= 0) break;
             const int d = target_dim(ps.ops[j]);
             if (d < 0 || std::find(grp.begin(), grp.end(), d) != grp.end()) continue;
             if (int(grp.size()) == M) break;
@@ -888,7 +891,7 @@ static void finalize_passes(const qf_plan* p, PassList& L, bool adjoint) {
             L.hops.push_back(so);
         }
         ps.nops = int(ps.ops.size());
-        if (!adjoint) build_rounds(p, ps, L, dim_of, moff);
+        build_rounds(p, ps, L, dim_of, moff, adjoint);
         ps.nmat = moff;
         L.nmats += moff;
     }
@@ -1032,6 +1035,20 @@ static qf_status ensure_ckpt(qf_plan* p, const StateView& v) {
     return QF_OK;
 }
 
+// One forward tile pass with the kernel the options select (register rounds,
+// pipelined rounds or one sweep per op).
+static qf_status launch_forward_pass(const qf_plan* p, const PassList& L, const Pass& ps, const StateView& v,
+                                     const void* mats, size_t mat_stride, hipStream_t st) {
+    const int kern = p->opts.stage_kernel;
+    if (ps.nrounds > 0 && kern == 2 && p->group <= 3 && stage_pipe_ok(ps.geom))
+        return launch_stage_pipe(v, p->group, ps.geom, L.drounds + ps.round_off, ps.nrounds, L.dops + ps.op_off, mats,
+                                 p->opts.pipe_wgs > 0 ? p->opts.pipe_wgs : 4, st, mat_stride);
+    if (ps.nrounds > 0 && kern != 1)
+        return launch_stage_rounds(v, p->group, ps.geom, L.drounds + ps.round_off, ps.nrounds, L.dops + ps.op_off,
+                                   mats, st, mat_stride);
+    return launch_stage(v, ps.geom, L.dops + ps.op_off, ps.nops, mats, st, mat_stride);
+}
+
 static qf_status run_tile_pass(qf_plan* p, const PassList& L, const Pass& ps, const StateView& v, void* lam,
                                double* partial, hipStream_t st) {
     const size_t esz = p->dtype == QF_C64 ? 8 : 16;
@@ -1039,14 +1056,14 @@ static qf_status run_tile_pass(qf_plan* p, const PassList& L, const Pass& ps, co
     hipEvent_t a;
     QF_CHECK(prof_begin(p, st, &a));
     if (lam == nullptr) {
-        if (ps.nrounds > 0 && p->opts.stage_kernel == 0)
-            QF_CHECK(launch_stage_rounds(v, p->group, ps.geom, L.drounds + ps.round_off, ps.nrounds,
-                                         L.dops + ps.op_off, mats, st));
-        else
-            QF_CHECK(launch_stage(v, ps.geom, L.dops + ps.op_off, ps.nops, mats, st));
+        QF_CHECK(launch_forward_pass(p, L, ps, v, mats, 0, st));
         QF_CHECK(prof_end(p, st, a, F_STAGE, 2.0 * state_bytes(v)));
     } else {
-        QF_CHECK(launch_stage_adj(v, lam, ps.geom, L.dops + ps.op_off, ps.nops, mats, partial, st));
+        if (ps.nrounds > 0 && p->opts.stage_kernel != 1)
+            QF_CHECK(launch_stage_adj_rounds(v, lam, std::min(p->group, 2), ps.geom, L.drounds + ps.round_off,
+                                             ps.nrounds, L.dops + ps.op_off, mats, partial, st));
+        else
+            QF_CHECK(launch_stage_adj(v, lam, ps.geom, L.dops + ps.op_off, ps.nops, mats, partial, st));
         QF_CHECK(prof_end(p, st, a, F_STAGE_ADJ, 4.0 * state_bytes(v)));
     }
     return QF_OK;
@@ -1138,7 +1155,8 @@ qf_status qf_plan_create(int32_t dim, int32_t n, int32_t dtype, const qf_op* ops
     p->group = p->opts.group_digits > 0 ? p->opts.group_digits : default_group(dim, dtype);
     QF_RETURN_IF(p->opts.tile_digits < 0 || p->opts.tile_digits > kMaxTileDims || p->opts.adj_tile_digits < 0 ||
                      p->opts.adj_tile_digits > kMaxTileDims || p->opts.low_digits < 0 || p->opts.ckpt_every < 0 ||
-                     p->opts.stage_kernel < 0 || p->opts.stage_kernel > 1,
+                     p->opts.stage_kernel < 0 || p->opts.stage_kernel > 2 || p->opts.pipe_wgs < 0 ||
+                     p->opts.pipe_wgs > 16,
                  QF_EINVAL, "bad tile / checkpoint options");
     p->gates.resize(nops);
     for (int i = 0; i < nops; ++i) {
@@ -1519,6 +1537,16 @@ qf_status qf_plan_autotune(qf_plan* plan, const qf_state* s, const double* theta
             o.tile_digits = k;
             o.stage_kernel = 1;
             cand.push_back(o);
+            for (int g = 1; g <= std::min(gmax, 3); ++g)
+                for (int w : {2, 4, 8}) {
+                    qf_plan_opts q = plan->opts;
+                    q.fuse = 0;
+                    q.tile_digits = k;
+                    q.group_digits = g;
+                    q.stage_kernel = 2;
+                    q.pipe_wgs = w;
+                    cand.push_back(q);
+                }
         }
         if (plan->D * plan->D >= 16) {
             qf_plan_opts o = plan->opts;
@@ -1714,11 +1742,7 @@ qf_status qf_plan_forward_dev(qf_plan* plan, const qf_state* s, const double* th
         const Pass& ps = L.passes[i];
         if (ps.tile) {
             const void* mats = reinterpret_cast<const unsigned char*>(L.dmats_b) + ps.mat_off * esz;
-            if (ps.nrounds > 0 && plan->opts.stage_kernel == 0)
-                QF_CHECK(launch_stage_rounds(v, plan->group, ps.geom, L.drounds + ps.round_off, ps.nrounds,
-                                             L.dops + ps.op_off, mats, st, L.nmats));
-            else
-                QF_CHECK(launch_stage(v, ps.geom, L.dops + ps.op_off, ps.nops, mats, st, L.nmats));
+            QF_CHECK(launch_forward_pass(plan, L, ps, v, mats, L.nmats, st));
         } else {
             const Gate& g = plan->gates[ps.fused.gi];
             QF_CHECK(launch_fused(v, g.op.q1, g.op.q0, g.dmat, st, g.real));
@@ -1765,8 +1789,13 @@ qf_status qf_adjoint_grad_dev(qf_plan* plan, const qf_state* psi, const qf_state
                                         hipMemcpyDeviceToDevice, st));
         if (ps.tile) {
             const void* mats = reinterpret_cast<const unsigned char*>(L.dmats_b) + ps.mat_off * esz;
-            QF_CHECK(launch_stage_adj(v, lam->amps, ps.geom, L.dops + ps.op_off, ps.nops, mats, plan->w_partial, st,
-                                      L.nmats));
+            if (ps.nrounds > 0 && plan->opts.stage_kernel != 1)
+                QF_CHECK(launch_stage_adj_rounds(v, lam->amps, std::min(plan->group, 2), ps.geom,
+                                                 L.drounds + ps.round_off, ps.nrounds, L.dops + ps.op_off, mats,
+                                                 plan->w_partial, st, L.nmats));
+            else
+                QF_CHECK(launch_stage_adj(v, lam->amps, ps.geom, L.dops + ps.op_off, ps.nops, mats, plan->w_partial,
+                                          st, L.nmats));
             QF_CHECK(launch_stage_mreduce(plan->w_partial, ps.nslots, ps.geom.ntiles, v.batch, uint32_t(E), plan->w_m,
                                           uint32_t(L.nslots), uint32_t(ps.slot0), st));
         } else {

@@ -131,6 +131,17 @@ qf_status launch_stage_rounds(const StateView& s, int M, const StageGeom& g, con
 // into partial[(slot * nblocks + block) * D*D] (complex FP64).
 qf_status launch_stage_adj(const StateView& s, void* lam, const StageGeom& g, const StageOp* dops, int nops,
                            const void* dmats, double* partial, hipStream_t st, size_t mat_stride = 0);
+// Pipelined persistent forward stage (register rounds, M <= 3): grid of at most
+// 256 * wgs_per_cu workgroups; needs stage_pipe_ok(g) (runs shorter than a
+// workgroup, at most 32 runs per lane).
+bool stage_pipe_ok(const StageGeom& g);
+qf_status launch_stage_pipe(const StateView& s, int M, const StageGeom& g, const RoundDesc* drounds, int nrounds,
+                            const StageOp* dops, const void* dmats, int wgs_per_cu, hipStream_t st,
+                            size_t mat_stride = 0);
+// Reverse stage in register rounds (M in {1, 2}); a U owning an M slot opens its round.
+qf_status launch_stage_adj_rounds(const StateView& s, void* lam, int M, const StageGeom& g, const RoundDesc* drounds,
+                                  int nrounds, const StageOp* dops, const void* dmats, double* partial, hipStream_t st,
+                                  size_t mat_stride = 0);
 // mout[(b * nslots_total + slot0 + j) * E] = sum over the tiles of register b of
 // partial[j], for j < nslots (fixed order).
 qf_status launch_stage_mreduce(const double* partial, uint32_t nslots, uint32_t ntiles, uint32_t batch, uint32_t E,

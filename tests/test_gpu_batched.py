@@ -47,14 +47,15 @@ def test_bound_mode_shared_theta(qf, make, dt):
     assert abs(lv[0] - measure.expect_diag(want, c.dim, c.n, terms).real) <= 1e-5
 
 
-def test_bound_mode_per_register_theta_and_checkpoints(qf):
+@pytest.mark.parametrize("kernel", [0, 2])
+def test_bound_mode_per_register_theta_and_checkpoints(qf, kernel):
     import torch
     c = qi.config2(n=5, layers=3)
     terms = qi.zsum_terms(c.n)
     B = 3
     rng = np.random.default_rng(9)
     thetas = rng.uniform(-np.pi, np.pi, size=(B, c.nparams))
-    p = qf.plan_for(c, "c64", ckpt_every=40)
+    p = qf.plan_for(c, "c64", ckpt_every=40, stage_kernel=kernel, tile_digits=3, pipe_wgs=1)
     p.bind(B)
     th = torch.tensor(thetas, dtype=torch.float64, device="cuda")
     t = qf.new_state(c.n, c.dim, "c64", batch=B)

@@ -40,7 +40,7 @@ CIRCUITS = [
 
 
 @pytest.mark.parametrize("name,make,dt", CIRCUITS, ids=[c[0] for c in CIRCUITS])
-@pytest.mark.parametrize("fuse,kernel", [(0, 0), (0, 1), (1, 0), (2, 0), (3, 0)])
+@pytest.mark.parametrize("fuse,kernel", [(0, 0), (0, 1), (0, 2), (1, 0), (2, 0), (3, 0)])
 def test_plan_forward_matches_oracle(qf, name, make, dt, fuse, kernel):
     c = make()
     _, t = run_gpu(qf, c, dt, fuse=fuse, stage_kernel=kernel)
@@ -52,7 +52,7 @@ TILES = [(3, 1), (3, 2), (4, 2), (5, 3), (2, 1)]
 
 
 @pytest.mark.parametrize("tile,low", TILES)
-@pytest.mark.parametrize("kernel,group", [(0, 0), (0, 1), (0, 9), (1, 0)])
+@pytest.mark.parametrize("kernel,group", [(0, 0), (0, 1), (0, 9), (1, 0), (2, 0), (2, 1), (2, 9)])
 def test_stage_tiles_small(qf, tile, low, kernel, group):
     """Small tiles force many passes, controls outside the tile and deferred gates;
     kernel 0 = register rounds (group 9 = the largest group compiled for D),
@@ -61,6 +61,8 @@ def test_stage_tiles_small(qf, tile, low, kernel, group):
                   (qi.config3(n=5, layers=2), "c64"), (qi.random_circuit(4, 5, 150, 22), "c64"),
                   (qi.random_circuit(2, 9, 200, 23), "c64"), (qi.random_circuit(7, 4, 100, 24), "c64")):
         gmax = {2: 5, 3: 3, 4: 2, 5: 2}.get(c.dim, 1)
+        if kernel == 2:
+            gmax = min(gmax, 3)
         p, t = run_gpu(qf, c, dt, tile_digits=min(tile, c.n), low_digits=low, stage_kernel=kernel,
                        group_digits=min(group, gmax))
         assert p.num_stages >= 1
