@@ -14,6 +14,7 @@
 //              any qudit, inside or outside the tile.  Pure data movement.
 //   SOP_PHASE  product of two-qudit diagonal factors table[x_a * D + x_b]; the
 //              digits come from the global index, so a and b may be any qudits.
+#include <algorithm>
 #include <type_traits>
 
 #include "qf_internal.h"
@@ -29,6 +30,23 @@ constexpr int kSB = 256;
 // the next tile's loads in flight across these barriers).  The memory clobber
 // keeps the compiler from moving memory accesses across it.
 __device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Logical tile (register-major) of this workgroup.  Workgroups are dispatched
+// round-robin over the 8 XCDs, each with its own L2; with g.xcd set, this
+// bijection of [0, gridDim.x) hands every XCD a contiguous range of tiles, so
+// neighbouring tiles (whose runs share cache lines when runs are short) go
+// through the same L2 at about the same time.
+constexpr uint32_t kXCD = 8;
+
+__device__ inline uint32_t xcd_range_start(uint32_t x, uint32_t total) {
+    const uint32_t q = total / kXCD, rem = total % kXCD;
+    return x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q;
+}
+
+__device__ inline uint32_t tile_of_block(const StageGeom& g) {
+    if (!g.xcd) return blockIdx.x;
+    return xcd_range_start(blockIdx.x % kXCD, gridDim.x) + blockIdx.x / kXCD;
+}
 
 template <int D>
 __device__ inline uint32_t tile_base(const StageGeom& g, uint32_t blk) {
@@ -221,11 +239,12 @@ template <typename T, int D>
 __global__ __launch_bounds__(kSB) void k_stage(cplx<T>* __restrict__ psi, StageGeom g,
                                                const StageOp* __restrict__ ops, int nops,
                                                const cplx<T>* __restrict__ mats, size_t mat_stride) {
-    mats += size_t(blockIdx.x / g.ntiles) * mat_stride;  // per-register matrices (stride 0: shared)
+    const uint32_t blk = tile_of_block(g);
+    mats += size_t(blk / g.ntiles) * mat_stride;  // per-register matrices (stride 0: shared)
     extern __shared__ unsigned char smem[];
     cplx<T>* tile = reinterpret_cast<cplx<T>*>(smem);
-    __shared__ uint32_t offhi[kMaxHi];
-    const uint32_t base = tile_base<D>(g, blockIdx.x);
+    uint32_t* offhi = reinterpret_cast<uint32_t*>(tile + g.TE);
+    const uint32_t base = tile_base<D>(g, blk);
     build_offhi<D>(g, offhi);
     __syncthreads();
     tile_load(psi, tile, g, offhi, base);
@@ -258,16 +277,17 @@ __global__ __launch_bounds__(kSB) void k_stage_adj(cplx<T>* __restrict__ psi, cp
                                                    StageGeom g, const StageOp* __restrict__ ops, int nops,
                                                    const cplx<T>* __restrict__ mats, size_t mat_stride,
                                                    double* __restrict__ partial) {
-    mats += size_t(blockIdx.x / g.ntiles) * mat_stride;
+    const uint32_t blk = tile_of_block(g);
+    mats += size_t(blk / g.ntiles) * mat_stride;
     extern __shared__ unsigned char smem[];
     cplx<T>* tp = reinterpret_cast<cplx<T>*>(smem);
     cplx<T>* tl = tp + g.TE;
-    __shared__ uint32_t offhi[kMaxHi];
+    uint32_t* offhi = reinterpret_cast<uint32_t*>(tl + g.TE);
     __shared__ double red[2][kSB];
     constexpr int E = D * D;
     constexpr int P = kSB / E;
     const uint32_t nblocks = gridDim.x;
-    const uint32_t base = tile_base<D>(g, blockIdx.x);
+    const uint32_t base = tile_base<D>(g, blk);
     build_offhi<D>(g, offhi);
     __syncthreads();
     tile_load(psi, tp, g, offhi, base);
@@ -300,7 +320,7 @@ __global__ __launch_bounds__(kSB) void k_stage_adj(cplx<T>* __restrict__ psi, cp
                         sr += red[0][p * E + threadIdx.x];
                         si += red[1][p * E + threadIdx.x];
                     }
-                    double* o = partial + ((size_t(op.slot) * nblocks + blockIdx.x) * E + threadIdx.x) * 2;
+                    double* o = partial + ((size_t(op.slot) * nblocks + blk) * E + threadIdx.x) * 2;
                     o[0] = sr;
                     o[1] = si;
                 }
@@ -369,6 +389,12 @@ __global__ __launch_bounds__(kSB) void k_stage_mreduce(const double* __restrict_
 // Register rounds.  Register index i of a lane's sub-tile has digits
 // (i_0, ..., i_{M-1}) (i_0 most significant); digit j belongs to the round's
 // j-th group qudit.  All register indices are compile-time constants.
+//
+// A round loads every lane's sub-tile from LDS, applies its in-place ops (U on
+// any group position, PHASE) in registers and stores the sub-tile back.  A
+// round may also carry permutation ops (SHIFT): they move data only, so they
+// are folded into the LDS addresses of the loads (before the in-place ops) or
+// of the stores (after them) and cost no register moves (load_addrs).
 // ---------------------------------------------------------------------------
 
 constexpr int cpow(int b, int e) { return e == 0 ? 1 : b * cpow(b, e - 1); }
@@ -378,59 +404,48 @@ __device__ constexpr int rdigit(int i) {
     return (i / cpow(D, M - 1 - J)) % D;
 }
 
-template <typename T, int D, int M, int J>
-__device__ inline void r_u(cplx<T> (&v)[cpow(D, M)], const cplx<T>* __restrict__ U, bool real) {
+// U on group position J: every fibre along J (digits of the other positions
+// fixed) is multiplied by U.  The matrix is uniform and held in scalar
+// registers; REAL uses only its real parts.
+template <typename T, int D, int M, int J, bool REAL>
+__device__ __forceinline__ void r_u(cplx<T> (&v)[cpow(D, M)], const cplx<T>* __restrict__ U) {
     constexpr int SJ = cpow(D, M - 1 - J);
     constexpr int NF = cpow(D, M - 1);
+    cplx<T> m[D * D];
+#pragma unroll
+    for (int e = 0; e < D * D; ++e) m[e] = U[e];
 #pragma unroll
     for (int c = 0; c < NF; ++c) {
         const int b0 = (c / SJ) * SJ * D + (c % SJ);
-        cplx<T> x[D], y[D];
+        cplx<T> y[D];
 #pragma unroll
-        for (int d = 0; d < D; ++d) x[d] = v[b0 + d * SJ];
-        matvec<T, D>(U, real, x, y);
+        for (int a = 0; a < D; ++a) {
+            if constexpr (REAL) {
+                T re = 0, im = 0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    re = fma(m[a * D + d].re, v[b0 + d * SJ].re, re);
+                    im = fma(m[a * D + d].re, v[b0 + d * SJ].im, im);
+                }
+                y[a] = cmake<T>(re, im);
+            } else {
+                cplx<T> acc = cmake<T>(0, 0);
+#pragma unroll
+                for (int d = 0; d < D; ++d) cmac(acc, m[a * D + d], v[b0 + d * SJ]);
+                y[a] = acc;
+            }
+        }
 #pragma unroll
         for (int d = 0; d < D; ++d) v[b0 + d * SJ] = y[d];
     }
 }
 
-// rotate x[b] <- x[(b - s) mod D] (barrel of compile-time rotations)
-template <typename T, int D>
-__device__ inline void rotate(cplx<T> (&x)[D], int s) {
-#pragma unroll
-    for (int bit = 1; bit < D; bit <<= 1) {
-        const bool on = (s & bit) != 0;
-        cplx<T> w[D];
-#pragma unroll
-        for (int b = 0; b < D; ++b) w[b] = x[(b - bit % D + D) % D];
-#pragma unroll
-        for (int b = 0; b < D; ++b) {
-            x[b].re = on ? w[b].re : x[b].re;
-            x[b].im = on ? w[b].im : x[b].im;
-        }
-    }
-}
-
-template <typename T, int D, int M, int J, int CJ>
-__device__ inline void r_shift(cplx<T> (&v)[cpow(D, M)], const StageOp& op, int s_thread) {
-    constexpr int SJ = cpow(D, M - 1 - J);
-    constexpr int NF = cpow(D, M - 1);
-#pragma unroll
-    for (int c = 0; c < NF; ++c) {
-        const int b0 = (c / SJ) * SJ * D + (c % SJ);
-        int s;
-        if constexpr (CJ >= 0) {
-            s = op.shifts[rdigit<D, M, CJ>(b0)];
-        } else {
-            s = s_thread;
-        }
-        cplx<T> x[D];
-#pragma unroll
-        for (int d = 0; d < D; ++d) x[d] = v[b0 + d * SJ];
-        rotate<T, D>(x, s);
-#pragma unroll
-        for (int d = 0; d < D; ++d) v[b0 + d * SJ] = x[d];
-    }
+template <typename T, int D, int M, int J>
+__device__ __forceinline__ void r_u_any(cplx<T> (&v)[cpow(D, M)], const cplx<T>* __restrict__ U, bool real) {
+    if (real)
+        r_u<T, D, M, J, true>(v, U);
+    else
+        r_u<T, D, M, J, false>(v, U);
 }
 
 // CZ factors multiply amplitude x by w^e(x) with e(x) = sum over factors of
@@ -439,7 +454,7 @@ __device__ inline void r_shift(cplx<T> (&v)[cpow(D, M)], const StageOp& op, int 
 //   e = e0 + sum_j lin_j d_j + sum_{j<l} quad_jl d_j d_l,
 // whose coefficients are accumulated once per sub-tile.
 template <typename T, int D, int M>
-__device__ inline void r_phase(cplx<T> (&v)[cpow(D, M)], const StageOp& op, const cplx<T>* __restrict__ mats,
+__device__ __forceinline__ void r_phase(cplx<T> (&v)[cpow(D, M)], const StageOp& op, const cplx<T>* __restrict__ mats,
                                uint32_t gidx0) {
     constexpr int DM = cpow(D, M);
     int e0 = 0;
@@ -479,57 +494,246 @@ __device__ inline void r_phase(cplx<T> (&v)[cpow(D, M)], const StageOp& op, cons
     }
 }
 
-template <typename T, int D, int M, int J>
-__device__ inline void r_shift_dispatch(cplx<T> (&v)[cpow(D, M)], const StageOp& op, int s_thread) {
-    switch (op.ctrl_gpos) {
-        case 0: if constexpr (M > 0 && J != 0) r_shift<T, D, M, J, 0>(v, op, s_thread); break;
-        case 1: if constexpr (M > 1 && J != 1) r_shift<T, D, M, J, 1>(v, op, s_thread); break;
-        case 2: if constexpr (M > 2 && J != 2) r_shift<T, D, M, J, 2>(v, op, s_thread); break;
-        case 3: if constexpr (M > 3 && J != 3) r_shift<T, D, M, J, 3>(v, op, s_thread); break;
-        case 4: if constexpr (M > 4 && J != 4) r_shift<T, D, M, J, 4>(v, op, s_thread); break;
-        default: r_shift<T, D, M, J, -1>(v, op, s_thread); break;
+// LDS offset of register i over group positions 1 .. M-1.
+template <int D, int M>
+__device__ __forceinline__ uint32_t rest_offset(int i, const uint32_t* gls) {
+    uint32_t o = 0;
+#pragma unroll
+    for (int j = 1; j < M; ++j) o += uint32_t((i / cpow(D, M - 1 - j)) % D) * gls[j];
+    return o;
+}
+
+// (d + s) mod D for d, s in [0, D)
+template <int D>
+__device__ __forceinline__ uint32_t add_mod(uint32_t d, uint32_t s) {
+    const uint32_t t = d + s;
+    return t >= uint32_t(D) ? t - uint32_t(D) : t;
+}
+
+// LDS offset of register i over group positions 2 .. M-1.
+template <int D, int M>
+__device__ __forceinline__ uint32_t rest2_offset(int i, const uint32_t* gls) {
+    uint32_t o = 0;
+#pragma unroll
+    for (int j = 2; j < M; ++j) o += uint32_t((i / cpow(D, M - 1 - j)) % D) * gls[j];
+    return o;
+}
+
+// Shift of a permutation op whose control is not a group qudit: one value per
+// lane (the control digit is constant over the sub-tile), or shifts[0] when
+// the op has no control.
+template <int D>
+__device__ __forceinline__ uint32_t lane_shift(const StageOp& P, uint32_t gidx0) {
+    uint32_t sh = uint32_t(P.shifts[0]);
+    if (P.has_ctrl) {
+        const uint32_t xc = P.ctrl_stride.div(gidx0) % D;
+#pragma unroll
+        for (int c = 1; c < D; ++c) sh = xc == uint32_t(c) ? uint32_t(P.shifts[c]) : sh;
     }
+    return sh;
+}
+
+template <int D>
+__device__ __forceinline__ uint32_t neg_mod(uint32_t s) {
+    return s == 0 ? 0u : uint32_t(D) - s;
+}
+
+// Permutation ops of a round (each x_t -> x_t + shifts[x_c] mod D):
+//   pre0  target group position 0, control position 1, per lane or none;
+//   pre1  target position 1, control position 0;
+//   post  target position 0, control position 1, per lane or none.
+// pre0 then pre1 act before the in-place ops: register (d0, d1) loads the
+// amplitude they bring there, from (d0 - s0, d1 - s1(d0)).  post acts after
+// them: register (d0, d1) stores to (d0 + s(d1), d1).
+template <int D, int M>
+__device__ __forceinline__ void load_addrs(uint32_t (&a)[cpow(D, M)], uint32_t tb, const RoundDesc& rd,
+                                           const StageOp* __restrict__ ops, uint32_t gidx0) {
+    constexpr int DM = cpow(D, M);
+    if constexpr (M >= 2) {
+        if (rd.pre1 >= 0) {
+            const StageOp& B = ops[rd.pre1];
+            uint32_t od[D];
+            const uint32_t s0 = rd.pre0 >= 0 ? neg_mod<D>(lane_shift<D>(ops[rd.pre0], gidx0)) : 0u;
+#pragma unroll
+            for (int d = 0; d < D; ++d) od[d] = add_mod<D>(uint32_t(d), s0) * rd.gls[0];
+#pragma unroll
+            for (int i = 0; i < DM; ++i) {
+                const int d0 = rdigit<D, M, 0>(i);
+                const uint32_t e1 = add_mod<D>(uint32_t(rdigit<D, M, 1>(i)), neg_mod<D>(uint32_t(B.shifts[d0])));
+                a[i] = tb + od[d0] + e1 * rd.gls[1] + rest2_offset<D, M>(i, rd.gls);
+            }
+            return;
+        }
+    }
+    if (rd.pre0 < 0) {
+#pragma unroll
+        for (int i = 0; i < DM; ++i) a[i] = tb + uint32_t(rdigit<D, M, 0>(i)) * rd.gls[0] + rest_offset<D, M>(i, rd.gls);
+        return;
+    }
+    const StageOp& P = ops[rd.pre0];
+    if constexpr (M >= 2) {
+        if (P.ctrl_gpos == 1) {
+#pragma unroll
+            for (int i = 0; i < DM; ++i) {
+                const uint32_t s = neg_mod<D>(uint32_t(P.shifts[rdigit<D, M, 1>(i)]));
+                a[i] = tb + add_mod<D>(uint32_t(rdigit<D, M, 0>(i)), s) * rd.gls[0] + rest_offset<D, M>(i, rd.gls);
+            }
+            return;
+        }
+    }
+    const uint32_t s = neg_mod<D>(lane_shift<D>(P, gidx0));
+    uint32_t od[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) od[d] = add_mod<D>(uint32_t(d), s) * rd.gls[0];
+#pragma unroll
+    for (int i = 0; i < DM; ++i) a[i] = tb + od[rdigit<D, M, 0>(i)] + rest_offset<D, M>(i, rd.gls);
+}
+
+template <int D, int M>
+__device__ __forceinline__ void store_addrs(uint32_t (&a)[cpow(D, M)], uint32_t tb, const RoundDesc& rd,
+                                            const StageOp* __restrict__ ops, uint32_t gidx0) {
+    constexpr int DM = cpow(D, M);
+    if (rd.post < 0) {
+#pragma unroll
+        for (int i = 0; i < DM; ++i) a[i] = tb + uint32_t(rdigit<D, M, 0>(i)) * rd.gls[0] + rest_offset<D, M>(i, rd.gls);
+        return;
+    }
+    const StageOp& P = ops[rd.post];
+    if constexpr (M >= 2) {
+        if (P.ctrl_gpos == 1) {
+#pragma unroll
+            for (int i = 0; i < DM; ++i) {
+                const uint32_t s = uint32_t(P.shifts[rdigit<D, M, 1>(i)]);
+                a[i] = tb + add_mod<D>(uint32_t(rdigit<D, M, 0>(i)), s) * rd.gls[0] + rest_offset<D, M>(i, rd.gls);
+            }
+            return;
+        }
+    }
+    const uint32_t s = lane_shift<D>(P, gidx0);
+    uint32_t od[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) od[d] = add_mod<D>(uint32_t(d), s) * rd.gls[0];
+#pragma unroll
+    for (int i = 0; i < DM; ++i) a[i] = tb + od[rdigit<D, M, 0>(i)] + rest_offset<D, M>(i, rd.gls);
 }
 
 template <typename T, int D, int M>
-__device__ inline void r_apply(cplx<T> (&v)[cpow(D, M)], const StageOp& op, const cplx<T>* __restrict__ mats,
-                               uint32_t gidx0) {
-    if (op.type == SOP_U) {
-        const cplx<T>* U = mats + op.mat;
-        const bool real = op.real != 0;
-        switch (op.gpos) {
-            case 0: r_u<T, D, M, 0>(v, U, real); break;
-            case 1: if constexpr (M > 1) r_u<T, D, M, 1>(v, U, real); break;
-            case 2: if constexpr (M > 2) r_u<T, D, M, 2>(v, U, real); break;
-            case 3: if constexpr (M > 3) r_u<T, D, M, 3>(v, U, real); break;
-            case 4: if constexpr (M > 4) r_u<T, D, M, 4>(v, U, real); break;
+__device__ __forceinline__ void round_ops(cplx<T> (&v)[cpow(D, M)], const RoundDesc& rd, const StageOp* __restrict__ ops,
+                                 const cplx<T>* __restrict__ mats, uint32_t gidx0) {
+    for (int oi = rd.op0; oi < rd.op0 + rd.nops; ++oi) {
+        const StageOp& op = ops[oi];
+        if (op.type == SOP_U) {
+            const cplx<T>* U = mats + op.mat;
+            const bool real = op.real != 0;
+            switch (op.gpos) {
+                case 0: r_u_any<T, D, M, 0>(v, U, real); break;
+                case 1: if constexpr (M > 1) r_u_any<T, D, M, 1>(v, U, real); break;
+                case 2: if constexpr (M > 2) r_u_any<T, D, M, 2>(v, U, real); break;
+                case 3: if constexpr (M > 3) r_u_any<T, D, M, 3>(v, U, real); break;
+                case 4: if constexpr (M > 4) r_u_any<T, D, M, 4>(v, U, real); break;
+            }
+        } else {
+            r_phase<T, D, M>(v, op, mats, gidx0);
         }
-    } else if (op.type == SOP_SHIFT) {
-        int s_thread = op.shifts[0];
-        if (op.has_ctrl && op.ctrl_gpos < 0) {
-            const uint32_t xc = op.ctrl_stride.div(gidx0) % D;
-#pragma unroll
-            for (int a = 1; a < D; ++a) s_thread = (xc == uint32_t(a)) ? op.shifts[a] : s_thread;
-        }
-        switch (op.gpos) {
-            case 0: r_shift_dispatch<T, D, M, 0>(v, op, s_thread); break;
-            case 1: if constexpr (M > 1) r_shift_dispatch<T, D, M, 1>(v, op, s_thread); break;
-            case 2: if constexpr (M > 2) r_shift_dispatch<T, D, M, 2>(v, op, s_thread); break;
-            case 3: if constexpr (M > 3) r_shift_dispatch<T, D, M, 3>(v, op, s_thread); break;
-            case 4: if constexpr (M > 4) r_shift_dispatch<T, D, M, 4>(v, op, s_thread); break;
-        }
-    } else {
-        r_phase<T, D, M>(v, op, mats, gidx0);
     }
 }
 
-// LDS offset of register i of a sub-tile relative to the sub-tile's first element.
-template <int D, int M>
-__device__ inline uint32_t sub_offset(int i, const uint32_t* gls) {
-    uint32_t o = 0;
+// Digits of sub-tile u over the k - M other tile qudits, 4 bits each, least
+// significant digit lowest.
+template <int D>
+__device__ inline uint64_t pack_digits(uint32_t u, int nother) {
+    uint64_t p = 0;
+    for (int j = 0; j < nother; ++j) {
+        const uint32_t q = u / D;
+        p |= uint64_t(u - q * D) << (4 * j);
+        u = q;
+    }
+    return p;
+}
+
+// LDS index of the sub-tile's register 0 in round rd.
+__device__ __forceinline__ uint32_t sub_base(uint64_t digits, const RoundDesc& rd) {
+    uint32_t tb = 0;
+    for (int j = rd.nother - 1; j >= 0; --j) {
+        tb += uint32_t(digits & 15u) * rd.ols[j];
+        digits >>= 4;
+    }
+    return tb;
+}
+
+// One round on the tiles t[0 .. NT) (the adjoint runs psi and lam together).
+// The common round shapes run straight from the LDS loads to the LDS stores
+// (no op dispatch while the sub-tile is live in registers, so no register
+// copies where dispatch paths meet); any other round goes through round_ops.
+template <typename T, int D, int M, int NT>
+__device__ __forceinline__ void run_round(cplx<T>* const (&t)[NT], const StageGeom& g, const uint32_t* offhi,
+                                          uint32_t base, const RoundDesc& rd, const StageOp* __restrict__ ops,
+                                          const cplx<T>* __restrict__ mats, uint64_t dig0) {
+    constexpr int DM = cpow(D, M);
+    const uint32_t nsub = g.TE / DM;
+    const int kind = rd.kind;
+    const cplx<T>* U0 = mats;
+    const cplx<T>* U1 = mats;
+    if (kind == RK_U0 || kind == RK_U0_REAL || kind == RK_U01) {
+        const StageOp& oa = ops[rd.op0];
+        U0 = mats + oa.mat;
+        if (kind == RK_U01) {
+            const StageOp& ob = ops[rd.op0 + 1];
+            U1 = mats + ob.mat;
+            if (oa.gpos != 0) {  // the two U act on different qudits and commute
+                const cplx<T>* x = U0;
+                U0 = U1;
+                U1 = x;
+            }
+        }
+    }
+    for (uint32_t u = threadIdx.x; u < nsub; u += kSB) {
+        const uint64_t dig = u == threadIdx.x ? dig0 : pack_digits<D>(u, rd.nother);
+        const uint32_t tb = sub_base(dig, rd);
+        const uint32_t gidx0 = rd.need_gidx ? global_index(g, offhi, base, tb) : 0u;
+        cplx<T> v[NT][DM];
+        {
+            uint32_t al[DM];
+            load_addrs<D, M>(al, tb, rd, ops, gidx0);
 #pragma unroll
-    for (int j = 0; j < M; ++j) o += uint32_t((i / cpow(D, M - 1 - j)) % D) * gls[j];
-    return o;
+            for (int x = 0; x < NT; ++x)
+#pragma unroll
+                for (int i = 0; i < DM; ++i) v[x][i] = t[x][al[i]];
+        }
+        // each shape stores from its own branch
+        auto store = [&]() {
+            uint32_t as[DM];
+            store_addrs<D, M>(as, tb, rd, ops, gidx0);
+#pragma unroll
+            for (int x = 0; x < NT; ++x)
+#pragma unroll
+                for (int i = 0; i < DM; ++i) t[x][as[i]] = v[x][i];
+        };
+        if (kind == RK_U0) {
+#pragma unroll
+            for (int x = 0; x < NT; ++x) r_u<T, D, M, 0, false>(v[x], U0);
+            store();
+        } else if (kind == RK_U01) {
+            if constexpr (M >= 2) {
+#pragma unroll
+                for (int x = 0; x < NT; ++x) {
+                    r_u<T, D, M, 0, false>(v[x], U0);
+                    r_u<T, D, M, 1, false>(v[x], U1);
+                }
+            }
+            store();
+        } else if (kind == RK_U0_REAL) {
+#pragma unroll
+            for (int x = 0; x < NT; ++x) r_u<T, D, M, 0, true>(v[x], U0);
+            store();
+        } else if (kind == RK_NONE) {
+            store();
+        } else {
+#pragma unroll
+            for (int x = 0; x < NT; ++x) round_ops<T, D, M>(v[x], rd, ops, mats, gidx0);
+            store();
+        }
+    }
 }
 
 template <typename T, int D, int M>
@@ -537,41 +741,27 @@ __global__ __launch_bounds__(kSB) void k_stage_rounds(cplx<T>* __restrict__ psi,
                                                       const RoundDesc* __restrict__ rounds, int nrounds,
                                                       const StageOp* __restrict__ ops,
                                                       const cplx<T>* __restrict__ mats, size_t mat_stride) {
-    mats += size_t(blockIdx.x / g.ntiles) * mat_stride;
-    constexpr int DM = cpow(D, M);
+    const uint32_t blk = tile_of_block(g);
+    mats += size_t(blk / g.ntiles) * mat_stride;
     extern __shared__ unsigned char smem[];
     cplx<T>* tile = reinterpret_cast<cplx<T>*>(smem);
-    __shared__ uint32_t offhi[kMaxHi];
-    const uint32_t base = tile_base<D>(g, blockIdx.x);
+    uint32_t* offhi = reinterpret_cast<uint32_t*>(tile + g.TE);
+    const uint32_t base = tile_base<D>(g, blk);
     build_offhi<D>(g, offhi);
     __syncthreads();
     tile_load(psi, tile, g, offhi, base);
     __syncthreads();
-    const uint32_t nsub = g.TE / DM;
+    const uint64_t dig0 = nrounds > 0 ? pack_digits<D>(threadIdx.x, rounds[0].nother) : 0;
+    cplx<T>* const tl[1] = {tile};
     for (int ri = 0; ri < nrounds; ++ri) {
-        const RoundDesc& rd = rounds[ri];
-        for (uint32_t u = threadIdx.x; u < nsub; u += kSB) {
-            uint32_t tb = 0, uu = u;
-            for (int j = rd.nother - 1; j >= 0; --j) {
-                const uint32_t q = uu / D;
-                tb += (uu - q * D) * rd.ols[j];
-                uu = q;
-            }
-            cplx<T> v[DM];
-#pragma unroll
-            for (int i = 0; i < DM; ++i) v[i] = tile[tb + sub_offset<D, M>(i, rd.gls)];
-            const uint32_t gidx0 = global_index(g, offhi, base, tb);
-            for (int oi = rd.op0; oi < rd.op0 + rd.nops; ++oi) r_apply<T, D, M>(v, ops[oi], mats, gidx0);
-#pragma unroll
-            for (int i = 0; i < DM; ++i) tile[tb + sub_offset<D, M>(i, rd.gls)] = v[i];
-        }
+        run_round<T, D, M, 1>(tl, g, offhi, base, rounds[ri], ops, mats, dig0);
         __syncthreads();
     }
     tile_store(psi, tile, g, offhi, base);
 }
 
-// Pipelined persistent variant: a workgroup walks tiles blockIdx.x,
-// blockIdx.x + gridDim.x, ...; the global loads of the next tile are issued into
+// Pipelined persistent variant: a workgroup walks a strided sequence of
+// tiles; the global loads of the next tile are issued into
 // registers before the current tile's rounds run from LDS, so their latency
 // overlaps the compute and the stores.  Runs are shorter than the workgroup
 // (R < 256): lane (gr, o) handles offset o of runs gr, gr + G, ... (at most
@@ -582,11 +772,15 @@ struct RunPlan {
 };
 
 template <typename T, int MAXE>
-__device__ inline void pipe_prefetch(const cplx<T>* __restrict__ psi, const StageGeom& g, const uint32_t* offhi,
+__device__ __forceinline__ void pipe_prefetch(const cplx<T>* __restrict__ psi, const StageGeom& g, const uint32_t* offhi,
                                      uint32_t base, const RunPlan<MAXE>& rp, cplx<T> (&buf)[MAXE]) {
+    // unpredicated loads (the run index is clamped; surplus values are never
+    // stored) keep buf in registers
 #pragma unroll
-    for (int j = 0; j < MAXE; ++j)
-        if (uint32_t(j) < rp.cnt) buf[j] = psi[base + offhi[rp.gr + uint32_t(j) * rp.G] + rp.o];
+    for (int j = 0; j < MAXE; ++j) {
+        const uint32_t h = min(rp.gr + uint32_t(j) * rp.G, g.nhi - 1);
+        buf[j] = psi[base + offhi[h] + rp.o];
+    }
 }
 
 template <typename T, int D, int M, int MAXE>
@@ -595,10 +789,9 @@ __global__ __launch_bounds__(kSB) void k_stage_pipe(cplx<T>* __restrict__ psi, S
                                                     const StageOp* __restrict__ ops,
                                                     const cplx<T>* __restrict__ mats0, size_t mat_stride,
                                                     uint32_t total) {
-    constexpr int DM = cpow(D, M);
     extern __shared__ unsigned char smem[];
     cplx<T>* tile = reinterpret_cast<cplx<T>*>(smem);
-    __shared__ uint32_t offhi[kMaxHi];
+    uint32_t* offhi = reinterpret_cast<uint32_t*>(tile + g.TE);
     build_offhi<D>(g, offhi);
     RunPlan<MAXE> rp;
     rp.G = kSB / g.R;
@@ -607,36 +800,31 @@ __global__ __launch_bounds__(kSB) void k_stage_pipe(cplx<T>* __restrict__ psi, S
     rp.cnt = rp.gr < rp.G && rp.gr < g.nhi ? (g.nhi - rp.gr + rp.G - 1) / rp.G : 0;
     __syncthreads();
     cplx<T> buf[MAXE];
-    uint32_t t = blockIdx.x;
-    if (t < total) pipe_prefetch<T, MAXE>(psi, g, offhi, tile_base<D>(g, t), rp, buf);
-    const uint32_t nsub = g.TE / DM;
-    for (; t < total; t += gridDim.x) {
+    // tiles of this workgroup: t, t + stride, ... below end (with g.xcd and a
+    // grid that is a multiple of 8, a contiguous range per XCD)
+    uint32_t t = blockIdx.x, stride = gridDim.x, end = total;
+    if (g.xcd && gridDim.x % kXCD == 0) {
+        const uint32_t x = blockIdx.x % kXCD;
+        stride = gridDim.x / kXCD;
+        t = xcd_range_start(x, total) + blockIdx.x / kXCD;
+        end = xcd_range_start(x + 1, total);
+    }
+    if (t < end) pipe_prefetch<T, MAXE>(psi, g, offhi, tile_base<D>(g, t), rp, buf);
+    const uint64_t dig0 = nrounds > 0 ? pack_digits<D>(threadIdx.x, rounds[0].nother) : 0;
+    cplx<T>* const tl[1] = {tile};
+    for (; t < end; t += stride) {
         const uint32_t base = tile_base<D>(g, t);
         const cplx<T>* mats = mats0 + size_t(t / g.ntiles) * mat_stride;
         lds_barrier();  // the previous tile's stores have read LDS
+        // clamped like the loads: a surplus register rewrites the last run's
+        // element with the value it already holds
 #pragma unroll
-        for (int j = 0; j < MAXE; ++j)
-            if (uint32_t(j) < rp.cnt) tile[(rp.gr + uint32_t(j) * rp.G) * g.R + rp.o] = buf[j];
+        for (int j = 0; j < MAXE; ++j) tile[min(rp.gr + uint32_t(j) * rp.G, g.nhi - 1) * g.R + rp.o] = buf[j];
         lds_barrier();
-        const uint32_t nxt = t + gridDim.x;
-        if (nxt < total) pipe_prefetch<T, MAXE>(psi, g, offhi, tile_base<D>(g, nxt), rp, buf);
+        const uint32_t nxt = t + stride;
+        if (nxt < end) pipe_prefetch<T, MAXE>(psi, g, offhi, tile_base<D>(g, nxt), rp, buf);
         for (int ri = 0; ri < nrounds; ++ri) {
-            const RoundDesc& rd = rounds[ri];
-            for (uint32_t u = threadIdx.x; u < nsub; u += kSB) {
-                uint32_t tb = 0, uu = u;
-                for (int j = rd.nother - 1; j >= 0; --j) {
-                    const uint32_t q = uu / D;
-                    tb += (uu - q * D) * rd.ols[j];
-                    uu = q;
-                }
-                cplx<T> v[DM];
-#pragma unroll
-                for (int i = 0; i < DM; ++i) v[i] = tile[tb + sub_offset<D, M>(i, rd.gls)];
-                const uint32_t gidx0 = global_index(g, offhi, base, tb);
-                for (int oi = rd.op0; oi < rd.op0 + rd.nops; ++oi) r_apply<T, D, M>(v, ops[oi], mats, gidx0);
-#pragma unroll
-                for (int i = 0; i < DM; ++i) tile[tb + sub_offset<D, M>(i, rd.gls)] = v[i];
-            }
+            run_round<T, D, M, 1>(tl, g, offhi, base, rounds[ri], ops, mats, dig0);
             lds_barrier();
         }
         // store this tile
@@ -651,7 +839,7 @@ __global__ __launch_bounds__(kSB) void k_stage_pipe(cplx<T>* __restrict__ psi, S
 // then added in a fixed order.
 template <typename T, int D>
 __device__ inline void tile_m(const cplx<T>* tp, const cplx<T>* tl, const StageGeom& g, const StageOp& op,
-                              double (*red)[kSB], double* __restrict__ partial) {
+                              uint32_t blk, double (*red)[kSB], double* __restrict__ partial) {
     constexpr int E = D * D;
     constexpr int P = kSB / E;
     const uint32_t nf = g.TE / D;
@@ -677,7 +865,7 @@ __device__ inline void tile_m(const cplx<T>* tp, const cplx<T>* tl, const StageG
             sr += red[0][q * E + threadIdx.x];
             si += red[1][q * E + threadIdx.x];
         }
-        double* o = partial + ((size_t(op.slot) * gridDim.x + blockIdx.x) * E + threadIdx.x) * 2;
+        double* o = partial + ((size_t(op.slot) * gridDim.x + blk) * E + threadIdx.x) * 2;
         o[0] = sr;
         o[1] = si;
     }
@@ -693,48 +881,29 @@ __global__ __launch_bounds__(kSB) void k_stage_adj_rounds(cplx<T>* __restrict__ 
                                                           int nrounds, const StageOp* __restrict__ ops,
                                                           const cplx<T>* __restrict__ mats, size_t mat_stride,
                                                           double* __restrict__ partial) {
-    constexpr int DM = cpow(D, M);
-    mats += size_t(blockIdx.x / g.ntiles) * mat_stride;
+    const uint32_t blk = tile_of_block(g);
+    mats += size_t(blk / g.ntiles) * mat_stride;
     extern __shared__ unsigned char smem[];
     cplx<T>* tp = reinterpret_cast<cplx<T>*>(smem);
     cplx<T>* tl = tp + g.TE;
-    __shared__ uint32_t offhi[kMaxHi];
+    uint32_t* offhi = reinterpret_cast<uint32_t*>(tl + g.TE);
     __shared__ double red[2][kSB];
-    const uint32_t base = tile_base<D>(g, blockIdx.x);
+    const uint32_t base = tile_base<D>(g, blk);
     build_offhi<D>(g, offhi);
     __syncthreads();
     tile_load(psi, tp, g, offhi, base);
     tile_load(lam, tl, g, offhi, base);
     __syncthreads();
-    const uint32_t nsub = g.TE / DM;
+    const uint64_t dig0 = nrounds > 0 ? pack_digits<D>(threadIdx.x, rounds[0].nother) : 0;
+    cplx<T>* const tt[2] = {tp, tl};
     for (int ri = 0; ri < nrounds; ++ri) {
         const RoundDesc& rd = rounds[ri];
-        const StageOp& op0 = ops[rd.op0];
-        if (op0.type == SOP_U && op0.slot >= 0) tile_m<T, D>(tp, tl, g, op0, red, partial);
-        for (uint32_t u = threadIdx.x; u < nsub; u += kSB) {
-            uint32_t tb = 0, uu = u;
-            for (int j = rd.nother - 1; j >= 0; --j) {
-                const uint32_t q = uu / D;
-                tb += (uu - q * D) * rd.ols[j];
-                uu = q;
-            }
-            cplx<T> vp[DM], vl[DM];
-#pragma unroll
-            for (int i = 0; i < DM; ++i) {
-                vp[i] = tp[tb + sub_offset<D, M>(i, rd.gls)];
-                vl[i] = tl[tb + sub_offset<D, M>(i, rd.gls)];
-            }
-            const uint32_t gidx0 = global_index(g, offhi, base, tb);
-            for (int oi = rd.op0; oi < rd.op0 + rd.nops; ++oi) {
-                r_apply<T, D, M>(vp, ops[oi], mats, gidx0);
-                r_apply<T, D, M>(vl, ops[oi], mats, gidx0);
-            }
-#pragma unroll
-            for (int i = 0; i < DM; ++i) {
-                tp[tb + sub_offset<D, M>(i, rd.gls)] = vp[i];
-                tl[tb + sub_offset<D, M>(i, rd.gls)] = vl[i];
-            }
+        // a slotted U opens its round (never after a leading permutation)
+        if (rd.nops > 0 && rd.pre0 < 0 && rd.pre1 < 0) {
+            const StageOp& op0 = ops[rd.op0];
+            if (op0.type == SOP_U && op0.slot >= 0) tile_m<T, D>(tp, tl, g, op0, blk, red, partial);
         }
+        run_round<T, D, M, 2>(tt, g, offhi, base, rd, ops, mats, dig0);
         __syncthreads();
     }
     tile_store(psi, tp, g, offhi, base);
@@ -765,9 +934,10 @@ qf_status with_dim_s(uint32_t D, F&& f) {
 
 }  // namespace
 
+// Dynamic LDS of a stage workgroup: the tile(s), then the nhi run offsets.
 size_t stage_lds_bytes(const StageGeom& g, int dtype, bool adjoint) {
     const size_t esz = dtype == QF_C64 ? 8 : 16;
-    return size_t(g.TE) * esz * (adjoint ? 2 : 1);
+    return size_t(g.TE) * esz * (adjoint ? 2 : 1) + size_t(g.nhi) * sizeof(uint32_t);
 }
 
 qf_status launch_stage(const StateView& s, const StageGeom& g, const StageOp* dops, int nops, const void* dmats,
@@ -806,11 +976,22 @@ static qf_status launch_pipe_m(const StateView& s, const StageGeom& g, const Rou
                                const StageOp* dops, const void* dmats, size_t mat_stride, int wgs_per_cu,
                                hipStream_t st) {
     const uint32_t total = g.ntiles * s.batch;
-    const uint32_t cap = 256u * uint32_t(wgs_per_cu);
-    const uint32_t grid = total < cap ? total : cap;
     const size_t lds = stage_lds_bytes(g, s.dtype, false);
     const uint32_t G = kSB / g.R;
     const uint32_t per = (g.nhi + G - 1) / G;
+    // never more workgroups per CU than can be resident at once: a persistent
+    // workgroup that waits for a slot only starts after others have finished
+    auto kern = per <= 8 ? (const void*)k_stage_pipe<T, D, M, 8>
+                         : per <= 16 ? (const void*)k_stage_pipe<T, D, M, 16> : (const void*)k_stage_pipe<T, D, M, 32>;
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kSB, lds) != hipSuccess || occ < 1) occ = 1;
+    int ncu = 256;
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    }
+    const uint32_t cap = uint32_t(ncu) * uint32_t(std::min(wgs_per_cu, occ));
+    const uint32_t grid = total < cap ? total : cap;
     if (per <= 8)
         hipLaunchKernelGGL((k_stage_pipe<T, D, M, 8>), dim3(grid), dim3(kSB), lds, st,
                            reinterpret_cast<cplx<T>*>(s.amps), g, drounds, nrounds, dops,
@@ -852,7 +1033,8 @@ qf_status launch_stage_pipe(const StateView& s, int M, const StageGeom& g, const
             }
             return set_error(QF_EUNSUPPORTED, "pipelined stage with a group of %d qudits for D = %d", M, D);
         };
-        return s.dtype == QF_C64 ? go(float{}) : go(double{});
+        if (s.dtype != QF_C64) return set_error(QF_EUNSUPPORTED, "the pipelined stage runs complex64 only");
+        return go(float{});
     });
 }
 
@@ -903,7 +1085,7 @@ qf_status launch_stage_adj_rounds(const StateView& s, void* lam, int M, const St
                     return launch_adj_rounds_m<T, D, 1>(s, lam, g, drounds, nrounds, dops, dmats, partial, mat_stride,
                                                         st);
                 case 2:
-                    if constexpr (D <= 5)
+                    if constexpr (D <= 5 && (sizeof(T) == 4 || D <= 3))
                         return launch_adj_rounds_m<T, D, 2>(s, lam, g, drounds, nrounds, dops, dmats, partial,
                                                             mat_stride, st);
                     break;

@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdint>
 #include <cstring>
 #include <memory>
 #include <vector>
@@ -339,6 +340,13 @@ namespace qf {
 // fuse 0 (LDS stages) and 3 (stages + two-qudit blocks) use pass lists.
 static bool staged(const qf_plan* p) { return p->opts.fuse == 0 || p->opts.fuse == 3; }
 
+// Register group of the adjoint rounds: psi and lam sub-tiles are both live, so
+// at most 2 qudits, and 1 for complex128 with D >= 4 (register budget).
+static int adj_group(const qf_plan* p) {
+    if (p->dtype == QF_C128 && p->D >= 4) return 1;
+    return std::min(p->group, 2);
+}
+
 static const char* kFamilies[] = {"stage", "stage_adj", "fused", "axis", "ctrl", "diag", "adj_axis", "checkpoint"};
 enum Family { F_STAGE, F_STAGE_ADJ, F_FUSED, F_AXIS, F_CTRL, F_DIAG, F_ADJ_AXIS, F_CKPT, F_COUNT };
 
@@ -629,8 +637,10 @@ static void tile_shape(int D, int n, int dtype, int tile_opt, int low_opt, bool 
     if (low_opt > 0) {
         r = low_opt;
     } else {
+        // the smallest r whose runs fill a 64-byte segment; qf_plan_create may
+        // raise it (choose_low)
         r = 1;
-        while (size_t(ipow(D, r)) * esz < 256 && r + 1 < k) ++r;
+        while (size_t(ipow(D, r)) * esz < 64 && r + 1 < k) ++r;
     }
     if (r >= k) r = k - 1;
     while (ipow(D, k - r) > uint32_t(kMaxHi)) ++r;
@@ -696,6 +706,7 @@ static void plan_passes(const qf_plan* p, const std::vector<GRef>& seq, int k, i
         for (int q = 0; q < n; ++q)
             if (inT[q]) ps.T.push_back(q);
         make_geom(p->D, n, k, r, ps.T, ps.geom);
+        ps.geom.xcd = p->opts.tile_order == 0 ? 1u : 0u;
         std::vector<char> bFull(n, 0), bDiag(n, 0);
         std::vector<std::vector<GRef>> pending(n);
         auto flush = [&](int q) {
@@ -749,6 +760,29 @@ static void plan_passes(const qf_plan* p, const std::vector<GRef>& seq, int k, i
     }
 }
 
+// Number of low qudits of the tiles: fewer low qudits leave more tile qudits to
+// the gates and so fewer passes, at the price of shorter contiguous runs (the
+// XCD-grouped tile order keeps neighbouring tiles' shared cache lines in one
+// L2).  Among r0 .. r0 + 3, the r with the fewest passes is taken; ties go to
+// the longer runs.
+static int choose_low(const qf_plan* p, const std::vector<std::vector<GRef>>& seqs, int k, int r0, bool adjoint) {
+    if (r0 >= k) return r0;
+    int best = r0;
+    size_t best_passes = SIZE_MAX;
+    for (int r = r0; r < k && r <= r0 + 3; ++r) {
+        PassList trial;
+        if (adjoint)
+            for (int sgi = int(seqs.size()) - 1; sgi >= 0; --sgi) plan_passes(p, seqs[sgi], k, r, sgi, trial);
+        else
+            for (size_t sgi = 0; sgi < seqs.size(); ++sgi) plan_passes(p, seqs[sgi], k, r, int(sgi), trial);
+        if (trial.passes.size() <= best_passes) {
+            best_passes = trial.passes.size();
+            best = r;
+        }
+    }
+    return best;
+}
+
 static Mat group_matrix(const qf_plan* p, const std::vector<GRef>& g, const double* theta) {
     Mat U = identity(p->D);
     for (const GRef& r : g) {
@@ -759,64 +793,194 @@ static Mat group_matrix(const qf_plan* p, const std::vector<GRef>& g, const doub
     return U;
 }
 
-// Register rounds of a forward tile pass: consecutive ops are grouped while the
-// qudits they act on (targets of U and SHIFT) fit in a group of M tile qudits;
-// the group is padded with the most significant unused tile qudits.
+// Register rounds of a tile pass.  A round starts with up to two SHIFT ops
+// folded into its loads (pre0: target on group position 0, control outside
+// the group or none; pre1: target on position 1, control on position 0; a
+// single leading SHIFT whose control is a tile qudit is taken as pre1), takes
+// consecutive in-place ops (U, PHASE) while the U targets fit in a group of M
+// tile qudits, and may end with one SHIFT folded into its stores (post: target
+// on position 0, control on position 1, outside the group or none).  The group
+// is padded with unused tile qudits.  Adjoint lists: a U that owns an M slot
+// opens its round (no SHIFT before it in the round).
 static void build_rounds(const qf_plan* p, Pass& ps, PassList& L, const std::vector<int>& dim_of, size_t& moff,
                          bool adjoint) {
     const int D = p->D;
     const int k = int(ps.geom.k);
-    const int M = adjoint ? std::min(p->group, 2) : p->group;
+    const int M = adjoint ? adj_group(p) : p->group;
     ps.nrounds = 0;
     ps.round_off = int(L.hrounds.size());
     if (k < M || ps.ops.empty()) return;
-    auto target_dim = [&](const HOp& h) { return h.type == SOP_PHASE ? -1 : dim_of[h.q]; };
+    const size_t nops = ps.ops.size();
+    auto has = [](const std::vector<int>& v, int d) { return std::find(v.begin(), v.end(), d) != v.end(); };
+    auto ctrl_dim = [&](const HOp& h) { return h.ctrl >= 0 ? dim_of[h.ctrl] : -1; };  // -1: none or outside
+    auto slotted = [&](size_t j) { return adjoint && ps.ops[j].type == SOP_U && L.hops[ps.op_off + j].slot >= 0; };
     size_t i = 0;
-    while (i < ps.ops.size()) {
-        std::vector<int> grp;
+    while (i < nops) {
+        std::vector<int> front;  // fixed group positions 0, 1, ...
+        std::vector<int> rest;   // other group qudits (U targets)
+        int pre0 = -1, pre1 = -1, post = -1;
         size_t j = i;
-        for (; j < ps.ops.size(); ++j) {
-            // adjoint: a U that owns an M slot opens its own round
-            if (adjoint && j > i && ps.ops[j].type == SOP_U && L.hops[ps.op_off + j].slot >= 0) break;
-            const int d = target_dim(ps.ops[j]);
-            if (d < 0 || std::find(grp.begin(), grp.end(), d) != grp.end()) continue;
-            if (int(grp.size()) == M) break;
-            grp.push_back(d);
+        if (ps.ops[j].type == SOP_SHIFT) {
+            const int t = dim_of[ps.ops[j].q], c = ctrl_dim(ps.ops[j]);
+            if (M >= 2 && c >= 0) {
+                front = {c, t};
+                pre1 = int(j);
+                ++j;
+            } else {
+                front = {t};
+                pre0 = int(j);
+                ++j;
+                if (M >= 2 && j < nops && ps.ops[j].type == SOP_SHIFT && ctrl_dim(ps.ops[j]) == t &&
+                    dim_of[ps.ops[j].q] != t) {
+                    front.push_back(dim_of[ps.ops[j].q]);
+                    pre1 = int(j);
+                    ++j;
+                }
+            }
         }
-        for (int d = 0; int(grp.size()) < M && d < k; ++d)
-            if (std::find(grp.begin(), grp.end(), d) == grp.end()) grp.push_back(d);
-        std::sort(grp.begin(), grp.end());
+        const size_t ip0 = j;
+        size_t ipe = j;
+        auto members = [&]() {
+            std::vector<int> m = front;
+            m.insert(m.end(), rest.begin(), rest.end());
+            return m;
+        };
+        for (; j < nops; ++j) {
+            const HOp& h = ps.ops[j];
+            if (j > i && slotted(j)) break;
+            if (h.type == SOP_PHASE) {
+                ipe = j + 1;
+                continue;
+            }
+            if (h.type == SOP_U) {
+                const int d = dim_of[h.q];
+                const std::vector<int> m = members();
+                if (!has(m, d)) {
+                    if (int(m.size()) == M) break;
+                    rest.push_back(d);
+                }
+                ipe = j + 1;
+                continue;
+            }
+            // a SHIFT after the in-place ops: post if it fits
+            const int t = dim_of[h.q], c = ctrl_dim(h);
+            if (front.empty()) {
+                std::vector<int> r2, r1;
+                for (int d : rest) {
+                    if (d != t && d != c) r2.push_back(d);
+                    if (d != t) r1.push_back(d);
+                }
+                if (c >= 0 && M >= 2 && int(r2.size()) + 2 <= M) {
+                    front = {t, c};
+                    rest = r2;
+                } else if (int(r1.size()) + 1 <= M && !has(r1, c)) {
+                    front = {t};
+                    rest = r1;
+                } else {
+                    break;
+                }
+            } else {
+                // positions are fixed: the target must be position 0 and the
+                // control position 1 or outside the group
+                const std::vector<int> m = members();
+                if (front[0] != t) break;
+                const bool c_at1 = m.size() >= 2 && c >= 0 && m[1] == c;
+                if (!c_at1 && c >= 0 && has(m, c)) break;
+                if (!c_at1 && c >= 0 && int(m.size()) < M) break;  // padding could place it in the group
+            }
+            post = int(j);
+            ++j;
+            break;
+        }
+        std::vector<int> grp = members();
+        auto pad = [&](int d) { return !has(grp, d); };
+        for (int d = 0; int(grp.size()) < M && d < k; ++d) {
+            // never pad with the control of a per-lane permutation (its digit must stay outside)
+            bool lane_ctrl = false;
+            for (int pi : {pre0, post})
+                if (pi >= 0 && ctrl_dim(ps.ops[size_t(pi)]) == d) lane_ctrl = true;
+            if (pad(d) && !lane_ctrl) grp.push_back(d);
+        }
         RoundDesc rd{};
-        rd.op0 = int(i);
-        rd.nops = int(j - i);
+        rd.op0 = int(ip0);
+        rd.nops = int(ipe - ip0);
+        rd.pre0 = pre0;
+        rd.pre1 = pre1;
+        rd.post = post;
         for (int g = 0; g < M; ++g) rd.gls[g] = ipow(D, k - 1 - grp[g]);
         rd.nother = k - M;
         int o = 0;
         for (int d = 0; d < k; ++d)
-            if (std::find(grp.begin(), grp.end(), d) == grp.end()) rd.ols[o++] = ipow(D, k - 1 - d);
+            if (!has(grp, d)) rd.ols[o++] = ipow(D, k - 1 - d);
         auto gpos_of_qudit = [&](int q) -> int {
             if (q < 0 || dim_of[q] < 0) return -1;
             auto it = std::find(grp.begin(), grp.end(), dim_of[q]);
             return it == grp.end() ? -1 : int(it - grp.begin());
         };
-        for (size_t oi = i; oi < j; ++oi) {
+        bool need = false;
+        for (size_t oi = ip0; oi < ipe; ++oi) {
             const HOp& h = ps.ops[oi];
             StageOp& so = L.hops[ps.op_off + oi];
             so.gpos = h.type == SOP_PHASE ? -1 : gpos_of_qudit(h.q);
-            so.ctrl_gpos = h.type == SOP_SHIFT ? gpos_of_qudit(h.ctrl) : -1;
+            so.ctrl_gpos = -1;
             if (h.type == SOP_PHASE) {
                 for (size_t pi = 0; pi < h.g.size(); ++pi) {
                     const qf_op& g = p->gates[h.g[pi].gi].op;
                     so.agpos[pi] = gpos_of_qudit(g.q0);
                     so.bgpos[pi] = gpos_of_qudit(g.q1);
+                    need = need || so.agpos[pi] < 0 || so.bgpos[pi] < 0;
                 }
                 so.wtab = int(moff);
                 moff += size_t(D);
             }
         }
+        for (int pi : {pre0, pre1, post}) {
+            if (pi < 0) continue;
+            const HOp& h = ps.ops[size_t(pi)];
+            StageOp& so = L.hops[ps.op_off + pi];
+            so.gpos = gpos_of_qudit(h.q);
+            so.ctrl_gpos = gpos_of_qudit(h.ctrl);
+            need = need || (so.has_ctrl && so.ctrl_gpos < 0);
+        }
+        rd.need_gidx = need ? 1 : 0;
+        rd.kind = RK_GENERIC;
+        if (rd.nops == 0) {
+            rd.kind = RK_NONE;
+        } else if (rd.nops <= 2) {
+            bool allu = true, anyreal = false;
+            int posmask = 0;
+            for (size_t oi = ip0; oi < ipe; ++oi) {
+                const StageOp& so = L.hops[ps.op_off + oi];
+                allu = allu && so.type == SOP_U;
+                anyreal = anyreal || so.real;
+                if (so.type == SOP_U && so.gpos >= 0 && so.gpos < 2) posmask |= 1 << so.gpos;
+            }
+            if (allu && rd.nops == 1 && posmask == 1) rd.kind = anyreal ? RK_U0_REAL : RK_U0;
+            if (allu && rd.nops == 2 && posmask == 3 && !anyreal && M >= 2) rd.kind = RK_U01;
+        }
         L.hrounds.push_back(rd);
         ++ps.nrounds;
         i = j;
+    }
+}
+
+// Moves every U of a stage up to right after the last earlier op that touches
+// its qudit (it commutes with the ops it passes, which act on other qudits), so
+// that it meets the SHIFT ops around its qudit in the same register round.
+static void hoist_u(const qf_plan* p, std::vector<HOp>& ops) {
+    auto touches_q = [&](const HOp& h, int q) {
+        if (h.type == SOP_U) return h.q == q;
+        if (h.type == SOP_SHIFT) return h.q == q || h.ctrl == q;
+        for (const GRef& r : h.g) {
+            const qf_op& g = p->gates[r.gi].op;
+            if (g.q0 == q || g.q1 == q) return true;
+        }
+        return false;
+    };
+    for (size_t idx = 1; idx < ops.size(); ++idx) {
+        if (ops[idx].type != SOP_U) continue;
+        const int q = ops[idx].q;
+        for (size_t j = idx; j > 0 && !touches_q(ops[j - 1], q); --j) std::swap(ops[j - 1], ops[j]);
     }
 }
 
@@ -837,6 +1001,7 @@ static void finalize_passes(const qf_plan* p, PassList& L, bool adjoint) {
             }
             continue;
         }
+        hoist_u(p, ps.ops);
         ps.op_off = int(L.hops.size());
         ps.mat_off = L.nmats;
         ps.nslots = 0;
@@ -1040,7 +1205,7 @@ static qf_status ensure_ckpt(qf_plan* p, const StateView& v) {
 static qf_status launch_forward_pass(const qf_plan* p, const PassList& L, const Pass& ps, const StateView& v,
                                      const void* mats, size_t mat_stride, hipStream_t st) {
     const int kern = p->opts.stage_kernel;
-    if (ps.nrounds > 0 && kern == 2 && p->group <= 3 && stage_pipe_ok(ps.geom))
+    if (ps.nrounds > 0 && kern == 2 && p->group <= 3 && v.dtype == QF_C64 && stage_pipe_ok(ps.geom))
         return launch_stage_pipe(v, p->group, ps.geom, L.drounds + ps.round_off, ps.nrounds, L.dops + ps.op_off, mats,
                                  p->opts.pipe_wgs > 0 ? p->opts.pipe_wgs : 4, st, mat_stride);
     if (ps.nrounds > 0 && kern != 1)
@@ -1060,7 +1225,7 @@ static qf_status run_tile_pass(qf_plan* p, const PassList& L, const Pass& ps, co
         QF_CHECK(prof_end(p, st, a, F_STAGE, 2.0 * state_bytes(v)));
     } else {
         if (ps.nrounds > 0 && p->opts.stage_kernel != 1)
-            QF_CHECK(launch_stage_adj_rounds(v, lam, std::min(p->group, 2), ps.geom, L.drounds + ps.round_off,
+            QF_CHECK(launch_stage_adj_rounds(v, lam, adj_group(p), ps.geom, L.drounds + ps.round_off,
                                              ps.nrounds, L.dops + ps.op_off, mats, partial, st));
         else
             QF_CHECK(launch_stage_adj(v, lam, ps.geom, L.dops + ps.op_off, ps.nops, mats, partial, st));
@@ -1156,7 +1321,7 @@ qf_status qf_plan_create(int32_t dim, int32_t n, int32_t dtype, const qf_op* ops
     QF_RETURN_IF(p->opts.tile_digits < 0 || p->opts.tile_digits > kMaxTileDims || p->opts.adj_tile_digits < 0 ||
                      p->opts.adj_tile_digits > kMaxTileDims || p->opts.low_digits < 0 || p->opts.ckpt_every < 0 ||
                      p->opts.stage_kernel < 0 || p->opts.stage_kernel > 2 || p->opts.pipe_wgs < 0 ||
-                     p->opts.pipe_wgs > 16,
+                     p->opts.pipe_wgs > 16 || p->opts.tile_order < 0 || p->opts.tile_order > 1,
                  QF_EINVAL, "bad tile / checkpoint options");
     p->gates.resize(nops);
     for (int i = 0; i < nops; ++i) {
@@ -1214,22 +1379,25 @@ qf_status qf_plan_create(int32_t dim, int32_t n, int32_t dtype, const qf_op* ops
         QF_RETURN_IF(size_t(ipow(dim, k)) * esz + 4096 > 160 * 1024 ||
                          2 * size_t(ipow(dim, ka)) * esz + 8192 > 160 * 1024,
                      QF_ERANGE, "tile of %d (adjoint %d) qudits exceeds the 160 KB LDS of a workgroup", k, ka);
+        std::vector<std::vector<GRef>> fseq(p->seg_end.size()), rseq(p->seg_end.size());
         int start = 0;
         for (size_t sgi = 0; sgi < p->seg_end.size(); ++sgi) {
-            std::vector<GRef> seq;
             if (p->opts.fuse == 3)
-                pair_fuse(p.get(), start, p->seg_end[sgi], seq);
+                pair_fuse(p.get(), start, p->seg_end[sgi], fseq[sgi]);
             else
-                for (int i = start; i < p->seg_end[sgi]; ++i) seq.push_back({i, false});
-            plan_passes(p.get(), seq, k, r, int(sgi), p->fwd);
+                for (int i = start; i < p->seg_end[sgi]; ++i) fseq[sgi].push_back({i, false});
             start = p->seg_end[sgi];
         }
         for (int sgi = int(p->seg_end.size()) - 1; sgi >= 0; --sgi) {
             const int lo = sgi == 0 ? 0 : p->seg_end[sgi - 1];
-            std::vector<GRef> seq;
-            for (int i = p->seg_end[sgi] - 1; i >= lo; --i) seq.push_back({i, true});
-            plan_passes(p.get(), seq, ka, ra, sgi, p->rev);
+            for (int i = p->seg_end[sgi] - 1; i >= lo; --i) rseq[sgi].push_back({i, true});
         }
+        if (p->opts.low_digits == 0) {
+            r = choose_low(p.get(), fseq, k, r, false);
+            ra = choose_low(p.get(), rseq, ka, ra, true);
+        }
+        for (size_t sgi = 0; sgi < fseq.size(); ++sgi) plan_passes(p.get(), fseq[sgi], k, r, int(sgi), p->fwd);
+        for (int sgi = int(rseq.size()) - 1; sgi >= 0; --sgi) plan_passes(p.get(), rseq[sgi], ka, ra, sgi, p->rev);
         finalize_passes(p.get(), p->fwd, false);
         finalize_passes(p.get(), p->rev, true);
     }
@@ -1790,7 +1958,7 @@ qf_status qf_adjoint_grad_dev(qf_plan* plan, const qf_state* psi, const qf_state
         if (ps.tile) {
             const void* mats = reinterpret_cast<const unsigned char*>(L.dmats_b) + ps.mat_off * esz;
             if (ps.nrounds > 0 && plan->opts.stage_kernel != 1)
-                QF_CHECK(launch_stage_adj_rounds(v, lam->amps, std::min(plan->group, 2), ps.geom,
+                QF_CHECK(launch_stage_adj_rounds(v, lam->amps, adj_group(plan), ps.geom,
                                                  L.drounds + ps.round_off, ps.nrounds, L.dops + ps.op_off, mats,
                                                  plan->w_partial, st, L.nmats));
             else

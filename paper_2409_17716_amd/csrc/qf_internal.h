@@ -79,19 +79,35 @@ struct StageGeom {
     uint32_t N;          // D^n
     uint32_t nout;       // n - k
     FastDiv divR;
+    uint32_t xcd;        // 1: tiles grouped per XCD (tile_of_block), 0: dispatch order
     uint32_t hi_stride[kMaxTileDims];  // global strides of the high tile qudits, most significant first
     uint32_t out_stride[kMaxOuter];    // global strides of the outer qudits, most significant first
 };
 
 enum StageOpType : int32_t { SOP_U = 0, SOP_SHIFT = 1, SOP_PHASE = 2 };
 
-// Register rounds of a forward stage: each lane holds a sub-tile of D^M
-// amplitudes (every combination of the M group qudits) in registers and applies
-// the round's ops [op0, op0 + nops) to it; the group position of each op's
-// qudits is stored in the op (gpos, ctrl_gpos, agpos/bgpos).
+// Register rounds of a stage: each lane holds a sub-tile of D^M amplitudes
+// (every combination of the M group qudits) in registers and applies the
+// round's in-place ops [op0, op0 + nops) (U, PHASE) to it; the group position
+// of each op's qudits is stored in the op (gpos, agpos/bgpos).  Permutation
+// ops (SHIFT) are folded into the LDS addresses: pre0 (target position 0,
+// control position 1, outside the group or none) and then pre1 (target
+// position 1, control position 0) before the in-place ops, post (like pre0)
+// after them.
 constexpr int kMaxGroup = 5;
+// Round shapes with a dispatch-free kernel path (RK_GENERIC: anything else).
+enum RoundKind : int32_t {
+    RK_GENERIC = 0,
+    RK_NONE = 1,     // no in-place op (a permutation only)
+    RK_U0 = 2,       // one complex U on group position 0
+    RK_U0_REAL = 3,  // one real U on group position 0
+    RK_U01 = 4,      // two complex U on group positions 0 and 1
+};
 struct RoundDesc {
+    int32_t kind;
     int32_t op0, nops;
+    int32_t pre0, pre1, post;       // permutation ops, -1 = none
+    int32_t need_gidx;              // some op reads a digit from the global index
     uint32_t gls[kMaxGroup];        // LDS strides of the group qudits, register digit 0 first
     int32_t nother;                 // k - M
     uint32_t ols[kMaxTileDims];     // LDS strides of the other tile qudits, most significant first
@@ -131,7 +147,7 @@ qf_status launch_stage_rounds(const StateView& s, int M, const StageGeom& g, con
 // into partial[(slot * nblocks + block) * D*D] (complex FP64).
 qf_status launch_stage_adj(const StateView& s, void* lam, const StageGeom& g, const StageOp* dops, int nops,
                            const void* dmats, double* partial, hipStream_t st, size_t mat_stride = 0);
-// Pipelined persistent forward stage (register rounds, M <= 3): grid of at most
+// Pipelined persistent forward stage (register rounds, M <= 3, complex64): grid of at most
 // 256 * wgs_per_cu workgroups; needs stage_pipe_ok(g) (runs shorter than a
 // workgroup, at most 32 runs per lane).
 bool stage_pipe_ok(const StageGeom& g);
