@@ -77,6 +77,7 @@ def write_traffic(fetch_dir: str, write_dir: str) -> None:
     import collections
     import csv
     import glob
+    import re
 
     N = 3 ** 16
 
@@ -98,7 +99,8 @@ def write_traffic(fetch_dir: str, write_dir: str) -> None:
     sf = sum(f[stagek]) / len(f[stagek])
     sw = sum(w[stagek]) / len(w[stagek])
     bpl = (sf * cal_f + sw * cal_w) * 1024
-    rec = {"kernel": stagek.split("(")[0], "launches": len(f[stagek]),
+    m = re.search(r"k_stage\w*(<[^>]*>)?", stagek)
+    rec = {"kernel": m.group(0) if m else stagek, "launches": len(f[stagek]),
            "workload": "qutrit ansatz D=3 n=16 complex64, default plan",
            "source_hash": _source_hash(), "fetch_kib_per_launch": sf, "write_kib_per_launch": sw,
            "copy_calibration": {"bytes": N * 8, "fetch_scale": cal_f, "write_scale": cal_w},
