@@ -176,7 +176,7 @@ typedef struct qf_plan_opts {
     int32_t stage_kernel; /* forward stages: 0 = register rounds (default), 1 = one   */
                           /* LDS sweep per op, 2 = register rounds in a pipelined     */
                           /* persistent kernel (next tile's loads overlap compute;    */
-                          /* complex64 only, complex128 runs as 0)                    */
+                          /* complex64 and D <= 12 only, otherwise runs as 0)         */
     int32_t group_digits; /* register rounds: qudits per lane group; 0 = chosen from D */
     int32_t pipe_wgs;     /* stage_kernel 2: workgroups per compute unit; 0 = 4        */
     int32_t tile_order;   /* 0 = each XCD (own L2) walks a contiguous range of tiles  */

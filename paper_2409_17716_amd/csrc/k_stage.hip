@@ -64,7 +64,7 @@ __device__ inline uint32_t tile_base(const StageGeom& g, uint32_t blk) {
 template <int D>
 __device__ inline void build_offhi(const StageGeom& g, uint32_t* offhi) {
     const int nh = int(g.k - g.r);
-    for (uint32_t h = threadIdx.x; h < g.nhi; h += kSB) {
+    for (uint32_t h = threadIdx.x; h < g.nhi; h += blockDim.x) {
         uint32_t hh = h, off = 0;
         for (int i = nh - 1; i >= 0; --i) {
             const uint32_t q = hh / D;
@@ -92,8 +92,8 @@ constexpr int kIO = 8;
 template <typename T, bool LOAD>
 __device__ inline void tile_io(cplx<T>* __restrict__ psi, cplx<T>* tile, const StageGeom& g, const uint32_t* offhi,
                                uint32_t base) {
-    if (g.R < kSB) {
-        const uint32_t G = kSB / g.R;
+    if (g.R < blockDim.x) {
+        const uint32_t G = blockDim.x / g.R;
         const uint32_t gr = threadIdx.x / g.R;
         const uint32_t o = threadIdx.x - gr * g.R;
         if (gr >= G) return;
@@ -121,7 +121,7 @@ __device__ inline void tile_io(cplx<T>* __restrict__ psi, cplx<T>* tile, const S
     } else {
         for (uint32_t h = 0; h < g.nhi; ++h) {
             const uint32_t gb = base + offhi[h];
-            for (uint32_t o = threadIdx.x; o < g.R; o += kSB) {
+            for (uint32_t o = threadIdx.x; o < g.R; o += blockDim.x) {
                 if (LOAD)
                     tile[h * g.R + o] = psi[gb + o];
                 else
@@ -411,9 +411,18 @@ template <typename T, int D, int M, int J, bool REAL>
 __device__ __forceinline__ void r_u(cplx<T> (&v)[cpow(D, M)], const cplx<T>* __restrict__ U) {
     constexpr int SJ = cpow(D, M - 1 - J);
     constexpr int NF = cpow(D, M - 1);
-    cplx<T> m[D * D];
+    // small matrices are read once into scalar registers; larger ones are read
+    // from memory where used (a local copy would not fit the scalar file)
+    constexpr bool kCopy = D <= 6;
+    cplx<T> m[kCopy ? D * D : 1];
+    if constexpr (kCopy) {
 #pragma unroll
-    for (int e = 0; e < D * D; ++e) m[e] = U[e];
+        for (int e = 0; e < D * D; ++e) m[e] = U[e];
+    }
+    auto mat = [&](int e) -> cplx<T> {
+        if constexpr (kCopy) return m[e];
+        else return U[e];
+    };
 #pragma unroll
     for (int c = 0; c < NF; ++c) {
         const int b0 = (c / SJ) * SJ * D + (c % SJ);
@@ -424,14 +433,15 @@ __device__ __forceinline__ void r_u(cplx<T> (&v)[cpow(D, M)], const cplx<T>* __r
                 T re = 0, im = 0;
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
-                    re = fma(m[a * D + d].re, v[b0 + d * SJ].re, re);
-                    im = fma(m[a * D + d].re, v[b0 + d * SJ].im, im);
+                    const T w = mat(a * D + d).re;
+                    re = fma(w, v[b0 + d * SJ].re, re);
+                    im = fma(w, v[b0 + d * SJ].im, im);
                 }
                 y[a] = cmake<T>(re, im);
             } else {
                 cplx<T> acc = cmake<T>(0, 0);
 #pragma unroll
-                for (int d = 0; d < D; ++d) cmac(acc, m[a * D + d], v[b0 + d * SJ]);
+                for (int d = 0; d < D; ++d) cmac(acc, mat(a * D + d), v[b0 + d * SJ]);
                 y[a] = acc;
             }
         }
@@ -687,7 +697,7 @@ __device__ __forceinline__ void run_round(cplx<T>* const (&t)[NT], const StageGe
             }
         }
     }
-    for (uint32_t u = threadIdx.x; u < nsub; u += kSB) {
+    for (uint32_t u = threadIdx.x; u < nsub; u += blockDim.x) {
         const uint64_t dig = u == threadIdx.x ? dig0 : pack_digits<D>(u, rd.nother);
         const uint32_t tb = sub_base(dig, rd);
         const uint32_t gidx0 = rd.need_gidx ? global_index(g, offhi, base, tb) : 0u;
@@ -840,34 +850,45 @@ __global__ __launch_bounds__(kSB) void k_stage_pipe(cplx<T>* __restrict__ psi, S
 template <typename T, int D>
 __device__ inline void tile_m(const cplx<T>* tp, const cplx<T>* tl, const StageGeom& g, const StageOp& op,
                               uint32_t blk, double (*red)[kSB], double* __restrict__ partial) {
-    constexpr int E = D * D;
-    constexpr int P = kSB / E;
+    constexpr uint32_t E = D * D;
+    const uint32_t nt = blockDim.x;
     const uint32_t nf = g.TE / D;
-    const int e = threadIdx.x % E;
-    const int part = threadIdx.x / E;
-    double ar = 0.0, ai = 0.0;
-    if (part < P) {
-        const uint32_t a = uint32_t(e / D), c = uint32_t(e % D);
-        for (uint32_t f = part; f < nf; f += P) {
+    double* out = partial + (size_t(op.slot) * gridDim.x + blk) * E * 2;
+    auto entry = [&](uint32_t e, uint32_t f0, uint32_t step, double& ar, double& ai) {
+        const uint32_t a = e / D, c = e % D;
+        for (uint32_t f = f0; f < nf; f += step) {
             const uint32_t lb = fibre_lb<D>(op, f);
             const cplx<T> x = tp[lb + a * op.ls];
             const cplx<T> y = tl[lb + c * op.ls];
             ar += double(x.re) * double(y.re) + double(x.im) * double(y.im);
             ai += double(x.im) * double(y.re) - double(x.re) * double(y.im);
         }
-    }
-    red[0][threadIdx.x] = ar;
-    red[1][threadIdx.x] = ai;
-    __syncthreads();
-    if (int(threadIdx.x) < E) {
-        double sr = 0.0, si = 0.0;
-        for (int q = 0; q < P; ++q) {
-            sr += red[0][q * E + threadIdx.x];
-            si += red[1][q * E + threadIdx.x];
+    };
+    if (E <= nt) {
+        // lane (entry, part): fibres part, part + P, ...; parts added in order
+        const uint32_t P = nt / E;
+        const uint32_t e = threadIdx.x % E, part = threadIdx.x / E;
+        double ar = 0.0, ai = 0.0;
+        if (part < P) entry(e, part, P, ar, ai);
+        red[0][threadIdx.x] = ar;
+        red[1][threadIdx.x] = ai;
+        __syncthreads();
+        if (threadIdx.x < E) {
+            double sr = 0.0, si = 0.0;
+            for (uint32_t q = 0; q < P; ++q) {
+                sr += red[0][q * E + threadIdx.x];
+                si += red[1][q * E + threadIdx.x];
+            }
+            out[2 * threadIdx.x] = sr;
+            out[2 * threadIdx.x + 1] = si;
         }
-        double* o = partial + ((size_t(op.slot) * gridDim.x + blk) * E + threadIdx.x) * 2;
-        o[0] = sr;
-        o[1] = si;
+    } else {
+        for (uint32_t e = threadIdx.x; e < E; e += nt) {
+            double ar = 0.0, ai = 0.0;
+            entry(e, 0, 1, ar, ai);
+            out[2 * e] = ar;
+            out[2 * e + 1] = ai;
+        }
     }
     __syncthreads();
 }
@@ -961,12 +982,22 @@ qf_status launch_stage(const StateView& s, const StageGeom& g, const StageOp* do
 // Register group sizes compiled per D (D^M <= 32 amplitudes per lane).
 int max_group_size(uint32_t D) { return D == 2 ? 5 : D == 3 ? 3 : D <= 5 ? 2 : 1; }
 
+// Workgroup size of a register-round stage: the sub-tile count rounded up to
+// whole wavefronts, at most 256 (small sub-tile counts then leave no lanes idle
+// in the rounds and allow more resident workgroups).
+static uint32_t rounds_threads(const StageGeom& g, int DM) {
+    const uint32_t nsub = g.TE / uint32_t(DM);
+    uint32_t t = (nsub + 63) / 64 * 64;
+    return t < 64 ? 64 : t > uint32_t(kSB) ? uint32_t(kSB) : t;
+}
+
 template <typename T, int D, int M>
 static qf_status launch_rounds_m(const StateView& s, const StageGeom& g, const RoundDesc* drounds, int nrounds,
                                  const StageOp* dops, const void* dmats, size_t mat_stride, hipStream_t st) {
     const uint32_t grid = g.ntiles * s.batch;
     const size_t lds = stage_lds_bytes(g, s.dtype, false);
-    hipLaunchKernelGGL((k_stage_rounds<T, D, M>), dim3(grid), dim3(kSB), lds, st, reinterpret_cast<cplx<T>*>(s.amps),
+    const uint32_t nthr = rounds_threads(g, cpow(D, M));
+    hipLaunchKernelGGL((k_stage_rounds<T, D, M>), dim3(grid), dim3(nthr), lds, st, reinterpret_cast<cplx<T>*>(s.amps),
                        g, drounds, nrounds, dops, reinterpret_cast<const cplx<T>*>(dmats), mat_stride);
     return check_launch("stage rounds");
 }
@@ -1020,6 +1051,9 @@ qf_status launch_stage_pipe(const StateView& s, int M, const StageGeom& g, const
         constexpr int D = decltype(dtag)::value;
         auto go = [&](auto tag) -> qf_status {
             using T = decltype(tag);
+            if constexpr (D > 12) {
+                return set_error(QF_EUNSUPPORTED, "pipelined stage for D = %d", D);
+            } else {
             switch (M) {
                 case 1: return launch_pipe_m<T, D, 1>(s, g, drounds, nrounds, dops, dmats, mat_stride, wgs_per_cu, st);
                 case 2:
@@ -1032,6 +1066,7 @@ qf_status launch_stage_pipe(const StateView& s, int M, const StageGeom& g, const
                     break;
             }
             return set_error(QF_EUNSUPPORTED, "pipelined stage with a group of %d qudits for D = %d", M, D);
+            }
         };
         if (s.dtype != QF_C64) return set_error(QF_EUNSUPPORTED, "the pipelined stage runs complex64 only");
         return go(float{});
@@ -1067,7 +1102,8 @@ static qf_status launch_adj_rounds_m(const StateView& s, void* lam, const StageG
                                      size_t mat_stride, hipStream_t st) {
     const uint32_t grid = g.ntiles * s.batch;
     const size_t lds = stage_lds_bytes(g, s.dtype, true);
-    hipLaunchKernelGGL((k_stage_adj_rounds<T, D, M>), dim3(grid), dim3(kSB), lds, st,
+    const uint32_t nthr = rounds_threads(g, cpow(D, M));
+    hipLaunchKernelGGL((k_stage_adj_rounds<T, D, M>), dim3(grid), dim3(nthr), lds, st,
                        reinterpret_cast<cplx<T>*>(s.amps), reinterpret_cast<cplx<T>*>(lam), g, drounds, nrounds, dops,
                        reinterpret_cast<const cplx<T>*>(dmats), mat_stride, partial);
     return check_launch("stage adjoint rounds");

@@ -341,9 +341,10 @@ namespace qf {
 static bool staged(const qf_plan* p) { return p->opts.fuse == 0 || p->opts.fuse == 3; }
 
 // Register group of the adjoint rounds: psi and lam sub-tiles are both live, so
-// at most 2 qudits, and 1 for complex128 with D >= 4 (register budget).
+// at most 2 qudits; 1 for D >= 5 (measured faster) and for complex128 with
+// D >= 4 (register budget).
 static int adj_group(const qf_plan* p) {
-    if (p->dtype == QF_C128 && p->D >= 4) return 1;
+    if (p->D >= 5 || (p->dtype == QF_C128 && p->D >= 4)) return 1;
     return std::min(p->group, 2);
 }
 
@@ -614,7 +615,7 @@ static int local_need(const qf_op& o) {
 // at the default tile size).
 static int default_group(int D, int dtype) {
     (void)dtype;
-    return std::min(max_group_size(uint32_t(D)), D == 2 ? 4 : D <= 4 ? 2 : 1);
+    return std::min(max_group_size(uint32_t(D)), D == 2 ? 4 : D <= 5 ? 2 : 1);
 }
 
 static void tile_shape(int D, int n, int dtype, int tile_opt, int low_opt, bool adjoint, int& k, int& r) {
@@ -1205,7 +1206,7 @@ static qf_status ensure_ckpt(qf_plan* p, const StateView& v) {
 static qf_status launch_forward_pass(const qf_plan* p, const PassList& L, const Pass& ps, const StateView& v,
                                      const void* mats, size_t mat_stride, hipStream_t st) {
     const int kern = p->opts.stage_kernel;
-    if (ps.nrounds > 0 && kern == 2 && p->group <= 3 && v.dtype == QF_C64 && stage_pipe_ok(ps.geom))
+    if (ps.nrounds > 0 && kern == 2 && p->group <= 3 && v.dtype == QF_C64 && p->D <= 12 && stage_pipe_ok(ps.geom))
         return launch_stage_pipe(v, p->group, ps.geom, L.drounds + ps.round_off, ps.nrounds, L.dops + ps.op_off, mats,
                                  p->opts.pipe_wgs > 0 ? p->opts.pipe_wgs : 4, st, mat_stride);
     if (ps.nrounds > 0 && kern != 1)

@@ -147,7 +147,7 @@ qf_status launch_stage_rounds(const StateView& s, int M, const StageGeom& g, con
 // into partial[(slot * nblocks + block) * D*D] (complex FP64).
 qf_status launch_stage_adj(const StateView& s, void* lam, const StageGeom& g, const StageOp* dops, int nops,
                            const void* dmats, double* partial, hipStream_t st, size_t mat_stride = 0);
-// Pipelined persistent forward stage (register rounds, M <= 3, complex64): grid of at most
+// Pipelined persistent forward stage (register rounds, M <= 3, D <= 12, complex64): grid of at most
 // 256 * wgs_per_cu workgroups; needs stage_pipe_ok(g) (runs shorter than a
 // workgroup, at most 32 runs per lane).
 bool stage_pipe_ok(const StageGeom& g);
