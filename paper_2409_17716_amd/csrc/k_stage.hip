@@ -671,15 +671,88 @@ __device__ __forceinline__ uint32_t sub_base(uint64_t digits, const RoundDesc& r
     return tb;
 }
 
+// Adjoint M of a fused run U (the first op of its round, on group position J):
+// M = sum over the fibres f along J of psi_f lam_f^dagger.  Each lane sums its
+// own fibres in registers (MAcc); mreduce_block then adds the lanes in a fixed
+// order (wavefront butterflies, then the waves in order, in FP64).
+template <typename T, int D>
+struct MAcc {
+    T re[D * D], im[D * D];
+};
+
+template <typename T, int D, int M, int J>
+__device__ __forceinline__ void macc_add(MAcc<T, D>& m, const cplx<T> (&p)[cpow(D, M)],
+                                         const cplx<T> (&l)[cpow(D, M)]) {
+    constexpr int SJ = cpow(D, M - 1 - J);
+    constexpr int NF = cpow(D, M - 1);
+#pragma unroll
+    for (int c = 0; c < NF; ++c) {
+        const int b0 = (c / SJ) * SJ * D + (c % SJ);
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int e = 0; e < D; ++e) {
+                const cplx<T> x = p[b0 + a * SJ], y = l[b0 + e * SJ];
+                m.re[a * D + e] = fma(x.re, y.re, fma(x.im, y.im, m.re[a * D + e]));
+                m.im[a * D + e] = fma(x.im, y.re, fma(-x.re, y.im, m.im[a * D + e]));
+            }
+    }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void mreduce_block(MAcc<T, D>& m, double (*red)[kSB], double* __restrict__ out) {
+    constexpr int E = D * D;
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            m.re[e] += __shfl_xor(m.re[e], off);
+            m.im[e] += __shfl_xor(m.im[e], off);
+        }
+    const uint32_t w = threadIdx.x / 64, nw = (blockDim.x + 63) / 64;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            red[0][w * E + e] = double(m.re[e]);
+            red[1][w * E + e] = double(m.im[e]);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < uint32_t(E)) {
+        double sr = 0.0, si = 0.0;
+        for (uint32_t q = 0; q < nw; ++q) {
+            sr += red[0][q * E + threadIdx.x];
+            si += red[1][q * E + threadIdx.x];
+        }
+        out[2 * threadIdx.x] = sr;
+        out[2 * threadIdx.x + 1] = si;
+    }
+    __syncthreads();
+}
+
+// Arguments of the M accumulation of an adjoint round (mslot < 0: none).
+struct MArgs {
+    int mslot = -1;
+    int mpos = 0;
+    double (*red)[kSB] = nullptr;
+    double* partial = nullptr;
+    uint32_t blk = 0;
+};
+
 // One round on the tiles t[0 .. NT) (the adjoint runs psi and lam together).
 // The common round shapes run straight from the LDS loads to the LDS stores
 // (no op dispatch while the sub-tile is live in registers, so no register
 // copies where dispatch paths meet); any other round goes through round_ops.
-template <typename T, int D, int M, int NT>
+template <typename T, int D, int M, int NT, bool MACC = false>
 __device__ __forceinline__ void run_round(cplx<T>* const (&t)[NT], const StageGeom& g, const uint32_t* offhi,
                                           uint32_t base, const RoundDesc& rd, const StageOp* __restrict__ ops,
-                                          const cplx<T>* __restrict__ mats, uint64_t dig0) {
+                                          const cplx<T>* __restrict__ mats, uint64_t dig0, const MArgs& ma = MArgs{}) {
     constexpr int DM = cpow(D, M);
+    MAcc<T, D> macc;
+    if constexpr (MACC) {
+#pragma unroll
+        for (int e = 0; e < D * D; ++e) macc.re[e] = macc.im[e] = T(0);
+    }
     const uint32_t nsub = g.TE / DM;
     const int kind = rd.kind;
     const cplx<T>* U0 = mats;
@@ -701,48 +774,56 @@ __device__ __forceinline__ void run_round(cplx<T>* const (&t)[NT], const StageGe
         const uint64_t dig = u == threadIdx.x ? dig0 : pack_digits<D>(u, rd.nother);
         const uint32_t tb = sub_base(dig, rd);
         const uint32_t gidx0 = rd.need_gidx ? global_index(g, offhi, base, tb) : 0u;
-        cplx<T> v[NT][DM];
-        {
-            uint32_t al[DM];
-            load_addrs<D, M>(al, tb, rd, ops, gidx0);
+        uint32_t al[DM];
+        load_addrs<D, M>(al, tb, rd, ops, gidx0);
+        // the tiles one after the other (one sub-tile live at a time)
 #pragma unroll
-            for (int x = 0; x < NT; ++x)
+        for (int x = 0; x < NT; ++x) {
+            cplx<T> v[DM];
 #pragma unroll
-                for (int i = 0; i < DM; ++i) v[x][i] = t[x][al[i]];
-        }
-        // each shape stores from its own branch
-        auto store = [&]() {
-            uint32_t as[DM];
-            store_addrs<D, M>(as, tb, rd, ops, gidx0);
+            for (int i = 0; i < DM; ++i) v[i] = t[x][al[i]];
+            if constexpr (MACC && NT == 2) {
+                if (x == 0 && ma.mslot >= 0) {
+                    cplx<T> w[DM];
 #pragma unroll
-            for (int x = 0; x < NT; ++x)
-#pragma unroll
-                for (int i = 0; i < DM; ++i) t[x][as[i]] = v[x][i];
-        };
-        if (kind == RK_U0) {
-#pragma unroll
-            for (int x = 0; x < NT; ++x) r_u<T, D, M, 0, false>(v[x], U0);
-            store();
-        } else if (kind == RK_U01) {
-            if constexpr (M >= 2) {
-#pragma unroll
-                for (int x = 0; x < NT; ++x) {
-                    r_u<T, D, M, 0, false>(v[x], U0);
-                    r_u<T, D, M, 1, false>(v[x], U1);
+                    for (int i = 0; i < DM; ++i) w[i] = t[1][al[i]];
+                    if (ma.mpos == 0) {
+                        macc_add<T, D, M, 0>(macc, v, w);
+                    } else {
+                        if constexpr (M >= 2) macc_add<T, D, M, 1>(macc, v, w);
+                    }
                 }
             }
-            store();
-        } else if (kind == RK_U0_REAL) {
+            // each shape stores from its own branch
+            auto store = [&]() {
+                uint32_t as[DM];
+                store_addrs<D, M>(as, tb, rd, ops, gidx0);
 #pragma unroll
-            for (int x = 0; x < NT; ++x) r_u<T, D, M, 0, true>(v[x], U0);
-            store();
-        } else if (kind == RK_NONE) {
-            store();
-        } else {
-#pragma unroll
-            for (int x = 0; x < NT; ++x) round_ops<T, D, M>(v[x], rd, ops, mats, gidx0);
-            store();
+                for (int i = 0; i < DM; ++i) t[x][as[i]] = v[i];
+            };
+            if (kind == RK_U0) {
+                r_u<T, D, M, 0, false>(v, U0);
+                store();
+            } else if (kind == RK_U01) {
+                if constexpr (M >= 2) {
+                    r_u<T, D, M, 0, false>(v, U0);
+                    r_u<T, D, M, 1, false>(v, U1);
+                }
+                store();
+            } else if (kind == RK_U0_REAL) {
+                r_u<T, D, M, 0, true>(v, U0);
+                store();
+            } else if (kind == RK_NONE) {
+                store();
+            } else {
+                round_ops<T, D, M>(v, rd, ops, mats, gidx0);
+                store();
+            }
         }
+    }
+    if constexpr (MACC) {
+        if (ma.mslot >= 0)
+            mreduce_block<T, D>(macc, ma.red, ma.partial + (size_t(ma.mslot) * gridDim.x + ma.blk) * (D * D) * 2);
     }
 }
 
@@ -920,11 +1001,24 @@ __global__ __launch_bounds__(kSB) void k_stage_adj_rounds(cplx<T>* __restrict__ 
     for (int ri = 0; ri < nrounds; ++ri) {
         const RoundDesc& rd = rounds[ri];
         // a slotted U opens its round (never after a leading permutation)
+        MArgs ma;
         if (rd.nops > 0 && rd.pre0 < 0 && rd.pre1 < 0) {
             const StageOp& op0 = ops[rd.op0];
-            if (op0.type == SOP_U && op0.slot >= 0) tile_m<T, D>(tp, tl, g, op0, blk, red, partial);
+            if (op0.type == SOP_U && op0.slot >= 0) {
+                ma.mslot = op0.slot;
+                ma.mpos = op0.gpos;
+            }
         }
-        run_round<T, D, M, 2>(tt, g, offhi, base, rd, ops, mats, dig0);
+        if constexpr (D <= 4) {
+            // M from the registers of the round
+            ma.red = red;
+            ma.partial = partial;
+            ma.blk = blk;
+            run_round<T, D, M, 2, true>(tt, g, offhi, base, rd, ops, mats, dig0, ma);
+        } else {
+            if (ma.mslot >= 0) tile_m<T, D>(tp, tl, g, ops[rd.op0], blk, red, partial);
+            run_round<T, D, M, 2>(tt, g, offhi, base, rd, ops, mats, dig0);
+        }
         __syncthreads();
     }
     tile_store(psi, tp, g, offhi, base);
