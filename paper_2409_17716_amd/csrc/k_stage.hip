@@ -648,26 +648,43 @@ __device__ __forceinline__ void round_ops(cplx<T> (&v)[cpow(D, M)], const RoundD
     }
 }
 
-// Digits of sub-tile u over the k - M other tile qudits, 4 bits each, least
-// significant digit lowest.
+// Digits of sub-tile u over the k - M other tile qudits, least significant
+// first, one byte each; the first 8 digits.
+struct SubDigits {
+    uint32_t w[2];
+};
+
 template <int D>
-__device__ inline uint64_t pack_digits(uint32_t u, int nother) {
-    uint64_t p = 0;
-    for (int j = 0; j < nother; ++j) {
-        const uint32_t q = u / D;
-        p |= uint64_t(u - q * D) << (4 * j);
-        u = q;
+__device__ __forceinline__ SubDigits sub_digits(uint32_t u, int nother) {
+    SubDigits s;
+    s.w[0] = s.w[1] = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        if (j < nother) {
+            const uint32_t q = u / D;
+            s.w[j >> 2] |= (u - q * D) << (8 * (j & 3));
+            u = q;
+        }
     }
-    return p;
+    return s;
 }
 
-// LDS index of the sub-tile's register 0 in round rd.
-__device__ __forceinline__ uint32_t sub_base(uint64_t digits, const RoundDesc& rd) {
+typedef unsigned short qf_u16x2 __attribute__((ext_vector_type(2)));
+
+// LDS index of the sub-tile's register 0 in round rd: dot products of the digit
+// pairs with the round's stride pairs (v_dot2_u32_u16).  Rounds have at most 8
+// other qudits (the planner runs larger tiles op by op).
+template <int D>
+__device__ __forceinline__ uint32_t sub_base(const SubDigits& s, const RoundDesc& rd) {
     uint32_t tb = 0;
-    for (int j = rd.nother - 1; j >= 0; --j) {
-        tb += uint32_t(digits & 15u) * rd.ols[j];
-        digits >>= 4;
-    }
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+        if (2 * w < rd.nother) {
+            // bytes 2w, 2w+1 of the digits as the two 16-bit halves (v_perm_b32)
+            const uint32_t pr = __builtin_amdgcn_perm(0u, s.w[w >> 1], (w & 1) ? 0x0C030C02u : 0x0C010C00u);
+            tb = __builtin_amdgcn_udot2(__builtin_bit_cast(qf_u16x2, pr), __builtin_bit_cast(qf_u16x2, rd.spair[w]),
+                                        tb, false);
+        }
     return tb;
 }
 
@@ -746,7 +763,8 @@ struct MArgs {
 template <typename T, int D, int M, int NT, bool MACC = false>
 __device__ __forceinline__ void run_round(cplx<T>* const (&t)[NT], const StageGeom& g, const uint32_t* offhi,
                                           uint32_t base, const RoundDesc& rd, const StageOp* __restrict__ ops,
-                                          const cplx<T>* __restrict__ mats, uint64_t dig0, const MArgs& ma = MArgs{}) {
+                                          const cplx<T>* __restrict__ mats, const SubDigits& dig0,
+                                          const MArgs& ma = MArgs{}) {
     constexpr int DM = cpow(D, M);
     MAcc<T, D> macc;
     if constexpr (MACC) {
@@ -771,8 +789,7 @@ __device__ __forceinline__ void run_round(cplx<T>* const (&t)[NT], const StageGe
         }
     }
     for (uint32_t u = threadIdx.x; u < nsub; u += blockDim.x) {
-        const uint64_t dig = u == threadIdx.x ? dig0 : pack_digits<D>(u, rd.nother);
-        const uint32_t tb = sub_base(dig, rd);
+        const uint32_t tb = sub_base<D>(u == threadIdx.x ? dig0 : sub_digits<D>(u, rd.nother), rd);
         const uint32_t gidx0 = rd.need_gidx ? global_index(g, offhi, base, tb) : 0u;
         uint32_t al[DM];
         load_addrs<D, M>(al, tb, rd, ops, gidx0);
@@ -842,7 +859,7 @@ __global__ __launch_bounds__(kSB) void k_stage_rounds(cplx<T>* __restrict__ psi,
     __syncthreads();
     tile_load(psi, tile, g, offhi, base);
     __syncthreads();
-    const uint64_t dig0 = nrounds > 0 ? pack_digits<D>(threadIdx.x, rounds[0].nother) : 0;
+    const SubDigits dig0 = sub_digits<D>(threadIdx.x, nrounds > 0 ? rounds[0].nother : 0);
     cplx<T>* const tl[1] = {tile};
     for (int ri = 0; ri < nrounds; ++ri) {
         run_round<T, D, M, 1>(tl, g, offhi, base, rounds[ri], ops, mats, dig0);
@@ -901,7 +918,7 @@ __global__ __launch_bounds__(kSB) void k_stage_pipe(cplx<T>* __restrict__ psi, S
         end = xcd_range_start(x + 1, total);
     }
     if (t < end) pipe_prefetch<T, MAXE>(psi, g, offhi, tile_base<D>(g, t), rp, buf);
-    const uint64_t dig0 = nrounds > 0 ? pack_digits<D>(threadIdx.x, rounds[0].nother) : 0;
+    const SubDigits dig0 = sub_digits<D>(threadIdx.x, nrounds > 0 ? rounds[0].nother : 0);
     cplx<T>* const tl[1] = {tile};
     for (; t < end; t += stride) {
         const uint32_t base = tile_base<D>(g, t);
@@ -996,7 +1013,7 @@ __global__ __launch_bounds__(kSB) void k_stage_adj_rounds(cplx<T>* __restrict__ 
     tile_load(psi, tp, g, offhi, base);
     tile_load(lam, tl, g, offhi, base);
     __syncthreads();
-    const uint64_t dig0 = nrounds > 0 ? pack_digits<D>(threadIdx.x, rounds[0].nother) : 0;
+    const SubDigits dig0 = sub_digits<D>(threadIdx.x, nrounds > 0 ? rounds[0].nother : 0);
     cplx<T>* const tt[2] = {tp, tl};
     for (int ri = 0; ri < nrounds; ++ri) {
         const RoundDesc& rd = rounds[ri];

@@ -810,7 +810,8 @@ static void build_rounds(const qf_plan* p, Pass& ps, PassList& L, const std::vec
     const int M = adjoint ? adj_group(p) : p->group;
     ps.nrounds = 0;
     ps.round_off = int(L.hrounds.size());
-    if (k < M || ps.ops.empty()) return;
+    // rounds address at most 8 other tile qudits (sub_base); larger tiles run op by op
+    if (k < M || k - M > 8 || ps.ops.empty()) return;
     const size_t nops = ps.ops.size();
     auto has = [](const std::vector<int>& v, int d) { return std::find(v.begin(), v.end(), d) != v.end(); };
     auto ctrl_dim = [&](const HOp& h) { return h.ctrl >= 0 ? dim_of[h.ctrl] : -1; };  // -1: none or outside
@@ -913,6 +914,8 @@ static void build_rounds(const qf_plan* p, Pass& ps, PassList& L, const std::vec
         int o = 0;
         for (int d = 0; d < k; ++d)
             if (!has(grp, d)) rd.ols[o++] = ipow(D, k - 1 - d);
+        for (int i = 0; i < 8 && i < rd.nother; ++i)  // strides < 2^16 (tiles hold < 2^16 amplitudes per LDS budget)
+            rd.spair[i / 2] |= (rd.ols[rd.nother - 1 - i] & 0xffffu) << (16 * (i % 2));
         auto gpos_of_qudit = [&](int q) -> int {
             if (q < 0 || dim_of[q] < 0) return -1;
             auto it = std::find(grp.begin(), grp.end(), dim_of[q]);

@@ -111,6 +111,7 @@ struct RoundDesc {
     uint32_t gls[kMaxGroup];        // LDS strides of the group qudits, register digit 0 first
     int32_t nother;                 // k - M
     uint32_t ols[kMaxTileDims];     // LDS strides of the other tile qudits, most significant first
+    uint32_t spair[4];              // the last 8 of ols, least significant first, two 16-bit halves per word
 };
 
 struct StageOp {
