@@ -943,49 +943,70 @@ __global__ __launch_bounds__(kSB) void k_stage_pipe(cplx<T>* __restrict__ psi, S
 
 // M = sum over the tile's fibres along the op's qudit of psi_f lam_f^dagger,
 // from the LDS tiles, into partial[(slot * nblocks + block) * D*D] (complex
-// FP64).  Lane (entry, part) sums fibres part, part + P, ...; the parts are
-// then added in a fixed order.
+// FP64).  Lane (block, part) sums a B x B block of entries (B = 2 for even
+// D >= 4: two psi and two lam reads feed four products) over the fibres
+// part, part + P, ... in the state's precision; the parts are then added in
+// FP64 in a fixed order.
 template <typename T, int D>
 __device__ inline void tile_m(const cplx<T>* tp, const cplx<T>* tl, const StageGeom& g, const StageOp& op,
                               uint32_t blk, double (*red)[kSB], double* __restrict__ partial) {
     constexpr uint32_t E = D * D;
+    constexpr int B = (D % 2 == 0 && D >= 4) ? 2 : 1;
+    constexpr uint32_t NBR = D / B, NB = NBR * NBR;
     const uint32_t nt = blockDim.x;
     const uint32_t nf = g.TE / D;
     double* out = partial + (size_t(op.slot) * gridDim.x + blk) * E * 2;
-    auto entry = [&](uint32_t e, uint32_t f0, uint32_t step, double& ar, double& ai) {
-        const uint32_t a = e / D, c = e % D;
+    auto block_sum = [&](uint32_t bi, uint32_t f0, uint32_t step, T (&ar)[B * B], T (&ai)[B * B]) {
+        const uint32_t a0 = (bi / NBR) * B, c0 = (bi % NBR) * B;
+#pragma unroll
+        for (int j = 0; j < B * B; ++j) ar[j] = ai[j] = T(0);
         for (uint32_t f = f0; f < nf; f += step) {
             const uint32_t lb = fibre_lb<D>(op, f);
-            const cplx<T> x = tp[lb + a * op.ls];
-            const cplx<T> y = tl[lb + c * op.ls];
-            ar += double(x.re) * double(y.re) + double(x.im) * double(y.im);
-            ai += double(x.im) * double(y.re) - double(x.re) * double(y.im);
+            cplx<T> x[B], y[B];
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                x[i] = tp[lb + (a0 + i) * op.ls];
+                y[i] = tl[lb + (c0 + i) * op.ls];
+            }
+#pragma unroll
+            for (int i = 0; i < B; ++i)
+#pragma unroll
+                for (int j = 0; j < B; ++j) {
+                    ar[i * B + j] = fma(x[i].re, y[j].re, fma(x[i].im, y[j].im, ar[i * B + j]));
+                    ai[i * B + j] = fma(x[i].im, y[j].re, fma(-x[i].re, y[j].im, ai[i * B + j]));
+                }
         }
     };
-    if (E <= nt) {
-        // lane (entry, part): fibres part, part + P, ...; parts added in order
-        const uint32_t P = nt / E;
-        const uint32_t e = threadIdx.x % E, part = threadIdx.x / E;
-        double ar = 0.0, ai = 0.0;
-        if (part < P) entry(e, part, P, ar, ai);
-        red[0][threadIdx.x] = ar;
-        red[1][threadIdx.x] = ai;
-        __syncthreads();
-        if (threadIdx.x < E) {
-            double sr = 0.0, si = 0.0;
-            for (uint32_t q = 0; q < P; ++q) {
-                sr += red[0][q * E + threadIdx.x];
-                si += red[1][q * E + threadIdx.x];
+    auto entry = [&](uint32_t bi, int j) { return ((bi / NBR) * B + j / B) * D + (bi % NBR) * B + j % B; };
+    if (nt >= NB) {
+        const uint32_t P = nt / NB;
+        const uint32_t bi = threadIdx.x % NB, part = threadIdx.x / NB;
+        T ar[B * B], ai[B * B];
+        block_sum(bi, part, P, ar, ai);
+        for (uint32_t q = 0; q < P; ++q) {
+            if (part == q) {
+#pragma unroll
+                for (int j = 0; j < B * B; ++j) {
+                    const uint32_t e = entry(bi, j);
+                    red[0][e] = (q ? red[0][e] : 0.0) + double(ar[j]);
+                    red[1][e] = (q ? red[1][e] : 0.0) + double(ai[j]);
+                }
             }
-            out[2 * threadIdx.x] = sr;
-            out[2 * threadIdx.x + 1] = si;
+            __syncthreads();
+        }
+        for (uint32_t e = threadIdx.x; e < E; e += nt) {
+            out[2 * e] = red[0][e];
+            out[2 * e + 1] = red[1][e];
         }
     } else {
-        for (uint32_t e = threadIdx.x; e < E; e += nt) {
-            double ar = 0.0, ai = 0.0;
-            entry(e, 0, 1, ar, ai);
-            out[2 * e] = ar;
-            out[2 * e + 1] = ai;
+        for (uint32_t bi = threadIdx.x; bi < NB; bi += nt) {
+            T ar[B * B], ai[B * B];
+            block_sum(bi, 0, 1, ar, ai);
+#pragma unroll
+            for (int j = 0; j < B * B; ++j) {
+                out[2 * entry(bi, j)] = double(ar[j]);
+                out[2 * entry(bi, j) + 1] = double(ai[j]);
+            }
         }
     }
     __syncthreads();
