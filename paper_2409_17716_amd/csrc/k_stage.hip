@@ -691,7 +691,7 @@ __device__ __forceinline__ uint32_t sub_base(const SubDigits& s, const RoundDesc
 // Adjoint M of a fused run U (the first op of its round, on group position J):
 // M = sum over the fibres f along J of psi_f lam_f^dagger.  Each lane sums its
 // own fibres in registers (MAcc); mreduce_block then adds the lanes in a fixed
-// order (DPP butterflies inside the wavefront, then the waves in order, in FP64).
+// order (DPP butterflies inside 16-lane rows, then the rows in order, in FP64).
 template <typename T, int D>
 struct MAcc {
     T re[D * D], im[D * D];
@@ -716,9 +716,7 @@ __device__ __forceinline__ void macc_add(MAcc<T, D>& m, const cplx<T> (&p)[cpow(
     }
 }
 
-// Sum over the 64 lanes of a wavefront, in a fixed order: DPP butterflies
-// inside each row of 16 lanes (VALU only, no LDS traffic), then the four row
-// sums read as scalars.  Every lane receives the total.
+// DPP moves (lane permutations inside 16-lane rows; VALU only, no LDS traffic).
 template <int CTRL>
 __device__ __forceinline__ float dpp_f32(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
@@ -732,31 +730,23 @@ __device__ __forceinline__ double dpp_f64(double v) {
     return __builtin_bit_cast(double, uint64_t(lo) | (uint64_t(hi) << 32));
 }
 
-__device__ __forceinline__ float lane_f32(float v, int l) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
-}
-
-__device__ __forceinline__ double lane_f64(double v, int l) {
-    const uint64_t b = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(b)), l));
-    const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(b >> 32)), l));
-    return __builtin_bit_cast(double, uint64_t(lo) | (uint64_t(hi) << 32));
-}
-
-__device__ __forceinline__ float wave_sum(float v) {
-    v += dpp_f32<0xB1>(v);   // quad_perm [1,0,3,2]
-    v += dpp_f32<0x4E>(v);   // quad_perm [2,3,0,1]
-    v += dpp_f32<0x124>(v);  // row_ror:4
-    v += dpp_f32<0x128>(v);  // row_ror:8
-    return (lane_f32(v, 0) + lane_f32(v, 16)) + (lane_f32(v, 32) + lane_f32(v, 48));
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-    v += dpp_f64<0xB1>(v);
-    v += dpp_f64<0x4E>(v);
-    v += dpp_f64<0x124>(v);
-    v += dpp_f64<0x128>(v);
-    return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
+// Row sums by DPP (every lane of a 16-lane row then holds its row's sum); the
+// first lane of each row writes it to LDS, and E lanes add the rows of all
+// wavefronts in a fixed order in FP64.
+template <typename T>
+__device__ __forceinline__ T row_sum(T v) {
+    if constexpr (sizeof(T) == 4) {
+        v += dpp_f32<0xB1>(v);   // quad_perm [1,0,3,2]
+        v += dpp_f32<0x4E>(v);   // quad_perm [2,3,0,1]
+        v += dpp_f32<0x124>(v);  // row_ror:4
+        v += dpp_f32<0x128>(v);  // row_ror:8
+    } else {
+        v += dpp_f64<0xB1>(v);
+        v += dpp_f64<0x4E>(v);
+        v += dpp_f64<0x124>(v);
+        v += dpp_f64<0x128>(v);
+    }
+    return v;
 }
 
 template <typename T, int D>
@@ -764,21 +754,21 @@ __device__ __forceinline__ void mreduce_block(MAcc<T, D>& m, double (*red)[kSB],
     constexpr int E = D * D;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        m.re[e] = wave_sum(m.re[e]);
-        m.im[e] = wave_sum(m.im[e]);
+        m.re[e] = row_sum(m.re[e]);
+        m.im[e] = row_sum(m.im[e]);
     }
-    const uint32_t w = threadIdx.x / 64, nw = (blockDim.x + 63) / 64;
-    if ((threadIdx.x & 63) == 0) {
+    const uint32_t row = threadIdx.x / 16, nrows = (blockDim.x + 15) / 16;
+    if ((threadIdx.x & 15) == 0) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            red[0][w * E + e] = double(m.re[e]);
-            red[1][w * E + e] = double(m.im[e]);
+            red[0][row * E + e] = double(m.re[e]);
+            red[1][row * E + e] = double(m.im[e]);
         }
     }
     __syncthreads();
     if (threadIdx.x < uint32_t(E)) {
         double sr = 0.0, si = 0.0;
-        for (uint32_t q = 0; q < nw; ++q) {
+        for (uint32_t q = 0; q < nrows; ++q) {
             sr += red[0][q * E + threadIdx.x];
             si += red[1][q * E + threadIdx.x];
         }
