@@ -537,8 +537,13 @@ __device__ __forceinline__ uint32_t lane_shift(const StageOp& P, uint32_t gidx0)
     uint32_t sh = uint32_t(P.shifts[0]);
     if (P.has_ctrl) {
         const uint32_t xc = P.ctrl_stride.div(gidx0) % D;
+        if (P.shift_mul >= 0) {
+            // affine table shifts[c] = (mul * c + shifts[0]) mod D (CSUM: mul = 1)
+            sh = (uint32_t(P.shift_mul) * xc + sh) % D;
+        } else {
 #pragma unroll
-        for (int c = 1; c < D; ++c) sh = xc == uint32_t(c) ? uint32_t(P.shifts[c]) : sh;
+            for (int c = 1; c < D; ++c) sh = xc == uint32_t(c) ? uint32_t(P.shifts[c]) : sh;
+        }
     }
     return sh;
 }
@@ -565,7 +570,7 @@ __device__ __forceinline__ void load_addrs(uint32_t (&a)[cpow(D, M)], uint32_t t
             uint32_t od[D];
             const uint32_t s0 = rd.pre0 >= 0 ? neg_mod<D>(lane_shift<D>(ops[rd.pre0], gidx0)) : 0u;
 #pragma unroll
-            for (int d = 0; d < D; ++d) od[d] = add_mod<D>(uint32_t(d), s0) * rd.gls[0];
+            for (int d = 0; d < D; ++d) od[d] = __umul24(add_mod<D>(uint32_t(d), s0), rd.gls[0]);
 #pragma unroll
             for (int i = 0; i < DM; ++i) {
                 const int d0 = rdigit<D, M, 0>(i);
@@ -594,7 +599,7 @@ __device__ __forceinline__ void load_addrs(uint32_t (&a)[cpow(D, M)], uint32_t t
     const uint32_t s = neg_mod<D>(lane_shift<D>(P, gidx0));
     uint32_t od[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d) od[d] = add_mod<D>(uint32_t(d), s) * rd.gls[0];
+    for (int d = 0; d < D; ++d) od[d] = __umul24(add_mod<D>(uint32_t(d), s), rd.gls[0]);
 #pragma unroll
     for (int i = 0; i < DM; ++i) a[i] = tb + od[rdigit<D, M, 0>(i)] + rest_offset<D, M>(i, rd.gls);
 }
@@ -622,7 +627,7 @@ __device__ __forceinline__ void store_addrs(uint32_t (&a)[cpow(D, M)], uint32_t 
     const uint32_t s = lane_shift<D>(P, gidx0);
     uint32_t od[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d) od[d] = add_mod<D>(uint32_t(d), s) * rd.gls[0];
+    for (int d = 0; d < D; ++d) od[d] = __umul24(add_mod<D>(uint32_t(d), s), rd.gls[0]);
 #pragma unroll
     for (int i = 0; i < DM; ++i) a[i] = tb + od[rdigit<D, M, 0>(i)] + rest_offset<D, M>(i, rd.gls);
 }

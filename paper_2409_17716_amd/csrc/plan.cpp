@@ -1058,6 +1058,12 @@ static void finalize_passes(const qf_plan* p, PassList& L, bool adjoint) {
                     const int v = shift_of(o, c, D);
                     so.shifts[c] = r.inv ? (D - v) % D : v;
                 }
+                so.shift_mul = -1;
+                for (int a = 0; a < D && so.shift_mul < 0; ++a) {
+                    bool ok = true;
+                    for (int c = 0; c < D; ++c) ok = ok && so.shifts[c] == (a * c + so.shifts[0]) % D;
+                    if (ok) so.shift_mul = a;
+                }
             } else {
                 so.npairs = int(h.g.size());
                 for (size_t j = 0; j < h.g.size(); ++j) {

@@ -122,6 +122,7 @@ struct StageOp {
     int32_t has_ctrl;     // SHIFT: 1 if controlled
     FastDiv ctrl_stride;  // SHIFT: global stride of the control qudit
     int32_t shifts[16];   // SHIFT: x_t -> x_t + shifts[x_c] (already in [0, D))
+    int32_t shift_mul;    // SHIFT: shifts[c] = (shift_mul * c + shifts[0]) mod D, or -1 if not affine
     int32_t mat;          // U: offset (complex elements) of the D x D matrix
     int32_t real;         // U: all imaginary parts are zero
     int32_t slot;         // adjoint: M slot of this U inside the stage, -1 = none
