@@ -793,7 +793,8 @@ struct MArgs {
 };
 
 // One round on the tiles t[0 .. NT) (the adjoint runs psi and lam together).
-// The common round shapes run straight from the LDS loads to the LDS stores
+// The common round shapes (one U on position 0 or 1, two U on positions 0 and
+// 1, one PHASE, permutations only) run straight from the LDS loads to the LDS stores
 // (no op dispatch while the sub-tile is live in registers, so no register
 // copies where dispatch paths meet); any other round goes through round_ops.
 template <typename T, int D, int M, int NT, bool MACC = false>
@@ -811,7 +812,7 @@ __device__ __forceinline__ void run_round(cplx<T>* const (&t)[NT], const StageGe
     const int kind = rd.kind;
     const cplx<T>* U0 = mats;
     const cplx<T>* U1 = mats;
-    if (kind == RK_U0 || kind == RK_U0_REAL || kind == RK_U01) {
+    if (kind == RK_U0 || kind == RK_U0_REAL || kind == RK_U01 || kind == RK_U1 || kind == RK_U1_REAL) {
         const StageOp& oa = ops[rd.op0];
         U0 = mats + oa.mat;
         if (kind == RK_U01) {
@@ -865,6 +866,15 @@ __device__ __forceinline__ void run_round(cplx<T>* const (&t)[NT], const StageGe
                 store();
             } else if (kind == RK_U0_REAL) {
                 r_u<T, D, M, 0, true>(v, U0);
+                store();
+            } else if (kind == RK_U1) {
+                if constexpr (M >= 2) r_u<T, D, M, 1, false>(v, U0);
+                store();
+            } else if (kind == RK_U1_REAL) {
+                if constexpr (M >= 2) r_u<T, D, M, 1, true>(v, U0);
+                store();
+            } else if (kind == RK_PHASE) {
+                r_phase<T, D, M>(v, ops[rd.op0], mats, gidx0);
                 store();
             } else if (kind == RK_NONE) {
                 store();

@@ -971,6 +971,8 @@ static void build_rounds(const qf_plan* p, Pass& ps, PassList& L, const std::vec
                 if (so.type == SOP_U && so.gpos >= 0 && so.gpos < 2) posmask |= 1 << so.gpos;
             }
             if (allu && rd.nops == 1 && posmask == 1) rd.kind = anyreal ? RK_U0_REAL : RK_U0;
+            if (allu && rd.nops == 1 && posmask == 2 && M >= 2) rd.kind = anyreal ? RK_U1_REAL : RK_U1;
+            if (rd.nops == 1 && L.hops[ps.op_off + ip0].type == SOP_PHASE) rd.kind = RK_PHASE;
             if (allu && rd.nops == 2 && posmask == 3 && !anyreal && M >= 2) rd.kind = RK_U01;
         }
         L.hrounds.push_back(rd);

@@ -102,6 +102,9 @@ enum RoundKind : int32_t {
     RK_U0 = 2,       // one complex U on group position 0
     RK_U0_REAL = 3,  // one real U on group position 0
     RK_U01 = 4,      // two complex U on group positions 0 and 1
+    RK_U1 = 5,       // one complex U on group position 1
+    RK_U1_REAL = 6,  // one real U on group position 1
+    RK_PHASE = 7,    // one PHASE op
 };
 struct RoundDesc {
     int32_t kind;
