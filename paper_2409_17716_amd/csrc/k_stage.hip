@@ -3,17 +3,22 @@
 //
 // Load/store: tile element e lives at base + offhi[e / R] + e % R; consecutive
 // lanes take consecutive e, so each wavefront reads contiguous runs of R = D^r
-// amplitudes (r low qudits are always in the tile).
+// amplitudes (r low qudits are always in the tile).  Workgroups map to tiles
+// through tile_of_block, which keeps neighbouring tiles on one XCD.
 //
 // Ops (read from a device array; every lane reads the same op, so the loads are
 // scalar):
-//   SOP_U      dense D x D matrix on one tile qudit: each lane takes whole fibres
-//              (D amplitudes at LDS stride D^(k-1-dim)) into registers.
-//   SOP_SHIFT  x_t -> x_t + shifts[x_c] mod D on a tile qudit t; the control
-//              digit comes from the fibre's global index, so the control may be
-//              any qudit, inside or outside the tile.  Pure data movement.
-//   SOP_PHASE  product of two-qudit diagonal factors table[x_a * D + x_b]; the
-//              digits come from the global index, so a and b may be any qudits.
+//   SOP_U      dense D x D matrix on one tile qudit.
+//   SOP_SHIFT  x_t -> x_t + shifts[x_c] mod D on a tile qudit t; the control may
+//              be any qudit, inside or outside the tile.  Pure data movement.
+//   SOP_PHASE  product of two-qudit diagonal factors table[x_a * D + x_b]; a and
+//              b may be any qudits.
+//
+// Kernels: k_stage (one LDS sweep per op), k_stage_rounds (register rounds, the
+// default; see "Register rounds" below), k_stage_pipe (register rounds in a
+// persistent grid with the next tile prefetched into registers), and the
+// reverse-stage kernels k_stage_adj / k_stage_adj_rounds, which apply the
+// inverted ops to psi and lam and accumulate the adjoint's M matrices.
 #include <algorithm>
 #include <type_traits>
 
