@@ -124,26 +124,102 @@ __global__ void k_build_mats(const DevGroup* __restrict__ groups, int ngroups, c
     }
 }
 
-// Hermitian generator S of a rotation, as a dense matrix.
+// One thread per (register, run): V_i = product of the run's gates after gate
+// i; contribution of rotation i = Im Tr(V_i S_i V_i^dagger M) = Im Tr(S_i W_i)
+// with W_i = V_i^dagger M V_i.  Walking the run backwards, W starts as M and
+// becomes G_i^dagger W G_i after gate i; rotations and phases touch two rows and
+// columns or scale them, so a step costs O(D) or O(D^2) (the Fourier gate O(D^3)).
 template <int D>
-__device__ inline void dm_generator(const DevGate& g, DMat<D>& s) {
+__device__ inline void dm_conj_diag(DMat<D>& w, const cplx<double> (&g)[D]) {
+    // W <- diag(g)^dagger W diag(g)
     for (int r = 0; r < D; ++r)
-        for (int c = 0; c < D; ++c) s.m[r][c] = cmake<double>(0.0, 0.0);
-    if (g.kind == QF_OP_RX) {
-        s.m[g.j][g.k] = cmake<double>(1.0, 0.0);
-        s.m[g.k][g.j] = cmake<double>(1.0, 0.0);
-    } else if (g.kind == QF_OP_RY) {
-        s.m[g.j][g.k] = cmake<double>(0.0, -1.0);
-        s.m[g.k][g.j] = cmake<double>(0.0, 1.0);
-    } else {
-        const double al = sqrt(2.0 / (double(g.j) * (g.j + 1)));
-        for (int l = 0; l < g.j; ++l) s.m[l][l] = cmake<double>(al, 0.0);
-        s.m[g.j][g.j] = cmake<double>(-al * g.j, 0.0);
+        for (int q = 0; q < D; ++q) w.m[r][q] = cmul(cmul(cmake<double>(g[r].re, -g[r].im), w.m[r][q]), g[q]);
+}
+
+template <int D>
+__device__ inline void dm_conj_gate(DMat<D>& w, const DevGate& gi, const double* th) {
+    const double t = gi.param >= 0 ? th[gi.param] : 0.0;
+    switch (gi.kind) {
+        case QF_OP_RX:
+        case QF_OP_RY: {
+            double sn, cs;
+            sincos(0.5 * t, &sn, &cs);
+            // 2x2 block on levels (j, k): [[a, b], [c, d]]
+            const cplx<double> a = cmake<double>(cs, 0.0), d = a;
+            const cplx<double> bb = gi.kind == QF_OP_RX ? cmake<double>(0.0, -sn) : cmake<double>(-sn, 0.0);
+            const cplx<double> cc = gi.kind == QF_OP_RX ? cmake<double>(0.0, -sn) : cmake<double>(sn, 0.0);
+            const int j = gi.j, k = gi.k;
+            for (int r = 0; r < D; ++r) {  // W <- W G (columns j, k)
+                const cplx<double> x = w.m[r][j], y = w.m[r][k];
+                w.m[r][j] = cadd(cmul(x, a), cmul(y, cc));
+                w.m[r][k] = cadd(cmul(x, bb), cmul(y, d));
+            }
+            for (int q = 0; q < D; ++q) {  // W <- G^dagger W (rows j, k)
+                const cplx<double> x = w.m[j][q], y = w.m[k][q];
+                w.m[j][q] = cadd(cmul(cconj(a), x), cmul(cconj(cc), y));
+                w.m[k][q] = cadd(cmul(cconj(bb), x), cmul(cconj(d), y));
+            }
+            return;
+        }
+        case QF_OP_RZ: {
+            const double al = sqrt(2.0 / (double(gi.j) * (gi.j + 1)));
+            cplx<double> g[D];
+            for (int r = 0; r < D; ++r) {
+                const double ang = r < gi.j ? -0.5 * t * al : r == gi.j ? 0.5 * t * al * gi.j : 0.0;
+                double sn, cs;
+                sincos(ang, &sn, &cs);
+                g[r] = cmake<double>(cs, sn);
+            }
+            dm_conj_diag<D>(w, g);
+            return;
+        }
+        case QF_OP_CLOCK: {
+            const int e = ((gi.j % D) + D) % D;
+            cplx<double> g[D];
+            for (int r = 0; r < D; ++r) {
+                double sn, cs;
+                if (gi.param >= 0)
+                    sincospi(2.0 * t * r / D, &sn, &cs);
+                else
+                    sincospi(2.0 * double((e * r) % D) / D, &sn, &cs);
+                g[r] = cmake<double>(cs, sn);
+            }
+            dm_conj_diag<D>(w, g);
+            return;
+        }
+        default: {
+            // Fourier: H[x][q] = w^(xq) / sqrt(D); W <- H^dagger (W H), row by row then column by column
+            const double s = 1.0 / sqrt(double(D));
+            cplx<double> tmp[D];
+            for (int r = 0; r < D; ++r) {
+                for (int q = 0; q < D; ++q) {
+                    cplx<double> acc = cmake<double>(0.0, 0.0);
+                    for (int x = 0; x < D; ++x) {
+                        double sn, cs;
+                        sincospi(2.0 * double((x * q) % D) / D, &sn, &cs);
+                        cmac(acc, w.m[r][x], cmake<double>(s * cs, s * sn));
+                    }
+                    tmp[q] = acc;
+                }
+                for (int q = 0; q < D; ++q) w.m[r][q] = tmp[q];
+            }
+            for (int q = 0; q < D; ++q) {
+                for (int r = 0; r < D; ++r) {
+                    cplx<double> acc = cmake<double>(0.0, 0.0);
+                    for (int x = 0; x < D; ++x) {
+                        double sn, cs;
+                        sincospi(2.0 * double((x * r) % D) / D, &sn, &cs);
+                        cmac(acc, cmake<double>(s * cs, -s * sn), w.m[x][q]);
+                    }
+                    tmp[r] = acc;
+                }
+                for (int r = 0; r < D; ++r) w.m[r][q] = tmp[r];
+            }
+            return;
+        }
     }
 }
 
-// One thread per (register, run): V_i = product of the run's gates after gate
-// i; contribution of rotation i = Im Tr(V_i S_i V_i^dagger M).
 template <int D>
 __global__ void k_grad_contrib(const DevGradGroup* __restrict__ gg, int ngg, const DevGate* __restrict__ gates,
                                const double* __restrict__ theta, int64_t theta_stride, const double* __restrict__ M,
@@ -154,45 +230,23 @@ __global__ void k_grad_contrib(const DevGradGroup* __restrict__ gg, int ngg, con
     const DevGradGroup g = gg[t - b * uint32_t(ngg)];
     const double* th = theta + size_t(b) * size_t(theta_stride);
     const double* Mb = M + (size_t(b) * nslots + g.gslot) * D * D * 2;
-    DMat<D> V, S, A;
-    dm_identity<D>(V);
+    DMat<D> W;
+    for (int r = 0; r < D; ++r)
+        for (int q = 0; q < D; ++q) W.m[r][q] = cmake<double>(Mb[2 * (r * D + q)], Mb[2 * (r * D + q) + 1]);
     int c = g.c0;
-    // walk the run backwards: V starts as the identity (after the last gate)
     for (int i = g.ng - 1; i >= 0; --i) {
         const DevGate& gi = gates[g.g0 + i];
-        const bool rot = gi.kind == QF_OP_RX || gi.kind == QF_OP_RY || gi.kind == QF_OP_RZ;
-        if (rot) {
-            dm_generator<D>(gi, S);
-            // A = V S V^dagger; contribution = Im sum_{r,q} A[r][q] M[q][r]
-            for (int r = 0; r < D; ++r)
-                for (int q = 0; q < D; ++q) {
-                    cplx<double> acc = cmake<double>(0.0, 0.0);
-                    for (int x = 0; x < D; ++x) cmac(acc, V.m[r][x], S.m[x][q]);
-                    A.m[r][q] = acc;
-                }
+        if (gi.kind == QF_OP_RX) {
+            contrib[size_t(b) * ncontrib + c++] = W.m[gi.k][gi.j].im + W.m[gi.j][gi.k].im;
+        } else if (gi.kind == QF_OP_RY) {
+            contrib[size_t(b) * ncontrib + c++] = W.m[gi.j][gi.k].re - W.m[gi.k][gi.j].re;
+        } else if (gi.kind == QF_OP_RZ) {
+            const double al = sqrt(2.0 / (double(gi.j) * (gi.j + 1)));
             double im = 0.0;
-            for (int r = 0; r < D; ++r)
-                for (int q = 0; q < D; ++q) {
-                    // (A V^dagger)[r][q] = sum_x A[r][x] conj(V[q][x])
-                    cplx<double> acc = cmake<double>(0.0, 0.0);
-                    for (int x = 0; x < D; ++x) cmac_conj(acc, V.m[q][x], A.m[r][x]);
-                    const double mr = Mb[2 * (q * D + r)], mi = Mb[2 * (q * D + r) + 1];
-                    im += acc.re * mi + acc.im * mr;
-                }
-            contrib[size_t(b) * ncontrib + c] = im;
-            ++c;
+            for (int l = 0; l < gi.j; ++l) im += W.m[l][l].im;
+            contrib[size_t(b) * ncontrib + c++] = al * im - al * gi.j * W.m[gi.j][gi.j].im;
         }
-        // V <- V G_i
-        DMat<D> Gt;
-        dm_identity<D>(Gt);
-        dm_apply_gate<D>(gi, th, false, Gt);
-        for (int r = 0; r < D; ++r)
-            for (int q = 0; q < D; ++q) {
-                cplx<double> acc = cmake<double>(0.0, 0.0);
-                for (int x = 0; x < D; ++x) cmac(acc, V.m[r][x], Gt.m[x][q]);
-                A.m[r][q] = acc;
-            }
-        V = A;
+        dm_conj_gate<D>(W, gi, th);
     }
 }
 

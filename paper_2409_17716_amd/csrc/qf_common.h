@@ -28,6 +28,16 @@ __host__ __device__ inline cplx<T> cmul(cplx<T> a, cplx<T> b) {
     return cmake<T>(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
 }
 
+template <typename T>
+__host__ __device__ inline cplx<T> cadd(cplx<T> a, cplx<T> b) {
+    return cmake<T>(a.re + b.re, a.im + b.im);
+}
+
+template <typename T>
+__host__ __device__ inline cplx<T> cconj(cplx<T> a) {
+    return cmake<T>(a.re, -a.im);
+}
+
 // acc += a * b
 template <typename T>
 __host__ __device__ inline void cmac(cplx<T>& acc, cplx<T> a, cplx<T> b) {
