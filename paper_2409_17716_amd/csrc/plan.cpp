@@ -626,15 +626,6 @@ static void tile_shape(int D, int n, int dtype, int tile_opt, int low_opt, bool 
     // 7 qudits; D = 5: 4 qudits, 2.4x faster per pass than 5 qudits in 50 KB),
     // 64 KB for D = 4 (6 qudits: 15% faster than 5 on batches of 4^8 registers).
     const size_t budget = (adjoint ? (D == 4 ? 64 : 40) * 1024 : 32 * 1024);
-    // A register that fits one workgroup's LDS (96 KB forward, 128 KB for psi
-    // and lam) is one tile: the whole circuit in one pass (small registers of a
-    // batch have few tiles, so workgroup count is set by the batch anyway).
-    const size_t whole = size_t(ipow(D, n)) * esz * (adjoint ? 2 : 1);
-    if (tile_opt == 0 && whole <= (adjoint ? 128 * 1024 : 96 * 1024)) {
-        k = n;
-        r = n;
-        return;
-    }
     if (tile_opt > 0) {
         k = tile_opt;
     } else {
