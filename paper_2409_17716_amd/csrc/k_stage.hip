@@ -94,6 +94,32 @@ constexpr int kIO = 8;
 // offset o inside a run and walks runs, so no per-element division is needed:
 // with R < 256 the lanes form G = 256 / R groups of R (group gr takes runs
 // gr, gr + G, ...); otherwise every lane strides through each run by 256.
+template <typename T, bool LOAD, typename Ref>
+__device__ __forceinline__ void tile_io_runs(cplx<T>* tile, const StageGeom& g, uint32_t G, uint32_t gr, uint32_t o,
+                                             Ref&& at) {
+    uint32_t h = gr;
+    for (; h + (kIO - 1) * G < g.nhi; h += G * kIO) {
+        cplx<T> t[kIO];
+        if (LOAD) {
+#pragma unroll
+            for (int j = 0; j < kIO; ++j) t[j] = at(h + j * G);
+#pragma unroll
+            for (int j = 0; j < kIO; ++j) tile[(h + j * G) * g.R + o] = t[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < kIO; ++j) t[j] = tile[(h + j * G) * g.R + o];
+#pragma unroll
+            for (int j = 0; j < kIO; ++j) at(h + j * G) = t[j];
+        }
+    }
+    for (; h < g.nhi; h += G) {
+        if (LOAD)
+            tile[h * g.R + o] = at(h);
+        else
+            at(h) = tile[h * g.R + o];
+    }
+}
+
 template <typename T, bool LOAD>
 __device__ inline void tile_io(cplx<T>* __restrict__ psi, cplx<T>* tile, const StageGeom& g, const uint32_t* offhi,
                                uint32_t base) {
@@ -102,36 +128,25 @@ __device__ inline void tile_io(cplx<T>* __restrict__ psi, cplx<T>* tile, const S
         const uint32_t gr = threadIdx.x / g.R;
         const uint32_t o = threadIdx.x - gr * g.R;
         if (gr >= G) return;
-        uint32_t h = gr;
-        for (; h + (kIO - 1) * G < g.nhi; h += G * kIO) {
-            cplx<T> t[kIO];
-            if (LOAD) {
-#pragma unroll
-                for (int j = 0; j < kIO; ++j) t[j] = psi[base + offhi[h + j * G] + o];
-#pragma unroll
-                for (int j = 0; j < kIO; ++j) tile[(h + j * G) * g.R + o] = t[j];
-            } else {
-#pragma unroll
-                for (int j = 0; j < kIO; ++j) t[j] = tile[(h + j * G) * g.R + o];
-#pragma unroll
-                for (int j = 0; j < kIO; ++j) psi[base + offhi[h + j * G] + o] = t[j];
-            }
+        if (uint64_t(g.N) * sizeof(cplx<T>) <= 0xffffffffull) {
+            // registers below 4 GB: one uniform 64-bit tile pointer and 32-bit
+            // byte offsets (scalar-base addressing, one VALU op per access)
+            char* pb = reinterpret_cast<char*>(psi + base);
+            tile_io_runs<T, LOAD>(tile, g, G, gr, o, [&](uint32_t h) -> cplx<T>& {
+                return *reinterpret_cast<cplx<T>*>(pb + (offhi[h] + o) * uint32_t(sizeof(cplx<T>)));
+            });
+            return;
         }
-        for (; h < g.nhi; h += G) {
+        tile_io_runs<T, LOAD>(tile, g, G, gr, o, [&](uint32_t h) -> cplx<T>& { return psi[base + offhi[h] + o]; });
+        return;
+    }
+    for (uint32_t h = 0; h < g.nhi; ++h) {
+        const uint32_t gb = base + offhi[h];
+        for (uint32_t o = threadIdx.x; o < g.R; o += blockDim.x) {
             if (LOAD)
-                tile[h * g.R + o] = psi[base + offhi[h] + o];
+                tile[h * g.R + o] = psi[gb + o];
             else
-                psi[base + offhi[h] + o] = tile[h * g.R + o];
-        }
-    } else {
-        for (uint32_t h = 0; h < g.nhi; ++h) {
-            const uint32_t gb = base + offhi[h];
-            for (uint32_t o = threadIdx.x; o < g.R; o += blockDim.x) {
-                if (LOAD)
-                    tile[h * g.R + o] = psi[gb + o];
-                else
-                    psi[gb + o] = tile[h * g.R + o];
-            }
+                psi[gb + o] = tile[h * g.R + o];
         }
     }
 }
