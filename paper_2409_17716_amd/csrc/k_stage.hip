@@ -881,6 +881,9 @@ __device__ __forceinline__ void run_round(cplx<T>* const (&t)[NT], const StageGe
             } else if (kind == RK_U01) {
                 if constexpr (M >= 2) {
                     r_u<T, D, M, 0, false>(v, U0);
+                    // keep the second matrix's loads after the first product
+                    // (hoisting them would hold both matrices in registers)
+                    asm volatile("" ::: "memory");
                     r_u<T, D, M, 1, false>(v, U1);
                 }
                 store();
@@ -899,7 +902,8 @@ __device__ __forceinline__ void run_round(cplx<T>* const (&t)[NT], const StageGe
             } else if (kind == RK_NONE) {
                 store();
             } else {
-                round_ops<T, D, M>(v, rd, ops, mats, gidx0);
+                // generic rounds exist only for groups of 3 or more qudits
+                if constexpr (M >= 3) round_ops<T, D, M>(v, rd, ops, mats, gidx0);
                 store();
             }
         }

@@ -849,14 +849,27 @@ static void build_rounds(const qf_plan* p, Pass& ps, PassList& L, const std::vec
             m.insert(m.end(), rest.begin(), rest.end());
             return m;
         };
+        // groups of at most 2 qudits take only the dispatch-free shapes: one U,
+        // one PHASE, or two complex U on different qudits (the kernels compile
+        // the generic interpreter for larger groups only)
+        const bool small = M <= 2;
+        auto is_real_u = [&](size_t x) { return L.hops[ps.op_off + x].real != 0; };
         for (; j < nops; ++j) {
             const HOp& h = ps.ops[j];
             if (j > i && slotted(j)) break;
+            const size_t nin = j - ip0;  // in-place ops taken so far
             if (h.type == SOP_PHASE) {
+                if (small && nin > 0) break;
                 ipe = j + 1;
                 continue;
             }
             if (h.type == SOP_U) {
+                if (small && nin > 0) {
+                    const HOp& f = ps.ops[ip0];
+                    const bool pair_ok = M == 2 && nin == 1 && f.type == SOP_U && f.q != h.q && !is_real_u(ip0) &&
+                                         !is_real_u(j);
+                    if (!pair_ok) break;
+                }
                 const int d = dim_of[h.q];
                 const std::vector<int> m = members();
                 if (!has(m, d)) {
@@ -965,6 +978,13 @@ static void build_rounds(const qf_plan* p, Pass& ps, PassList& L, const std::vec
             if (allu && rd.nops == 1 && posmask == 2 && M >= 2) rd.kind = anyreal ? RK_U1_REAL : RK_U1;
             if (rd.nops == 1 && L.hops[ps.op_off + ip0].type == SOP_PHASE) rd.kind = RK_PHASE;
             if (allu && rd.nops == 2 && posmask == 3 && !anyreal && M >= 2) rd.kind = RK_U01;
+        }
+        if (M <= 2 && rd.kind == RK_GENERIC) {
+            // the shape rules above exclude this; should it happen, the pass
+            // runs op by op (the round kernels for M <= 2 have no interpreter)
+            L.hrounds.resize(size_t(ps.round_off));
+            ps.nrounds = 0;
+            return;
         }
         L.hrounds.push_back(rd);
         ++ps.nrounds;
