@@ -431,9 +431,10 @@ template <typename T, int D, int M, int J, bool REAL>
 __device__ __forceinline__ void r_u(cplx<T> (&v)[cpow(D, M)], const cplx<T>* __restrict__ U) {
     constexpr int SJ = cpow(D, M - 1 - J);
     constexpr int NF = cpow(D, M - 1);
-    // small matrices are read once into scalar registers; larger ones are read
-    // from memory where used (a local copy would not fit the scalar file)
-    constexpr bool kCopy = D <= 6;
+    // matrices up to 4 x 4 are read once into scalar registers; larger ones
+    // are read from memory where used (a local copy spills into vector
+    // registers and lowers occupancy)
+    constexpr bool kCopy = D <= 4;
     cplx<T> m[kCopy ? D * D : 1];
     if constexpr (kCopy) {
 #pragma unroll
