@@ -670,17 +670,50 @@ static void make_geom(int D, int n, int k, int r, const std::vector<int>& T, Sta
         if (!in[q]) g.out_stride[o++] = ipow(D, n - 1 - q);
 }
 
-// Greedy stage builder over a gate sequence.  Each pass picks a tile (the low
-// r qudits plus the qudits the earliest remaining gates need), then takes, in
-// order, every remaining gate whose target is in the tile and that commutes
-// with every gate left behind so far (two gates commute when every qudit they
-// share is one on which both act block-diagonally).
-static void plan_passes(const qf_plan* p, const std::vector<GRef>& seq, int k, int r, int seg, PassList& out) {
+// Gates a pass over tile inT would take: every remaining gate (from index
+// first on) whose target is in the tile and that commutes with every gate left
+// behind so far (two gates commute when every qudit they share is one on which
+// both act block-diagonally).  Returns the count of multi-qudit gates taken in
+// the high 32 bits and the count of all gates taken in the low 32 bits.
+static uint64_t pass_take(const qf_plan* p, const std::vector<GRef>& seq, const std::vector<char>& done, int first,
+                          const std::vector<char>& inT, std::vector<char>& bFull, std::vector<char>& bDiag,
+                          std::vector<Touch>& tv) {
+    std::fill(bFull.begin(), bFull.end(), 0);
+    std::fill(bDiag.begin(), bDiag.end(), 0);
+    uint64_t multi = 0, all = 0;
+    for (int i = first; i < int(seq.size()); ++i) {
+        if (done[i]) continue;
+        const qf_op& o = op_of(p, seq[i]);
+        touches(o, tv);
+        bool conflict = false;
+        for (const Touch& t : tv) conflict = conflict || bFull[t.q] || (!t.diag && bDiag[t.q]);
+        const int need = local_need(o);
+        if (!conflict && o.kind != QF_OP_U && (need < 0 || inT[need])) {
+            ++all;
+            multi += tv.size() > 1 ? 1 : 0;
+        } else {
+            for (const Touch& t : tv) (t.diag ? bDiag : bFull)[t.q] = 1;
+        }
+    }
+    return (multi << 32) | all;
+}
+
+// Greedy stage builder over a gate sequence.  Each pass picks a tile of k
+// qudits (the low r qudits plus the qudits the earliest remaining gates need),
+// then takes the gates pass_take admits, in order.  With climb set, the tile is
+// then improved by single swaps of a non-low qudit in for one out (the qudit
+// the first remaining gate needs stays), each taken when it raises the number
+// of multi-qudit gates the pass takes, then the number of all gates: the
+// entangling gates are the chain that orders a circuit's layers, so a tile that
+// advances that chain further leaves less for later passes.
+static void plan_passes_one(const qf_plan* p, const std::vector<GRef>& seq, int k, int r, int seg, bool climb,
+                            std::vector<Pass>& out) {
     const int n = p->n;
     const int m = int(seq.size());
     std::vector<char> done(m, 0);
     int remaining = m, first = 0;
     std::vector<Touch> tv;
+    std::vector<char> tb0(n), tb1(n);
     while (remaining > 0) {
         while (done[first]) ++first;
         const qf_op& o0 = op_of(p, seq[first]);
@@ -691,7 +724,7 @@ static void plan_passes(const qf_plan* p, const std::vector<GRef>& seq, int k, i
             pf.seg = seg;
             done[first] = 1;
             --remaining;
-            out.passes.push_back(pf);
+            out.push_back(pf);
             continue;
         }
         std::vector<char> inT(n, 0);
@@ -704,6 +737,29 @@ static void plan_passes(const qf_plan* p, const std::vector<GRef>& seq, int k, i
         }
         for (int q = n - r - 1; q >= 0 && cnt < k; --q)
             if (!inT[q]) inT[q] = 1, ++cnt;
+        if (climb) {
+            const int keep = local_need(o0);
+            uint64_t best = pass_take(p, seq, done, first, inT, tb0, tb1, tv);
+            for (bool improved = true; improved;) {
+                improved = false;
+                for (int a = 0; a < n - r && !improved; ++a) {
+                    if (!inT[a] || a == keep) continue;
+                    for (int b = 0; b < n - r && !improved; ++b) {
+                        if (inT[b]) continue;
+                        inT[a] = 0;
+                        inT[b] = 1;
+                        const uint64_t sc = pass_take(p, seq, done, first, inT, tb0, tb1, tv);
+                        if (sc > best) {
+                            best = sc;
+                            improved = true;
+                        } else {
+                            inT[a] = 1;
+                            inT[b] = 0;
+                        }
+                    }
+                }
+            }
+        }
         Pass ps;
         ps.seg = seg;
         for (int q = 0; q < n; ++q)
@@ -759,8 +815,24 @@ static void plan_passes(const qf_plan* p, const std::vector<GRef>& seq, int k, i
             }
         }
         for (int q = 0; q < n; ++q) flush(q);
-        out.passes.push_back(ps);
+        out.push_back(ps);
     }
+}
+
+// Passes of one gate sequence: the greedy plan, and for states of at least
+// 2^20 amplitudes (where every pass is a full sweep of HBM) also the climbed
+// one; the plan with fewer passes is kept (ties: the greedy plan).
+static void plan_passes(const qf_plan* p, const std::vector<GRef>& seq, int k, int r, int seg, PassList& out) {
+    std::vector<Pass> greedy;
+    plan_passes_one(p, seq, k, r, seg, false, greedy);
+    double amps = 1;
+    for (int i = 0; i < p->n; ++i) amps *= p->D;
+    if (amps >= double(1 << 20) && r < p->n && k < p->n) {
+        std::vector<Pass> climbed;
+        plan_passes_one(p, seq, k, r, seg, true, climbed);
+        if (climbed.size() < greedy.size()) greedy.swap(climbed);
+    }
+    for (Pass& ps : greedy) out.passes.push_back(std::move(ps));
 }
 
 // Number of low qudits of the tiles: fewer low qudits leave more tile qudits to
