@@ -70,8 +70,9 @@ def build(jobs: int = 8, verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     shutil.move(tmp, LIB)
-    # the matrix-build and gradient kernels keep D x D FP64 matrices in private memory by design
-    expected = [w for w in warnings if "k_build_mats" in w or "k_grad_contrib" in w]
+    # the matrix-build and gradient kernels keep D x D FP64 matrices in private memory by design;
+    # the 8-wave round kernels trade a small spill for occupancy
+    expected = [w for w in warnings if "k_build_mats" in w or "k_grad_contrib" in w or "k_stage_rounds_w8" in w]
     for w in warnings:
         if w not in expected:
             print("[qf build] warning:", w, file=sys.stderr)

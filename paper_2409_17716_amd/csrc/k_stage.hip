@@ -916,10 +916,10 @@ __device__ __forceinline__ void run_round(cplx<T>* const (&t)[NT], const StageGe
 }
 
 template <typename T, int D, int M>
-__global__ __launch_bounds__(kSB) void k_stage_rounds(cplx<T>* __restrict__ psi, StageGeom g,
-                                                      const RoundDesc* __restrict__ rounds, int nrounds,
-                                                      const StageOp* __restrict__ ops,
-                                                      const cplx<T>* __restrict__ mats, size_t mat_stride) {
+__device__ __forceinline__ void stage_rounds(cplx<T>* __restrict__ psi, const StageGeom& g,
+                                             const RoundDesc* __restrict__ rounds, int nrounds,
+                                             const StageOp* __restrict__ ops, const cplx<T>* __restrict__ mats,
+                                             size_t mat_stride) {
     const uint32_t blk = tile_of_block(g);
     mats += size_t(blk / g.ntiles) * mat_stride;
     extern __shared__ unsigned char smem[];
@@ -937,6 +937,36 @@ __global__ __launch_bounds__(kSB) void k_stage_rounds(cplx<T>* __restrict__ psi,
         __syncthreads();
     }
     tile_store(psi, tile, g, offhi, base);
+}
+
+template <typename T, int D, int M>
+__global__ __launch_bounds__(kSB) void k_stage_rounds(cplx<T>* __restrict__ psi, StageGeom g,
+                                                      const RoundDesc* __restrict__ rounds, int nrounds,
+                                                      const StageOp* __restrict__ ops,
+                                                      const cplx<T>* __restrict__ mats, size_t mat_stride) {
+    stage_rounds<T, D, M>(psi, g, rounds, nrounds, ops, mats, mat_stride);
+}
+
+// The same kernel compiled for 8 waves per SIMD.  The default build of these
+// instantiations holds 106 scalar registers, which caps a SIMD at 7 waves
+// (800 scalar registers each); this one is held to 78 at the price of at
+// most 64 bytes of spill per lane (measured 2% faster for D = 10 in
+// complex64; no change for D = 3 groups of 2, whose rounds are bound by the
+// latency of their LDS and scalar-load round trips, so those keep the default
+// build).
+template <typename T, int D, int M>
+__global__ __launch_bounds__(kSB) __attribute__((amdgpu_waves_per_eu(8))) void k_stage_rounds_w8(
+    cplx<T>* __restrict__ psi, StageGeom g, const RoundDesc* __restrict__ rounds, int nrounds,
+    const StageOp* __restrict__ ops, const cplx<T>* __restrict__ mats, size_t mat_stride) {
+    stage_rounds<T, D, M>(psi, g, rounds, nrounds, ops, mats, mat_stride);
+}
+
+// Instantiations that take k_stage_rounds_w8: default occupancy below 8 and
+// the 8-wave build spills at most 64 bytes per lane.
+template <typename T, int D, int M>
+constexpr bool rounds_w8() {
+    if constexpr (sizeof(T) == 4) return M == 2 ? D == 2 : (M == 1 && D >= 5 && D <= 11);
+    else return M == 2 ? D == 2 : (M == 1 && D >= 3 && D <= 5);
 }
 
 // Pipelined persistent variant: a workgroup walks a strided sequence of
@@ -1200,8 +1230,14 @@ static qf_status launch_rounds_m(const StateView& s, const StageGeom& g, const R
     const uint32_t grid = g.ntiles * s.batch;
     const size_t lds = stage_lds_bytes(g, s.dtype, false);
     const uint32_t nthr = rounds_threads(g, cpow(D, M));
-    hipLaunchKernelGGL((k_stage_rounds<T, D, M>), dim3(grid), dim3(nthr), lds, st, reinterpret_cast<cplx<T>*>(s.amps),
-                       g, drounds, nrounds, dops, reinterpret_cast<const cplx<T>*>(dmats), mat_stride);
+    if constexpr (rounds_w8<T, D, M>())
+        hipLaunchKernelGGL((k_stage_rounds_w8<T, D, M>), dim3(grid), dim3(nthr), lds, st,
+                           reinterpret_cast<cplx<T>*>(s.amps), g, drounds, nrounds, dops,
+                           reinterpret_cast<const cplx<T>*>(dmats), mat_stride);
+    else
+        hipLaunchKernelGGL((k_stage_rounds<T, D, M>), dim3(grid), dim3(nthr), lds, st,
+                           reinterpret_cast<cplx<T>*>(s.amps), g, drounds, nrounds, dops,
+                           reinterpret_cast<const cplx<T>*>(dmats), mat_stride);
     return check_launch("stage rounds");
 }
 
@@ -1222,7 +1258,9 @@ static qf_status launch_pipe_m(const StateView& s, const StageGeom& g, const Rou
     int ncu = 256;
     {
         int dev = 0;
-        if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            ncu = 256;
     }
     const uint32_t cap = uint32_t(ncu) * uint32_t(std::min(wgs_per_cu, occ));
     const uint32_t grid = total < cap ? total : cap;
