@@ -181,6 +181,10 @@ typedef struct qf_plan_opts {
     int32_t pipe_wgs;     /* stage_kernel 2: workgroups per compute unit; 0 = 4        */
     int32_t tile_order;   /* 0 = each XCD (own L2) walks a contiguous range of tiles  */
                           /* (default); 1 = tiles in plain dispatch order            */
+    int32_t tile_search;  /* stage tiles: 0 = the greedy choice, and for states of   */
+                          /* at least 2^20 amplitudes also the greedy choice improved */
+                          /* by single-qudit swaps, keeping the plan with fewer      */
+                          /* passes (default); 1 = greedy only; 2 = as 0 at any size */
 } qf_plan_opts;
 
 /* Compile a circuit (ops applied in order) for registers of n qudits of

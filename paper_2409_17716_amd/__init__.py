@@ -43,7 +43,8 @@ class qf_op(ctypes.Structure):
 class qf_plan_opts(ctypes.Structure):
     _fields_ = [("fuse", ctypes.c_int32), ("tile_digits", ctypes.c_int32), ("low_digits", ctypes.c_int32),
                 ("ckpt_every", ctypes.c_int32), ("adj_tile_digits", ctypes.c_int32), ("stage_kernel", ctypes.c_int32),
-                ("group_digits", ctypes.c_int32), ("pipe_wgs", ctypes.c_int32), ("tile_order", ctypes.c_int32)]
+                ("group_digits", ctypes.c_int32), ("pipe_wgs", ctypes.c_int32), ("tile_order", ctypes.c_int32),
+                ("tile_search", ctypes.c_int32)]
 
 
 class qf_kernel_stat(ctypes.Structure):
@@ -285,12 +286,12 @@ class Plan:
     def __init__(self, dim: int, n: int, ops: Sequence[tuple], nparams: int, dtype: str = "c64",
                  fuse: int = 0, tile_digits: int = 0, low_digits: int = 0, ckpt_every: int = 0,
                  adj_tile_digits: int = 0, stage_kernel: int = 0, group_digits: int = 0, pipe_wgs: int = 0,
-                 tile_order: int = 0):
+                 tile_order: int = 0, tile_search: int = 0):
         self.dim, self.n, self.nparams = dim, n, nparams
         self.dtype = QF_C64 if dtype == "c64" else QF_C128
         arr, keep = ops_to_c(ops)
         opts = qf_plan_opts(fuse, tile_digits, low_digits, ckpt_every, adj_tile_digits, stage_kernel, group_digits,
-                            pipe_wgs, tile_order)
+                            pipe_wgs, tile_order, tile_search)
         h = ctypes.c_void_p()
         _check(lib.qf_plan_create(dim, n, self.dtype, arr, len(ops), nparams, ctypes.byref(opts), ctypes.byref(h)))
         self._h = h

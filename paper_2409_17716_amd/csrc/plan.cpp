@@ -819,15 +819,17 @@ static void plan_passes_one(const qf_plan* p, const std::vector<GRef>& seq, int 
     }
 }
 
-// Passes of one gate sequence: the greedy plan, and for states of at least
-// 2^20 amplitudes (where every pass is a full sweep of HBM) also the climbed
-// one; the plan with fewer passes is kept (ties: the greedy plan).
+// Passes of one gate sequence: the greedy plan, and (tile_search 0: for
+// states of at least 2^20 amplitudes, where every pass is a full sweep of HBM;
+// 2: at any size) also the climbed one; the plan with fewer passes is kept
+// (ties: the greedy plan).
 static void plan_passes(const qf_plan* p, const std::vector<GRef>& seq, int k, int r, int seg, PassList& out) {
     std::vector<Pass> greedy;
     plan_passes_one(p, seq, k, r, seg, false, greedy);
     double amps = 1;
     for (int i = 0; i < p->n; ++i) amps *= p->D;
-    if (amps >= double(1 << 20) && r < p->n && k < p->n) {
+    const int search = p->opts.tile_search;
+    if (search != 1 && (search == 2 || amps >= double(1 << 20)) && r < p->n && k < p->n) {
         std::vector<Pass> climbed;
         plan_passes_one(p, seq, k, r, seg, true, climbed);
         if (climbed.size() < greedy.size()) greedy.swap(climbed);
@@ -1427,7 +1429,8 @@ qf_status qf_plan_create(int32_t dim, int32_t n, int32_t dtype, const qf_op* ops
     QF_RETURN_IF(p->opts.tile_digits < 0 || p->opts.tile_digits > kMaxTileDims || p->opts.adj_tile_digits < 0 ||
                      p->opts.adj_tile_digits > kMaxTileDims || p->opts.low_digits < 0 || p->opts.ckpt_every < 0 ||
                      p->opts.stage_kernel < 0 || p->opts.stage_kernel > 2 || p->opts.pipe_wgs < 0 ||
-                     p->opts.pipe_wgs > 16 || p->opts.tile_order < 0 || p->opts.tile_order > 1,
+                     p->opts.pipe_wgs > 16 || p->opts.tile_order < 0 || p->opts.tile_order > 1 ||
+                     p->opts.tile_search < 0 || p->opts.tile_search > 2,
                  QF_EINVAL, "bad tile / checkpoint options");
     p->gates.resize(nops);
     for (int i = 0; i < nops; ++i) {

@@ -98,3 +98,20 @@ def test_plan_validation_and_schedule(qf):
     for bad in ([("rx", 0, 1, 1, 0)], [("rz", 0, 0, 0)], [("csum", 1, 1)], [("h", 9)], [("rx", 0, 0, 1, 5)]):
         with pytest.raises(qf.QfError):
             qf.Plan(3, 4, bad, 1)
+
+
+def test_tile_search(qf):
+    """Stage planning on the host: the swap-improved tile choice never costs
+    passes (the plan keeps whichever choice has fewer), and it saves passes on
+    the D=10, n=8 ansatz, whose greedy tiles leave entangling gates behind."""
+    for c in (qi.config2(), qi.config3(), qi.config5(), qi.config2(n=8, layers=3)):
+        greedy = qf.plan_for(c, tile_search=1)
+        auto = qf.plan_for(c)
+        full = qf.plan_for(c, tile_search=2)
+        assert auto.num_stages <= greedy.num_stages
+        assert full.num_stages <= greedy.num_stages
+        assert auto.num_adjoint_stages <= greedy.num_adjoint_stages
+    c5 = qi.config5()
+    assert qf.plan_for(c5).num_stages < qf.plan_for(c5, tile_search=1).num_stages
+    with pytest.raises(qf.QfError):
+        qf.plan_for(c5, tile_search=3)

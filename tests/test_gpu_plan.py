@@ -221,3 +221,21 @@ def test_tile_order(qf, order, kernel):
     g = p1.adjoint_grad(psi, lam, c.theta, terms)
     gref = grad.adjoint(c, terms)
     assert np.abs(g - gref).max() <= 1e-4 * max(1.0, np.abs(gref).max())
+
+
+@pytest.mark.parametrize("search", [1, 2])
+def test_tile_search(qf, search):
+    """Greedy tiles and swap-improved tiles (forced at this small size): forward
+    and adjoint against the oracle, with tiles small enough that the two
+    choices give different pass lists."""
+    c = qi.config2(n=8, layers=3)
+    p = qf.plan_for(c, "c64", tile_digits=4, low_digits=1, adj_tile_digits=4, tile_search=search)
+    t = qf.new_state(c.n, c.dim, "c64")
+    qf.qf_state_init(t, c.n, c.dim, None)
+    p.forward(t, c.theta)
+    assert maxabs(to_np(t), sim.run(c)) <= 2e-5
+    terms = qi.zsum_terms(c.n)
+    lam = qf.new_state(c.n, c.dim, "c64")
+    g = p.adjoint_grad(t, lam, c.theta, terms)
+    gref = grad.adjoint(c, terms)
+    assert np.abs(g - gref).max() <= 1e-4 * max(1.0, np.abs(gref).max())
