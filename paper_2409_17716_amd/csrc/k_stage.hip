@@ -587,7 +587,6 @@ __device__ __forceinline__ void load_addrs(uint32_t (&a)[cpow(D, M)], uint32_t t
     constexpr int DM = cpow(D, M);
     if constexpr (M >= 2) {
         if (rd.pre1 >= 0) {
-            const StageOp& B = ops[rd.pre1];
             uint32_t od[D];
             const uint32_t s0 = rd.pre0 >= 0 ? neg_mod<D>(lane_shift<D>(ops[rd.pre0], gidx0)) : 0u;
 #pragma unroll
@@ -595,7 +594,7 @@ __device__ __forceinline__ void load_addrs(uint32_t (&a)[cpow(D, M)], uint32_t t
 #pragma unroll
             for (int i = 0; i < DM; ++i) {
                 const int d0 = rdigit<D, M, 0>(i);
-                const uint32_t e1 = add_mod<D>(uint32_t(rdigit<D, M, 1>(i)), neg_mod<D>(uint32_t(B.shifts[d0])));
+                const uint32_t e1 = add_mod<D>(uint32_t(rdigit<D, M, 1>(i)), neg_mod<D>(uint32_t(rd.pre1_shifts[d0])));
                 a[i] = tb + od[d0] + e1 * rd.gls[1] + rest2_offset<D, M>(i, rd.gls);
             }
             return;
@@ -831,21 +830,9 @@ __device__ __forceinline__ void run_round(cplx<T>* const (&t)[NT], const StageGe
     }
     const uint32_t nsub = g.TE / DM;
     const int kind = rd.kind;
-    const cplx<T>* U0 = mats;
-    const cplx<T>* U1 = mats;
-    if (kind == RK_U0 || kind == RK_U0_REAL || kind == RK_U01 || kind == RK_U1 || kind == RK_U1_REAL) {
-        const StageOp& oa = ops[rd.op0];
-        U0 = mats + oa.mat;
-        if (kind == RK_U01) {
-            const StageOp& ob = ops[rd.op0 + 1];
-            U1 = mats + ob.mat;
-            if (oa.gpos != 0) {  // the two U act on different qudits and commute
-                const cplx<T>* x = U0;
-                U0 = U1;
-                U1 = x;
-            }
-        }
-    }
+    // U shapes: the matrices of position 0 (or the one U) and position 1
+    const cplx<T>* U0 = mats + rd.mat0;
+    const cplx<T>* U1 = mats + rd.mat1;
     for (uint32_t u = threadIdx.x; u < nsub; u += blockDim.x) {
         const uint32_t tb = sub_base<D>(u == threadIdx.x ? dig0 : sub_digits<D>(u, rd.nother), rd);
         const uint32_t gidx0 = rd.need_gidx ? global_index(g, offhi, base, tb) : 0u;

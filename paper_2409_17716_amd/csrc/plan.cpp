@@ -1053,6 +1053,23 @@ static void build_rounds(const qf_plan* p, Pass& ps, PassList& L, const std::vec
             if (rd.nops == 1 && L.hops[ps.op_off + ip0].type == SOP_PHASE) rd.kind = RK_PHASE;
             if (allu && rd.nops == 2 && posmask == 3 && !anyreal && M >= 2) rd.kind = RK_U01;
         }
+        if (rd.kind == RK_U0 || rd.kind == RK_U0_REAL || rd.kind == RK_U1 || rd.kind == RK_U1_REAL ||
+            rd.kind == RK_U01) {
+            const StageOp& a = L.hops[ps.op_off + ip0];
+            rd.mat0 = rd.mat1 = a.mat;
+            if (rd.kind == RK_U01) {
+                const StageOp& b = L.hops[ps.op_off + ip0 + 1];
+                // the two U act on different qudits and commute: mat0 is position 0's
+                if (a.gpos == 0) {
+                    rd.mat1 = b.mat;
+                } else {
+                    rd.mat0 = b.mat;
+                    rd.mat1 = a.mat;
+                }
+            }
+        }
+        if (pre1 >= 0)
+            for (int c = 0; c < 16; ++c) rd.pre1_shifts[c] = L.hops[ps.op_off + size_t(pre1)].shifts[c];
         if (M <= 2 && rd.kind == RK_GENERIC) {
             // the shape rules above exclude this; should it happen, the pass
             // runs op by op (the round kernels for M <= 2 have no interpreter)

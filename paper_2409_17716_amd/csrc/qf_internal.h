@@ -115,6 +115,10 @@ struct RoundDesc {
     int32_t nother;                 // k - M
     uint32_t ols[kMaxTileDims];     // LDS strides of the other tile qudits, most significant first
     uint32_t spair[4];              // the last 8 of ols, least significant first, two 16-bit halves per word
+    // copies of op fields the round's common shapes read, so that a round needs
+    // no op lookup before its matrix loads
+    int32_t mat0, mat1;             // U shapes: matrix offset of the U on position 0 (or the one U), position 1
+    int32_t pre1_shifts[16];        // pre1: the permutation's shifts[x_c]
 };
 
 struct StageOp {
