@@ -553,8 +553,8 @@ __device__ __forceinline__ uint32_t rest2_offset(int i, const uint32_t* gls) {
 // Shift of a permutation op whose control is not a group qudit: one value per
 // lane (the control digit is constant over the sub-tile), or shifts[0] when
 // the op has no control.
-template <int D>
-__device__ __forceinline__ uint32_t lane_shift(const StageOp& P, uint32_t gidx0) {
+template <int D, class Perm>
+__device__ __forceinline__ uint32_t lane_shift(const Perm& P, uint32_t gidx0) {
     uint32_t sh = uint32_t(P.shifts[0]);
     if (P.has_ctrl) {
         const uint32_t xc = P.ctrl_stride.div(gidx0) % D;
@@ -588,13 +588,13 @@ __device__ __forceinline__ void load_addrs(uint32_t (&a)[cpow(D, M)], uint32_t t
     if constexpr (M >= 2) {
         if (rd.pre1 >= 0) {
             uint32_t od[D];
-            const uint32_t s0 = rd.pre0 >= 0 ? neg_mod<D>(lane_shift<D>(ops[rd.pre0], gidx0)) : 0u;
+            const uint32_t s0 = rd.pre0 >= 0 ? neg_mod<D>(lane_shift<D>(rd.perm[0], gidx0)) : 0u;
 #pragma unroll
             for (int d = 0; d < D; ++d) od[d] = __umul24(add_mod<D>(uint32_t(d), s0), rd.gls[0]);
 #pragma unroll
             for (int i = 0; i < DM; ++i) {
                 const int d0 = rdigit<D, M, 0>(i);
-                const uint32_t e1 = add_mod<D>(uint32_t(rdigit<D, M, 1>(i)), neg_mod<D>(uint32_t(rd.pre1_shifts[d0])));
+                const uint32_t e1 = add_mod<D>(uint32_t(rdigit<D, M, 1>(i)), neg_mod<D>(uint32_t(rd.perm[1].shifts[d0])));
                 a[i] = tb + od[d0] + e1 * rd.gls[1] + rest2_offset<D, M>(i, rd.gls);
             }
             return;
@@ -605,7 +605,7 @@ __device__ __forceinline__ void load_addrs(uint32_t (&a)[cpow(D, M)], uint32_t t
         for (int i = 0; i < DM; ++i) a[i] = tb + uint32_t(rdigit<D, M, 0>(i)) * rd.gls[0] + rest_offset<D, M>(i, rd.gls);
         return;
     }
-    const StageOp& P = ops[rd.pre0];
+    const PermDesc& P = rd.perm[0];
     if constexpr (M >= 2) {
         if (P.ctrl_gpos == 1) {
 #pragma unroll
@@ -633,7 +633,7 @@ __device__ __forceinline__ void store_addrs(uint32_t (&a)[cpow(D, M)], uint32_t 
         for (int i = 0; i < DM; ++i) a[i] = tb + uint32_t(rdigit<D, M, 0>(i)) * rd.gls[0] + rest_offset<D, M>(i, rd.gls);
         return;
     }
-    const StageOp& P = ops[rd.post];
+    const PermDesc& P = rd.perm[2];
     if constexpr (M >= 2) {
         if (P.ctrl_gpos == 1) {
 #pragma unroll
@@ -1128,13 +1128,8 @@ __global__ __launch_bounds__(kSB) void k_stage_adj_rounds(cplx<T>* __restrict__ 
         const RoundDesc& rd = rounds[ri];
         // a slotted U opens its round (never after a leading permutation)
         MArgs ma;
-        if (rd.nops > 0 && rd.pre0 < 0 && rd.pre1 < 0) {
-            const StageOp& op0 = ops[rd.op0];
-            if (op0.type == SOP_U && op0.slot >= 0) {
-                ma.mslot = op0.slot;
-                ma.mpos = op0.gpos;
-            }
-        }
+        ma.mslot = rd.mslot;
+        ma.mpos = rd.mpos;
         if constexpr (D <= 4) {
             // M from the registers of the round
             ma.red = red;

@@ -1068,8 +1068,27 @@ static void build_rounds(const qf_plan* p, Pass& ps, PassList& L, const std::vec
                 }
             }
         }
-        if (pre1 >= 0)
-            for (int c = 0; c < 16; ++c) rd.pre1_shifts[c] = L.hops[ps.op_off + size_t(pre1)].shifts[c];
+        rd.mslot = rd.mpos = -1;
+        if (rd.nops > 0 && pre0 < 0 && pre1 < 0) {
+            const StageOp& so = L.hops[ps.op_off + ip0];
+            if (so.type == SOP_U && so.slot >= 0) {
+                rd.mslot = so.slot;
+                rd.mpos = so.gpos;
+            }
+        }
+        {
+            const int perm_ops[3] = {pre0, pre1, post};
+            for (int j = 0; j < 3; ++j) {
+                if (perm_ops[j] < 0) continue;
+                const StageOp& so = L.hops[ps.op_off + size_t(perm_ops[j])];
+                PermDesc& pd = rd.perm[j];
+                pd.has_ctrl = so.has_ctrl;
+                pd.ctrl_gpos = so.ctrl_gpos;
+                pd.shift_mul = so.shift_mul;
+                pd.ctrl_stride = so.ctrl_stride;
+                for (int c = 0; c < 16; ++c) pd.shifts[c] = so.shifts[c];
+            }
+        }
         if (M <= 2 && rd.kind == RK_GENERIC) {
             // the shape rules above exclude this; should it happen, the pass
             // runs op by op (the round kernels for M <= 2 have no interpreter)

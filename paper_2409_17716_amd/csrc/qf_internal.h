@@ -106,6 +106,16 @@ enum RoundKind : int32_t {
     RK_U1_REAL = 6,  // one real U on group position 1
     RK_PHASE = 7,    // one PHASE op
 };
+// A permutation op folded into a round's loads or stores (a copy of its op's
+// fields, so that the round reads them with its own descriptor).
+struct PermDesc {
+    int32_t has_ctrl;       // 1 if controlled
+    int32_t ctrl_gpos;      // group position of the control, -1 = not in the group
+    int32_t shift_mul;      // shifts[c] = (shift_mul * c + shifts[0]) mod D, or -1 if not affine
+    FastDiv ctrl_stride;    // global stride of the control qudit
+    int32_t shifts[16];     // x_t -> x_t + shifts[x_c]
+};
+
 struct RoundDesc {
     int32_t kind;
     int32_t op0, nops;
@@ -116,9 +126,10 @@ struct RoundDesc {
     uint32_t ols[kMaxTileDims];     // LDS strides of the other tile qudits, most significant first
     uint32_t spair[4];              // the last 8 of ols, least significant first, two 16-bit halves per word
     // copies of op fields the round's common shapes read, so that a round needs
-    // no op lookup before its matrix loads
+    // no op lookup before its matrix loads or its addresses
     int32_t mat0, mat1;             // U shapes: matrix offset of the U on position 0 (or the one U), position 1
-    int32_t pre1_shifts[16];        // pre1: the permutation's shifts[x_c]
+    PermDesc perm[3];               // the pre0, pre1 and post permutations (where present)
+    int32_t mslot, mpos;            // adjoint: M slot and group position of the U that opens the round, -1 = none
 };
 
 struct StageOp {
