@@ -52,14 +52,18 @@ TILES = [(3, 1), (3, 2), (4, 2), (5, 3), (2, 1)]
 
 
 @pytest.mark.parametrize("tile,low", TILES)
-@pytest.mark.parametrize("kernel,group", [(0, 0), (0, 1), (0, 9), (1, 0), (2, 0), (2, 1), (2, 9)])
+@pytest.mark.parametrize("kernel,group", [(0, 0), (0, 1), (0, 2), (0, 9), (1, 0), (2, 0), (2, 1), (2, 9)])
 def test_stage_tiles_small(qf, tile, low, kernel, group):
     """Small tiles force many passes, controls outside the tile and deferred gates;
     kernel 0 = register rounds (group 9 = the largest group compiled for D),
-    1 = one LDS sweep per op."""
+    1 = one LDS sweep per op.  The group sizes reach both builds of the round
+    kernel (the 8-wave one for single-qudit groups of D = 5..11 in complex64,
+    D = 3..5 in complex128, and D = 2 pairs)."""
     for c, dt in ((qi.config2(n=7, layers=3), "c64"), (qi.random_circuit(3, 6, 150, 21), "c128"),
                   (qi.config3(n=5, layers=2), "c64"), (qi.random_circuit(4, 5, 150, 22), "c64"),
-                  (qi.random_circuit(2, 9, 200, 23), "c64"), (qi.random_circuit(7, 4, 100, 24), "c64")):
+                  (qi.random_circuit(2, 9, 200, 23), "c64"), (qi.random_circuit(7, 4, 100, 24), "c64"),
+                  (qi.random_circuit(5, 4, 100, 25), "c128"), (qi.random_circuit(4, 4, 100, 26), "c128"),
+                  (qi.random_circuit(2, 8, 150, 27), "c128")):
         gmax = {2: 5, 3: 3, 4: 2, 5: 2}.get(c.dim, 1)
         if kernel == 2:
             gmax = min(gmax, 3)
