@@ -583,7 +583,7 @@ __device__ __forceinline__ uint32_t neg_mod(uint32_t s) {
 // them: register (d0, d1) stores to (d0 + s(d1), d1).
 template <int D, int M>
 __device__ __forceinline__ void load_addrs(uint32_t (&a)[cpow(D, M)], uint32_t tb, const RoundDesc& rd,
-                                           const StageOp* __restrict__ ops, uint32_t gidx0) {
+                                           uint32_t gidx0) {
     constexpr int DM = cpow(D, M);
     if constexpr (M >= 2) {
         if (rd.pre1 >= 0) {
@@ -626,7 +626,7 @@ __device__ __forceinline__ void load_addrs(uint32_t (&a)[cpow(D, M)], uint32_t t
 
 template <int D, int M>
 __device__ __forceinline__ void store_addrs(uint32_t (&a)[cpow(D, M)], uint32_t tb, const RoundDesc& rd,
-                                            const StageOp* __restrict__ ops, uint32_t gidx0) {
+                                            uint32_t gidx0) {
     constexpr int DM = cpow(D, M);
     if (rd.post < 0) {
 #pragma unroll
@@ -837,7 +837,7 @@ __device__ __forceinline__ void run_round(cplx<T>* const (&t)[NT], const StageGe
         const uint32_t tb = sub_base<D>(u == threadIdx.x ? dig0 : sub_digits<D>(u, rd.nother), rd);
         const uint32_t gidx0 = rd.need_gidx ? global_index(g, offhi, base, tb) : 0u;
         uint32_t al[DM];
-        load_addrs<D, M>(al, tb, rd, ops, gidx0);
+        load_addrs<D, M>(al, tb, rd, gidx0);
         // the tiles one after the other (one sub-tile live at a time)
 #pragma unroll
         for (int x = 0; x < NT; ++x) {
@@ -859,7 +859,7 @@ __device__ __forceinline__ void run_round(cplx<T>* const (&t)[NT], const StageGe
             // each shape stores from its own branch
             auto store = [&]() {
                 uint32_t as[DM];
-                store_addrs<D, M>(as, tb, rd, ops, gidx0);
+                store_addrs<D, M>(as, tb, rd, gidx0);
 #pragma unroll
                 for (int i = 0; i < DM; ++i) t[x][as[i]] = v[i];
             };
