@@ -681,7 +681,9 @@ static uint64_t pass_take(const qf_plan* p, const std::vector<GRef>& seq, const 
     std::fill(bFull.begin(), bFull.end(), 0);
     std::fill(bDiag.begin(), bDiag.end(), 0);
     uint64_t multi = 0, all = 0;
-    for (int i = first; i < int(seq.size()); ++i) {
+    int nfull = 0;
+    const int n = int(bFull.size());
+    for (int i = first; i < int(seq.size()) && nfull < n; ++i) {
         if (done[i]) continue;
         const qf_op& o = op_of(p, seq[i]);
         touches(o, tv);
@@ -692,7 +694,14 @@ static uint64_t pass_take(const qf_plan* p, const std::vector<GRef>& seq, const 
             ++all;
             multi += tv.size() > 1 ? 1 : 0;
         } else {
-            for (const Touch& t : tv) (t.diag ? bDiag : bFull)[t.q] = 1;
+            for (const Touch& t : tv) {
+                if (t.diag) {
+                    bDiag[t.q] = 1;
+                } else if (!bFull[t.q]) {
+                    bFull[t.q] = 1;
+                    ++nfull;  // once every qudit is blocked no later gate can be taken
+                }
+            }
         }
     }
     return (multi << 32) | all;
@@ -706,6 +715,11 @@ static uint64_t pass_take(const qf_plan* p, const std::vector<GRef>& seq, const 
 // of multi-qudit gates the pass takes, then the number of all gates: the
 // entangling gates are the chain that orders a circuit's layers, so a tile that
 // advances that chain further leaves less for later passes.
+// Gate visits the swap climb may spend on one gate sequence; past it the
+// remaining passes keep their greedy tiles (bounds the planning time of very
+// long circuits on many qudits).
+constexpr uint64_t kClimbBudget = uint64_t(1) << 27;
+
 static void plan_passes_one(const qf_plan* p, const std::vector<GRef>& seq, int k, int r, int seg, bool climb,
                             std::vector<Pass>& out) {
     const int n = p->n;
@@ -714,6 +728,7 @@ static void plan_passes_one(const qf_plan* p, const std::vector<GRef>& seq, int 
     int remaining = m, first = 0;
     std::vector<Touch> tv;
     std::vector<char> tb0(n), tb1(n);
+    uint64_t spent = 0;
     while (remaining > 0) {
         while (done[first]) ++first;
         const qf_op& o0 = op_of(p, seq[first]);
@@ -737,10 +752,10 @@ static void plan_passes_one(const qf_plan* p, const std::vector<GRef>& seq, int 
         }
         for (int q = n - r - 1; q >= 0 && cnt < k; --q)
             if (!inT[q]) inT[q] = 1, ++cnt;
-        if (climb) {
+        if (climb && spent < kClimbBudget) {
             const int keep = local_need(o0);
             uint64_t best = pass_take(p, seq, done, first, inT, tb0, tb1, tv);
-            for (bool improved = true; improved;) {
+            for (bool improved = true; improved && spent < kClimbBudget;) {
                 improved = false;
                 for (int a = 0; a < n - r && !improved; ++a) {
                     if (!inT[a] || a == keep) continue;
@@ -748,6 +763,7 @@ static void plan_passes_one(const qf_plan* p, const std::vector<GRef>& seq, int 
                         if (inT[b]) continue;
                         inT[a] = 0;
                         inT[b] = 1;
+                        spent += uint64_t(m - first);
                         const uint64_t sc = pass_take(p, seq, done, first, inT, tb0, tb1, tv);
                         if (sc > best) {
                             best = sc;
