@@ -115,6 +115,66 @@ def test_fourier_shift_clock_identities(D):
             assert Xs[(x + s) % D, x] == 1
 
 
+def test_printed_fourier_and_phase_shift():
+    """The paper's printed Fourier matrix H (entries w^(r c) / sqrt D, so
+    H[1][1] = w / sqrt D and H[1][2] = w^2 / sqrt D) and phase-shift matrix
+    P = diag(1, w, .., w^(D-1)), written out for D = 3, 4 (5 for P).  A conjugated
+    Fourier gate (w^(-r c)) fails here."""
+    fx = json.load(open(os.path.join(GOLDEN, "paper_fourier_phase.json")))
+    for case in fx["fourier"]:
+        D = case["D"]
+        w = np.exp(2j * np.pi / D)
+        want = w ** np.array(case["exponents"], dtype=float) / np.sqrt(D)
+        assert np.abs(gates.fourier(D) - want).max() < TOL, D
+    for case in fx["phase_shift"]:
+        D = case["D"]
+        w = np.exp(2j * np.pi / D)
+        assert np.abs(gates.clock(D, 1) - np.diag(w ** np.array(case["exponents"], dtype=float))).max() < TOL
+
+
+@pytest.mark.parametrize("D", [2, 3, 4, 5, 7])
+def test_fourier_diagonalises_the_shift(D):
+    """H maps the shift to the clock: H X = Z H, i.e. H X H^dagger = Z
+    (column n+1 of H is column n times w^m in row m).  The conjugate H^dagger
+    gives Z^dagger instead, so a sign flip of the exponent fails."""
+    H, X, Z = gates.fourier(D), gates.shift(D, 1), gates.clock(D, 1)
+    assert np.abs(H @ X - Z @ H).max() < TOL
+    assert np.abs(H @ X @ H.conj().T - Z).max() < TOL
+    if D > 2:
+        assert np.abs(H.conj().T @ X @ H - Z).max() > 0.1
+
+
+@pytest.mark.parametrize("D", [2, 3, 4, 5, 10])
+def test_clock_power(D):
+    """Z^a is the a-th power of the printed phase-shift matrix P for every a
+    (a = 0 gives the identity, a = D wraps to the identity), and satisfies the
+    Weyl relation Z^a X = w^a X Z^a.  A clock that ignores a fails for a != 1."""
+    w = np.exp(2j * np.pi / D)
+    P = np.diag(w ** np.arange(D, dtype=float))
+    X = gates.shift(D, 1)
+    for a in range(-1, 2 * D + 1):
+        Za = gates.clock(D, a)
+        assert np.abs(Za - np.linalg.matrix_power(P, a % D)).max() < 1e-12, a
+        assert np.abs(Za @ X - w ** a * X @ Za).max() < 1e-12, a
+    assert np.abs(gates.clock(D, 0) - np.eye(D)).max() < TOL
+    assert np.abs(gates.clock(D, D) - np.eye(D)).max() < 1e-12
+
+
+def test_clock_exponents_in_circuits():
+    """A register run through clock gates of every exponent: qudit q at level
+    x_q picks up w^(a_q x_q), checked on basis states against the power of the
+    printed P (the workloads draw a in {0, .., D-1})."""
+    D, n = 3, 3
+    w = np.exp(2j * np.pi / D)
+    for a in ([0, 1, 2], [2, 2, 0], [1, 0, 2]):
+        c = qi.Circuit(D, n, [("clock", q, a[q]) for q in range(n)])
+        for digs in ([0, 0, 0], [1, 2, 1], [2, 1, 2]):
+            psi = sim.run(c, sim.basis_state(D, n, digs))
+            want = np.prod([w ** (a[q] * digs[q]) for q in range(n)])
+            assert abs(psi[sim.index_of(D, digs)] - want) < TOL
+            assert abs(np.abs(psi).sum() - 1) < TOL
+
+
 @pytest.mark.parametrize("D", [2, 3, 5])
 def test_rotation_inverse_and_unitary(D):
     for j in range(D):
