@@ -93,7 +93,10 @@ qf_status qf_apply_ctrl(const qf_state* s, int32_t ctrl, int32_t tgt,
                         const int32_t* shift, void* stream);
 
 /* Diagonal gate on k qudits: psi_x <- phases[y] psi_x with
- * y = sum_i x_{qudits[i]} D^(k-1-i) (clock/phase gate, R_z, controlled phase).
+ * y = sum_i x_{qudits[i]} D^(k-1-i).  Covers the phase-shift (clock) gate and
+ * its powers (subsection "Generalized phase-shift gate"), R_z (subsection
+ * "Generalized rotation gate", diagonal generator) and a controlled phase
+ * w^(x_c x_t) built from the same phase rule.
  * qudits: host, k distinct indices in [0, n); phases: host, D^k complex FP64.
  * Limit: D^k <= 256 (complex64) or 128 (complex128). */
 qf_status qf_apply_diag(const qf_state* s, int32_t k, const int32_t* qudits,
@@ -224,18 +227,32 @@ qf_status qf_plan_read_profile(qf_plan* plan, qf_kernel_stat* out, int32_t cap, 
 qf_status qf_plan_forward(qf_plan* plan, const qf_state* s, const double* theta,
                           void* stream);
 
-/* Adjoint-method gradient of L(theta) = Re <psi| O |psi> for O a sum of
- * one-qudit diagonal terms (as in qf_expect), psi = circuit(theta) psi0
- * (Jones & Gacon, arXiv:2009.02823; rotations R = exp(-i theta S / 2),
- * subsection "Generalized rotation gate", give dL/dtheta = Im <lam|S|psi>).
+/* Flags of the adjoint entry points. */
+#define QF_SEED 1u  /* lam holds the seed on input (see qf_adjoint_grad) */
+
+/* Adjoint-method gradient of a real loss L(psi) of the final state
+ * psi = circuit(theta) psi0 (Jones & Gacon, arXiv:2009.02823; rotations
+ * R = exp(-i theta S / 2), subsection "Generalized rotation gate", give
+ * dL/dtheta = Im <lam|S|psi> with lam = dL/d(conj psi) carried back through the
+ * circuit together with psi).
+ *  - flags = 0: L = Re <psi| O |psi> for O a sum of one-qudit diagonal terms
+ *    (as in qf_expect); lam is scratch, the library sets lam = H_O psi with
+ *    H_O = (O + O^dagger) / 2.
+ *  - flags = QF_SEED: L is any real function of psi (the paper's training
+ *    losses, section "Code style"); on input lam holds g = 2 dL/d(conj psi),
+ *    the gradient torch's complex autograd delivers for psi.  nterms,
+ *    term_qudit and term_diag are ignored.
  * psi: in = the final state produced by qf_plan_forward; out = clobbered
- * (un-applied back towards psi0).  lam: scratch state of the same shape.
+ * (un-applied back towards psi0).  lam: same shape, clobbered.  A plan with
+ * checkpoints (ckpt_every > 0) re-anchors psi from the checkpoints of the last
+ * qf_plan_forward, which must have run on this same psi buffer and batch
+ * (QF_EINVAL otherwise).
  * grad: host, batch*nparams doubles (register b writes grad[b*nparams ..]).
  * Synchronises `stream` before returning. */
 qf_status qf_adjoint_grad(qf_plan* plan, const qf_state* psi, const qf_state* lam,
                           const double* theta, int32_t nterms,
                           const int32_t* term_qudit, const double* term_diag,
-                          double* grad, void* stream);
+                          double* grad, uint32_t flags, void* stream);
 
 /* ---- device-parameter (bound) mode: graph-capturable steps ----
  * qf_plan_bind allocates, once, everything a forward + adjoint step needs for
@@ -253,14 +270,15 @@ qf_status qf_plan_bind(qf_plan* plan, int64_t batch);
 qf_status qf_plan_forward_dev(qf_plan* plan, const qf_state* s, const double* theta,
                               int64_t theta_stride, void* stream);
 
-/* Adjoint gradient as qf_adjoint_grad, all on the device: grad (DEVICE,
- * batch*nparams doubles), and, if loss is not NULL, <O> per register (DEVICE,
- * batch complex values, 2 doubles each) taken before the reverse walk.
- * Per-parameter sums run in a fixed order (bitwise reproducible). */
+/* Adjoint gradient as qf_adjoint_grad (same flags), all on the device: grad
+ * (DEVICE, batch*nparams doubles), and, if loss is not NULL (flags = 0 only),
+ * <O> per register (DEVICE, batch complex values, 2 doubles each) taken before
+ * the reverse walk.  Per-parameter sums run in a fixed order (bitwise
+ * reproducible). */
 qf_status qf_adjoint_grad_dev(qf_plan* plan, const qf_state* psi, const qf_state* lam,
                               const double* theta, int64_t theta_stride, int32_t nterms,
                               const int32_t* term_qudit, const double* term_diag,
-                              double* grad, double* loss, void* stream);
+                              double* grad, double* loss, uint32_t flags, void* stream);
 
 /* Autotuner: times candidate schedules of this plan's circuit on the caller's
  * state s (stage tiles of the default size +-1 qudit with every register group
@@ -284,6 +302,17 @@ const char* qf_last_error(void);
 
 /* Library version as major*10000 + minor*100 + patch. */
 int32_t qf_version(void);
+
+/* Releases library-wide state: the autotuner's cache of chosen options.  Plans
+ * stay valid (each owns its buffers until qf_plan_destroy).  Safe to call more
+ * than once; the library re-creates the state on demand. */
+void qf_shutdown(void);
+
+/* Environment variables read by the library:
+ *   QF_LOG=1               planner and autotuner choices on stderr;
+ *   QF_CHECK_NORM=<tol>    after every qf_plan_forward, synchronise and fail
+ *                          with QF_ERANGE if | |psi| - 1 | > tol for a register;
+ *   QF_TEST_FAIL_ALLOC=1   every allocation fails with QF_ENOMEM (tests). */
 
 #ifdef __cplusplus
 }

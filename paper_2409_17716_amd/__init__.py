@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libqf.so")
 
 QF_OK, QF_EINVAL, QF_EDTYPE, QF_ERANGE, QF_ENOMEM, QF_EHIP, QF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 QF_C64, QF_C128 = 0, 1
+QF_SEED = 1  # adjoint flag: lam holds torch's gradient of the output state
 (QF_OP_H, QF_OP_X, QF_OP_CLOCK, QF_OP_RX, QF_OP_RY, QF_OP_RZ, QF_OP_CSUM, QF_OP_CSHIFT, QF_OP_CZ,
  QF_OP_U) = range(10)
 
@@ -69,12 +70,12 @@ _SIGS = {
     "qf_plan_create": [_I32, _I32, _I32, ctypes.POINTER(qf_op), _I32, _I32, ctypes.POINTER(qf_plan_opts),
                        ctypes.POINTER(ctypes.c_void_p)],
     "qf_plan_forward": [_P, _PS, _PD, _P],
-    "qf_adjoint_grad": [_P, _PS, _PS, _PD, _I32, _PI32, _PD, _PD, _P],
+    "qf_adjoint_grad": [_P, _PS, _PS, _PD, _I32, _PI32, _PD, _PD, ctypes.c_uint32, _P],
     "qf_plan_set_profiling": [_P, _I32],
     "qf_plan_autotune": [_P, _PS, _PD, ctypes.POINTER(qf_plan_opts), _P],
     "qf_plan_bind": [_P, ctypes.c_int64],
     "qf_plan_forward_dev": [_P, _PS, _P, ctypes.c_int64, _P],
-    "qf_adjoint_grad_dev": [_P, _PS, _PS, _P, ctypes.c_int64, _I32, _PI32, _PD, _P, _P, _P],
+    "qf_adjoint_grad_dev": [_P, _PS, _PS, _P, ctypes.c_int64, _I32, _PI32, _PD, _P, _P, ctypes.c_uint32, _P],
     "qf_plan_read_profile": [_P, ctypes.POINTER(qf_kernel_stat), _I32, _PI32],
 }
 
@@ -100,6 +101,8 @@ def _load() -> ctypes.CDLL:
         getattr(lib, name).argtypes = [_P]
     lib.qf_plan_destroy.restype = None
     lib.qf_plan_destroy.argtypes = [_P]
+    lib.qf_shutdown.restype = None
+    lib.qf_shutdown.argtypes = []
     return lib
 
 
@@ -324,17 +327,24 @@ class Plan:
                                        int(theta_stride), _stream(stream)))
 
     def adjoint_grad_dev(self, psi, lam, theta_dev, theta_stride: int, terms, grad_dev, loss_dev=None,
-                         stream=None) -> None:
+                         stream=None, seed: bool = False) -> None:
+        """qf_adjoint_grad_dev.  seed=True: lam holds torch's gradient of the
+        final state (QF_SEED) and terms is ignored."""
         s = state_of(psi, self.n, self.dim)
         sl = state_of(lam, self.n, self.dim)
-        qs, tab = _terms_arrays(self.dim, terms)
-        self._keep = (_i32(qs), _c128(tab))
+        if seed:
+            self._keep = ((None, None), (None, None))
+            nt = 0
+        else:
+            qs, tab = _terms_arrays(self.dim, terms)
+            self._keep = (_i32(qs), _c128(tab))
+            nt = len(qs)
         (qa, qp), (ta, tp) = self._keep
         _check(lib.qf_adjoint_grad_dev(self._h, ctypes.byref(s), ctypes.byref(sl),
-                                       ctypes.c_void_p(theta_dev.data_ptr()), int(theta_stride), len(qs), qp, tp,
+                                       ctypes.c_void_p(theta_dev.data_ptr()), int(theta_stride), nt, qp, tp,
                                        ctypes.c_void_p(grad_dev.data_ptr()),
                                        ctypes.c_void_p(loss_dev.data_ptr()) if loss_dev is not None else None,
-                                       _stream(stream)))
+                                       QF_SEED if seed else 0, _stream(stream)))
 
     def set_profiling(self, enable: bool) -> None:
         _check(lib.qf_plan_set_profiling(self._h, 1 if enable else 0))
@@ -352,16 +362,23 @@ class Plan:
         th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
         _check(lib.qf_plan_forward(self._h, ctypes.byref(s), th.ctypes.data_as(_PD), _stream(stream)))
 
-    def adjoint_grad(self, psi, lam, theta, terms, stream=None) -> np.ndarray:
+    def adjoint_grad(self, psi, lam, theta, terms, stream=None, seed: bool = False) -> np.ndarray:
+        """qf_adjoint_grad (synchronises).  seed=True: lam holds torch's gradient
+        of the final state (QF_SEED) and terms is ignored."""
         s = state_of(psi, self.n, self.dim)
         sl = state_of(lam, self.n, self.dim)
         th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
-        qs, tab = _terms_arrays(self.dim, terms)
-        qa, qp = _i32(qs)
-        ta, tp = _c128(tab)
+        if seed:
+            qa = qp = ta = tp = None
+            nt = 0
+        else:
+            qs, tab = _terms_arrays(self.dim, terms)
+            qa, qp = _i32(qs)
+            ta, tp = _c128(tab)
+            nt = len(qs)
         g = np.zeros(s.batch * self.nparams, dtype=np.float64)
-        _check(lib.qf_adjoint_grad(self._h, ctypes.byref(s), ctypes.byref(sl), th.ctypes.data_as(_PD), len(qs),
-                                   qp, tp, g.ctypes.data_as(_PD), _stream(stream)))
+        _check(lib.qf_adjoint_grad(self._h, ctypes.byref(s), ctypes.byref(sl), th.ctypes.data_as(_PD), nt,
+                                   qp, tp, g.ctypes.data_as(_PD), QF_SEED if seed else 0, _stream(stream)))
         return g.reshape(s.batch, self.nparams) if s.batch > 1 else g
 
     def __del__(self):
@@ -373,6 +390,11 @@ class Plan:
 
 def plan_for(circuit, dtype: str = "c64", **kw) -> Plan:
     return Plan(circuit.dim, circuit.n, circuit.ops, circuit.nparams, dtype, **kw)
+
+
+def qf_shutdown() -> None:
+    """Release library-wide state (the autotuner cache)."""
+    lib.qf_shutdown()
 
 
 def new_state(n: int, dim: int, dtype: str = "c64", batch: int = 1, device="cuda"):

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -24,6 +25,59 @@ qf_status check_launch(const char* what) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_error(QF_EHIP, "%s: launch failed: %s", what, hipGetErrorString(e));
     return QF_OK;
+}
+
+static bool env_on(const char* name) {
+    const char* e = std::getenv(name);
+    return e != nullptr && e[0] != '\0' && !(e[0] == '0' && e[1] == '\0');
+}
+
+qf_status dev_malloc(void** p, size_t bytes, const char* what) {
+    *p = nullptr;
+    if (env_on("QF_TEST_FAIL_ALLOC")) return set_error(QF_ENOMEM, "%s: allocation of %zu bytes refused "
+                                                       "(QF_TEST_FAIL_ALLOC)", what, bytes);
+    if (hipMalloc(p, bytes < 16 ? 16 : bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return set_error(QF_ENOMEM, "%s: device allocation of %zu bytes failed", what, bytes);
+    }
+    return QF_OK;
+}
+
+qf_status dev_malloc_async(void** p, size_t bytes, hipStream_t st, const char* what) {
+    *p = nullptr;
+    if (env_on("QF_TEST_FAIL_ALLOC")) return set_error(QF_ENOMEM, "%s: allocation of %zu bytes refused "
+                                                       "(QF_TEST_FAIL_ALLOC)", what, bytes);
+    if (hipMallocAsync(p, bytes < 16 ? 16 : bytes, st) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return set_error(QF_ENOMEM, "%s: stream-ordered allocation of %zu bytes failed", what, bytes);
+    }
+    return QF_OK;
+}
+
+qf_status host_malloc_pinned(void** p, size_t bytes, const char* what) {
+    *p = nullptr;
+    if (env_on("QF_TEST_FAIL_ALLOC")) return set_error(QF_ENOMEM, "%s: allocation of %zu bytes refused "
+                                                       "(QF_TEST_FAIL_ALLOC)", what, bytes);
+    if (hipHostMalloc(p, bytes < 16 ? 16 : bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return set_error(QF_ENOMEM, "%s: pinned host allocation of %zu bytes failed", what, bytes);
+    }
+    return QF_OK;
+}
+
+bool log_enabled() { return env_on("QF_LOG"); }
+
+void log_msg(const char* fmt, ...) {
+    if (!log_enabled()) return;
+    va_list ap;
+    va_start(ap, fmt);
+    std::fputs("[qf] ", stderr);
+    std::vfprintf(stderr, fmt, ap);
+    std::fputc('\n', stderr);
+    va_end(ap);
 }
 
 qf_status make_view(const qf_state* s, StateView& v) {
@@ -98,7 +152,7 @@ extern "C" {
 
 const char* qf_last_error(void) { return g_err; }
 
-int32_t qf_version(void) { return 100; }
+int32_t qf_version(void) { return 200; }
 
 qf_status qf_state_init(const qf_state* s, const int32_t* digits, void* stream) {
     StateView v;

@@ -439,7 +439,8 @@ qf_status launch_init(const StateView& s, const std::vector<uint32_t>& index, hi
         uint32_t* didx = nullptr;
         uint32_t idx0 = index.empty() ? 0u : index[0];
         if (index.size() > 1) {
-            QF_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&didx), index.size() * sizeof(uint32_t), st));
+            QF_CHECK(dev_malloc_async(reinterpret_cast<void**>(&didx), index.size() * sizeof(uint32_t), st,
+                                      "init digits"));
             QF_HIP_CHECK(hipMemcpyAsync(didx, index.data(), index.size() * sizeof(uint32_t),
                                         hipMemcpyHostToDevice, st));
         }
@@ -543,7 +544,8 @@ qf_status launch_probs_marginal(const StateView& s, int m, const int32_t* qudits
     return with_type(s.dtype, [&](auto tag) -> qf_status {
         using T = decltype(tag);
         double* partial = nullptr;
-        QF_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&partial), nblocks * sizeof(double), st));
+        QF_CHECK(dev_malloc_async(reinterpret_cast<void**>(&partial), nblocks * sizeof(double), st,
+                                  "marginal partial sums"));
         hipLaunchKernelGGL(k_marg_partial<T>, dim3(uint32_t(nblocks)), dim3(kBlock), 0, st,
                            reinterpret_cast<const cplx<T>*>(s.amps), a, partial);
         qf_status r1 = check_launch("qf_probs marginal");
@@ -589,7 +591,8 @@ qf_status launch_expect(const StateView& s, const std::vector<int>& active, cons
     return with_type(s.dtype, [&](auto tag) -> qf_status {
         using T = decltype(tag);
         double* partial = nullptr;
-        QF_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&partial), nblocks * 2 * sizeof(double), st));
+        QF_CHECK(dev_malloc_async(reinterpret_cast<void**>(&partial), nblocks * 2 * sizeof(double), st,
+                                  "expectation partial sums"));
         hipLaunchKernelGGL(k_expect_partial<T>, dim3(uint32_t(nblocks)), dim3(kBlock), 0, st,
                            reinterpret_cast<const cplx<T>*>(s.amps), s.N, chunk, nblk, a, partial);
         qf_status r1 = check_launch("qf_expect");

@@ -250,16 +250,17 @@ __global__ void k_grad_contrib(const DevGradGroup* __restrict__ gg, int ngg, con
     }
 }
 
-// grad[b][p] = sum of the contributions listed for p, in list order.
+// grad[b][p] = scale * (sum of the contributions listed for p, in list order).
 __global__ void k_grad_sum(const double* __restrict__ contrib, int ncontrib, const int32_t* __restrict__ p_off,
-                           const int32_t* __restrict__ p_list, int nparams, uint32_t batch, double* __restrict__ grad) {
+                           const int32_t* __restrict__ p_list, int nparams, uint32_t batch, double scale,
+                           double* __restrict__ grad) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= uint32_t(nparams) * batch) return;
     const uint32_t b = t / uint32_t(nparams);
     const int p = int(t - b * uint32_t(nparams));
     double s = 0.0;
     for (int i = p_off[p]; i < p_off[p + 1]; ++i) s += contrib[size_t(b) * ncontrib + p_list[i]];
-    grad[size_t(b) * nparams + p] = s;
+    grad[size_t(b) * nparams + p] = scale * s;
 }
 
 template <class F>
@@ -305,7 +306,8 @@ qf_status launch_build_mats(int D, int dtype, const DevGroup* groups, int ngroup
 
 qf_status launch_grad(int D, const DevGradGroup* gg, int ngg, const DevGate* gates, const double* theta,
                       int64_t theta_stride, const double* M, int nslots, uint32_t batch, double* contrib, int ncontrib,
-                      const int32_t* p_off, const int32_t* p_list, int nparams, double* grad, hipStream_t st) {
+                      const int32_t* p_off, const int32_t* p_list, int nparams, double scale, double* grad,
+                      hipStream_t st) {
     if (nparams == 0) return QF_OK;
     if (ngg > 0) {
         const uint32_t n = uint32_t(ngg) * batch;
@@ -319,7 +321,7 @@ qf_status launch_grad(int D, const DevGradGroup* gg, int ngg, const DevGate* gat
     }
     const uint32_t n = uint32_t(nparams) * batch;
     hipLaunchKernelGGL(k_grad_sum, dim3((n + 255) / 256), dim3(256), 0, st, contrib, ncontrib, p_off, p_list, nparams,
-                       batch, grad);
+                       batch, scale, grad);
     return check_launch("gradient sum");
 }
 

@@ -15,6 +15,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <vector>
@@ -255,6 +256,8 @@ struct qf_plan {
     std::vector<int> seg_end;         // gate index where each checkpoint segment ends
     void* ckpt = nullptr;             // (nseg - 1) saved states
     size_t ckpt_bytes = 0;
+    const void* ckpt_amps = nullptr;  // state and batch of the forward that wrote the checkpoints
+    uint32_t ckpt_batch = 0;
     bool profiling = false;
     std::vector<qf::ProfRec> prof;
     std::vector<hipEvent_t> ev_pool;
@@ -305,6 +308,8 @@ struct qf_plan {
         seg_end.swap(o.seg_end);
         std::swap(ckpt, o.ckpt);
         std::swap(ckpt_bytes, o.ckpt_bytes);
+        std::swap(ckpt_amps, o.ckpt_amps);
+        std::swap(ckpt_batch, o.ckpt_batch);
         std::swap(profiling, o.profiling);
         prof.swap(o.prof);
         ev_pool.swap(o.ev_pool);
@@ -1225,17 +1230,17 @@ static void finalize_passes(const qf_plan* p, PassList& L, bool adjoint) {
 static qf_status upload_ops(const qf_plan* p, PassList& L) {
     const size_t esz = p->dtype == QF_C64 ? 8 : 16;
     if (!L.hops.empty()) {
-        QF_HIP_CHECK(hipMalloc(reinterpret_cast<void**>(&L.dops), L.hops.size() * sizeof(StageOp)));
+        QF_CHECK(dev_malloc(reinterpret_cast<void**>(&L.dops), L.hops.size() * sizeof(StageOp), "stage ops"));
         QF_HIP_CHECK(hipMemcpy(L.dops, L.hops.data(), L.hops.size() * sizeof(StageOp), hipMemcpyHostToDevice));
     }
     if (!L.hrounds.empty()) {
-        QF_HIP_CHECK(hipMalloc(reinterpret_cast<void**>(&L.drounds), L.hrounds.size() * sizeof(RoundDesc)));
+        QF_CHECK(dev_malloc(reinterpret_cast<void**>(&L.drounds), L.hrounds.size() * sizeof(RoundDesc), "rounds"));
         QF_HIP_CHECK(hipMemcpy(L.drounds, L.hrounds.data(), L.hrounds.size() * sizeof(RoundDesc),
                                hipMemcpyHostToDevice));
     }
     const size_t mb = std::max<size_t>(L.nmats, 1) * esz;
-    QF_HIP_CHECK(hipMalloc(&L.dmats, mb));
-    QF_HIP_CHECK(hipHostMalloc(&L.hmats, mb, hipHostMallocDefault));
+    QF_CHECK(dev_malloc(&L.dmats, mb, "stage matrices"));
+    QF_CHECK(host_malloc_pinned(&L.hmats, mb, "stage matrix staging"));
     QF_HIP_CHECK(hipEventCreateWithFlags(&L.copied, hipEventDisableTiming));
     QF_HIP_CHECK(hipEventCreateWithFlags(&L.done, hipEventDisableTiming));
     return QF_OK;
@@ -1351,12 +1356,25 @@ static qf_status ensure_ckpt(qf_plan* p, const StateView& v) {
     if (p->ckpt) QF_HIP_CHECK(hipFree(p->ckpt));
     p->ckpt = nullptr;
     p->ckpt_bytes = 0;
-    if (hipMalloc(&p->ckpt, need) != hipSuccess) {
-        (void)hipGetLastError();
-        p->ckpt = nullptr;
-        return set_error(QF_ENOMEM, "checkpoint allocation of %zu bytes failed", need);
-    }
+    p->ckpt_amps = nullptr;
+    p->ckpt_batch = 0;
+    QF_CHECK(dev_malloc(&p->ckpt, need, "checkpoints"));
     p->ckpt_bytes = need;
+    return QF_OK;
+}
+
+// A checkpointed reverse walk re-anchors psi from the checkpoints of the last
+// forward pass, so they must come from a forward pass of this very state
+// buffer at this batch size.
+static qf_status check_ckpt_source(const qf_plan* p, const StateView& v) {
+    if (p->seg_end.size() <= 1) return QF_OK;
+    QF_RETURN_IF(p->ckpt == nullptr || p->ckpt_amps == nullptr, QF_EINVAL,
+                 "checkpointed plan: run the forward pass on this state first");
+    QF_RETURN_IF(p->ckpt_amps != v.amps || p->ckpt_batch != v.batch, QF_EINVAL,
+                 "checkpointed plan: the checkpoints hold the forward pass of another state buffer or batch size; "
+                 "run the forward pass on this state first");
+    QF_RETURN_IF((p->seg_end.size() - 1) * state_bytes(v) > p->ckpt_bytes, QF_EINVAL,
+                 "checkpointed plan: checkpoint buffer smaller than this state");
     return QF_OK;
 }
 
@@ -1442,6 +1460,34 @@ static void add_group_grad(const qf_plan* p, const std::vector<int>& fwd_gates, 
     }
 }
 
+// QF_CHECK_NORM=<tol>: after a forward pass, synchronise and check every
+// register's norm (sum of |psi_x|^2 in FP64 by the expectation kernel with the
+// constant observable 1).
+static qf_status check_norm_env(const StateView& v, hipStream_t st) {
+    const char* e = std::getenv("QF_CHECK_NORM");
+    if (e == nullptr || e[0] == '\0') return QF_OK;
+    const double tol = std::atof(e);
+    if (!(tol > 0.0)) return QF_OK;
+    std::vector<int> active{0};
+    std::vector<double> table(2 * v.D, 0.0);
+    for (uint32_t d = 0; d < v.D; ++d) table[2 * d] = 1.0;
+    double* out = nullptr;
+    QF_CHECK(dev_malloc_async(reinterpret_cast<void**>(&out), size_t(v.batch) * 2 * sizeof(double), st, "norm check"));
+    qf_status rs = launch_expect(v, active, table, out, st);
+    std::vector<double> h(size_t(v.batch) * 2);
+    if (rs == QF_OK && hipMemcpyAsync(h.data(), out, h.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
+        rs = set_error(QF_EHIP, "norm check copy failed");
+    (void)hipFreeAsync(out, st);
+    if (hipStreamSynchronize(st) != hipSuccess && rs == QF_OK) rs = set_error(QF_EHIP, "norm check sync failed");
+    if (rs != QF_OK) return rs;
+    for (uint32_t b = 0; b < v.batch; ++b) {
+        const double nrm = std::sqrt(h[2 * b]);
+        QF_RETURN_IF(!(std::fabs(nrm - 1.0) <= tol), QF_ERANGE,
+                     "QF_CHECK_NORM: register %u has norm %.9g after the forward pass (tolerance %g)", b, nrm, tol);
+    }
+    return QF_OK;
+}
+
 }  // namespace qf
 
 using namespace qf;
@@ -1519,8 +1565,8 @@ qf_status qf_plan_create(int32_t dim, int32_t n, int32_t dtype, const qf_op* ops
                         db[1] = y.imag();
                     }
                 }
-            QF_HIP_CHECK(hipMalloc(&g.dmat, a.size()));
-            QF_HIP_CHECK(hipMalloc(&g.dmat_adj, b.size()));
+            QF_CHECK(dev_malloc(&g.dmat, a.size(), "custom gate matrix"));
+            QF_CHECK(dev_malloc(&g.dmat_adj, b.size(), "custom gate matrix"));
             QF_HIP_CHECK(hipMemcpy(g.dmat, a.data(), a.size(), hipMemcpyHostToDevice));
             QF_HIP_CHECK(hipMemcpy(g.dmat_adj, b.data(), b.size(), hipMemcpyHostToDevice));
         }
@@ -1531,6 +1577,8 @@ qf_status qf_plan_create(int32_t dim, int32_t n, int32_t dtype, const qf_op* ops
     p->seg_end.push_back(nops);
     if (!staged(p.get())) {
         build_steps(p.get());
+        log_msg("plan D=%d n=%d: %d gates, per-gate schedule (fuse %d): %zu steps", dim, n, nops, p->opts.fuse,
+                p->steps.size());
     } else if (nops > 0) {
         int k, r, ka, ra;
         tile_shape(dim, n, dtype, p->opts.tile_digits, p->opts.low_digits, false, k, r);
@@ -1561,6 +1609,9 @@ qf_status qf_plan_create(int32_t dim, int32_t n, int32_t dtype, const qf_op* ops
         for (int sgi = int(rseq.size()) - 1; sgi >= 0; --sgi) plan_passes(p.get(), rseq[sgi], ka, ra, sgi, p->rev);
         finalize_passes(p.get(), p->fwd, false);
         finalize_passes(p.get(), p->rev, true);
+        log_msg("plan D=%d n=%d %s: %d gates, tile %d qudits (%d low), group %d: %zu forward passes; adjoint tile %d "
+                "(%d low): %zu passes, %d M slots", dim, n, dtype == QF_C64 ? "c64" : "c128", nops, k, r, p->group,
+                p->fwd.passes.size(), ka, ra, p->rev.passes.size(), p->rev.nslots);
     }
     *out = p.release();
     return QF_OK;
@@ -1593,7 +1644,7 @@ qf_status qf_plan_forward(qf_plan* plan, const qf_state* s, const double* theta,
                                                    : F_FUSED;
             QF_CHECK(prof_end(plan, st, a, fam, 2.0 * state_bytes(v)));
         }
-        return QF_OK;
+        return check_norm_env(v, st);
     }
     if (plan->fwd.passes.empty()) return QF_OK;
     const bool save = plan->seg_end.size() > 1;
@@ -1617,15 +1668,21 @@ qf_status qf_plan_forward(qf_plan* plan, const qf_state* s, const double* theta,
     }
     QF_HIP_CHECK(hipEventRecord(plan->fwd.done, st));
     plan->fwd.done_valid = true;
-    return QF_OK;
+    if (save) {
+        plan->ckpt_amps = v.amps;
+        plan->ckpt_batch = v.batch;
+    }
+    return check_norm_env(v, st);
 }
 
 qf_status qf_adjoint_grad(qf_plan* plan, const qf_state* psi, const qf_state* lam, const double* theta,
                           int32_t nterms, const int32_t* term_qudit, const double* term_diag, double* grad,
-                          void* stream) {
+                          uint32_t flags, void* stream) {
     StateView v, vl;
     QF_CHECK(check_plan_state(plan, psi, v));
     QF_CHECK(check_plan_state(plan, lam, vl));
+    QF_RETURN_IF((flags & ~uint32_t(QF_SEED)) != 0, QF_EINVAL, "unknown flags 0x%x", flags);
+    const bool seed = (flags & QF_SEED) != 0;
     QF_RETURN_IF(vl.batch != v.batch, QF_EINVAL, "psi and lam batch differ");
     QF_RETURN_IF(psi->amps == lam->amps, QF_EINVAL, "psi and lam must not alias");
     QF_RETURN_IF(grad == nullptr, QF_EINVAL, "grad is NULL");
@@ -1633,7 +1690,7 @@ qf_status qf_adjoint_grad(qf_plan* plan, const qf_state* psi, const qf_state* la
     QF_CHECK(check_finite_theta(theta, plan->nparams));
     std::vector<int> active;
     std::vector<double> table;
-    QF_CHECK(combine_terms(v, nterms, term_qudit, term_diag, active, table));
+    if (!seed) QF_CHECK(combine_terms(v, nterms, term_qudit, term_diag, active, table));
     std::vector<double> table_re(active.size() * v.D);
     for (size_t i = 0; i < table_re.size(); ++i) table_re[i] = table[2 * i];
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -1641,11 +1698,7 @@ qf_status qf_adjoint_grad(qf_plan* plan, const qf_state* psi, const qf_state* la
     const size_t E = size_t(D) * D;
     const bool stg = staged(plan);
     const int nslots = stg ? plan->rev.nslots : plan->nslots;
-    QF_RETURN_IF(stg && plan->seg_end.size() > 1 && (plan->ckpt == nullptr || !plan->fwd.done_valid), QF_EINVAL,
-                 "checkpointed plan: run qf_plan_forward on this state first");
-
-    // lam = H_O psi with H_O the Hermitian part of O
-    QF_CHECK(launch_diag_observable(v, lam->amps, active, table_re, st));
+    if (stg) QF_CHECK(check_ckpt_source(plan, v));
 
     size_t pdoubles = 1;
     if (stg) {
@@ -1657,10 +1710,12 @@ qf_status qf_adjoint_grad(qf_plan* plan, const qf_state* psi, const qf_state* la
     double* partial = nullptr;
     double* mdev = nullptr;
     const size_t mcount = size_t(v.batch) * std::max(nslots, 1) * E * 2;
-    QF_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&partial), pdoubles * sizeof(double), st));
-    QF_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&mdev), mcount * sizeof(double), st));
-    qf_status rs = QF_OK;
-    if (stg) {
+    qf_status rs = dev_malloc_async(reinterpret_cast<void**>(&partial), pdoubles * sizeof(double), st,
+                                    "adjoint partial sums");
+    if (rs == QF_OK) rs = dev_malloc_async(reinterpret_cast<void**>(&mdev), mcount * sizeof(double), st, "adjoint M");
+    // lam = H_O psi with H_O the Hermitian part of O (seed mode: lam already holds the seed)
+    if (rs == QF_OK && !seed) rs = launch_diag_observable(v, lam->amps, active, table_re, st);
+    if (rs == QF_OK && stg) {
         rs = upload_mats(plan, plan->rev, theta, st);
         const size_t sb = state_bytes(v);
         for (size_t i = 0; i < plan->rev.passes.size() && rs == QF_OK; ++i) {
@@ -1687,7 +1742,7 @@ qf_status qf_adjoint_grad(qf_plan* plan, const qf_state* psi, const qf_state* la
             hipError_t e = hipEventRecord(plan->rev.done, st);
             if (e == hipSuccess) plan->rev.done_valid = true;
         }
-    } else {
+    } else if (rs == QF_OK) {
         for (int si = int(plan->steps.size()) - 1; si >= 0 && rs == QF_OK; --si) {
             const Step& s = plan->steps[si];
             if (s.type == ST_AXIS && s.has_param) {
@@ -1710,8 +1765,8 @@ qf_status qf_adjoint_grad(qf_plan* plan, const qf_state* psi, const qf_state* la
         hipError_t e = hipMemcpyAsync(mhost.data(), mdev, mcount * sizeof(double), hipMemcpyDeviceToHost, st);
         if (e != hipSuccess) rs = set_error(QF_EHIP, "copy of M matrices failed: %s", hipGetErrorString(e));
     }
-    (void)hipFreeAsync(partial, st);
-    (void)hipFreeAsync(mdev, st);
+    if (partial) (void)hipFreeAsync(partial, st);
+    if (mdev) (void)hipFreeAsync(mdev, st);
     hipError_t e = hipStreamSynchronize(st);
     if (rs != QF_OK) return rs;
     QF_RETURN_IF(e != hipSuccess, QF_EHIP, "stream synchronisation failed: %s", hipGetErrorString(e));
@@ -1734,6 +1789,9 @@ qf_status qf_adjoint_grad(qf_plan* plan, const qf_state* psi, const qf_state* la
                     add_group_grad(plan, s.gates, theta, mhost.data() + ((size_t(b) * nslots + s.slot) * E) * 2, gb);
         }
     }
+    // seed mode: lam held torch's gradient g = 2 dL/d(conj psi), the adjoint needs dL/d(conj psi)
+    if (seed)
+        for (size_t i = 0; i < size_t(v.batch) * plan->nparams; ++i) grad[i] *= 0.5;
     return QF_OK;
 }
 
@@ -1824,6 +1882,8 @@ static TuneCache g_tune;
 
 }  // namespace qf
 
+extern "C" void qf_shutdown(void) { std::vector<std::pair<uint64_t, qf_plan_opts>>().swap(qf::g_tune.entries); }
+
 extern "C" {
 
 qf_status qf_plan_autotune(qf_plan* plan, const qf_state* s, const double* theta, qf_plan_opts* chosen,
@@ -1913,6 +1973,9 @@ qf_status qf_plan_autotune(qf_plan* plan, const qf_state* s, const double* theta
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         QF_RETURN_IF(best_ms >= 1e30f, QF_EHIP, "no autotuning candidate ran");
+        log_msg("autotune D=%d n=%d batch %u: %zu candidates, chose fuse %d tile %d group %d kernel %d (%.3f ms for "
+                "two forwards)", plan->D, plan->n, v.batch, cand.size(), best.fuse, best.tile_digits, best.group_digits,
+                best.stage_kernel, double(best_ms));
         g_tune.entries.push_back({key, best});
     }
     // rebuild this plan with the chosen options
@@ -1955,18 +2018,13 @@ static void bound_groups(qf_plan* p, PassList& L) {
 template <typename X>
 static qf_status dev_upload(X** dst, const std::vector<X>& src) {
     if (src.empty()) return QF_OK;
-    QF_HIP_CHECK(hipMalloc(reinterpret_cast<void**>(dst), src.size() * sizeof(X)));
+    QF_CHECK(dev_malloc(reinterpret_cast<void**>(dst), src.size() * sizeof(X), "bound-mode tables"));
     QF_HIP_CHECK(hipMemcpy(*dst, src.data(), src.size() * sizeof(X), hipMemcpyHostToDevice));
     return QF_OK;
 }
 
 static qf_status dev_alloc(void** dst, size_t bytes) {
-    if (hipMalloc(dst, std::max<size_t>(bytes, 16)) != hipSuccess) {
-        (void)hipGetLastError();
-        *dst = nullptr;
-        return set_error(QF_ENOMEM, "device allocation of %zu bytes failed", bytes);
-    }
-    return QF_OK;
+    return dev_malloc(dst, bytes, "bound-mode workspace");
 }
 
 static qf_status check_bound(const qf_plan* p, const StateView& v, int64_t theta_stride) {
@@ -2081,23 +2139,31 @@ qf_status qf_plan_forward_dev(qf_plan* plan, const qf_state* s, const double* th
             QF_HIP_CHECK(hipMemcpyAsync(reinterpret_cast<unsigned char*>(plan->ckpt) + size_t(ps.seg) * sb, v.amps,
                                         sb, hipMemcpyDeviceToDevice, st));
     }
+    if (plan->seg_end.size() > 1) {
+        plan->ckpt_amps = v.amps;
+        plan->ckpt_batch = v.batch;
+    }
     return QF_OK;
 }
 
 qf_status qf_adjoint_grad_dev(qf_plan* plan, const qf_state* psi, const qf_state* lam, const double* theta,
                               int64_t theta_stride, int32_t nterms, const int32_t* term_qudit,
-                              const double* term_diag, double* grad, double* loss, void* stream) {
+                              const double* term_diag, double* grad, double* loss, uint32_t flags, void* stream) {
     StateView v, vl;
     QF_CHECK(check_plan_state(plan, psi, v));
     QF_CHECK(check_plan_state(plan, lam, vl));
     QF_CHECK(check_bound(plan, v, theta_stride));
+    QF_RETURN_IF((flags & ~uint32_t(QF_SEED)) != 0, QF_EINVAL, "unknown flags 0x%x", flags);
+    const bool seed = (flags & QF_SEED) != 0;
+    QF_RETURN_IF(seed && loss != nullptr, QF_EINVAL, "seed mode has no observable: loss must be NULL");
     QF_RETURN_IF(vl.batch != v.batch, QF_EINVAL, "psi and lam batch differ");
     QF_RETURN_IF(psi->amps == lam->amps, QF_EINVAL, "psi and lam must not alias");
     QF_RETURN_IF(grad == nullptr && plan->nparams > 0, QF_EINVAL, "grad is NULL");
     QF_RETURN_IF(plan->nparams > 0 && theta == nullptr, QF_EINVAL, "theta is NULL");
+    QF_CHECK(check_ckpt_source(plan, v));
     std::vector<int> active;
     std::vector<double> table;
-    QF_CHECK(combine_terms(v, nterms, term_qudit, term_diag, active, table));
+    if (!seed) QF_CHECK(combine_terms(v, nterms, term_qudit, term_diag, active, table));
     std::vector<double> table_re(active.size() * v.D);
     for (size_t i = 0; i < table_re.size(); ++i) table_re[i] = table[2 * i];
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -2105,7 +2171,7 @@ qf_status qf_adjoint_grad_dev(qf_plan* plan, const qf_state* psi, const qf_state
     const size_t E = size_t(D) * D;
     const size_t esz = plan->dtype == QF_C64 ? 8 : 16;
     if (loss) QF_CHECK(launch_expect_ws(v, active, table, loss, plan->w_expect, st));
-    QF_CHECK(launch_diag_observable(v, lam->amps, active, table_re, st));
+    if (!seed) QF_CHECK(launch_diag_observable(v, lam->amps, active, table_re, st));
     PassList& L = plan->rev;
     QF_CHECK(launch_build_mats(plan->D, plan->dtype, L.dgroups, int(L.hgroups.size()), plan->dgates, theta,
                                theta_stride, v.batch, L.dmats_b, L.nmats, st));
@@ -2133,8 +2199,10 @@ qf_status qf_adjoint_grad_dev(qf_plan* plan, const qf_state* psi, const qf_state
             QF_CHECK(launch_fused(vl, g.op.q1, g.op.q0, g.dmat_adj, st, g.real));
         }
     }
+    // seed mode: lam held torch's gradient g = 2 dL/d(conj psi), the adjoint needs dL/d(conj psi)
     return launch_grad(D, plan->dgg, int(plan->hgg.size()), plan->dgates, theta, theta_stride, plan->w_m, L.nslots,
-                       v.batch, plan->w_contrib, plan->ncontrib, plan->d_poff, plan->d_plist, plan->nparams, grad, st);
+                       v.batch, plan->w_contrib, plan->ncontrib, plan->d_poff, plan->d_plist, plan->nparams,
+                       seed ? 0.5 : 1.0, grad, st);
 }
 
 }  // extern "C"

@@ -72,8 +72,12 @@ struct FastDiv {
         d = div;
         s = 0;
         while ((uint64_t(1) << s) < uint64_t(div)) ++s;
-        uint64_t m = ((uint64_t(1) << (32 + s)) + div - 1) / div;
-        mprime = uint32_t(m - (uint64_t(1) << 32));
+        // s reaches 32 for divisors above 2^31 (registers of more than 2^31
+        // amplitudes), so 2^(32+s) needs 128-bit arithmetic; m - 2^32 still
+        // fits in 32 bits because 2^(32+s) / d < 2^33.
+        const unsigned __int128 one = 1;
+        const unsigned __int128 m = ((one << (32 + s)) + div - 1) / div;
+        mprime = uint32_t(uint64_t(m - (one << 32)));
     }
 
     __device__ inline uint32_t div(uint32_t n) const {
@@ -94,6 +98,15 @@ struct FastDiv {
 namespace qf {
 qf_status set_error(qf_status st, const char* fmt, ...);
 qf_status check_launch(const char* what);
+// Every device and pinned-host allocation of the library goes through these.
+// With the environment variable QF_TEST_FAIL_ALLOC set to a non-zero value they
+// fail with QF_ENOMEM before calling HIP (failure injection for tests).
+qf_status dev_malloc(void** p, size_t bytes, const char* what);
+qf_status dev_malloc_async(void** p, size_t bytes, hipStream_t st, const char* what);
+qf_status host_malloc_pinned(void** p, size_t bytes, const char* what);
+// QF_LOG set to a non-zero value: planner and autotuner choices go to stderr.
+bool log_enabled();
+void log_msg(const char* fmt, ...);
 }  // namespace qf
 
 #define QF_RETURN_IF(cond, st, ...)                      \

@@ -213,6 +213,7 @@ qf_status launch_build_mats(int D, int dtype, const DevGroup* groups, int ngroup
                             hipStream_t st);
 qf_status launch_grad(int D, const DevGradGroup* gg, int ngg, const DevGate* gates, const double* theta,
                       int64_t theta_stride, const double* M, int nslots, uint32_t batch, double* contrib, int ncontrib,
-                      const int32_t* p_off, const int32_t* p_list, int nparams, double* grad, hipStream_t st);
+                      const int32_t* p_off, const int32_t* p_list, int nparams, double scale, double* grad,
+                      hipStream_t st);
 
 }  // namespace qf

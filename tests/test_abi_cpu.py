@@ -115,3 +115,69 @@ def test_tile_search(qf):
     assert qf.plan_for(c5).num_stages < qf.plan_for(c5, tile_search=1).num_stages
     with pytest.raises(qf.QfError):
         qf.plan_for(c5, tile_search=3)
+
+
+def test_fastdiv_host(tmp_path):
+    """The library's division by invariant divisors (Granlund & Montgomery)
+    matches plain division for divisors up to 2^32 - 1 (registers of more than
+    2^31 amplitudes need the s = 32 case) on edge and random numerators."""
+    import shutil
+    import subprocess
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path / "fastdiv_check")
+    src = os.path.join(ROOT, "tests", "fastdiv_check.cpp")
+    r = subprocess.run([hipcc, "-O2", "-std=c++17", "-x", "hip", "--offload-arch=gfx950", src, "-o", exe],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([exe], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout
+    assert "OK" in r.stdout
+
+
+def test_forced_allocation_failure_returns_enomem():
+    """QF_TEST_FAIL_ALLOC=1 makes every library allocation fail with QF_ENOMEM
+    before any HIP call: a plan with a custom dense gate allocates its matrix
+    at creation, so creation reports QF_ENOMEM and leaves no plan behind."""
+    import subprocess
+    import sys
+    code = (
+        "import numpy as np, paper_2409_17716_amd as qf\n"
+        "try:\n"
+        "    qf.Plan(3, 2, [('u', 0, 2, np.eye(9))], 0)\n"
+        "    print('NO ERROR')\n"
+        "except qf.QfError as e:\n"
+        "    print('STATUS', e.status, str(e))\n")
+    env = dict(os.environ, QF_TEST_FAIL_ALLOC="1", PYTHONPATH=ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, cwd=ROOT)
+    assert "STATUS -4" in r.stdout, r.stdout + r.stderr
+    assert "QF_TEST_FAIL_ALLOC" in r.stdout
+
+
+def test_adjoint_flag_validation(qf):
+    """Unknown adjoint flags are refused synchronously (no HIP call)."""
+    c = qi.config2(n=3, layers=1)
+    p = qf.plan_for(c, fuse=1)
+    s = _fake_state(qf)
+    lam = qf.qf_state(0x2000, 3, 3, 1, 0)
+    th = np.zeros(c.nparams)
+    g = np.zeros(c.nparams)
+    qs = (ctypes.c_int32 * 1)(0)
+    td = (ctypes.c_double * 6)()
+    PD = ctypes.POINTER(ctypes.c_double)
+    st = qf.lib.qf_adjoint_grad(p._h, ctypes.byref(s), ctypes.byref(lam), th.ctypes.data_as(PD), 1, qs, td,
+                                g.ctypes.data_as(PD), 4, None)
+    assert st == qf.QF_EINVAL
+    assert b"flags" in qf.lib.qf_last_error()
+
+
+def test_single_qudit_plans(qf):
+    """n = 1 registers: every schedule plans (the tile is the whole register)."""
+    c = qi.Circuit(5, 1, [("h", 0), ("rx", 0, 0, 3, 0), ("clock", 0, 2), ("ry", 0, 1, 4, 1), ("x", 0, 3)],
+                   np.array([0.3, -1.1]))
+    for fuse in (0, 1, 2, 3):
+        p = qf.plan_for(c, fuse=fuse)
+        assert p.num_stages >= 1
+    qf.qf_shutdown()
+    qf.qf_shutdown()

@@ -224,7 +224,7 @@ def test_tile_order(qf, order, kernel):
     lam = qf.new_state(c.n, c.dim, "c64")
     g = p1.adjoint_grad(psi, lam, c.theta, terms)
     gref = grad.adjoint(c, terms)
-    assert np.abs(g - gref).max() <= 1e-4 * max(1.0, np.abs(gref).max())
+    assert _grad_close(g, gref, 1e-4, "c64"), np.abs(g - gref).max()
 
 
 @pytest.mark.parametrize("search", [1, 2])
@@ -242,4 +242,35 @@ def test_tile_search(qf, search):
     lam = qf.new_state(c.n, c.dim, "c64")
     g = p.adjoint_grad(t, lam, c.theta, terms)
     gref = grad.adjoint(c, terms)
-    assert np.abs(g - gref).max() <= 1e-4 * max(1.0, np.abs(gref).max())
+    assert _grad_close(g, gref, 1e-4, "c64"), np.abs(g - gref).max()
+
+
+@pytest.mark.parametrize("make", [lambda: qi.config2(n=10, layers=3), lambda: qi.config3(n=7, layers=2)],
+                         ids=["config2_n10", "config3_n7"])
+def test_default_tile_shapes_against_oracle(qf, make):
+    """Registers large enough that the default plans use the full-size tile
+    shapes (D=3: 7-qudit tiles with 2 low qudits and outer digits; D=5: 5-qudit
+    forward and 4-qudit adjoint tiles with outer digits): forward state and
+    adjoint gradient against the oracle."""
+    c = make()
+    terms = qi.zsum_terms(c.n)
+    p, t = run_gpu(qf, c, "c64")
+    want = sim.run(c)
+    assert maxabs(to_np(t), want) <= 2e-5
+    lam = qf.new_state(c.n, c.dim, "c64")
+    g = p.adjoint_grad(t, lam, c.theta, terms)
+    ref = grad.adjoint(c, terms, psi_final=want)
+    assert _grad_close(g, ref, 1e-4, "c64"), np.abs(g - ref).max()
+
+
+@pytest.mark.parametrize("fuse", [0, 1, 2, 3])
+def test_single_qudit_register(qf, fuse):
+    """n = 1: forward and adjoint of every schedule against the oracle."""
+    c = qi.Circuit(5, 1, [("h", 0), ("rx", 0, 0, 3, 0), ("clock", 0, 2), ("ry", 0, 1, 4, 1), ("rz", 0, 3, 2),
+                          ("x", 0, 3)], np.array([0.3, -1.1, 2.2]))
+    terms = qi.zsum_terms(1)
+    p, t = run_gpu(qf, c, "c128", fuse=fuse)
+    assert maxabs(to_np(t), sim.run(c)) <= 1e-12
+    lam = qf.new_state(1, 5, "c128")
+    g = p.adjoint_grad(t, lam, c.theta, terms)
+    assert _grad_close(g, grad.adjoint(c, terms), 1e-9, "c128")

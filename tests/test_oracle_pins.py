@@ -383,3 +383,22 @@ def test_adjoint_shared_parameter():
     g = grad.adjoint(c, qi.zsum_terms(2))
     fd = grad.finite_diff(c, qi.zsum_terms(2), [0], h=1e-5)
     assert abs(g[0] - fd[0]) < 1e-9
+
+
+@pytest.mark.parametrize("D,n,seed", [(3, 3, 5), (4, 2, 6), (2, 4, 7)])
+def test_seeded_adjoint_of_a_state_loss(D, n, seed):
+    """The paper's training loss on the output state, L = sum_x |t_x - psi_x|
+    (section "Code style"): the seeded adjoint from lam = dL/d(conj psi) =
+    -(t - psi) / (2 |t - psi|) equals central differences of L, and the seed
+    lam = H_O psi reproduces the expectation adjoint."""
+    c = qi.random_circuit(D, n, 40, seed)
+    target = qi.random_state(D, n, seed + 50)
+    psi = sim.run(c)
+    r = target - psi
+    lam = -r / (2 * np.abs(r))
+    g = grad.adjoint_seeded(c, lam, psi_final=psi)
+    fd = grad.finite_diff_state(c, lambda p: float(np.abs(target - p).sum()), np.arange(c.nparams), h=1e-6)
+    assert np.abs(g - fd).max() <= 1e-7 * max(1.0, np.abs(fd).max())
+    terms = qi.zsum_terms(n)
+    lam_o = measure.hermitian_part_diag(D, n, terms) * psi
+    assert np.abs(grad.adjoint_seeded(c, lam_o, psi_final=psi) - grad.adjoint(c, terms)).max() < 1e-12
