@@ -130,6 +130,18 @@ qf_status qf_probs(const qf_state* s, int32_t m, const int32_t* qudits, void* ou
 qf_status qf_expect(const qf_state* s, int32_t nterms, const int32_t* term_qudit,
                     const double* term_diag, double* out, void* stream);
 
+/* qf_expect for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same kernels and summation order (bitwise the same result), with the
+ * partial sums in a library-owned device array of 4 MiB per GPU, held until
+ * the process ends, instead of a stream-ordered allocation.  Calls no
+ * allocating routine.  Limit: batch * ceil(D^n / 4096) <= 262144 (one register
+ * of up to 2^30 amplitudes); beyond it QF_ERANGE.  Every call on a GPU shares
+ * that GPU's array: calls that overlap on one GPU (other streams, other
+ * threads) race, so the caller must order them. */
+qf_status qf_expect_noalloc(const qf_state* s, int32_t nterms, const int32_t* term_qudit,
+                            const double* term_diag, double* out, void* stream);
+
 /* ------------------------------------------------------------------------- */
 /* Circuit programs (plans): fused forward and adjoint gradient              */
 /* ------------------------------------------------------------------------- */

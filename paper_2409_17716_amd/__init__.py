@@ -67,6 +67,7 @@ _SIGS = {
     "qf_apply_fused": [_PS, _I32, _I32, _P, _P],
     "qf_probs": [_PS, _I32, _PI32, _P, _P],
     "qf_expect": [_PS, _I32, _PI32, _PD, _PD, _P],
+    "qf_expect_noalloc": [_PS, _I32, _PI32, _PD, _PD, _P],
     "qf_plan_create": [_I32, _I32, _I32, ctypes.POINTER(qf_op), _I32, _I32, ctypes.POINTER(qf_plan_opts),
                        ctypes.POINTER(ctypes.c_void_p)],
     "qf_plan_forward": [_P, _PS, _PD, _P],
@@ -236,6 +237,18 @@ def qf_expect(t, n: int, dim: int, terms, out=None, stream=None):
         out = torch.empty(2 * s.batch, dtype=torch.float64, device=t.device)
     _check(lib.qf_expect(ctypes.byref(s), len(qs), qp, tp,
                          ctypes.cast(ctypes.c_void_p(out.data_ptr()), _PD), _stream(stream)))
+    return out
+
+
+def qf_expect_noalloc(t, n: int, dim: int, terms, out, stream=None):
+    """qf_expect into a caller-allocated out (2 * batch doubles on the device),
+    with the library's static scratch array: no allocation."""
+    s = state_of(t, n, dim)
+    qs, tab = _terms_arrays(dim, terms)
+    qa, qp = _i32(qs)
+    ta, tp = _c128(tab)
+    _check(lib.qf_expect_noalloc(ctypes.byref(s), len(qs), qp, tp,
+                                 ctypes.cast(ctypes.c_void_p(out.data_ptr()), _PD), _stream(stream)))
     return out
 
 

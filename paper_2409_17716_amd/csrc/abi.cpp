@@ -257,4 +257,15 @@ qf_status qf_expect(const qf_state* s, int32_t nterms, const int32_t* term_qudit
     return launch_expect(v, active, table, out, reinterpret_cast<hipStream_t>(stream));
 }
 
+qf_status qf_expect_noalloc(const qf_state* s, int32_t nterms, const int32_t* term_qudit, const double* term_diag,
+                            double* out, void* stream) {
+    StateView v;
+    QF_CHECK(make_view(s, v));
+    QF_RETURN_IF(out == nullptr, QF_EINVAL, "out is NULL");
+    std::vector<int> active;
+    std::vector<double> table;
+    QF_CHECK(combine_terms(v, nterms, term_qudit, term_diag, active, table));
+    return launch_expect_noalloc(v, active, table, out, reinterpret_cast<hipStream_t>(stream));
+}
+
 }  // extern "C"

@@ -9,7 +9,9 @@
 //    loads of a wavefront is one contiguous 64-element run (coalesced).
 //  * L <  64: a workgroup stages whole [D][L] rows (contiguous in HBM) through
 //    LDS with coalesced loads/stores and each lane processes one fibre from LDS.
+#include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "qf_internal.h"
 
@@ -601,6 +603,47 @@ qf_status launch_expect(const StateView& s, const std::vector<int>& active, cons
         QF_HIP_CHECK(hipFreeAsync(partial, st));
         return r1 != QF_OK ? r1 : r2;
     });
+}
+
+// ---------------------------------------------------------------------------
+// Expectation values without allocation: the partial sums of every call on a
+// GPU go to one file-scope device array, `scratch` (each GPU holds its own copy
+// until the process ends).  Host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device, looked up once per
+// device on the first call there.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kScratchDoubles = size_t(1) << 19;  // 4 MiB
+__device__ __align__(256) double scratch[kScratchDoubles];
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_addr;  // device address of scratch, per device id
+}  // namespace
+
+static qf_status scratch_address(double** out) {
+    int dev = 0;
+    QF_HIP_CHECK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (size_t(dev) >= g_scratch_addr.size()) g_scratch_addr.resize(size_t(dev) + 1, nullptr);
+    if (g_scratch_addr[size_t(dev)] == nullptr) {
+        void* p = nullptr;
+        QF_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_addr[size_t(dev)] = static_cast<double*>(p);
+    }
+    *out = g_scratch_addr[size_t(dev)];
+    return QF_OK;
+}
+
+qf_status launch_expect_noalloc(const StateView& s, const std::vector<int>& active, const std::vector<double>& table,
+                                double* out, hipStream_t st) {
+    const size_t need = expect_ws_doubles(s);
+    if (need > kScratchDoubles)
+        return set_error(QF_ERANGE, "qf_expect_noalloc: %zu partial sums exceed the %zu of the library's scratch "
+                         "array (batch * ceil(D^n / 4096) must be <= %zu)", need / 2, kScratchDoubles / 2,
+                         kScratchDoubles / 2);
+    double* ws = nullptr;
+    QF_CHECK(scratch_address(&ws));
+    // every partial is written before it is read: nothing to clear
+    return launch_expect_ws(s, active, table, out, ws, st);
 }
 
 qf_status launch_diag_observable(const StateView& s, void* lam_amps, const std::vector<int>& active,

@@ -44,6 +44,9 @@ qf_status launch_expect(const StateView& s, const std::vector<int>& active,
 size_t expect_ws_doubles(const StateView& s);
 qf_status launch_expect_ws(const StateView& s, const std::vector<int>& active, const std::vector<double>& table,
                            double* out, double* ws, hipStream_t st);
+// Same with the library's static scratch array (no allocation; QF_ERANGE past its size).
+qf_status launch_expect_noalloc(const StateView& s, const std::vector<int>& active, const std::vector<double>& table,
+                                double* out, hipStream_t st);
 // Elementwise lam = f(x) * psi with f(x) = sum over active qudits of the real
 // table value (the Hermitian part of a diagonal observable).
 qf_status launch_diag_observable(const StateView& psi, void* lam_amps, const std::vector<int>& active,
