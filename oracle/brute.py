@@ -48,6 +48,43 @@ def sparse_diag(D: int, n: int, phase) -> np.ndarray:
     return P
 
 
+def sparse_controlled_rotation(op, D: int, n: int, theta) -> np.ndarray:
+    """The controlled rotation from the paper's sparse element rules
+    (subsection "Controlled Rotation Gate"): with k_c the control digit, the
+    two-level x- and y-type rotations put cos(k_c theta/2) on the j and k levels
+    of the target and -i sin(k_c theta/2) (x) or -sin / +sin (y, the
+    antisymmetric order of the plain R_y) between them; the z-type rotation puts
+    exp(-i k_c theta/2 sqrt(2/(j(j+1))) (-j)^[level = j]) on target levels
+    0..j; every other target level keeps its amplitude."""
+    kind, c, t = op[0], op[1], op[2]
+    th = float(theta[op[-1]])
+    N = D ** n
+    U = np.zeros((N, N), dtype=np.complex128)
+    for digs in itertools.product(range(D), repeat=n):
+        col = _index(D, digs)
+        kc, kt = digs[c], digs[t]
+        half = kc * th / 2
+        if kind == "crz":
+            j = op[3]
+            a = np.sqrt(2.0 / (j * (j + 1)))
+            ph = np.exp(-1j * half * a * ((-j) if kt == j else 1)) if kt <= j else 1.0
+            U[col, col] = ph
+            continue
+        j, k = op[3], op[4]
+        if kt not in (j, k):
+            U[col, col] = 1.0
+            continue
+        other = list(digs)
+        other[t] = k if kt == j else j
+        row_other = _index(D, other)
+        U[col, col] = np.cos(half)
+        if kind == "crx":
+            U[row_other, col] = -1j * np.sin(half)
+        else:  # <j|R|k> = -sin, <k|R|j> = +sin
+            U[row_other, col] = -np.sin(half) if kt == k else np.sin(half)
+    return U
+
+
 def op_unitary(op, D: int, n: int, theta) -> np.ndarray:
     kind = op[0]
     if kind in ("h", "clock", "rx", "ry", "rz"):
@@ -82,6 +119,8 @@ def op_unitary(op, D: int, n: int, theta) -> np.ndarray:
         c, t = op[1], op[2]
         w = gates.omega(D)
         return sparse_diag(D, n, lambda d: w ** ((d[c] * d[t]) % D))
+    if kind in ("crx", "cry", "crz"):
+        return sparse_controlled_rotation(op, D, n, theta)
     raise ValueError(kind)
 
 

@@ -103,6 +103,28 @@ def generator(op, D: int) -> np.ndarray:
     raise ValueError(f"{kind} has no generator")
 
 
+def crot_generator(op, D: int) -> np.ndarray:
+    """Generator S of a controlled rotation descriptor ("crx", c, t, j, k, p),
+    ("cry", c, t, j, k, p) or ("crz", c, t, j, p)."""
+    kind = op[0]
+    if kind == "crx":
+        return gm_sym(D, op[3], op[4])
+    if kind == "cry":
+        return gm_asym(D, op[3], op[4])
+    if kind == "crz":
+        return gm_diag(D, op[3])
+    raise ValueError(f"{kind} is not a controlled rotation")
+
+
+def crot_mats(op, D: int, theta: np.ndarray) -> list:
+    """The differentiable controlled rotation sum_m |m><m| (x) R(m theta)
+    (Appendix, subsection "Controlled Rotation Gate"): the target matrix for
+    each control level m, R(m theta) = exp(-i m theta S / 2)."""
+    S = crot_generator(op, D)
+    t = float(theta[op[-1]])
+    return [expm_hermitian(S, m * t) for m in range(D)]
+
+
 def op_matrix(op, D: int, theta: np.ndarray) -> np.ndarray:
     """Dense matrix of a one-qudit descriptor (or of a custom block)."""
     kind = op[0]

@@ -24,6 +24,21 @@ import numpy as np
 from . import gates, measure, sim
 
 
+def _rotation_derivative_term(op, D, n, psi, lam) -> float:
+    """Im <lam| S |psi> for a rotation exp(-i theta S / 2); for the controlled
+    rotation sum_m |m><m| (x) exp(-i m theta S / 2) the generator of the slab at
+    control level m is m S."""
+    if op[0] in ("rx", "ry", "rz"):
+        Spsi = sim.apply_1q(psi, D, n, op[1], gates.generator(op, D))
+    else:
+        S = gates.crot_generator(op, D)
+        Spsi = sim.apply_controlled_stack(psi, D, n, op[1], op[2], [m * S for m in range(D)])
+    return float(np.vdot(lam, Spsi).imag)
+
+
+ROTATIONS = ("rx", "ry", "rz", "crx", "cry", "crz")
+
+
 def loss(circuit, terms, theta=None) -> float:
     psi = sim.run(circuit, theta=theta)
     return float(measure.expect_diag(psi, circuit.dim, circuit.n, terms).real)
@@ -36,10 +51,8 @@ def adjoint(circuit, terms, theta=None, psi_final=None) -> np.ndarray:
     lam = measure.hermitian_part_diag(D, n, terms) * psi
     g = np.zeros(len(theta))
     for op in reversed(circuit.ops):
-        if op[0] in ("rx", "ry", "rz"):
-            S = gates.generator(op, D)
-            Spsi = sim.apply_1q(psi, D, n, op[1], S)
-            g[op[-1]] += float(np.vdot(lam, Spsi).imag)
+        if op[0] in ROTATIONS:
+            g[op[-1]] += _rotation_derivative_term(op, D, n, psi, lam)
         psi = sim.apply_inverse(psi, D, n, op, theta)
         lam = sim.apply_inverse(lam, D, n, op, theta)
     return g
@@ -54,9 +67,8 @@ def adjoint_seeded(circuit, lam_final, theta=None, psi_final=None) -> np.ndarray
     lam = np.array(lam_final, dtype=np.complex128)
     g = np.zeros(len(theta))
     for op in reversed(circuit.ops):
-        if op[0] in ("rx", "ry", "rz"):
-            S = gates.generator(op, D)
-            g[op[-1]] += float(np.vdot(lam, sim.apply_1q(psi, D, n, op[1], S)).imag)
+        if op[0] in ROTATIONS:
+            g[op[-1]] += _rotation_derivative_term(op, D, n, psi, lam)
         psi = sim.apply_inverse(psi, D, n, op, theta)
         lam = sim.apply_inverse(lam, D, n, op, theta)
     return g

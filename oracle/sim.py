@@ -112,6 +112,19 @@ def apply_swap(psi, D, n, a, b):
     return apply_digit_map(psi, D, n, fn)
 
 
+def apply_controlled_stack(psi, D, n, c, t, mats) -> np.ndarray:
+    """sum_m |m><m|_c (x) mats[m]_t: on the slab where qudit c is at level m,
+    every fibre along qudit t is multiplied by mats[m]."""
+    v = np.array(psi, dtype=np.complex128).reshape((D,) * n)
+    tt = t if t < c else t - 1  # the target's axis once axis c is indexed away
+    for m in range(D):
+        idx = [slice(None)] * n
+        idx[c] = m
+        sub = v[tuple(idx)]
+        v[tuple(idx)] = np.moveaxis(np.tensordot(np.asarray(mats[m]), sub, axes=([1], [tt])), 0, tt)
+    return v.reshape(-1)
+
+
 def apply_phase(psi, D, n, phase_of_digits) -> np.ndarray:
     """Diagonal gate: psi_x <- phi(digits(x)) psi_x."""
     dig = digits_of(D, n, np.arange(D ** n))
@@ -140,6 +153,10 @@ def apply_op(psi: np.ndarray, D: int, n: int, op, theta) -> np.ndarray:
         return apply_cz(psi, D, n, op[1], op[2])
     if kind == "swap":
         return apply_swap(psi, D, n, op[1], op[2])
+    if kind in ("crx", "cry", "crz"):
+        return apply_controlled_stack(psi, D, n, op[1], op[2], gates.crot_mats(op, D, theta))
+    if kind == "cstack":
+        return apply_controlled_stack(psi, D, n, op[1], op[2], op[3])
     raise ValueError(f"unknown gate kind {kind}")
 
 
@@ -170,6 +187,8 @@ def inverse_op(op, D: int, theta):
         return ("cz_inv", op[1], op[2])
     if kind == "swap":
         return op
+    if kind in ("crx", "cry", "crz"):
+        return ("cstack", op[1], op[2], [m.conj().T for m in gates.crot_mats(op, D, theta)])
     raise ValueError(kind)
 
 

@@ -19,6 +19,9 @@ significant digit of the basis index):
     ("cshift", c, t, shifts) x_t -> x_t + shifts[x_c] mod D (c = -1: shifts[0])
     ("cz", c, t)             phase omega^(x_c x_t)
     ("u", q0, k, mat)        dense D^k x D^k matrix on qudits q0..q0+k-1
+    ("crx", c, t, j, k, p)   controlled rotation sum_m |m><m|_c (x) R_x^{jk}(m theta)_t
+    ("cry", c, t, j, k, p)   the same with R_y^{jk}
+    ("crz", c, t, j, p)      the same with R_z^{j}
 
 The angle of a rotation is ``theta[p]``.
 """
@@ -256,7 +259,35 @@ def random_circuit(D: int, n: int, depth: int, seed: int, kinds=None) -> Circuit
         elif kind == "u2" and n >= 2:
             q0 = int(rng.integers(n - 1))
             ops.append(("u", q0, 2, random_unitary(D * D, rng)))
+        elif kind in ("crx", "cry", "crz") and n >= 2:
+            c, t = rng.choice(n, size=2, replace=False).tolist()
+            if kind == "crz":
+                ops.append(("crz", int(c), int(t), int(rng.integers(1, D)), len(thetas)))
+            else:
+                j, k = sorted(rng.choice(D, size=2, replace=False).tolist())
+                ops.append((kind, int(c), int(t), int(j), int(k), len(thetas)))
+            thetas.append(float(rng.uniform(-np.pi, np.pi)))
     return Circuit(D, n, ops, np.asarray(thetas, dtype=np.float64), f"random_d{D}_n{n}_s{seed}")
+
+
+def cr_ansatz(D: int, n: int, layers: int, seed: int) -> Circuit:
+    """Ansatz with the paper's differentiable controlled rotations: per layer
+    R_y on level pairs (0,1), (1,2) of every qudit, then controlled rotations
+    i -> i+1 mod n cycling through the x, y and z types (x, y on levels (0,1),
+    z with j = 1), each with its own angle.  Angles ~ U[-pi, pi] from the seed."""
+    rng = np.random.default_rng(seed)
+    ops: List[Op] = []
+    p = 0
+    for _ in range(layers):
+        p = _rot_layer(ops, n, ("y",), adjacent_pairs(D, 2), p)
+        for i in range(n):
+            kind = ("crx", "cry", "crz")[i % 3]
+            if kind == "crz":
+                ops.append(("crz", i, (i + 1) % n, 1, p))
+            else:
+                ops.append((kind, i, (i + 1) % n, 0, 1, p))
+            p += 1
+    return Circuit(D, n, ops, rng.uniform(-np.pi, np.pi, size=p), f"cr_ansatz_d{D}_n{n}_l{layers}")
 
 
 def grover_d3_n2_marker22() -> dict:

@@ -402,3 +402,73 @@ def test_seeded_adjoint_of_a_state_loss(D, n, seed):
     terms = qi.zsum_terms(n)
     lam_o = measure.hermitian_part_diag(D, n, terms) * psi
     assert np.abs(grad.adjoint_seeded(c, lam_o, psi_final=psi) - grad.adjoint(c, terms)).max() < 1e-12
+
+
+# ---------------------------------------------------------- controlled rotation
+
+def _cr_op(case, c=0, t=1, p=0):
+    if case["gate"] == "crz":
+        return ("crz", c, t, case["j"], p)
+    return (case["gate"], c, t, case["j"], case["k"], p)
+
+
+def test_controlled_rotation_is_the_textbook_gate_for_qubits():
+    """D = 2: sum_m |m><m| (x) R(m theta) is |0><0| (x) I + |1><1| (x) R(theta),
+    the textbook controlled rotation, for all three types."""
+    fx = json.load(open(os.path.join(GOLDEN, "textbook_controlled_rotations.json")))
+    for case in fx["cases"]:
+        for theta in (0.4, -2.3, np.pi):
+            c = qi.Circuit(2, 2, [_cr_op(case)], np.array([theta]))
+            want = _eval_matrix(case["matrix"], theta)
+            assert np.abs(brute.circuit_unitary(c) - want).max() < TOL, case["name"]
+            assert np.abs(np.column_stack([sim.run(c, np.eye(4)[:, i]) for i in range(4)]) - want).max() < TOL
+
+
+@pytest.mark.parametrize("D,n,seed", [(3, 3, 1), (4, 3, 2), (5, 2, 3), (2, 4, 4)])
+def test_controlled_rotation_sparse_rules_match_definition(D, n, seed):
+    """The paper's sparse element rules (brute route) against the definition as
+    a control-indexed stack of rotations exp(-i m theta S / 2), on random
+    circuits mixing controlled rotations of every type with the other gates."""
+    c = qi.random_circuit(D, n, 40, seed, kinds=["h", "ry", "csum", "crx", "cry", "crz", "clock"])
+    assert any(op[0].startswith("cr") for op in c.ops)
+    U = brute.circuit_unitary(c)
+    assert np.abs(U.conj().T @ U - np.eye(D ** n)).max() < 1e-10
+    psi0 = qi.random_state(D, n, seed + 7)
+    assert np.abs(sim.run(c, psi0) - U @ psi0).max() < 1e-12
+
+
+@pytest.mark.parametrize("D", [3, 4, 6])
+def test_controlled_rotation_identities(D):
+    """theta = 0 is the identity; the control's level-0 slab never changes; on
+    the slab at control level 1 the gate is the plain rotation R(theta), at level
+    m it is R(m theta); angles add: C(a) C(b) = C(a + b)."""
+    n = 2
+    psi = qi.random_state(D, n, 3 + D)
+    for kind, extra in (("crx", (0, D - 1)), ("cry", (1, 2)), ("crz", (D - 1,))):
+        op = (kind, 0, 1) + extra + (0,)
+        plain = ({"crx": "rx", "cry": "ry", "crz": "rz"}[kind], 1) + extra + (0,)
+        out0 = sim.apply_op(psi, D, n, op, np.array([0.0]))
+        assert np.abs(out0 - psi).max() < TOL
+        th = np.array([0.83])
+        out = sim.apply_op(psi, D, n, op, th)
+        v, w = psi.reshape(D, D), out.reshape(D, D)
+        assert np.abs(w[0] - v[0]).max() < TOL
+        assert np.abs(w[1] - gates.op_matrix(plain, D, th) @ v[1]).max() < TOL
+        assert np.abs(w[2] - gates.op_matrix(plain, D, 2 * th) @ v[2]).max() < TOL
+        ab = sim.apply_op(sim.apply_op(psi, D, n, op, np.array([0.5])), D, n, op, np.array([-1.2]))
+        assert np.abs(ab - sim.apply_op(psi, D, n, op, np.array([-0.7]))).max() < TOL
+
+
+@pytest.mark.parametrize("D,n,seed", [(3, 3, 11), (4, 2, 12), (2, 4, 13)])
+def test_controlled_rotation_adjoint_matches_finite_differences(D, n, seed):
+    """The adjoint of the controlled rotation (slab generator m S) against
+    central differences, alone and with shared angles."""
+    c = qi.random_circuit(D, n, 40, seed, kinds=["h", "rx", "csum", "crx", "cry", "crz", "cz"])
+    terms = qi.zsum_terms(n)
+    g = grad.adjoint(c, terms)
+    fd = grad.finite_diff(c, terms, np.arange(c.nparams), h=1e-5)
+    assert np.abs(g - fd).max() <= 1e-8 * max(1.0, np.abs(fd).max())
+    c2 = qi.cr_ansatz(D, n, 2, seed)
+    g2 = grad.adjoint(c2, terms)
+    fd2 = grad.finite_diff(c2, terms, np.arange(c2.nparams), h=1e-5)
+    assert np.abs(g2 - fd2).max() <= 1e-8 * max(1.0, np.abs(fd2).max())
