@@ -102,6 +102,15 @@ qf_status qf_apply_ctrl(const qf_state* s, int32_t ctrl, int32_t tgt,
 qf_status qf_apply_diag(const qf_state* s, int32_t k, const int32_t* qudits,
                         const double* phases, void* stream);
 
+/* The paper's differentiable controlled rotation (Appendix, subsection
+ * "Controlled Rotation Gate"): sum_m |m><m|_ctrl (x) R(m theta)_tgt with
+ * R = exp(-i theta S / 2) and S = S_x^{jk} (kind QF_OP_CRX), S_y^{jk}
+ * (QF_OP_CRY, j < k) or the diagonal S_z^{j} (QF_OP_CRZ, 1 <= j < D, k ignored).
+ * ctrl != tgt, both in [0, n); theta in radians.  The x and y types read and
+ * write only target levels j and k; the control's level-0 slab is untouched. */
+qf_status qf_apply_crot(const qf_state* s, int32_t kind, int32_t ctrl, int32_t tgt,
+                        int32_t j, int32_t k, double theta, void* stream);
+
 /* Custom dense gate on the k adjacent qudits q0..q0+k-1 (the paper's
  * U(matrix, index), section "Grover's algorithm"): psi[h, :, l] <- B psi[h, :, l]
  * with the register viewed as [D^q0][D^k][D^(n-q0-k)].
@@ -156,14 +165,17 @@ typedef enum {
     QF_OP_CSUM = 6,    /* x_q1 -> x_q1 + x_q0 mod D  (q0 control, q1 target)       */
     QF_OP_CSHIFT = 7,  /* x_q1 -> x_q1 + shifts[x_q0] mod D                        */
     QF_OP_CZ = 8,      /* phase w^(x_q0 x_q1)                                      */
-    QF_OP_U = 9        /* dense D^k x D^k matrix `mat` on qudits q0..q0+k-1        */
+    QF_OP_U = 9,       /* dense D^k x D^k matrix `mat` on qudits q0..q0+k-1        */
+    QF_OP_CRX = 10,    /* controlled rotation sum_m |m><m|_q0 (x) R_x^{jk}(m theta)_q1 */
+    QF_OP_CRY = 11,    /* the same with R_y^{jk}                                   */
+    QF_OP_CRZ = 12     /* the same with R_z^{j}, 1 <= j < D                        */
 } qf_op_kind;
 
 typedef struct qf_op {
     int32_t kind;        /* qf_op_kind                                              */
     int32_t q0;          /* target of one-qudit gates; control of CSUM/CSHIFT/CZ;    */
                          /* first qudit of U                                         */
-    int32_t q1;          /* target of CSUM/CSHIFT/CZ; k (qudit count) of U           */
+    int32_t q1;          /* target of CSUM/CSHIFT/CZ/CR*; k (qudit count) of U       */
     int32_t j, k;        /* levels: RX/RY use j < k; RZ uses j; X and CLOCK use j as */
                          /* the shift / exponent a                                   */
     int32_t param;       /* rotation angle slot in theta, -1 for fixed gates; a     */

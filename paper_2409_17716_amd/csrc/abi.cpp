@@ -212,6 +212,38 @@ qf_status qf_apply_diag(const qf_state* s, int32_t k, const int32_t* qudits, con
     return launch_diag(v, k, qudits, phases, reinterpret_cast<hipStream_t>(stream));
 }
 
+qf_status qf_apply_crot(const qf_state* s, int32_t kind, int32_t ctrl, int32_t tgt, int32_t j, int32_t k,
+                        double theta, void* stream) {
+    StateView v;
+    QF_CHECK(make_view(s, v));
+    QF_RETURN_IF(kind != QF_OP_CRX && kind != QF_OP_CRY && kind != QF_OP_CRZ, QF_EINVAL,
+                 "kind %d is not a controlled rotation", kind);
+    QF_CHECK(check_qudit(v, ctrl, "control"));
+    QF_CHECK(check_qudit(v, tgt, "target"));
+    QF_RETURN_IF(ctrl == tgt, QF_EINVAL, "control and target are both %d", ctrl);
+    if (kind == QF_OP_CRZ)
+        QF_RETURN_IF(j < 1 || uint32_t(j) >= v.D, QF_EINVAL, "R_z level j = %d needs 1 <= j < D", j);
+    else
+        QF_RETURN_IF(!(j >= 0 && j < k && uint32_t(k) < v.D), QF_EINVAL, "levels (%d, %d) need 0 <= j < k < D", j, k);
+    QF_RETURN_IF(!std::isfinite(theta), QF_EINVAL, "theta is not finite");
+    // table for control levels m = 0..D-1 (layout in k_crot.hip)
+    std::vector<double> tab(size_t(4) * v.D, 0.0);
+    for (uint32_t m = 0; m < v.D; ++m) {
+        if (kind == QF_OP_CRZ) {
+            const double a = std::sqrt(2.0 / (double(j) * (j + 1)));
+            tab[4 * m] = std::cos(-0.5 * m * theta * a);
+            tab[4 * m + 1] = std::sin(-0.5 * m * theta * a);
+            tab[4 * m + 2] = std::cos(0.5 * m * theta * a * j);
+            tab[4 * m + 3] = std::sin(0.5 * m * theta * a * j);
+        } else {
+            tab[4 * m] = std::cos(0.5 * m * theta);
+            tab[4 * m + 1] = std::sin(0.5 * m * theta);
+        }
+    }
+    return launch_crot(v, CrotArgs{kind - QF_OP_CRX, ctrl, tgt, j, k}, nullptr, 0, tab.data(),
+                       reinterpret_cast<hipStream_t>(stream));
+}
+
 qf_status qf_apply_fused(const qf_state* s, int32_t k, int32_t q0, const void* B, void* stream) {
     StateView v;
     QF_CHECK(make_view(s, v));

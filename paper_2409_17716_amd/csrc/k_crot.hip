@@ -1,0 +1,244 @@
+// The differentiable controlled rotation sum_m |m><m|_c (x) R^{jk}_alpha(m theta)_t
+// (arXiv:2409.17716, Appendix, subsection "Controlled Rotation Gate").
+//
+// The register is viewed as [H][D][L] for the target t (L = D^(n-1-t)); a
+// fibre is the D amplitudes psi[h, :, l], and its control digit m is read from
+// its index.  The x- and y-type rotations mix only target levels j and k, so a
+// lane reads and writes just those two amplitudes of its fibre (2/D of the
+// state); the z type scales levels 0..j.  Fibres at control level 0 are left
+// alone.  Consecutive lanes take consecutive l, so for L >= 64 every access of
+// a wavefront is one contiguous run.
+//
+// Per control level m the kernels read a two-entry table: x, y types
+// (cos(m theta / 2), sin(m theta / 2)) in one complex entry (the inverse
+// negates the sine); z type the phase of levels below j and the phase of level
+// j.  The adjoint kernel takes the inverse table, adds
+//   m * Im <lam_f| S |psi_f>   (the slab generator is m S)
+// over its fibres in FP64 (fixed tree per workgroup, then a fixed-order sum per
+// register) and un-applies the gate on psi and lam.
+#include <type_traits>
+
+#include "qf_internal.h"
+
+namespace qf {
+namespace {
+
+constexpr int kCB = 256;
+
+struct CrGeom {
+    uint32_t L;          // stride of the target qudit
+    FastDiv divL;
+    FastDiv cstride;     // stride of the control qudit
+    uint32_t nfib;       // fibres per register, D^(n-1)
+    uint32_t N;          // D^n
+    uint32_t bpr;        // workgroups per register
+    int32_t kind;        // 0 = x, 1 = y, 2 = z
+    int32_t j, k;        // levels (z: j)
+    double alpha;        // z: sqrt(2 / (j (j + 1)))
+};
+
+template <typename T>
+struct CrTab {
+    cplx<T> t[2 * kMaxDim];
+};
+
+template <typename T, int D>
+__device__ __forceinline__ void load_tab(const CrTab<T>& harg, const cplx<T>* __restrict__ dtab, size_t tab_stride,
+                                         uint32_t b, cplx<T>* tab) {
+    if (threadIdx.x < 2 * D) tab[threadIdx.x] = dtab ? dtab[size_t(b) * tab_stride + threadIdx.x] : harg.t[threadIdx.x];
+    __syncthreads();
+}
+
+// Applies the table's rotation for control level m to the fibre at base.
+template <typename T, int D>
+__device__ __forceinline__ void rotate(cplx<T>* __restrict__ psi, const CrGeom& g, uint32_t base, const cplx<T>* tab,
+                                       uint32_t m) {
+    if (g.kind == 2) {
+        const cplx<T> p1 = tab[2 * m], p2 = tab[2 * m + 1];
+        for (int d = 0; d < g.j; ++d) psi[base + uint32_t(d) * g.L] = cmul(psi[base + uint32_t(d) * g.L], p1);
+        psi[base + uint32_t(g.j) * g.L] = cmul(psi[base + uint32_t(g.j) * g.L], p2);
+        return;
+    }
+    const T c = tab[2 * m].re, s = tab[2 * m].im;
+    const uint32_t ia = base + uint32_t(g.j) * g.L, ib = base + uint32_t(g.k) * g.L;
+    const cplx<T> a = psi[ia], b = psi[ib];
+    if (g.kind == 0) {  // [[c, -i s], [-i s, c]]
+        psi[ia] = cmake<T>(c * a.re + s * b.im, c * a.im - s * b.re);
+        psi[ib] = cmake<T>(c * b.re + s * a.im, c * b.im - s * a.re);
+    } else {            // [[c, -s], [s, c]]
+        psi[ia] = cmake<T>(c * a.re - s * b.re, c * a.im - s * b.im);
+        psi[ib] = cmake<T>(s * a.re + c * b.re, s * a.im + c * b.im);
+    }
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(kCB) void k_crot(cplx<T>* __restrict__ psi, CrGeom g, CrTab<T> harg,
+                                              const cplx<T>* __restrict__ dtab, size_t tab_stride) {
+    __shared__ cplx<T> tab[2 * D];
+    const uint32_t b = blockIdx.x / g.bpr;
+    load_tab<T, D>(harg, dtab, tab_stride, b, tab);
+    const uint32_t f = (blockIdx.x - b * g.bpr) * kCB + threadIdx.x;
+    if (f >= g.nfib) return;
+    const uint32_t h = g.divL.div(f);
+    const uint32_t local = h * (uint32_t(D) * g.L) + (f - h * g.L);
+    const uint32_t m = g.cstride.div(local) % D;
+    if (m == 0) return;
+    rotate<T, D>(psi + size_t(b) * g.N, g, local, tab, m);
+}
+
+// Deterministic workgroup sum (fixed tree).
+__device__ inline double cr_block_sum(double v, double* sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = kCB / 2; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(kCB) void k_crot_adj(cplx<T>* __restrict__ psi, cplx<T>* __restrict__ lam, CrGeom g,
+                                                  CrTab<T> harg, const cplx<T>* __restrict__ dtab, size_t tab_stride,
+                                                  double* __restrict__ partial) {
+    __shared__ cplx<T> tab[2 * D];
+    __shared__ double sh[kCB];
+    const uint32_t b = blockIdx.x / g.bpr;
+    load_tab<T, D>(harg, dtab, tab_stride, b, tab);
+    const uint32_t f = (blockIdx.x - b * g.bpr) * kCB + threadIdx.x;
+    double acc = 0.0;
+    if (f < g.nfib) {
+        const uint32_t h = g.divL.div(f);
+        const uint32_t local = h * (uint32_t(D) * g.L) + (f - h * g.L);
+        const uint32_t m = g.cstride.div(local) % D;
+        if (m != 0) {
+            cplx<T>* p = psi + size_t(b) * g.N;
+            cplx<T>* l = lam + size_t(b) * g.N;
+            double im = 0.0;  // Im <lam_f| S |psi_f>
+            if (g.kind == 2) {
+                for (int d = 0; d <= g.j; ++d) {
+                    const cplx<T> x = p[local + uint32_t(d) * g.L], y = l[local + uint32_t(d) * g.L];
+                    const double w = d < g.j ? g.alpha : -g.alpha * g.j;
+                    im += w * (double(y.re) * double(x.im) - double(y.im) * double(x.re));
+                }
+            } else {
+                const uint32_t ia = local + uint32_t(g.j) * g.L, ib = local + uint32_t(g.k) * g.L;
+                const cplx<T> pj = p[ia], pk = p[ib], lj = l[ia], lk = l[ib];
+                // conj(lj) pk and conj(lk) pj
+                const double r1 = double(lj.re) * pk.re + double(lj.im) * pk.im;
+                const double i1 = double(lj.re) * pk.im - double(lj.im) * pk.re;
+                const double r2 = double(lk.re) * pj.re + double(lk.im) * pj.im;
+                const double i2 = double(lk.re) * pj.im - double(lk.im) * pj.re;
+                im = g.kind == 0 ? i1 + i2 : r2 - r1;  // x: Im(z1 + z2); y: Im(-i z1 + i z2)
+            }
+            acc = double(m) * im;
+            rotate<T, D>(p, g, local, tab, m);
+            rotate<T, D>(l, g, local, tab, m);
+        }
+    }
+    const double s = cr_block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// out[b * ostride] = sum of the bpr partials of register b (fixed order).
+__global__ __launch_bounds__(kCB) void k_crot_reduce(const double* __restrict__ partial, uint32_t bpr,
+                                                     double* __restrict__ out, uint32_t ostride) {
+    __shared__ double sh[kCB];
+    const uint32_t b = blockIdx.x;
+    double s = 0.0;
+    for (uint32_t i = threadIdx.x; i < bpr; i += kCB) s += partial[size_t(b) * bpr + i];
+    s = cr_block_sum(s, sh);
+    if (threadIdx.x == 0) out[size_t(b) * ostride] = s;
+}
+
+template <class F>
+qf_status with_dim_c(uint32_t D, F&& f) {
+    switch (D) {
+        case 2: return f(std::integral_constant<int, 2>{});
+        case 3: return f(std::integral_constant<int, 3>{});
+        case 4: return f(std::integral_constant<int, 4>{});
+        case 5: return f(std::integral_constant<int, 5>{});
+        case 6: return f(std::integral_constant<int, 6>{});
+        case 7: return f(std::integral_constant<int, 7>{});
+        case 8: return f(std::integral_constant<int, 8>{});
+        case 9: return f(std::integral_constant<int, 9>{});
+        case 10: return f(std::integral_constant<int, 10>{});
+        case 11: return f(std::integral_constant<int, 11>{});
+        case 12: return f(std::integral_constant<int, 12>{});
+        case 13: return f(std::integral_constant<int, 13>{});
+        case 14: return f(std::integral_constant<int, 14>{});
+        case 15: return f(std::integral_constant<int, 15>{});
+        case 16: return f(std::integral_constant<int, 16>{});
+        default: return set_error(QF_EUNSUPPORTED, "dim %u outside 2..16", D);
+    }
+}
+
+CrGeom make_geom(const StateView& s, const CrotArgs& a) {
+    CrGeom g{};
+    g.L = ipow(s.D, s.n - 1 - uint32_t(a.tgt));
+    g.divL.init(g.L);
+    g.cstride.init(ipow(s.D, s.n - 1 - uint32_t(a.ctrl)));
+    g.nfib = s.N / s.D;
+    g.N = s.N;
+    g.bpr = (g.nfib + kCB - 1) / kCB;
+    g.kind = a.kind;
+    g.j = a.j;
+    g.k = a.k;
+    g.alpha = a.kind == 2 ? std::sqrt(2.0 / (double(a.j) * (a.j + 1))) : 0.0;
+    return g;
+}
+
+template <typename T>
+CrTab<T> host_tab(const double* htab, uint32_t D) {
+    CrTab<T> t{};
+    if (htab)
+        for (uint32_t i = 0; i < 2 * D; ++i) t.t[i] = cmake<T>(T(htab[2 * i]), T(htab[2 * i + 1]));
+    return t;
+}
+
+}  // namespace
+
+size_t crot_partial_doubles(const StateView& s) {
+    const uint32_t nfib = s.N / s.D;
+    return size_t((nfib + kCB - 1) / kCB) * s.batch;
+}
+
+qf_status launch_crot(const StateView& s, const CrotArgs& a, const void* dtab, size_t tab_stride, const double* htab,
+                      hipStream_t st) {
+    const CrGeom g = make_geom(s, a);
+    return with_dim_c(s.D, [&](auto dtag) -> qf_status {
+        constexpr int D = decltype(dtag)::value;
+        if (s.dtype == QF_C64)
+            hipLaunchKernelGGL((k_crot<float, D>), dim3(g.bpr * s.batch), dim3(kCB), 0, st,
+                               reinterpret_cast<cplx<float>*>(s.amps), g, host_tab<float>(htab, s.D),
+                               reinterpret_cast<const cplx<float>*>(dtab), tab_stride);
+        else
+            hipLaunchKernelGGL((k_crot<double, D>), dim3(g.bpr * s.batch), dim3(kCB), 0, st,
+                               reinterpret_cast<cplx<double>*>(s.amps), g, host_tab<double>(htab, s.D),
+                               reinterpret_cast<const cplx<double>*>(dtab), tab_stride);
+        return check_launch("controlled rotation");
+    });
+}
+
+qf_status launch_crot_adj(const StateView& s, void* lam, const CrotArgs& a, const void* dtab, size_t tab_stride,
+                          const double* htab, double* partial, double* out, uint32_t ostride, hipStream_t st) {
+    const CrGeom g = make_geom(s, a);
+    return with_dim_c(s.D, [&](auto dtag) -> qf_status {
+        constexpr int D = decltype(dtag)::value;
+        if (s.dtype == QF_C64)
+            hipLaunchKernelGGL((k_crot_adj<float, D>), dim3(g.bpr * s.batch), dim3(kCB), 0, st,
+                               reinterpret_cast<cplx<float>*>(s.amps), reinterpret_cast<cplx<float>*>(lam), g,
+                               host_tab<float>(htab, s.D), reinterpret_cast<const cplx<float>*>(dtab), tab_stride,
+                               partial);
+        else
+            hipLaunchKernelGGL((k_crot_adj<double, D>), dim3(g.bpr * s.batch), dim3(kCB), 0, st,
+                               reinterpret_cast<cplx<double>*>(s.amps), reinterpret_cast<cplx<double>*>(lam), g,
+                               host_tab<double>(htab, s.D), reinterpret_cast<const cplx<double>*>(dtab), tab_stride,
+                               partial);
+        QF_CHECK(check_launch("controlled rotation adjoint"));
+        hipLaunchKernelGGL(k_crot_reduce, dim3(s.batch), dim3(kCB), 0, st, partial, g.bpr, out, ostride);
+        return check_launch("controlled rotation gradient sum");
+    });
+}
+
+}  // namespace qf

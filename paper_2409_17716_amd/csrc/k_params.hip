@@ -108,6 +108,24 @@ __global__ void k_build_mats(const DevGroup* __restrict__ groups, int ngroups, c
         for (int i = 0; i < gr.ng; ++i) dm_apply_gate<D>(gates[gr.g0 + i], th, gr.inv != 0, a);
         for (int r = 0; r < D; ++r)
             for (int c = 0; c < D; ++c) out[r * D + c] = cmake<T>(T(a.m[r][c].re), T(a.m[r][c].im));
+    } else if (gr.type == DG_CR) {
+        // controlled rotation table (layout in k_crot.hip); inverse: R(-m t)
+        const DevGate& g = gates[gr.g0];
+        const double t = th[g.param] * sg;
+        for (int m = 0; m < D; ++m) {
+            double sn, cs;
+            if (g.kind == QF_OP_CRZ) {
+                const double a = sqrt(2.0 / (double(g.j) * (g.j + 1)));
+                sincos(-0.5 * m * t * a, &sn, &cs);
+                out[2 * m] = cmake<T>(T(cs), T(sn));
+                sincos(0.5 * m * t * a * g.j, &sn, &cs);
+                out[2 * m + 1] = cmake<T>(T(cs), T(sn));
+            } else {
+                sincos(0.5 * m * t, &sn, &cs);
+                out[2 * m] = cmake<T>(T(cs), T(sn));
+                out[2 * m + 1] = cmake<T>(T(0), T(0));
+            }
+        }
     } else if (gr.type == DG_CZ) {
         for (int x = 0; x < D; ++x)
             for (int y = 0; y < D; ++y) {

@@ -78,6 +78,33 @@ static bool is_1q(int kind) {
     return kind == QF_OP_H || kind == QF_OP_CLOCK || kind == QF_OP_RX || kind == QF_OP_RY || kind == QF_OP_RZ;
 }
 static bool is_rot(int kind) { return kind == QF_OP_RX || kind == QF_OP_RY || kind == QF_OP_RZ; }
+static bool is_crot(int kind) { return kind == QF_OP_CRX || kind == QF_OP_CRY || kind == QF_OP_CRZ; }
+// Gates that never enter an LDS tile: each makes a pass of its own (dense
+// blocks, controlled rotations).
+static bool pass_gate(int kind) { return kind == QF_OP_U || is_crot(kind); }
+static CrotArgs crot_args(const qf_op& o) { return CrotArgs{o.kind - QF_OP_CRX, o.q0, o.q1, o.j, o.k}; }
+
+// Table of a controlled rotation for control levels m = 0..D-1 (2 D complex
+// entries, interleaved FP64; layout in k_crot.hip): x, y types
+// (cos(m t / 2), sin(m t / 2)) at 2m; z type exp(-i m t a / 2) (levels below
+// j) at 2m and exp(+i m t a j / 2) (level j) at 2m + 1, a = sqrt(2/(j(j+1))).
+// The inverse is R(-m t).
+static void crot_table(const qf_op& o, int D, const double* theta, bool inverse, std::vector<double>& out) {
+    out.assign(size_t(4) * D, 0.0);
+    const double t = theta[o.param] * (inverse ? -1.0 : 1.0);
+    for (int m = 0; m < D; ++m) {
+        if (o.kind == QF_OP_CRZ) {
+            const double a = std::sqrt(2.0 / (double(o.j) * (o.j + 1)));
+            out[4 * m] = std::cos(-0.5 * m * t * a);
+            out[4 * m + 1] = std::sin(-0.5 * m * t * a);
+            out[4 * m + 2] = std::cos(0.5 * m * t * a * o.j);
+            out[4 * m + 3] = std::sin(0.5 * m * t * a * o.j);
+        } else {
+            out[4 * m] = std::cos(0.5 * m * t);
+            out[4 * m + 1] = std::sin(0.5 * m * t);
+        }
+    }
+}
 
 static qf_status check_finite_theta(const double* theta, int nparams) {
     for (int i = 0; i < nparams; ++i)
@@ -156,7 +183,7 @@ static Mat generator(const qf_op& g, int D) {
 // of one-qudit gates on a qudit).
 // ---------------------------------------------------------------------------
 
-enum StepType { ST_AXIS, ST_CTRL, ST_DIAG, ST_FUSED };
+enum StepType { ST_AXIS, ST_CTRL, ST_DIAG, ST_FUSED, ST_CROT };
 
 struct Step {
     StepType type;
@@ -166,6 +193,7 @@ struct Step {
     std::vector<int> gates;  // gate indices folded into this step, in order
     bool has_param = false;
     int slot = -1;           // adjoint M slot
+    int cr_slot = -1;        // ST_CROT: index among the controlled rotations
 };
 
 // ---------------------------------------------------------------------------
@@ -198,6 +226,7 @@ struct Pass {
     GRef fused{-1, false};   // !tile: the dense block gate
     int seg = 0;             // checkpoint segment
     int round_off = 0, nrounds = 0;  // register rounds (forward); nrounds = 0: op-by-op kernel
+    int cr_slot = -1;        // !tile controlled rotation: its index among the list's controlled rotations
 };
 
 struct PassList {
@@ -210,6 +239,7 @@ struct PassList {
     void* dmats_b = nullptr;         // bound mode: batch x nmats matrices
     size_t nmats = 0;
     int nslots = 0;
+    int ncr = 0;                     // controlled-rotation passes
     StageOp* dops = nullptr;
     void* dmats = nullptr;
     void* hmats = nullptr;
@@ -252,6 +282,8 @@ struct qf_plan {
     std::vector<qf::Synth> synth;     // fuse = 3
     std::vector<qf::Step> steps;      // fuse = 1, 2
     int nslots = 0;                   // fuse = 1, 2
+    int ncr_steps = 0;                // fuse = 1, 2: controlled rotations
+    std::vector<int> cr_contrib;      // bound mode: contribution slot of each reverse controlled rotation
     qf::PassList fwd, rev;            // fuse = 0
     std::vector<int> seg_end;         // gate index where each checkpoint segment ends
     void* ckpt = nullptr;             // (nseg - 1) saved states
@@ -303,6 +335,8 @@ struct qf_plan {
         synth.swap(o.synth);
         steps.swap(o.steps);
         std::swap(nslots, o.nslots);
+        std::swap(ncr_steps, o.ncr_steps);
+        cr_contrib.swap(o.cr_contrib);
         std::swap(fwd, o.fwd);
         std::swap(rev, o.rev);
         seg_end.swap(o.seg_end);
@@ -353,8 +387,9 @@ static int adj_group(const qf_plan* p) {
     return std::min(p->group, 2);
 }
 
-static const char* kFamilies[] = {"stage", "stage_adj", "fused", "axis", "ctrl", "diag", "adj_axis", "checkpoint"};
-enum Family { F_STAGE, F_STAGE_ADJ, F_FUSED, F_AXIS, F_CTRL, F_DIAG, F_ADJ_AXIS, F_CKPT, F_COUNT };
+static const char* kFamilies[] = {"stage", "stage_adj", "fused", "axis", "ctrl", "diag", "adj_axis", "checkpoint",
+                                  "crot", "crot_adj"};
+enum Family { F_STAGE, F_STAGE_ADJ, F_FUSED, F_AXIS, F_CTRL, F_DIAG, F_ADJ_AXIS, F_CKPT, F_CROT, F_CROT_ADJ, F_COUNT };
 
 static qf_status validate_op(const qf_op& o, int D, int n, int nparams) {
     auto qok = [&](int q) { return q >= 0 && q < n; };
@@ -385,6 +420,18 @@ static qf_status validate_op(const qf_op& o, int D, int n, int nparams) {
         case QF_OP_CZ:
             QF_RETURN_IF(!qok(o.q0) || !qok(o.q1) || o.q0 == o.q1, QF_EINVAL, "two-qudit gate on (%d, %d)", o.q0,
                          o.q1);
+            break;
+        case QF_OP_CRX:
+        case QF_OP_CRY:
+        case QF_OP_CRZ:
+            QF_RETURN_IF(!qok(o.q0) || !qok(o.q1) || o.q0 == o.q1, QF_EINVAL, "controlled rotation on (%d, %d)", o.q0,
+                         o.q1);
+            if (o.kind == QF_OP_CRZ)
+                QF_RETURN_IF(!(o.j >= 1 && o.j < D), QF_EINVAL, "R_z level j = %d needs 1 <= j < D", o.j);
+            else
+                QF_RETURN_IF(!(o.j >= 0 && o.j < o.k && o.k < D), QF_EINVAL, "levels (%d, %d) need 0 <= j < k < D",
+                             o.j, o.k);
+            QF_RETURN_IF(o.param < 0 || o.param >= nparams, QF_EINVAL, "param %d outside [0, %d)", o.param, nparams);
             break;
         case QF_OP_U:
             QF_RETURN_IF(o.q1 < 1 || o.q0 < 0 || o.q0 + o.q1 > n, QF_EINVAL, "U on qudits %d..%d", o.q0,
@@ -474,13 +521,25 @@ static void build_steps(qf_plan* p) {
                 s.q = o.q0;
                 s.k = o.q1;
                 break;
+            case QF_OP_CRX:
+            case QF_OP_CRY:
+            case QF_OP_CRZ:
+                flush(o.q0);
+                flush(o.q1);
+                s.type = ST_CROT;
+                s.q = o.q1;
+                s.q2 = o.q0;
+                break;
         }
         p->steps.push_back(s);
     }
     for (int q = 0; q < p->n; ++q) flush(q);
     p->nslots = 0;
-    for (auto& s : p->steps)
+    p->ncr_steps = 0;
+    for (auto& s : p->steps) {
         if (s.type == ST_AXIS && s.has_param) s.slot = p->nslots++;
+        if (s.type == ST_CROT) s.cr_slot = p->ncr_steps++;
+    }
 }
 
 static Mat step_matrix(const qf_plan* p, const Step& s, const double* theta) {
@@ -520,6 +579,12 @@ static qf_status run_step(const qf_plan* p, const Step& s, const StateView& v, c
             const Gate& g = p->gates[s.gates[0]];
             return launch_fused(v, s.k, s.q, inverse ? g.dmat_adj : g.dmat, st);
         }
+        case ST_CROT: {
+            const qf_op& o = p->gates[s.gates[0]].op;
+            std::vector<double> tab;
+            crot_table(o, p->D, theta, inverse, tab);
+            return launch_crot(v, crot_args(o), nullptr, 0, tab.data(), st);
+        }
     }
     return QF_OK;
 }
@@ -552,6 +617,12 @@ static void touches(const qf_op& o, std::vector<Touch>& t) {
         case QF_OP_CZ:
             t.push_back({o.q0, true});
             t.push_back({o.q1, true});
+            break;
+        case QF_OP_CRX:
+        case QF_OP_CRY:
+        case QF_OP_CRZ:
+            t.push_back({o.q0, true});
+            t.push_back({o.q1, o.kind == QF_OP_CRZ});
             break;
         case QF_OP_U:
             for (int q = o.q0; q < o.q0 + o.q1; ++q) t.push_back({q, false});
@@ -695,7 +766,7 @@ static uint64_t pass_take(const qf_plan* p, const std::vector<GRef>& seq, const 
         bool conflict = false;
         for (const Touch& t : tv) conflict = conflict || bFull[t.q] || (!t.diag && bDiag[t.q]);
         const int need = local_need(o);
-        if (!conflict && o.kind != QF_OP_U && (need < 0 || inT[need])) {
+        if (!conflict && !pass_gate(o.kind) && (need < 0 || inT[need])) {
             ++all;
             multi += tv.size() > 1 ? 1 : 0;
         } else {
@@ -737,7 +808,7 @@ static void plan_passes_one(const qf_plan* p, const std::vector<GRef>& seq, int 
     while (remaining > 0) {
         while (done[first]) ++first;
         const qf_op& o0 = op_of(p, seq[first]);
-        if (o0.kind == QF_OP_U) {
+        if (pass_gate(o0.kind)) {
             Pass pf;
             pf.tile = false;
             pf.fused = seq[first];
@@ -805,7 +876,7 @@ static void plan_passes_one(const qf_plan* p, const std::vector<GRef>& seq, int 
             bool conflict = false;
             for (const Touch& t : tv) conflict = conflict || bFull[t.q] || (!t.diag && bDiag[t.q]);
             const int need = local_need(o);
-            const bool local = o.kind != QF_OP_U && (need < 0 || inT[need]);
+            const bool local = !pass_gate(o.kind) && (need < 0 || inT[need]);
             if (!conflict && local) {
                 done[i] = 1;
                 --remaining;
@@ -1150,6 +1221,7 @@ static void finalize_passes(const qf_plan* p, PassList& L, bool adjoint) {
     L.hrounds.clear();
     L.nmats = 0;
     L.nslots = 0;
+    L.ncr = 0;
     const int ng = int(p->gates.size());
     for (Pass& ps : L.passes) {
         if (!ps.tile) {
@@ -1157,6 +1229,11 @@ static void finalize_passes(const qf_plan* p, PassList& L, bool adjoint) {
                 ps.mat_off = L.nmats;
                 ps.nmat = size_t(D) * D * D * D;
                 L.nmats += ps.nmat;
+            } else if (is_crot(p->gates[ps.fused.gi].op.kind)) {  // controlled rotation: its 2 D table
+                ps.mat_off = L.nmats;
+                ps.nmat = size_t(2) * D;
+                L.nmats += ps.nmat;
+                ps.cr_slot = L.ncr++;
             }
             continue;
         }
@@ -1277,6 +1354,15 @@ static qf_status upload_mats(const qf_plan* p, PassList& L, const double* theta,
                     put_mat<float>(L.hmats, ps.mat_off, Kr);
                 else
                     put_mat<double>(L.hmats, ps.mat_off, Kr);
+            } else if (ps.cr_slot >= 0) {
+                std::vector<double> tab;
+                crot_table(p->gates[ps.fused.gi].op, D, theta, ps.fused.inv, tab);
+                Mat t(size_t(2) * D);
+                for (size_t i = 0; i < t.size(); ++i) t[i] = cd(tab[2 * i], tab[2 * i + 1]);
+                if (p->dtype == QF_C64)
+                    put_mat<float>(L.hmats, ps.mat_off, t);
+                else
+                    put_mat<double>(L.hmats, ps.mat_off, t);
             }
             continue;
         }
@@ -1421,6 +1507,11 @@ static qf_status run_fused_pass(qf_plan* p, const PassList& L, const Pass& ps, c
         const size_t esz = p->dtype == QF_C64 ? 8 : 16;
         const void* m = reinterpret_cast<const unsigned char*>(L.dmats) + ps.mat_off * esz;
         QF_CHECK(launch_fused(v, 2, sy.op.q0, m, st, sy.real));
+    } else if (ps.cr_slot >= 0) {
+        const size_t esz = p->dtype == QF_C64 ? 8 : 16;
+        const void* tab = reinterpret_cast<const unsigned char*>(L.dmats) + ps.mat_off * esz;
+        QF_CHECK(launch_crot(v, crot_args(p->gates[ps.fused.gi].op), tab, 0, nullptr, st));
+        return prof_end(p, st, a, F_CROT, 2.0 * state_bytes(v) * 2.0 / p->D);
     } else {
         const Gate& g = p->gates[ps.fused.gi];
         QF_CHECK(launch_fused(v, g.op.q1, g.op.q0, ps.fused.inv ? g.dmat_adj : g.dmat, st, g.real));
@@ -1641,6 +1732,7 @@ qf_status qf_plan_forward(qf_plan* plan, const qf_state* s, const double* theta,
             const int fam = step.type == ST_AXIS ? F_AXIS
                             : step.type == ST_CTRL ? F_CTRL
                             : step.type == ST_DIAG ? F_DIAG
+                            : step.type == ST_CROT ? F_CROT
                                                    : F_FUSED;
             QF_CHECK(prof_end(plan, st, a, fam, 2.0 * state_bytes(v)));
         }
@@ -1707,12 +1799,19 @@ qf_status qf_adjoint_grad(qf_plan* plan, const qf_state* psi, const qf_state* la
     } else {
         pdoubles = std::max<size_t>(adj_axis_partial_doubles(v), 1);
     }
+    const int ncr = stg ? plan->rev.ncr : plan->ncr_steps;
+    if (ncr > 0) pdoubles = std::max(pdoubles, crot_partial_doubles(v));
     double* partial = nullptr;
     double* mdev = nullptr;
+    double* crout = nullptr;
     const size_t mcount = size_t(v.batch) * std::max(nslots, 1) * E * 2;
+    const size_t crcount = size_t(v.batch) * std::max(ncr, 1);
     qf_status rs = dev_malloc_async(reinterpret_cast<void**>(&partial), pdoubles * sizeof(double), st,
                                     "adjoint partial sums");
     if (rs == QF_OK) rs = dev_malloc_async(reinterpret_cast<void**>(&mdev), mcount * sizeof(double), st, "adjoint M");
+    if (rs == QF_OK && ncr > 0)
+        rs = dev_malloc_async(reinterpret_cast<void**>(&crout), crcount * sizeof(double), st,
+                              "controlled-rotation gradients");
     // lam = H_O psi with H_O the Hermitian part of O (seed mode: lam already holds the seed)
     if (rs == QF_OK && !seed) rs = launch_diag_observable(v, lam->amps, active, table_re, st);
     if (rs == QF_OK && stg) {
@@ -1733,6 +1832,15 @@ qf_status qf_adjoint_grad(qf_plan* plan, const qf_state* psi, const qf_state* la
                 if (rs == QF_OK)
                     rs = launch_stage_mreduce(partial, ps.nslots, ps.geom.ntiles, v.batch, uint32_t(E), mdev,
                                               uint32_t(plan->rev.nslots), uint32_t(ps.slot0), st);
+            } else if (ps.cr_slot >= 0) {
+                const size_t esz = plan->dtype == QF_C64 ? 8 : 16;
+                const void* tab = reinterpret_cast<const unsigned char*>(plan->rev.dmats) + ps.mat_off * esz;
+                hipEvent_t a;
+                rs = prof_begin(plan, st, &a);
+                if (rs == QF_OK)
+                    rs = launch_crot_adj(v, lam->amps, crot_args(plan->gates[ps.fused.gi].op), tab, 0, nullptr,
+                                         partial, crout + ps.cr_slot, uint32_t(ncr), st);
+                if (rs == QF_OK) rs = prof_end(plan, st, a, F_CROT_ADJ, 4.0 * state_bytes(v) * 2.0 / D);
             } else {
                 rs = run_fused_pass(plan, plan->rev, ps, v, st);
                 if (rs == QF_OK) rs = run_fused_pass(plan, plan->rev, ps, vl, st);
@@ -1754,19 +1862,31 @@ qf_status qf_adjoint_grad(qf_plan* plan, const qf_state* psi, const qf_state* la
                 if (rs == QF_OK)
                     rs = launch_adj_axis(v, lam->amps, s.q, buf.data(), partial, mdev, plan->nslots, s.slot, st);
                 if (rs == QF_OK) rs = prof_end(plan, st, a, F_ADJ_AXIS, 4.0 * state_bytes(v));
+            } else if (s.type == ST_CROT) {
+                const qf_op& o = plan->gates[s.gates[0]].op;
+                std::vector<double> tab;
+                crot_table(o, D, theta, true, tab);
+                rs = launch_crot_adj(v, lam->amps, crot_args(o), nullptr, 0, tab.data(), partial, crout + s.cr_slot,
+                                     uint32_t(ncr), st);
             } else {
                 rs = run_step(plan, s, v, theta, true, st);
                 if (rs == QF_OK) rs = run_step(plan, s, vl, theta, true, st);
             }
         }
     }
-    std::vector<double> mhost(mcount);
+    std::vector<double> mhost(mcount), crhost(crcount, 0.0);
     if (rs == QF_OK && nslots > 0) {
         hipError_t e = hipMemcpyAsync(mhost.data(), mdev, mcount * sizeof(double), hipMemcpyDeviceToHost, st);
         if (e != hipSuccess) rs = set_error(QF_EHIP, "copy of M matrices failed: %s", hipGetErrorString(e));
     }
+    if (rs == QF_OK && ncr > 0) {
+        hipError_t e = hipMemcpyAsync(crhost.data(), crout, crcount * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) rs = set_error(QF_EHIP, "copy of controlled-rotation gradients failed: %s",
+                                            hipGetErrorString(e));
+    }
     if (partial) (void)hipFreeAsync(partial, st);
     if (mdev) (void)hipFreeAsync(mdev, st);
+    if (crout) (void)hipFreeAsync(crout, st);
     hipError_t e = hipStreamSynchronize(st);
     if (rs != QF_OK) return rs;
     QF_RETURN_IF(e != hipSuccess, QF_EHIP, "stream synchronisation failed: %s", hipGetErrorString(e));
@@ -1783,10 +1903,14 @@ qf_status qf_adjoint_grad(qf_plan* plan, const qf_state* psi, const qf_state* la
                     add_group_grad(plan, fwd_gates, theta, mhost.data() + ((size_t(b) * nslots + h.gslot) * E) * 2,
                                    gb);
                 }
+            for (const Pass& ps : plan->rev.passes)
+                if (ps.cr_slot >= 0) gb[plan->gates[ps.fused.gi].op.param] += crhost[size_t(b) * ncr + ps.cr_slot];
         } else {
-            for (const Step& s : plan->steps)
+            for (const Step& s : plan->steps) {
                 if (s.type == ST_AXIS && s.has_param)
                     add_group_grad(plan, s.gates, theta, mhost.data() + ((size_t(b) * nslots + s.slot) * E) * 2, gb);
+                if (s.type == ST_CROT) gb[plan->gates[s.gates[0]].op.param] += crhost[size_t(b) * ncr + s.cr_slot];
+            }
         }
     }
     // seed mode: lam held torch's gradient g = 2 dL/d(conj psi), the adjoint needs dL/d(conj psi)
@@ -1996,6 +2120,11 @@ static DevGate dev_gate(const qf_op& o) { return DevGate{o.kind, o.j, o.k, o.par
 static void bound_groups(qf_plan* p, PassList& L) {
     L.hgroups.clear();
     for (const Pass& ps : L.passes) {
+        if (!ps.tile && ps.cr_slot >= 0) {
+            L.hgroups.push_back(DevGroup{DG_CR, uint32_t(ps.mat_off), int32_t(p->hgates.size()), 1,
+                                         ps.fused.inv ? 1 : 0});
+            p->hgates.push_back(dev_gate(p->gates[ps.fused.gi].op));
+        }
         if (!ps.tile) continue;
         for (size_t i = 0; i < ps.ops.size(); ++i) {
             const HOp& h = ps.ops[i];
@@ -2067,6 +2196,12 @@ qf_status qf_plan_bind(qf_plan* plan, int64_t batch) {
             }
             plan->hgg.push_back(g);
         }
+    plan->cr_contrib.assign(size_t(plan->rev.ncr), -1);
+    for (const Pass& ps : plan->rev.passes)
+        if (ps.cr_slot >= 0) {
+            contrib.push_back({plan->gates[ps.fused.gi].op.param, nc});
+            plan->cr_contrib[size_t(ps.cr_slot)] = nc++;
+        }
     plan->ncontrib = nc;
     std::vector<int32_t> poff(plan->nparams + 1, 0), plist(nc);
     for (auto& c : contrib) poff[c.first + 1]++;
@@ -2092,6 +2227,14 @@ qf_status qf_plan_bind(qf_plan* plan, int64_t batch) {
     size_t pd = 1;
     for (const Pass& ps : plan->rev.passes)
         if (ps.tile) pd = std::max(pd, size_t(ps.nslots) * ps.geom.ntiles * size_t(batch) * E * 2);
+    if (plan->rev.ncr > 0) {
+        StateView vb{};
+        vb.n = plan->n;
+        vb.D = D;
+        vb.N = uint32_t(N);
+        vb.batch = uint32_t(batch);
+        pd = std::max(pd, crot_partial_doubles(vb));
+    }
     step(dev_alloc(reinterpret_cast<void**>(&plan->w_partial), pd * sizeof(double)));
     step(dev_alloc(reinterpret_cast<void**>(&plan->w_m),
                    size_t(batch) * std::max(plan->rev.nslots, 1) * E * 2 * sizeof(double)));
@@ -2130,6 +2273,9 @@ qf_status qf_plan_forward_dev(qf_plan* plan, const qf_state* s, const double* th
         if (ps.tile) {
             const void* mats = reinterpret_cast<const unsigned char*>(L.dmats_b) + ps.mat_off * esz;
             QF_CHECK(launch_forward_pass(plan, L, ps, v, mats, L.nmats, st));
+        } else if (ps.cr_slot >= 0) {
+            const void* tab = reinterpret_cast<const unsigned char*>(L.dmats_b) + ps.mat_off * esz;
+            QF_CHECK(launch_crot(v, crot_args(plan->gates[ps.fused.gi].op), tab, L.nmats, nullptr, st));
         } else {
             const Gate& g = plan->gates[ps.fused.gi];
             QF_CHECK(launch_fused(v, g.op.q1, g.op.q0, g.dmat, st, g.real));
@@ -2193,6 +2339,11 @@ qf_status qf_adjoint_grad_dev(qf_plan* plan, const qf_state* psi, const qf_state
                                           st, L.nmats));
             QF_CHECK(launch_stage_mreduce(plan->w_partial, ps.nslots, ps.geom.ntiles, v.batch, uint32_t(E), plan->w_m,
                                           uint32_t(L.nslots), uint32_t(ps.slot0), st));
+        } else if (ps.cr_slot >= 0) {
+            const void* tab = reinterpret_cast<const unsigned char*>(L.dmats_b) + ps.mat_off * esz;
+            QF_CHECK(launch_crot_adj(v, lam->amps, crot_args(plan->gates[ps.fused.gi].op), tab, L.nmats, nullptr,
+                                     plan->w_partial, plan->w_contrib + plan->cr_contrib[size_t(ps.cr_slot)],
+                                     uint32_t(plan->ncontrib), st));
         } else {
             const Gate& g = plan->gates[ps.fused.gi];
             QF_CHECK(launch_fused(v, g.op.q1, g.op.q0, g.dmat_adj, st, g.real));

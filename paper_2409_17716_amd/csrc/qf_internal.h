@@ -52,6 +52,25 @@ qf_status launch_expect_noalloc(const StateView& s, const std::vector<int>& acti
 qf_status launch_diag_observable(const StateView& psi, void* lam_amps, const std::vector<int>& active,
                                  const std::vector<double>& table_re, hipStream_t st);
 
+// ---- controlled rotation (k_crot.hip) ----
+// sum_m |m><m|_ctrl (x) R(m theta)_tgt; kind 0 = x, 1 = y, 2 = z type.  The
+// table holds 2*D complex entries per register (see k_crot.hip), from the
+// device (dtab, register stride tab_stride) or, when dtab is NULL, from htab
+// (host, 2*D complex FP64, shared by every register).
+struct CrotArgs {
+    int kind;
+    int ctrl, tgt;
+    int j, k;
+};
+qf_status launch_crot(const StateView& s, const CrotArgs& a, const void* dtab, size_t tab_stride, const double* htab,
+                      hipStream_t st);
+// Un-applies the gate (inverse table) on psi and lam and writes, per register b,
+// sum over fibres of m * Im <lam_f| S |psi_f> to out[b * ostride].  partial:
+// crot_partial_doubles(s) doubles of scratch.
+qf_status launch_crot_adj(const StateView& s, void* lam, const CrotArgs& a, const void* dtab, size_t tab_stride,
+                          const double* htab, double* partial, double* out, uint32_t ostride, hipStream_t st);
+size_t crot_partial_doubles(const StateView& s);
+
 // ---- fused dense blocks (k_fused.hip) ----
 // real: every imaginary part of B is zero (halves the matrix-core products).
 qf_status launch_fused(const StateView& s, int k, int q0, const void* B, hipStream_t st, bool real = false);
@@ -197,11 +216,11 @@ struct DevGate {
     int32_t kind, j, k, param;
 };
 // One matrix a register needs: a fused run product, a CZ table or a w^e table.
-enum DevGroupType : int32_t { DG_U = 0, DG_CZ = 1, DG_W = 2 };
+enum DevGroupType : int32_t { DG_U = 0, DG_CZ = 1, DG_W = 2, DG_CR = 3 };
 struct DevGroup {
     int32_t type;
     uint32_t mat_off;  // complex elements from the start of a register's matrices
-    int32_t g0, ng;    // DG_U: gates [g0, g0 + ng) of the gate list, application order
+    int32_t g0, ng;    // DG_U: gates [g0, g0 + ng) of the gate list, application order; DG_CR: gate g0
     int32_t inv;       // DG_U: every gate is applied as its inverse; DG_CZ / DG_W: conjugated
 };
 // A fused run that owns an adjoint M slot; its gates in forward order.

@@ -181,3 +181,20 @@ def test_single_qudit_plans(qf):
         assert p.num_stages >= 1
     qf.qf_shutdown()
     qf.qf_shutdown()
+
+
+def test_crot_validation(qf):
+    """qf_apply_crot rejects bad kinds, qudits and levels synchronously."""
+    s = _fake_state(qf)  # D = 3, n = 3
+    f = qf.lib.qf_apply_crot
+    assert f(ctypes.byref(s), qf.QF_OP_RX, 0, 1, 0, 1, 0.5, None) == qf.QF_EINVAL
+    assert f(ctypes.byref(s), qf.QF_OP_CRX, 1, 1, 0, 1, 0.5, None) == qf.QF_EINVAL
+    assert f(ctypes.byref(s), qf.QF_OP_CRX, 0, 3, 0, 1, 0.5, None) == qf.QF_EINVAL
+    assert f(ctypes.byref(s), qf.QF_OP_CRY, 0, 1, 1, 1, 0.5, None) == qf.QF_EINVAL
+    assert f(ctypes.byref(s), qf.QF_OP_CRY, 0, 1, 0, 3, 0.5, None) == qf.QF_EINVAL
+    assert f(ctypes.byref(s), qf.QF_OP_CRZ, 0, 1, 0, 0, 0.5, None) == qf.QF_EINVAL
+    assert f(ctypes.byref(s), qf.QF_OP_CRZ, 0, 1, 1, 0, float("nan"), None) == qf.QF_EINVAL
+    with pytest.raises(qf.QfError):
+        qf.Plan(3, 3, [("crx", 0, 0, 0, 1, 0)], 1)
+    p = qf.Plan(3, 3, [("cry", 0, 2, 0, 2, 0), ("h", 1), ("crz", 2, 1, 2, 1)], 2)
+    assert p.num_stages >= 2
