@@ -6,7 +6,8 @@ One step = |0...0> init, the depth-10 qutrit ansatz on n = 16 qudits
 pairs (0,1), (1,2) of every qudit, clock Z^a, CSUM ring; 1280 gates), the full
 probability vector and <Z_0>.  Inputs and outputs stay resident in HBM.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--cpu-seconds S]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-batched] [--no-legs] [--no-cpu-baseline]
+    python bench.py --profile-workload {stage,axis,fused,adjoint,batched}   (for rocprofv3)
 
 Prints one JSON line.  value = amplitude updates per second
 = (gates of the circuit as written) * 3^16 / step time.  The roofline entry
@@ -14,7 +15,10 @@ covers the dominant kernel (the fused LDS stage), timed with HIP events
 recorded around each of its launches on the launch stream during the timed
 steps; its algorithmic traffic is one read and one write of the state per
 launch.  cpu_baseline times the FP64 oracle on a bounded sample of the same
-workload on one host core.
+workload (the circuit's mix of rotations, clock gates and CSUM) on one host
+core and on several at once.  Extra records: the ragged 1024-circuit batch
+(graph replay vs the plain per-circuit loop) and two gradient legs (D=5 n=10
+forward + adjoint; D=10 n=8 forward + checkpointed adjoint).
 """
 from __future__ import annotations
 
@@ -38,14 +42,20 @@ def _args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the ragged-batch measurement")
     ap.add_argument("--pmc-workload", action="store_true",
                     help="run only the counter workload: two plain copies of the state size, then one step")
-    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
-                    help="turn two rocprofv3 --pmc runs of --pmc-workload (FETCH_SIZE, WRITE_SIZE) into "
-                         "profiles/stage_d3_n16_traffic.json")
+    ap.add_argument("--profile-workload", choices=["stage", "axis", "fused", "adjoint", "batched"],
+                    help="run only a short workload for rocprofv3 (kernel traces and counters), printing its "
+                         "own HIP-event timings: stage = --pmc-workload; axis = one random unitary on each of "
+                         "the 16 qudits of the 3^16 state; fused = dense blocks K = 100 (real, D=10 n=8) and "
+                         "K = 49 (complex, D=7 n=9); adjoint = the D=5 n=10 forward + adjoint gradient; "
+                         "batched = one graph replay of the 1024-circuit batch")
+    ap.add_argument("--no-legs", action="store_true", help="skip the D=5 n=10 and D=10 n=8 gradient legs")
+    ap.add_argument("--write-traffic", nargs="+", metavar="DIR",
+                    help="turn rocprofv3 --pmc runs of --profile-workload stage (FETCH_SIZE, WRITE_SIZE, and "
+                         "optionally the read- and write-request counters) into profiles/stage_d3_n16_traffic.json")
     return ap.parse_args()
 
 
@@ -70,47 +80,86 @@ def _traffic():
     return t.get("bytes_per_launch")
 
 
-def write_traffic(fetch_dir: str, write_dir: str) -> None:
-    """Per-launch HBM bytes of the stage kernel from FETCH_SIZE and WRITE_SIZE
-    (KiB per dispatch), each scaled by what the same counter reads for the plain
-    copy of the state size that --pmc-workload runs first."""
+def _counter_rows(d, counters):
+    """{kernel name: {counter: [value per dispatch]}} from a rocprofv3 --pmc run."""
     import collections
     import csv
     import glob
+    out = collections.defaultdict(lambda: collections.defaultdict(list))
+    for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] in counters:
+                out[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    return out
+
+
+def write_traffic(fetch_dir: str, write_dir: str, rdreq_dir: str | None = None, wrreq_dir: str | None = None) -> None:
+    """Per-launch HBM bytes of the stage kernel from FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch), each scaled by what the same counter reads for the two
+    plain copies of the state size that --pmc-workload runs first.  With the
+    request counters (TCC_EA0_RDREQ / _32B, TCC_BUBBLE, TCC_EA0_RDREQ_DRAM;
+    TCC_EA0_WRREQ / _64B / _DRAM) the same bytes are also counted from raw
+    requests, 128 B per read request (what the copy of known size shows on
+    gfx950) and 64 / 32 B per write request."""
     import re
 
     N = 3 ** 16
-
-    def per_kernel(d, counter):
-        out = collections.defaultdict(list)
-        for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
-            for r in csv.DictReader(open(path)):
-                if r["Counter_Name"] == counter:
-                    out[r["Kernel_Name"]].append(float(r["Counter_Value"]))
-        return out
-
-    f = per_kernel(fetch_dir, "FETCH_SIZE")
-    w = per_kernel(write_dir, "WRITE_SIZE")
-    copyk = next(k for k in f if "copyBuffer" in k or "copy" in k.lower())
+    state = N * 8
+    f = _counter_rows(fetch_dir, ("FETCH_SIZE",))
+    w = _counter_rows(write_dir, ("WRITE_SIZE",))
+    copyk = next(k for k in f if "copyBuffer" in k)
     stagek = next(k for k in f if "k_stage" in k)
-    copy_kib = N * 8 / 1024
-    cal_f = copy_kib / (sum(f[copyk]) / 2)
-    cal_w = copy_kib / (sum(w[copyk]) / 2)
-    sf = sum(f[stagek]) / len(f[stagek])
-    sw = sum(w[stagek]) / len(w[stagek])
+    # the calibration copies are the two dispatches of the state size (the plan's matrix upload is another copy)
+    cf = sorted(f[copyk]["FETCH_SIZE"])[-2:]
+    cw = sorted(w[copyk]["WRITE_SIZE"])[-2:]
+    cal_f = (state / 1024) / (sum(cf) / 2)
+    cal_w = (state / 1024) / (sum(cw) / 2)
+    sf = sum(f[stagek]["FETCH_SIZE"]) / len(f[stagek]["FETCH_SIZE"])
+    sw = sum(w[stagek]["WRITE_SIZE"]) / len(w[stagek]["WRITE_SIZE"])
     bpl = (sf * cal_f + sw * cal_w) * 1024
     m = re.search(r"k_stage\w*(<[^>]*>)?", stagek)
-    rec = {"kernel": m.group(0) if m else stagek, "launches": len(f[stagek]),
+    rec = {"kernel": m.group(0) if m else stagek, "launches": len(f[stagek]["FETCH_SIZE"]),
            "workload": "qutrit ansatz D=3 n=16 complex64, default plan",
            "source_hash": _source_hash(), "fetch_kib_per_launch": sf, "write_kib_per_launch": sw,
-           "copy_calibration": {"bytes": N * 8, "fetch_scale": cal_f, "write_scale": cal_w},
-           "bytes_per_launch": round(bpl), "algorithmic_bytes_per_launch": 2 * N * 8,
-           "ratio": bpl / (2 * N * 8),
-           "commands": ["timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch "
-                        "-o run -- python3 bench.py --pmc-workload",
-                        "timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write "
-                        "-o run -- python3 bench.py --pmc-workload",
-                        "python3 bench.py --write-traffic gpurun_out/pmc_fetch gpurun_out/pmc_write"]}
+           "copy_calibration": {"bytes": state, "fetch_scale": cal_f, "write_scale": cal_w},
+           "bytes_per_launch": round(bpl), "algorithmic_bytes_per_launch": 2 * state,
+           "ratio": bpl / (2 * state),
+           "commands": ["timeout -s KILL 150 rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof/stage_fetch "
+                        "-o run -- python3 bench.py --profile-workload stage",
+                        "timeout -s KILL 150 rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof/stage_write "
+                        "-o run -- python3 bench.py --profile-workload stage"]}
+    if rdreq_dir and wrreq_dir:
+        rd = _counter_rows(rdreq_dir, ("TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_32B_sum", "TCC_BUBBLE_sum",
+                                       "TCC_EA0_RDREQ_DRAM_sum"))
+        wr = _counter_rows(wrreq_dir, ("TCC_EA0_WRREQ_sum", "TCC_EA0_WRREQ_64B_sum", "TCC_EA0_WRREQ_DRAM_sum"))
+        ck = next(k for k in rd if "copyBuffer" in k)
+        sk = next(k for k in rd if "k_stage" in k)
+
+        def avg(rows, c):
+            return sum(rows[c]) / len(rows[c])
+        copy_rd = sorted(rd[ck]["TCC_EA0_RDREQ_sum"])[-1]
+        read_bytes_per_req = state / copy_rd
+        rq = avg(rd[sk], "TCC_EA0_RDREQ_sum")
+        wq = avg(wr[sk], "TCC_EA0_WRREQ_sum")
+        wq64 = avg(wr[sk], "TCC_EA0_WRREQ_64B_sum")
+        rbytes = rq * read_bytes_per_req
+        wbytes = wq64 * 64 + (wq - wq64) * 32
+        rec["request_cross_check"] = {
+            "copy_read_requests": copy_rd, "bytes_per_read_request": read_bytes_per_req,
+            "read_requests_per_launch": rq, "read_requests_32B": avg(rd[sk], "TCC_EA0_RDREQ_32B_sum"),
+            "read_requests_bubble": avg(rd[sk], "TCC_BUBBLE_sum"),
+            "read_requests_to_dram": avg(rd[sk], "TCC_EA0_RDREQ_DRAM_sum"),
+            "write_requests_per_launch": wq, "write_requests_64B": wq64,
+            "write_requests_to_dram": avg(wr[sk], "TCC_EA0_WRREQ_DRAM_sum"),
+            "bytes_per_launch": round(rbytes + wbytes), "ratio": (rbytes + wbytes) / (2 * state),
+            "commands": ["timeout -s KILL 150 rocprofv3 --pmc TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_BUBBLE_sum "
+                         "TCC_EA0_RDREQ_DRAM_sum --output-format csv -d gpurun_out/prof/stage_rdreq -o run -- "
+                         "python3 bench.py --profile-workload stage",
+                         "timeout -s KILL 150 rocprofv3 --pmc TCC_EA0_WRREQ_sum TCC_EA0_WRREQ_64B_sum "
+                         "TCC_EA0_WRREQ_DRAM_sum --output-format csv -d gpurun_out/prof/stage_wrreq -o run -- "
+                         "python3 bench.py --profile-workload stage"]}
+    rec["commands"].append("python3 bench.py --write-traffic gpurun_out/prof/stage_fetch gpurun_out/prof/stage_write"
+                           + (" gpurun_out/prof/stage_rdreq gpurun_out/prof/stage_wrreq" if rdreq_dir else ""))
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec))
@@ -155,38 +204,223 @@ def batched_measurement(steps: int) -> dict:
             "speedup": tp / tb, "max_rel_grad_diff_vs_plain": rel}
 
 
-def cpu_baseline(c, seconds: float) -> dict:
-    """The FP64 oracle, as it stands, on the first gates of the same workload."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_sample(c, n_rot: int, n_clock: int, n_csum: int):
+    """Gates of the circuit in the proportion it holds them (rotations, clock
+    gates, CSUM), taken in circuit order."""
+    want = {"rot": n_rot, "clock": n_clock, "csum": n_csum}
+    out = []
+    for op in c.ops:
+        k = "rot" if op[0] in ("rx", "ry", "rz") else op[0]
+        if want.get(k, 0) > 0:
+            out.append(op)
+            want[k] -= 1
+    return out
+
+
+def _oracle_run(mix):
+    """One host process: the FP64 oracle applying the sample to the full state."""
     from threadpoolctl import threadpool_limits
 
+    import qf_inputs as qi
     from oracle import sim
-    D, n = c.dim, c.n
-    N = D ** n
-    psi = sim.basis_state(D, n)
-    done = 0
+    c = qi.config2()
+    ops = _oracle_sample(c, *mix)
+    psi = sim.basis_state(c.dim, c.n)
     with threadpool_limits(1):
         t0 = time.perf_counter()
-        for op in c.ops:
-            psi = sim.apply_op(psi, D, n, op, c.theta)
-            done += 1
-            if time.perf_counter() - t0 >= seconds:
-                break
-        el = time.perf_counter() - t0
-    kinds = sorted({op[0] for op in c.ops[:done]})
-    return {"value": done * N / el, "unit": "amp-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {done} of {len(c.ops)} gates ({', '.join(kinds)}) of the same circuit on the full "
-                      f"3^16 state in complex128, {el:.1f} s on one host core"}
+        for op in ops:
+            psi = sim.apply_op(psi, c.dim, c.n, op, c.theta)
+        return len(ops), time.perf_counter() - t0
+
+
+def cpu_baseline(c) -> dict:
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload:
+    6 rotations, 1 clock gate and 1 CSUM (the circuit's 6 : 1 : 1 mix) on the
+    full 3^16 state, first on one host core, then as independent copies on
+    several cores at once (aggregate rate; copies limited by free memory, the
+    oracle's digit maps take about 12 GB each)."""
+    import concurrent.futures as cf
+
+    import psutil
+    N = c.dim ** c.n
+    mix = (6, 1, 1)
+    ngates, el = _oracle_run(mix)
+    single = ngates * N / el
+    ncpu = os.cpu_count() or 1
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    par = max(1, min(ncpu, 16, int(psutil.virtual_memory().available // (12 << 30))))
+    agg = None
+    if par > 1:
+        with cf.ProcessPoolExecutor(max_workers=par) as ex:
+            t0 = time.perf_counter()
+            res = list(ex.map(_oracle_run, [mix] * par))
+            wall = time.perf_counter() - t0
+        agg = sum(r[0] for r in res) * N / wall
+    return {"value": agg if agg else single, "unit": "amp-updates/s", "cores": par, "kind": "oracle",
+            "single_core": single, "nproc": ncpu, "cpu_model": _cpu_model(),
+            "sample": f"{ngates} gates in the circuit's mix (6 rotations, 1 clock, 1 CSUM) on the full 3^16 "
+                      f"state in complex128: {el:.1f} s on one core; value = {par} independent copies on "
+                      f"{par} cores at once (aggregate)"}
+
+
+def _event_time(fn, reps: int) -> float:
+    """Mean milliseconds of fn() over reps, with HIP events on the current stream."""
+    import torch
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def gradient_legs() -> dict:
+    """D=5 n=10 (960 angles) forward + adjoint gradient, and D=10 n=8 (864
+    angles) forward + adjoint with a checkpoint every 4 layers, default plans,
+    complex64, host-returned gradients (the adjoint call synchronises)."""
+    import torch
+
+    import paper_2409_17716_amd as qf
+    import qf_inputs as qi
+    out = {}
+    for name, c, kw in (("d5_n10_fwd_grad", qi.config3(), {}),
+                        ("d10_n8_fwd_ckpt_grad", qi.config5(), {"ckpt_every": 320})):
+        p = qf.plan_for(c, "c64", **kw)
+        psi = qf.new_state(c.n, c.dim, "c64")
+        lam = qf.new_state(c.n, c.dim, "c64")
+        terms = qi.zsum_terms(c.n)
+
+        def fwd():
+            qf.qf_state_init(psi, c.n, c.dim, None)
+            p.forward(psi, c.theta)
+
+        def step():
+            fwd()
+            p.adjoint_grad(psi, lam, c.theta, terms)
+        step()
+        torch.cuda.synchronize()
+        reps = 5 if c.dim == 5 else 2
+        t_fwd = _event_time(fwd, reps)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            step()
+        torch.cuda.synchronize()
+        t_step = (time.perf_counter() - t0) / reps * 1e3
+        out[name] = {"amplitudes": c.dim ** c.n, "gates": len(c.ops), "params": c.nparams,
+                     "forward_passes": p.num_stages, "adjoint_passes": p.num_adjoint_stages,
+                     "forward_ms": round(t_fwd, 3), "forward_plus_gradient_ms": round(t_step, 3),
+                     "forward_amp_updates_per_s": len(c.ops) * c.dim ** c.n / (t_fwd * 1e-3)}
+        del p, psi, lam
+        torch.cuda.empty_cache()
+    return out
+
+
+def profile_workload(kind: str) -> int:
+    """Short workloads for rocprofv3; each prints its own HIP-event timings."""
+    import numpy as np
+    import torch
+
+    import paper_2409_17716_amd as qf
+    import qf_inputs as qi
+    torch.cuda.set_device(0)
+    rec = {"workload": kind}
+    if kind == "axis":
+        D, n = 3, 16
+        N = D ** n
+        psi = qf.new_state(n, D, "c64")
+        src = torch.zeros(N, dtype=torch.complex64, device="cuda")
+        for _ in range(2):
+            psi.copy_(src)  # calibration copies of the state size for the traffic counters
+        qf.qf_state_init(psi, n, D, None)
+        rng = np.random.default_rng(7)
+        per = []
+        for q in range(n):
+            U = qi.random_unitary(D, rng)
+            qf.qf_apply_1q(psi, n, D, q, U)  # warm-up
+            ms = _event_time(lambda: qf.qf_apply_1q(psi, n, D, q, U), 3)
+            per.append({"qudit": q, "stride": D ** (n - 1 - q), "us": round(ms * 1e3, 2),
+                        "GBps": round(2 * N * 8 / (ms * 1e-3) / 1e9, 1)})
+        rec["per_axis"] = per
+    elif kind == "fused":
+        for D, n, k, real in ((10, 8, 2, True), (7, 9, 2, False)):
+            K = D ** k
+            psi = qf.new_state(n, D, "c64")
+            qf.qf_state_init(psi, n, D, None)
+            rng = np.random.default_rng(K)
+            if real:
+                q, _ = np.linalg.qr(rng.standard_normal((K, K)))
+                B = q.astype(np.complex128)
+            else:
+                B = qi.random_unitary(K, rng)
+            Bt = torch.tensor(B, dtype=torch.complex64, device="cuda")
+            positions = list(range(0, n - k + 1, 2))
+            for q0 in positions:
+                qf.qf_apply_fused(psi, n, D, q0, k, Bt)
+            ms = {q0: _event_time(lambda: qf.qf_apply_fused(psi, n, D, q0, k, Bt), 3) for q0 in positions}
+            N = D ** n
+            flops = (4 if real else 8) * K * N
+            rec[f"K{K}_{'real' if real else 'complex'}"] = {
+                "D": D, "n": n, "flops_per_launch": flops,
+                "per_position": {str(q0): {"us": round(v * 1e3, 1), "TFLOPs": round(flops / (v * 1e-3) / 1e12, 2)}
+                                 for q0, v in ms.items()}}
+            del psi
+            torch.cuda.empty_cache()
+    elif kind == "adjoint":
+        c = qi.config3()
+        terms = qi.zsum_terms(c.n)
+        p = qf.plan_for(c, "c64")
+        psi = qf.new_state(c.n, c.dim, "c64")
+        lam = qf.new_state(c.n, c.dim, "c64")
+        for i in range(3):
+            if i == 2:
+                p.set_profiling(True)
+            qf.qf_state_init(psi, c.n, c.dim, None)
+            p.forward(psi, c.theta)
+            p.adjoint_grad(psi, lam, c.theta, terms)
+        prof = p.read_profile()
+        rec["families"] = {k: {"launches": v[0], "ms": round(v[1], 3),
+                               "GBps": round(v[2] / (v[1] * 1e-3) / 1e9, 1)} for k, v in prof.items()}
+    elif kind == "batched":
+        from paper_2409_17716_amd.batched import RaggedBatch
+        rb = RaggedBatch(qi.config4())
+        rb.capture()
+        rb.replay()
+        torch.cuda.synchronize()
+        rec["replay_ms"] = round(_event_time(rb.replay, 3), 3)
+    torch.cuda.synchronize()
+    print(json.dumps(rec), flush=True)
+    return 0
 
 
 def main() -> int:
     a = _args()
     if a.write_traffic:
+        if len(a.write_traffic) not in (2, 4):
+            print("bench.py: --write-traffic takes FETCH_DIR WRITE_DIR [RDREQ_DIR WRREQ_DIR]", file=sys.stderr)
+            return 2
         write_traffic(*a.write_traffic)
         return 0
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
         print("bench.py: this build measures one GPU; --gpus above 1 is not supported", file=sys.stderr)
         return 2
+    if a.profile_workload and a.profile_workload != "stage":
+        return profile_workload(a.profile_workload)
     import torch
 
     import paper_2409_17716_amd as qf
@@ -208,7 +442,7 @@ def main() -> int:
         qf.qf_probs(psi, n, D, out=probs)
         qf.qf_expect(psi, n, D, terms, out=z0)
 
-    if a.pmc_workload:
+    if a.pmc_workload or a.profile_workload == "stage":
         src = torch.zeros(N, dtype=torch.complex64, device="cuda")
         for _ in range(2):
             psi.copy_(src)
@@ -263,8 +497,10 @@ def main() -> int:
     }
     if not a.no_batched:
         out["batched"] = batched_measurement(max(1, a.steps // 2))
+    if not a.no_legs:
+        out["legs"] = gradient_legs()
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(c, a.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(c)
     print(json.dumps(out), flush=True)
     return 0
 
