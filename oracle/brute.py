@@ -115,6 +115,16 @@ def op_unitary(op, D: int, n: int, theta) -> np.ndarray:
             d[a], d[b] = d[b], d[a]
             return d
         return sparse_perm(D, n, rule)
+    if kind == "mcx":
+        controls, t = list(op[1]), op[2]
+
+        def rule(d):
+            prod = 1
+            for c in controls:
+                prod *= d[c]
+            d[t] = (d[t] + prod) % D
+            return d
+        return sparse_perm(D, n, rule)
     if kind == "cz":
         c, t = op[1], op[2]
         w = gates.omega(D)

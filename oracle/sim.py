@@ -125,6 +125,22 @@ def apply_controlled_stack(psi, D, n, c, t, mats) -> np.ndarray:
     return v.reshape(-1)
 
 
+def apply_mcx(psi, D, n, controls, t):
+    """Multi-controlled shift: x_t -> x_t + prod_i x_{c_i} mod D.  The paper
+    names the Toffoli and multi-controlled NOT gates without a formula; this
+    is the generalization of its CNOT index rule (x_t -> x_t + x_c), equal to
+    CSUM for one control and to the Toffoli / multi-controlled NOT for qubits."""
+    controls = list(controls)
+
+    def fn(d):
+        prod = np.ones_like(d[t])
+        for c in controls:
+            prod = prod * d[c]
+        d[t] = (d[t] + prod) % D
+        return d
+    return apply_digit_map(psi, D, n, fn)
+
+
 def apply_phase(psi, D, n, phase_of_digits) -> np.ndarray:
     """Diagonal gate: psi_x <- phi(digits(x)) psi_x."""
     dig = digits_of(D, n, np.arange(D ** n))
@@ -153,6 +169,18 @@ def apply_op(psi: np.ndarray, D: int, n: int, op, theta) -> np.ndarray:
         return apply_cz(psi, D, n, op[1], op[2])
     if kind == "swap":
         return apply_swap(psi, D, n, op[1], op[2])
+    if kind == "mcx":
+        return apply_mcx(psi, D, n, op[1], op[2])
+    if kind == "mcx_inv":
+        controls, t = op[1], op[2]
+
+        def fn(d):
+            prod = np.ones_like(d[t])
+            for c in controls:
+                prod = prod * d[c]
+            d[t] = (d[t] - prod) % D
+            return d
+        return apply_digit_map(psi, D, n, fn)
     if kind in ("crx", "cry", "crz"):
         return apply_controlled_stack(psi, D, n, op[1], op[2], gates.crot_mats(op, D, theta))
     if kind == "cstack":
@@ -187,6 +215,8 @@ def inverse_op(op, D: int, theta):
         return ("cz_inv", op[1], op[2])
     if kind == "swap":
         return op
+    if kind == "mcx":
+        return ("mcx_inv", op[1], op[2])
     if kind in ("crx", "cry", "crz"):
         return ("cstack", op[1], op[2], [m.conj().T for m in gates.crot_mats(op, D, theta)])
     raise ValueError(kind)

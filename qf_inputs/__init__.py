@@ -22,6 +22,8 @@ significant digit of the basis index):
     ("crx", c, t, j, k, p)   controlled rotation sum_m |m><m|_c (x) R_x^{jk}(m theta)_t
     ("cry", c, t, j, k, p)   the same with R_y^{jk}
     ("crz", c, t, j, p)      the same with R_z^{j}
+    ("swap", a, b)           exchange the digits of qudits a and b
+    ("mcx", (c1, ..), t)     x_t -> x_t + prod_i x_{c_i} mod D (Toffoli for two controls)
 
 The angle of a rotation is ``theta[p]``.
 """
@@ -259,6 +261,13 @@ def random_circuit(D: int, n: int, depth: int, seed: int, kinds=None) -> Circuit
         elif kind == "u2" and n >= 2:
             q0 = int(rng.integers(n - 1))
             ops.append(("u", q0, 2, random_unitary(D * D, rng)))
+        elif kind == "swap" and n >= 2:
+            a_, b_ = rng.choice(n, size=2, replace=False).tolist()
+            ops.append(("swap", int(a_), int(b_)))
+        elif kind == "mcx" and n >= 3:
+            nc = int(rng.integers(1, min(4, n)))
+            qs = rng.choice(n, size=nc + 1, replace=False).tolist()
+            ops.append(("mcx", tuple(int(v) for v in qs[:nc]), int(qs[nc])))
         elif kind in ("crx", "cry", "crz") and n >= 2:
             c, t = rng.choice(n, size=2, replace=False).tolist()
             if kind == "crz":

@@ -472,3 +472,65 @@ def test_controlled_rotation_adjoint_matches_finite_differences(D, n, seed):
     g2 = grad.adjoint(c2, terms)
     fd2 = grad.finite_diff(c2, terms, np.arange(c2.nparams), h=1e-5)
     assert np.abs(g2 - fd2).max() <= 1e-8 * max(1.0, np.abs(fd2).max())
+
+
+# ------------------------------------------------------------- SWAP and MCX
+
+def test_swap_and_toffoli_textbook_qubits():
+    """D = 2: SWAP and the two-control MCX are the textbook SWAP and Toffoli
+    (basis permutations from the fixture)."""
+    fx = json.load(open(os.path.join(GOLDEN, "textbook_swap_toffoli.json")))
+    for x, y in enumerate(fx["swap_2q"]):
+        psi = np.zeros(4, dtype=complex)
+        psi[x] = 1
+        assert sim.apply_swap(psi, 2, 2, 0, 1)[y] == 1
+    for x, y in enumerate(fx["toffoli_3q_controls_0_1_target_2"]):
+        psi = np.zeros(8, dtype=complex)
+        psi[x] = 1
+        assert sim.apply_mcx(psi, 2, 3, [0, 1], 2)[y] == 1
+
+
+@pytest.mark.parametrize("D", [3, 4, 5])
+def test_swap_exchanges_product_factors(D):
+    """SWAP on a product state |u> (x) |v> (x) |w> gives |w> (x) |v> (x) |u>
+    (built with Kronecker products), and SWAP^2 = I."""
+    rng = np.random.default_rng(D)
+    u, v, w = (qi.random_unitary(D, rng)[:, 0] for _ in range(3))
+    psi = np.kron(np.kron(u, v), w)
+    assert np.abs(sim.apply_swap(psi, D, 3, 0, 2) - np.kron(np.kron(w, v), u)).max() < TOL
+    r = qi.random_state(D, 3, 4)
+    assert np.abs(sim.apply_swap(sim.apply_swap(r, D, 3, 1, 2), D, 3, 1, 2) - r).max() < TOL
+
+
+@pytest.mark.parametrize("D", [2, 3, 5])
+def test_mcx_identities(D):
+    """One control: the CSUM routine; a control at level 0 disables it; D
+    applications give the identity; with controls at levels (a, b) the target
+    moves by a b mod D."""
+    n = 4
+    r = qi.random_state(D, n, 9)
+    assert np.abs(sim.apply_mcx(r, D, n, [2], 0) - sim.apply_csum(r, D, n, 2, 0)).max() < TOL
+    p = r.copy()
+    for _ in range(D):
+        p = sim.apply_mcx(p, D, n, [0, 3], 1)
+    assert np.abs(p - r).max() < TOL
+    for a in range(D):
+        for b in range(D):
+            digs = [a, 0, b, 1]
+            out = sim.apply_mcx(sim.basis_state(D, n, digs), D, n, [0, 2], 3)
+            assert out[sim.index_of(D, [a, 0, b, (1 + a * b) % D])] == 1
+
+
+@pytest.mark.parametrize("D,n,seed", [(3, 4, 1), (2, 5, 2), (4, 3, 3)])
+def test_swap_mcx_bruteforce_and_adjoint(D, n, seed):
+    """Circuits with SWAP and MCX: gate-by-gate runner vs the brute-force
+    unitary, and the adjoint (un-applying both) vs central differences."""
+    c = qi.random_circuit(D, n, 50, seed, kinds=["h", "ry", "rz", "swap", "mcx", "csum", "crx"])
+    assert any(op[0] == "swap" for op in c.ops) and any(op[0] == "mcx" for op in c.ops)
+    U = brute.circuit_unitary(c)
+    psi0 = qi.random_state(D, n, seed + 3)
+    assert np.abs(sim.run(c, psi0) - U @ psi0).max() < 1e-12
+    terms = qi.zsum_terms(n)
+    g = grad.adjoint(c, terms)
+    fd = grad.finite_diff(c, terms, np.arange(c.nparams), h=1e-5)
+    assert np.abs(g - fd).max() <= 1e-8 * max(1.0, np.abs(fd).max())
