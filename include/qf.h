@@ -111,6 +111,27 @@ qf_status qf_apply_diag(const qf_state* s, int32_t k, const int32_t* qudits,
 qf_status qf_apply_crot(const qf_state* s, int32_t kind, int32_t ctrl, int32_t tgt,
                         int32_t j, int32_t k, double theta, void* stream);
 
+/* A single rotation exp(-i theta S / 2) (subsection "Generalized rotation
+ * gate"; kind QF_OP_RX / QF_OP_RY with levels j < k, or QF_OP_RZ with
+ * 1 <= j < D) as a slab sweep: only the levels it moves are read and written
+ * (2 of D for R_x, R_y; j + 1 for R_z), the memory form of the paper's sparse
+ * rotation.  Same result as qf_apply_1q with the rotation's matrix. */
+qf_status qf_apply_rot(const qf_state* s, int32_t kind, int32_t q, int32_t j, int32_t k,
+                       double theta, void* stream);
+
+/* SWAP of qudits a and b (subsection "Generalized SWAP Gate"): the digits of
+ * a and b are exchanged, |.. x_a .. x_b ..> -> |.. x_b .. x_a ..>.  a != b, both
+ * in [0, n).  Bit-exact: amplitudes are moved, never recomputed. */
+qf_status qf_apply_swap(const qf_state* s, int32_t a, int32_t b, void* stream);
+
+/* Multi-controlled shift (the Toffoli and multi-controlled NOT gates the paper
+ * names in section "Quantum Gates", generalized like its CNOT index rule):
+ * |.. x_t ..> -> |.. (x_t + prod_i x_{ctrls[i]}) mod D ..>.  For qubits this is
+ * the Toffoli (2 controls) / multi-controlled NOT; with one control it is CSUM.
+ * ctrls: host, nctrl (1..8) distinct qudits, none equal to tgt.  Bit-exact. */
+qf_status qf_apply_mcx(const qf_state* s, int32_t nctrl, const int32_t* ctrls, int32_t tgt,
+                       void* stream);
+
 /* Custom dense gate on the k adjacent qudits q0..q0+k-1 (the paper's
  * U(matrix, index), section "Grover's algorithm"): psi[h, :, l] <- B psi[h, :, l]
  * with the register viewed as [D^q0][D^k][D^(n-q0-k)].
@@ -168,7 +189,10 @@ typedef enum {
     QF_OP_U = 9,       /* dense D^k x D^k matrix `mat` on qudits q0..q0+k-1        */
     QF_OP_CRX = 10,    /* controlled rotation sum_m |m><m|_q0 (x) R_x^{jk}(m theta)_q1 */
     QF_OP_CRY = 11,    /* the same with R_y^{jk}                                   */
-    QF_OP_CRZ = 12     /* the same with R_z^{j}, 1 <= j < D                        */
+    QF_OP_CRZ = 12,    /* the same with R_z^{j}, 1 <= j < D                        */
+    QF_OP_SWAP = 13,   /* exchange the digits of q0 and q1                         */
+    QF_OP_MCX = 14     /* x_q1 -> x_q1 + prod_i x_{shifts[i]} mod D, i < j (1..8   */
+                       /* controls listed in shifts[0 .. j-1])                     */
 } qf_op_kind;
 
 typedef struct qf_op {

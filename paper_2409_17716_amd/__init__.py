@@ -21,7 +21,7 @@ QF_OK, QF_EINVAL, QF_EDTYPE, QF_ERANGE, QF_ENOMEM, QF_EHIP, QF_EUNSUPPORTED = 0,
 QF_C64, QF_C128 = 0, 1
 QF_SEED = 1  # adjoint flag: lam holds torch's gradient of the output state
 (QF_OP_H, QF_OP_X, QF_OP_CLOCK, QF_OP_RX, QF_OP_RY, QF_OP_RZ, QF_OP_CSUM, QF_OP_CSHIFT, QF_OP_CZ,
- QF_OP_U, QF_OP_CRX, QF_OP_CRY, QF_OP_CRZ) = range(13)
+ QF_OP_U, QF_OP_CRX, QF_OP_CRY, QF_OP_CRZ, QF_OP_SWAP, QF_OP_MCX) = range(15)
 
 
 class QfError(RuntimeError):
@@ -66,6 +66,9 @@ _SIGS = {
     "qf_apply_diag": [_PS, _I32, _PI32, _PD, _P],
     "qf_apply_fused": [_PS, _I32, _I32, _P, _P],
     "qf_apply_crot": [_PS, _I32, _I32, _I32, _I32, _I32, ctypes.c_double, _P],
+    "qf_apply_rot": [_PS, _I32, _I32, _I32, _I32, ctypes.c_double, _P],
+    "qf_apply_swap": [_PS, _I32, _I32, _P],
+    "qf_apply_mcx": [_PS, _I32, _PI32, _I32, _P],
     "qf_probs": [_PS, _I32, _PI32, _P, _P],
     "qf_expect": [_PS, _I32, _PI32, _PD, _PD, _P],
     "qf_expect_noalloc": [_PS, _I32, _PI32, _PD, _PD, _P],
@@ -197,6 +200,24 @@ def qf_apply_crot(t, n: int, dim: int, kind: str, ctrl: int, tgt: int, j: int, k
     _check(lib.qf_apply_crot(ctypes.byref(s), _KIND[kind], ctrl, tgt, j, k, float(theta), _stream(stream)))
 
 
+def qf_apply_rot(t, n: int, dim: int, kind: str, q: int, j: int, k: int, theta: float, stream=None) -> None:
+    """One rotation ("rx", "ry" on levels j < k, or "rz" with level j) as a slab sweep."""
+    s = state_of(t, n, dim)
+    _check(lib.qf_apply_rot(ctypes.byref(s), _KIND[kind], q, j, k, float(theta), _stream(stream)))
+
+
+def qf_apply_swap(t, n: int, dim: int, a: int, b: int, stream=None) -> None:
+    s = state_of(t, n, dim)
+    _check(lib.qf_apply_swap(ctypes.byref(s), a, b, _stream(stream)))
+
+
+def qf_apply_mcx(t, n: int, dim: int, ctrls: Sequence[int], tgt: int, stream=None) -> None:
+    """x_tgt -> x_tgt + prod of the control digits mod dim."""
+    s = state_of(t, n, dim)
+    ca, cp = _i32(ctrls)
+    _check(lib.qf_apply_mcx(ctypes.byref(s), len(ctrls), cp, tgt, _stream(stream)))
+
+
 def qf_apply_fused(t, n: int, dim: int, q0: int, k: int, B, stream=None) -> None:
     """B: device tensor (K x K) in the state's precision."""
     s = state_of(t, n, dim)
@@ -267,7 +288,7 @@ def qf_expect_noalloc(t, n: int, dim: int, terms, out, stream=None):
 
 _KIND = {"h": QF_OP_H, "x": QF_OP_X, "clock": QF_OP_CLOCK, "clockp": QF_OP_CLOCK, "rx": QF_OP_RX, "ry": QF_OP_RY,
          "rz": QF_OP_RZ, "csum": QF_OP_CSUM, "cshift": QF_OP_CSHIFT, "cz": QF_OP_CZ, "u": QF_OP_U,
-         "crx": QF_OP_CRX, "cry": QF_OP_CRY, "crz": QF_OP_CRZ}
+         "crx": QF_OP_CRX, "cry": QF_OP_CRY, "crz": QF_OP_CRZ, "swap": QF_OP_SWAP, "mcx": QF_OP_MCX}
 
 
 def ops_to_c(ops: Sequence[tuple]):
@@ -300,6 +321,15 @@ def ops_to_c(ops: Sequence[tuple]):
             o.q0, o.q1, o.j, o.k, o.param = op[1], op[2], op[3], op[4], op[5]
         elif kind == "crz":
             o.q0, o.q1, o.j, o.param = op[1], op[2], op[3], op[4]
+        elif kind == "swap":
+            o.q0, o.q1 = op[1], op[2]
+        elif kind == "mcx":
+            ctrls = list(op[1])
+            if not 1 <= len(ctrls) <= 8:
+                raise QfError(QF_EINVAL, "mcx takes 1..8 controls")
+            o.q1, o.j = op[2], len(ctrls)
+            for i, c in enumerate(ctrls):
+                o.shifts[i] = int(c)
         elif kind == "u":
             o.q0, o.q1 = op[1], op[2]
             m, p = _c128(op[3])

@@ -244,6 +244,57 @@ qf_status qf_apply_crot(const qf_state* s, int32_t kind, int32_t ctrl, int32_t t
                        reinterpret_cast<hipStream_t>(stream));
 }
 
+qf_status qf_apply_swap(const qf_state* s, int32_t a, int32_t b, void* stream) {
+    StateView v;
+    QF_CHECK(make_view(s, v));
+    QF_CHECK(check_qudit(v, a, "first"));
+    QF_CHECK(check_qudit(v, b, "second"));
+    QF_RETURN_IF(a == b, QF_EINVAL, "SWAP of qudit %d with itself", a);
+    return launch_swap(v, a, b, reinterpret_cast<hipStream_t>(stream));
+}
+
+qf_status qf_apply_mcx(const qf_state* s, int32_t nctrl, const int32_t* ctrls, int32_t tgt, void* stream) {
+    StateView v;
+    QF_CHECK(make_view(s, v));
+    QF_RETURN_IF(nctrl < 1 || nctrl > 8, QF_EINVAL, "nctrl = %d outside 1..8", nctrl);
+    QF_RETURN_IF(ctrls == nullptr, QF_EINVAL, "ctrls is NULL");
+    QF_CHECK(check_qudit(v, tgt, "target"));
+    for (int i = 0; i < nctrl; ++i) {
+        QF_CHECK(check_qudit(v, ctrls[i], "control"));
+        QF_RETURN_IF(ctrls[i] == tgt, QF_EINVAL, "control %d is the target", ctrls[i]);
+        for (int j = 0; j < i; ++j) QF_RETURN_IF(ctrls[i] == ctrls[j], QF_EINVAL, "control %d listed twice", ctrls[i]);
+    }
+    return launch_mcx(v, nctrl, ctrls, tgt, false, reinterpret_cast<hipStream_t>(stream));
+}
+
+qf_status qf_apply_rot(const qf_state* s, int32_t kind, int32_t q, int32_t j, int32_t k, double theta,
+                       void* stream) {
+    StateView v;
+    QF_CHECK(make_view(s, v));
+    QF_RETURN_IF(kind != QF_OP_RX && kind != QF_OP_RY && kind != QF_OP_RZ, QF_EINVAL, "kind %d is not a rotation",
+                 kind);
+    QF_CHECK(check_qudit(v, q, "target"));
+    if (kind == QF_OP_RZ)
+        QF_RETURN_IF(j < 1 || uint32_t(j) >= v.D, QF_EINVAL, "R_z level j = %d needs 1 <= j < D", j);
+    else
+        QF_RETURN_IF(!(j >= 0 && j < k && uint32_t(k) < v.D), QF_EINVAL, "levels (%d, %d) need 0 <= j < k < D", j, k);
+    QF_RETURN_IF(!std::isfinite(theta), QF_EINVAL, "theta is not finite");
+    // the slab kernel's table at control level m = 1 (layout in k_crot.hip)
+    std::vector<double> tab(size_t(4) * v.D, 0.0);
+    if (kind == QF_OP_RZ) {
+        const double a = std::sqrt(2.0 / (double(j) * (j + 1)));
+        tab[4] = std::cos(-0.5 * theta * a);
+        tab[5] = std::sin(-0.5 * theta * a);
+        tab[6] = std::cos(0.5 * theta * a * j);
+        tab[7] = std::sin(0.5 * theta * a * j);
+    } else {
+        tab[4] = std::cos(0.5 * theta);
+        tab[5] = std::sin(0.5 * theta);
+    }
+    return launch_crot(v, CrotArgs{kind - QF_OP_RX, -1, q, j, k}, nullptr, 0, tab.data(),
+                       reinterpret_cast<hipStream_t>(stream));
+}
+
 qf_status qf_apply_fused(const qf_state* s, int32_t k, int32_t q0, const void* B, void* stream) {
     StateView v;
     QF_CHECK(make_view(s, v));

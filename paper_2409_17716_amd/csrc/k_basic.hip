@@ -9,6 +9,7 @@
 //    loads of a wavefront is one contiguous 64-element run (coalesced).
 //  * L <  64: a workgroup stages whole [D][L] rows (contiguous in HBM) through
 //    LDS with coalesced loads/stores and each lane processes one fibre from LDS.
+#include <algorithm>
 #include <mutex>
 #include <type_traits>
 #include <vector>
@@ -65,6 +66,39 @@ struct OpShift {
     __device__ bool skip(uint32_t gidx) const { return amount(gidx) == 0; }
     // v[b] <- v[(b - s) mod D] as a barrel of rotations by 1, 2, 4, ...: every
     // register index is a compile-time constant, so nothing is spilled.
+    __device__ void apply(cplx<T> (&v)[D], uint32_t gidx) const {
+        const int s = amount(gidx);
+#pragma unroll
+        for (int bit = 1; bit < D; bit <<= 1) {
+            const bool on = (s & bit) != 0;
+            cplx<T> w[D];
+#pragma unroll
+            for (int b = 0; b < D; ++b) w[b] = v[(b - bit % D + D) % D];
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                v[b].re = on ? w[b].re : v[b].re;
+                v[b].im = on ? w[b].im : v[b].im;
+            }
+        }
+    }
+};
+
+// Multi-controlled shift x_t -> x_t + sign * prod_i x_{c_i} mod D (the
+// Toffoli / multi-controlled NOT generalized like the CNOT index rule); the
+// control digits are read from the global index of the fibre.
+constexpr int kMaxMcxCtrl = 8;
+
+template <typename T, int D>
+struct OpShiftMulti {
+    FastDiv strideC[kMaxMcxCtrl];
+    int32_t nctrl;
+    int32_t inverse;
+    __device__ int amount(uint32_t gidx) const {
+        uint32_t prod = 1;
+        for (int i = 0; i < nctrl; ++i) prod = (prod * (strideC[i].div(gidx) % D)) % D;
+        return inverse ? int((D - prod) % D) : int(prod);
+    }
+    __device__ bool skip(uint32_t gidx) const { return amount(gidx) == 0; }
     __device__ void apply(cplx<T> (&v)[D], uint32_t gidx) const {
         const int s = amount(gidx);
 #pragma unroll
@@ -176,6 +210,28 @@ qf_status with_type(int dtype, F&& f) {
     if (dtype == QF_C64) return f(float{});
     if (dtype == QF_C128) return f(double{});
     return set_error(QF_EDTYPE, "unknown dtype %d", dtype);
+}
+
+// ---------------------------------------------------------------------------
+// SWAP of two qudits: amplitude x (digits x_a < x_b) trades places with the
+// amplitude whose a and b digits are exchanged, x' = x + (x_b - x_a)(S_a - S_b)
+// for strides S_a > S_b; each pair is moved once, by the lane of its x_a < x_b
+// member.  Consecutive lanes touch consecutive x and x'.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_swap(cplx<T>* __restrict__ psi, uint32_t total, FastDiv sa, FastDiv sb,
+                                                 uint32_t D, FastDiv divD, uint32_t delta_unit) {
+    for (uint32_t x = blockIdx.x * kBlock + threadIdx.x; x < total; x += gridDim.x * kBlock) {
+        const uint32_t qa = sa.div(x), qb = sb.div(x);
+        const uint32_t xa = qa - divD.div(qa) * D, xb = qb - divD.div(qb) * D;
+        if (xa < xb) {
+            const uint32_t y = x + (xb - xa) * delta_unit;
+            const cplx<T> u = psi[x], v = psi[y];
+            psi[x] = v;
+            psi[y] = u;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -485,6 +541,33 @@ qf_status launch_ctrl(const StateView& s, int ctrl, int tgt, const int32_t* shif
             op.strideC = FastDiv(ctrl >= 0 ? ipow(D, s.n - 1 - ctrl) : 1u);
             return run_axis<T, D>(s, tgt, op, st, "qf_apply_ctrl");
         });
+    });
+}
+
+qf_status launch_mcx(const StateView& s, int nctrl, const int32_t* ctrls, int tgt, bool inverse, hipStream_t st) {
+    if (nctrl < 1 || nctrl > kMaxMcxCtrl) return set_error(QF_ERANGE, "%d controls outside 1..%d", nctrl, kMaxMcxCtrl);
+    return with_type(s.dtype, [&](auto tag) -> qf_status {
+        using T = decltype(tag);
+        return with_dim(s.D, [&](auto dtag) -> qf_status {
+            constexpr int D = decltype(dtag)::value;
+            OpShiftMulti<T, D> op;
+            op.nctrl = nctrl;
+            op.inverse = inverse ? 1 : 0;
+            for (int i = 0; i < kMaxMcxCtrl; ++i) op.strideC[i] = FastDiv(i < nctrl ? ipow(D, s.n - 1 - ctrls[i]) : 1u);
+            return run_axis<T, D>(s, tgt, op, st, "multi-controlled shift");
+        });
+    });
+}
+
+qf_status launch_swap(const StateView& s, int a, int b, hipStream_t st) {
+    if (a > b) std::swap(a, b);  // a: the more significant qudit
+    const uint32_t Sa = ipow(s.D, s.n - 1 - uint32_t(a)), Sb = ipow(s.D, s.n - 1 - uint32_t(b));
+    return with_type(s.dtype, [&](auto tag) -> qf_status {
+        using T = decltype(tag);
+        hipLaunchKernelGGL(k_swap<T>, dim3(grid_for(s.total, kBlock * 4)), dim3(kBlock), 0, st,
+                           reinterpret_cast<cplx<T>*>(s.amps), s.total, FastDiv(Sa), FastDiv(Sb), s.D, FastDiv(s.D),
+                           Sa - Sb);
+        return check_launch("swap");
     });
 }
 

@@ -1,5 +1,7 @@
 // The differentiable controlled rotation sum_m |m><m|_c (x) R^{jk}_alpha(m theta)_t
-// (arXiv:2409.17716, Appendix, subsection "Controlled Rotation Gate").
+// (arXiv:2409.17716, Appendix, subsection "Controlled Rotation Gate"), and
+// without a control the plain two-level rotation as a slab sweep (the memory
+// form of the paper's sparse rotation, subsection "Generalized rotation gate").
 //
 // The register is viewed as [H][D][L] for the target t (L = D^(n-1-t)); a
 // fibre is the D amplitudes psi[h, :, l], and its control digit m is read from
@@ -26,6 +28,7 @@ namespace {
 constexpr int kCB = 256;
 
 struct CrGeom {
+    int32_t has_ctrl;    // 0: plain rotation, every fibre uses table entry 1
     uint32_t L;          // stride of the target qudit
     FastDiv divL;
     FastDiv cstride;     // stride of the control qudit
@@ -81,7 +84,7 @@ __global__ __launch_bounds__(kCB) void k_crot(cplx<T>* __restrict__ psi, CrGeom 
     if (f >= g.nfib) return;
     const uint32_t h = g.divL.div(f);
     const uint32_t local = h * (uint32_t(D) * g.L) + (f - h * g.L);
-    const uint32_t m = g.cstride.div(local) % D;
+    const uint32_t m = g.has_ctrl ? g.cstride.div(local) % D : 1u;
     if (m == 0) return;
     rotate<T, D>(psi + size_t(b) * g.N, g, local, tab, m);
 }
@@ -110,7 +113,7 @@ __global__ __launch_bounds__(kCB) void k_crot_adj(cplx<T>* __restrict__ psi, cpl
     if (f < g.nfib) {
         const uint32_t h = g.divL.div(f);
         const uint32_t local = h * (uint32_t(D) * g.L) + (f - h * g.L);
-        const uint32_t m = g.cstride.div(local) % D;
+        const uint32_t m = g.has_ctrl ? g.cstride.div(local) % D : 1u;
         if (m != 0) {
             cplx<T>* p = psi + size_t(b) * g.N;
             cplx<T>* l = lam + size_t(b) * g.N;
@@ -175,9 +178,10 @@ qf_status with_dim_c(uint32_t D, F&& f) {
 
 CrGeom make_geom(const StateView& s, const CrotArgs& a) {
     CrGeom g{};
+    g.has_ctrl = a.ctrl >= 0 ? 1 : 0;
     g.L = ipow(s.D, s.n - 1 - uint32_t(a.tgt));
     g.divL.init(g.L);
-    g.cstride.init(ipow(s.D, s.n - 1 - uint32_t(a.ctrl)));
+    g.cstride.init(a.ctrl >= 0 ? ipow(s.D, s.n - 1 - uint32_t(a.ctrl)) : 1u);
     g.nfib = s.N / s.D;
     g.N = s.N;
     g.bpr = (g.nfib + kCB - 1) / kCB;

@@ -81,8 +81,19 @@ static bool is_rot(int kind) { return kind == QF_OP_RX || kind == QF_OP_RY || ki
 static bool is_crot(int kind) { return kind == QF_OP_CRX || kind == QF_OP_CRY || kind == QF_OP_CRZ; }
 // Gates that never enter an LDS tile: each makes a pass of its own (dense
 // blocks, controlled rotations).
-static bool pass_gate(int kind) { return kind == QF_OP_U || is_crot(kind); }
+static bool pass_gate(int kind) {
+    return kind == QF_OP_U || is_crot(kind) || kind == QF_OP_SWAP || kind == QF_OP_MCX;
+}
 static CrotArgs crot_args(const qf_op& o) { return CrotArgs{o.kind - QF_OP_CRX, o.q0, o.q1, o.j, o.k}; }
+// A lone rotation as a controlled rotation whose every fibre takes table
+// entry m = 1 (the two-level slab kernel).
+static qf_op slab_op(const qf_op& o) {
+    qf_op t = o;
+    t.kind = QF_OP_CRX + (o.kind - QF_OP_RX);
+    t.q1 = o.q0;
+    t.q0 = -1;
+    return t;
+}
 
 // Table of a controlled rotation for control levels m = 0..D-1 (2 D complex
 // entries, interleaved FP64; layout in k_crot.hip): x, y types
@@ -104,6 +115,12 @@ static void crot_table(const qf_op& o, int D, const double* theta, bool inverse,
             out[4 * m + 1] = std::sin(0.5 * m * t);
         }
     }
+}
+
+// SWAP and multi-controlled shifts (inverse: the shift subtracts; SWAP is its own inverse).
+static qf_status launch_perm_gate(const StateView& v, const qf_op& o, bool inverse, hipStream_t st) {
+    if (o.kind == QF_OP_SWAP) return launch_swap(v, o.q0, o.q1, st);
+    return launch_mcx(v, o.j, o.shifts, o.q1, inverse, st);
 }
 
 static qf_status check_finite_theta(const double* theta, int nparams) {
@@ -183,7 +200,7 @@ static Mat generator(const qf_op& g, int D) {
 // of one-qudit gates on a qudit).
 // ---------------------------------------------------------------------------
 
-enum StepType { ST_AXIS, ST_CTRL, ST_DIAG, ST_FUSED, ST_CROT };
+enum StepType { ST_AXIS, ST_CTRL, ST_DIAG, ST_FUSED, ST_CROT, ST_PERM };
 
 struct Step {
     StepType type;
@@ -193,7 +210,8 @@ struct Step {
     std::vector<int> gates;  // gate indices folded into this step, in order
     bool has_param = false;
     int slot = -1;           // adjoint M slot
-    int cr_slot = -1;        // ST_CROT: index among the controlled rotations
+    int cr_slot = -1;        // ST_CROT, slab steps: index among the gradient outputs
+    bool slab = false;       // ST_AXIS holding one rotation: run as a two-level slab sweep
 };
 
 // ---------------------------------------------------------------------------
@@ -433,6 +451,18 @@ static qf_status validate_op(const qf_op& o, int D, int n, int nparams) {
                              o.j, o.k);
             QF_RETURN_IF(o.param < 0 || o.param >= nparams, QF_EINVAL, "param %d outside [0, %d)", o.param, nparams);
             break;
+        case QF_OP_SWAP:
+            QF_RETURN_IF(!qok(o.q0) || !qok(o.q1) || o.q0 == o.q1, QF_EINVAL, "SWAP of (%d, %d)", o.q0, o.q1);
+            break;
+        case QF_OP_MCX:
+            QF_RETURN_IF(!qok(o.q1), QF_EINVAL, "MCX target %d outside [0, %d)", o.q1, n);
+            QF_RETURN_IF(o.j < 1 || o.j > 8, QF_EINVAL, "MCX with %d controls (1..8)", o.j);
+            for (int i = 0; i < o.j; ++i) {
+                QF_RETURN_IF(!qok(o.shifts[i]) || o.shifts[i] == o.q1, QF_EINVAL, "MCX control %d", o.shifts[i]);
+                for (int m = 0; m < i; ++m)
+                    QF_RETURN_IF(o.shifts[m] == o.shifts[i], QF_EINVAL, "MCX control %d listed twice", o.shifts[i]);
+            }
+            break;
         case QF_OP_U:
             QF_RETURN_IF(o.q1 < 1 || o.q0 < 0 || o.q0 + o.q1 > n, QF_EINVAL, "U on qudits %d..%d", o.q0,
                          o.q0 + o.q1 - 1);
@@ -530,6 +560,18 @@ static void build_steps(qf_plan* p) {
                 s.q = o.q1;
                 s.q2 = o.q0;
                 break;
+            case QF_OP_SWAP:
+                flush(o.q0);
+                flush(o.q1);
+                s.type = ST_PERM;
+                s.q = o.q1;
+                break;
+            case QF_OP_MCX:
+                for (int i = 0; i < o.j; ++i) flush(o.shifts[i]);
+                flush(o.q1);
+                s.type = ST_PERM;
+                s.q = o.q1;
+                break;
         }
         p->steps.push_back(s);
     }
@@ -537,8 +579,12 @@ static void build_steps(qf_plan* p) {
     p->nslots = 0;
     p->ncr_steps = 0;
     for (auto& s : p->steps) {
-        if (s.type == ST_AXIS && s.has_param) s.slot = p->nslots++;
-        if (s.type == ST_CROT) s.cr_slot = p->ncr_steps++;
+        // a step of one lone rotation runs as a slab sweep: it reads and writes
+        // only the levels the rotation moves, and its gradient comes straight
+        // from the slab adjoint kernel
+        s.slab = s.type == ST_AXIS && s.gates.size() == 1 && is_rot(p->gates[s.gates[0]].op.kind);
+        if (s.type == ST_AXIS && s.has_param && !s.slab) s.slot = p->nslots++;
+        if (s.type == ST_CROT || s.slab) s.cr_slot = p->ncr_steps++;
     }
 }
 
@@ -552,6 +598,12 @@ static qf_status run_step(const qf_plan* p, const Step& s, const StateView& v, c
                           hipStream_t st) {
     switch (s.type) {
         case ST_AXIS: {
+            if (s.slab) {
+                const qf_op so = slab_op(p->gates[s.gates[0]].op);
+                std::vector<double> tab;
+                crot_table(so, p->D, theta, inverse, tab);
+                return launch_crot(v, crot_args(so), nullptr, 0, tab.data(), st);
+            }
             Mat U = step_matrix(p, s, theta);
             if (inverse) U = dagger(U, p->D);
             std::vector<double> buf;
@@ -585,6 +637,8 @@ static qf_status run_step(const qf_plan* p, const Step& s, const StateView& v, c
             crot_table(o, p->D, theta, inverse, tab);
             return launch_crot(v, crot_args(o), nullptr, 0, tab.data(), st);
         }
+        case ST_PERM:
+            return launch_perm_gate(v, p->gates[s.gates[0]].op, inverse, st);
     }
     return QF_OK;
 }
@@ -623,6 +677,14 @@ static void touches(const qf_op& o, std::vector<Touch>& t) {
         case QF_OP_CRZ:
             t.push_back({o.q0, true});
             t.push_back({o.q1, o.kind == QF_OP_CRZ});
+            break;
+        case QF_OP_SWAP:
+            t.push_back({o.q0, false});
+            t.push_back({o.q1, false});
+            break;
+        case QF_OP_MCX:
+            for (int i = 0; i < o.j; ++i) t.push_back({o.shifts[i], true});
+            t.push_back({o.q1, false});
             break;
         case QF_OP_U:
             for (int q = o.q0; q < o.q0 + o.q1; ++q) t.push_back({q, false});
@@ -1512,6 +1574,9 @@ static qf_status run_fused_pass(qf_plan* p, const PassList& L, const Pass& ps, c
         const void* tab = reinterpret_cast<const unsigned char*>(L.dmats) + ps.mat_off * esz;
         QF_CHECK(launch_crot(v, crot_args(p->gates[ps.fused.gi].op), tab, 0, nullptr, st));
         return prof_end(p, st, a, F_CROT, 2.0 * state_bytes(v) * 2.0 / p->D);
+    } else if (p->gates[ps.fused.gi].op.kind == QF_OP_SWAP || p->gates[ps.fused.gi].op.kind == QF_OP_MCX) {
+        QF_CHECK(launch_perm_gate(v, p->gates[ps.fused.gi].op, ps.fused.inv, st));
+        return prof_end(p, st, a, F_CTRL, 2.0 * state_bytes(v));
     } else {
         const Gate& g = p->gates[ps.fused.gi];
         QF_CHECK(launch_fused(v, g.op.q1, g.op.q0, ps.fused.inv ? g.dmat_adj : g.dmat, st, g.real));
@@ -1733,6 +1798,7 @@ qf_status qf_plan_forward(qf_plan* plan, const qf_state* s, const double* theta,
                             : step.type == ST_CTRL ? F_CTRL
                             : step.type == ST_DIAG ? F_DIAG
                             : step.type == ST_CROT ? F_CROT
+                            : step.type == ST_PERM ? F_CTRL
                                                    : F_FUSED;
             QF_CHECK(prof_end(plan, st, a, fam, 2.0 * state_bytes(v)));
         }
@@ -1853,7 +1919,13 @@ qf_status qf_adjoint_grad(qf_plan* plan, const qf_state* psi, const qf_state* la
     } else if (rs == QF_OK) {
         for (int si = int(plan->steps.size()) - 1; si >= 0 && rs == QF_OK; --si) {
             const Step& s = plan->steps[si];
-            if (s.type == ST_AXIS && s.has_param) {
+            if (s.type == ST_AXIS && s.slab) {
+                const qf_op so = slab_op(plan->gates[s.gates[0]].op);
+                std::vector<double> tab;
+                crot_table(so, D, theta, true, tab);
+                rs = launch_crot_adj(v, lam->amps, crot_args(so), nullptr, 0, tab.data(), partial, crout + s.cr_slot,
+                                     uint32_t(ncr), st);
+            } else if (s.type == ST_AXIS && s.has_param) {
                 Mat W = dagger(step_matrix(plan, s, theta), D);
                 std::vector<double> buf;
                 to_interleaved(W, buf);
@@ -1907,9 +1979,9 @@ qf_status qf_adjoint_grad(qf_plan* plan, const qf_state* psi, const qf_state* la
                 if (ps.cr_slot >= 0) gb[plan->gates[ps.fused.gi].op.param] += crhost[size_t(b) * ncr + ps.cr_slot];
         } else {
             for (const Step& s : plan->steps) {
-                if (s.type == ST_AXIS && s.has_param)
+                if (s.type == ST_AXIS && s.has_param && !s.slab)
                     add_group_grad(plan, s.gates, theta, mhost.data() + ((size_t(b) * nslots + s.slot) * E) * 2, gb);
-                if (s.type == ST_CROT) gb[plan->gates[s.gates[0]].op.param] += crhost[size_t(b) * ncr + s.cr_slot];
+                if (s.cr_slot >= 0) gb[plan->gates[s.gates[0]].op.param] += crhost[size_t(b) * ncr + s.cr_slot];
             }
         }
     }
@@ -1995,6 +2067,8 @@ static uint64_t plan_key(const qf_plan* p, uint32_t batch) {
         mix(uint64_t(g.op.kind));
         mix(uint64_t(uint32_t(g.op.q0)) | (uint64_t(uint32_t(g.op.q1)) << 32));
         mix(uint64_t(uint32_t(g.op.j)) | (uint64_t(uint32_t(g.op.k)) << 32));
+        if (g.op.kind == QF_OP_MCX || g.op.kind == QF_OP_CSHIFT)
+            for (int i = 0; i < 16; ++i) mix(uint64_t(uint32_t(g.op.shifts[i])));
     }
     return h;
 }
@@ -2276,6 +2350,8 @@ qf_status qf_plan_forward_dev(qf_plan* plan, const qf_state* s, const double* th
         } else if (ps.cr_slot >= 0) {
             const void* tab = reinterpret_cast<const unsigned char*>(L.dmats_b) + ps.mat_off * esz;
             QF_CHECK(launch_crot(v, crot_args(plan->gates[ps.fused.gi].op), tab, L.nmats, nullptr, st));
+        } else if (plan->gates[ps.fused.gi].op.kind == QF_OP_SWAP || plan->gates[ps.fused.gi].op.kind == QF_OP_MCX) {
+            QF_CHECK(launch_perm_gate(v, plan->gates[ps.fused.gi].op, false, st));
         } else {
             const Gate& g = plan->gates[ps.fused.gi];
             QF_CHECK(launch_fused(v, g.op.q1, g.op.q0, g.dmat, st, g.real));
@@ -2344,6 +2420,9 @@ qf_status qf_adjoint_grad_dev(qf_plan* plan, const qf_state* psi, const qf_state
             QF_CHECK(launch_crot_adj(v, lam->amps, crot_args(plan->gates[ps.fused.gi].op), tab, L.nmats, nullptr,
                                      plan->w_partial, plan->w_contrib + plan->cr_contrib[size_t(ps.cr_slot)],
                                      uint32_t(plan->ncontrib), st));
+        } else if (plan->gates[ps.fused.gi].op.kind == QF_OP_SWAP || plan->gates[ps.fused.gi].op.kind == QF_OP_MCX) {
+            QF_CHECK(launch_perm_gate(v, plan->gates[ps.fused.gi].op, true, st));
+            QF_CHECK(launch_perm_gate(vl, plan->gates[ps.fused.gi].op, true, st));
         } else {
             const Gate& g = plan->gates[ps.fused.gi];
             QF_CHECK(launch_fused(v, g.op.q1, g.op.q0, g.dmat_adj, st, g.real));

@@ -34,6 +34,10 @@ qf_status launch_apply_1q(const StateView& s, int q, const double* U, hipStream_
 qf_status launch_ctrl(const StateView& s, int ctrl, int tgt, const int32_t* shift, hipStream_t st);
 qf_status launch_diag(const StateView& s, int k, const int32_t* qudits, const double* phases,
                       hipStream_t st);
+// x_tgt -> x_tgt +/- prod_i x_{ctrls[i]} mod D (1 <= nctrl <= 8); inverse subtracts.
+qf_status launch_mcx(const StateView& s, int nctrl, const int32_t* ctrls, int tgt, bool inverse, hipStream_t st);
+// Exchange the digits of qudits a and b (a != b).
+qf_status launch_swap(const StateView& s, int a, int b, hipStream_t st);
 qf_status launch_probs_full(const StateView& s, void* out, hipStream_t st);
 qf_status launch_probs_marginal(const StateView& s, int m, const int32_t* qudits, void* out,
                                 hipStream_t st);
@@ -53,7 +57,10 @@ qf_status launch_diag_observable(const StateView& psi, void* lam_amps, const std
                                  const std::vector<double>& table_re, hipStream_t st);
 
 // ---- controlled rotation (k_crot.hip) ----
-// sum_m |m><m|_ctrl (x) R(m theta)_tgt; kind 0 = x, 1 = y, 2 = z type.  The
+// sum_m |m><m|_ctrl (x) R(m theta)_tgt; kind 0 = x, 1 = y, 2 = z type; with
+// ctrl = -1 the plain rotation R(theta) (table entry m = 1 for every fibre:
+// the two-level slab kernel, which reads and writes only the levels the
+// rotation moves).  The
 // table holds 2*D complex entries per register (see k_crot.hip), from the
 // device (dtab, register stride tab_stride) or, when dtab is NULL, from htab
 // (host, 2*D complex FP64, shared by every register).

@@ -198,3 +198,22 @@ def test_crot_validation(qf):
         qf.Plan(3, 3, [("crx", 0, 0, 0, 1, 0)], 1)
     p = qf.Plan(3, 3, [("cry", 0, 2, 0, 2, 0), ("h", 1), ("crz", 2, 1, 2, 1)], 2)
     assert p.num_stages >= 2
+
+
+def test_swap_mcx_rot_validation(qf):
+    s = _fake_state(qf)  # D = 3, n = 3
+    assert qf.lib.qf_apply_swap(ctypes.byref(s), 1, 1, None) == qf.QF_EINVAL
+    assert qf.lib.qf_apply_swap(ctypes.byref(s), 0, 3, None) == qf.QF_EINVAL
+    c2 = (ctypes.c_int32 * 2)(0, 0)
+    assert qf.lib.qf_apply_mcx(ctypes.byref(s), 2, c2, 2, None) == qf.QF_EINVAL
+    c1 = (ctypes.c_int32 * 1)(2)
+    assert qf.lib.qf_apply_mcx(ctypes.byref(s), 1, c1, 2, None) == qf.QF_EINVAL
+    assert qf.lib.qf_apply_mcx(ctypes.byref(s), 0, c1, 1, None) == qf.QF_EINVAL
+    assert qf.lib.qf_apply_rot(ctypes.byref(s), qf.QF_OP_CRX, 0, 0, 1, 0.1, None) == qf.QF_EINVAL
+    assert qf.lib.qf_apply_rot(ctypes.byref(s), qf.QF_OP_RX, 0, 1, 1, 0.1, None) == qf.QF_EINVAL
+    assert qf.lib.qf_apply_rot(ctypes.byref(s), qf.QF_OP_RZ, 0, 3, 0, 0.1, None) == qf.QF_EINVAL
+    for bad in ([("swap", 1, 1)], [("mcx", (0, 0), 2)], [("mcx", (2,), 2)], [("mcx", tuple(range(9)), 2)]):
+        with pytest.raises(qf.QfError):
+            qf.Plan(3, 3, bad, 0)
+    p = qf.Plan(3, 4, [("swap", 0, 3), ("mcx", (0, 1, 2), 3), ("h", 2)], 0)
+    assert p.num_stages >= 2

@@ -1,0 +1,134 @@
+"""GPU parity of SWAP, the multi-controlled shift (Toffoli / MCX) and the
+two-level slab rotation against the FP64 oracle: permutations bit for bit,
+circuits in every schedule with their adjoint gradients, and bound mode."""
+import numpy as np
+import pytest
+
+import qf_inputs as qi
+from oracle import gates, grad, sim
+from tests.gpu_helpers import TOL, maxabs, rounded, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qf():
+    import paper_2409_17716_amd as qf
+    return qf
+
+
+def _grad_close(g, ref, rel, dtype="c64"):
+    floor = (1e-2 if dtype == "c64" else 1e-3) * np.abs(ref).max()
+    return np.all(np.abs(g - ref) <= rel * np.maximum(np.abs(ref), floor))
+
+
+@pytest.mark.parametrize("D,n,dt", [(3, 7, "c64"), (2, 11, "c128"), (5, 4, "c64"), (10, 3, "c128")])
+def test_swap_every_pair_bit_exact(qf, D, n, dt):
+    psi = rounded(qi.random_state(D, n, 3, batch=2).reshape(-1), dt)
+    for a in range(n):
+        for b in range(n):
+            if a == b:
+                continue
+            x = to_dev(psi, dt)
+            qf.qf_apply_swap(x, n, D, a, b)
+            want = np.concatenate([sim.apply_swap(r, D, n, a, b) for r in psi.reshape(2, -1)])
+            assert np.array_equal(to_np(x), want), (a, b)
+
+
+@pytest.mark.parametrize("D,n,dt", [(3, 6, "c64"), (2, 9, "c128"), (4, 5, "c64"), (5, 4, "c128")])
+def test_mcx_bit_exact(qf, D, n, dt):
+    """1..3 controls on every target, on random states (bit for bit) and on
+    basis states (the exact basis state)."""
+    rng = np.random.default_rng(D + n)
+    psi = rounded(qi.random_state(D, n, 4), dt)
+    for t in range(n):
+        for nc in (1, 2, 3):
+            ctrls = [int(c) for c in rng.choice([q for q in range(n) if q != t], size=nc, replace=False)]
+            x = to_dev(psi, dt)
+            qf.qf_apply_mcx(x, n, D, ctrls, t)
+            assert np.array_equal(to_np(x), sim.apply_mcx(psi, D, n, ctrls, t)), (ctrls, t)
+    for _ in range(5):
+        digs = [int(v) for v in rng.integers(0, D, size=n)]
+        x = to_dev(np.zeros(D ** n), dt)
+        qf.qf_state_init(x, n, D, digs)
+        qf.qf_apply_mcx(x, n, D, [0, 1], n - 1)
+        want = list(digs)
+        want[n - 1] = (want[n - 1] + digs[0] * digs[1]) % D
+        assert np.array_equal(to_np(x), sim.basis_state(D, n, want))
+
+
+@pytest.mark.parametrize("D,n,dt", [(3, 8, "c64"), (5, 4, "c128"), (10, 3, "c64"), (2, 10, "c128")])
+def test_slab_rotation_every_axis(qf, D, n, dt):
+    """qf_apply_rot (only the moved levels are read and written) against the
+    oracle's rotation on every qudit, for the x, y and z types."""
+    rng = np.random.default_rng(5 * D + n)
+    psi = qi.random_state(D, n, 6)
+    for q in range(n):
+        for kind in ("rx", "ry", "rz"):
+            th = float(rng.uniform(-np.pi, np.pi))
+            if kind == "rz":
+                j = int(rng.integers(1, D))
+                op, k = ("rz", q, j, 0), 0
+            else:
+                j, k = (int(v) for v in sorted(rng.choice(D, size=2, replace=False)))
+                op = (kind, q, j, k, 0)
+            x = to_dev(psi, dt)
+            qf.qf_apply_rot(x, n, D, kind, q, j, k, th)
+            want = sim.apply_1q(rounded(psi, dt), D, n, q, gates.op_matrix(op, D, np.array([th])))
+            assert maxabs(to_np(x), want) <= TOL[dt], (q, kind)
+
+
+CIRCS = [
+    ("d3", lambda: qi.random_circuit(3, 6, 120, 7, kinds=["h", "rx", "ry", "rz", "swap", "mcx", "csum", "cz",
+                                                           "clock"]), "c64"),
+    ("d2", lambda: qi.random_circuit(2, 9, 150, 8, kinds=["rx", "ry", "swap", "mcx", "csum", "crx"]), "c128"),
+    ("d5", lambda: qi.random_circuit(5, 4, 80, 9, kinds=["ry", "rz", "swap", "mcx", "cry", "u2"]), "c128"),
+]
+
+
+@pytest.mark.parametrize("name,make,dt", CIRCS, ids=[c[0] for c in CIRCS])
+@pytest.mark.parametrize("fuse", [0, 1, 2, 3])
+def test_swap_mcx_circuits(qf, name, make, dt, fuse):
+    """SWAP and MCX mixed with rotations, controlled rotations and the other
+    gates in every schedule (fuse = 1 runs lone rotations as slab sweeps):
+    final state and adjoint gradient against the oracle."""
+    c = make()
+    terms = qi.zsum_terms(c.n)
+    p = qf.plan_for(c, dt, fuse=fuse)
+    t = qf.new_state(c.n, c.dim, dt)
+    qf.qf_state_init(t, c.n, c.dim, None)
+    p.forward(t, c.theta)
+    want = sim.run(c)
+    assert maxabs(to_np(t), want) <= TOL[dt]
+    lam = qf.new_state(c.n, c.dim, dt)
+    g = p.adjoint_grad(t, lam, c.theta, terms)
+    ref = grad.adjoint(c, terms, psi_final=want)
+    assert _grad_close(g, ref, 1e-4 if dt == "c64" else 1e-9, dt), np.abs(g - ref).max()
+
+
+@pytest.mark.parametrize("fuse", [1, 2])
+def test_per_gate_schedules_adjoint(qf, fuse):
+    """The per-gate schedules' adjoint on the D=3 and D=5 workload shapes (lone
+    rotations as slab sweeps with fuse = 1, fused runs with fuse = 2)."""
+    for c, dt in ((qi.config2(n=6, layers=2), "c64"), (qi.config3(n=4, layers=2), "c128")):
+        terms = qi.zsum_terms(c.n)
+        p = qf.plan_for(c, dt, fuse=fuse)
+        t = qf.new_state(c.n, c.dim, dt)
+        qf.qf_state_init(t, c.n, c.dim, None)
+        p.forward(t, c.theta)
+        lam = qf.new_state(c.n, c.dim, dt)
+        g = p.adjoint_grad(t, lam, c.theta, terms)
+        assert _grad_close(g, grad.adjoint(c, terms), 1e-4 if dt == "c64" else 1e-9, dt)
+
+
+def test_swap_mcx_bound_mode(qf):
+    import torch
+    from paper_2409_17716_amd.autograd import DeviceCircuit
+    c = qi.random_circuit(3, 5, 90, 12, kinds=["h", "ry", "rz", "swap", "mcx", "csum", "crz"])
+    terms = qi.zsum_terms(c.n)
+    dc = DeviceCircuit(c, dtype="c128")
+    th = torch.tensor(c.theta, dtype=torch.float64, device="cuda", requires_grad=True)
+    L = dc.expectation(th, terms)
+    L.backward()
+    assert abs(L.item() - grad.loss(c, terms)) <= 1e-12
+    assert _grad_close(th.grad.cpu().numpy(), grad.adjoint(c, terms), 1e-9, "c128")
