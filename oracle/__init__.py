@@ -22,7 +22,7 @@ definitions directly (Appendix "Matrix form of the quantum gates"):
                 paper's sparse digit rules and Kronecker products, as an
                 independent second route.
 
-Parity status of each function is recorded in its docstring; none is unpinned
-except ``measure.sample_counts`` (statistical only).
+Parity status of each function is recorded in its docstring; every function
+is pinned (``tests/test_oracle_pins.py``).
 """
 from . import gates, sim, measure, grad, brute  # noqa: F401

@@ -25,10 +25,22 @@ def marginal(psi: np.ndarray, D: int, n: int, qudits) -> np.ndarray:
     return np.ascontiguousarray(s).reshape(-1)
 
 
-def sample_counts(p: np.ndarray, shots: int, seed: int) -> np.ndarray:
-    """Histogram of ``shots`` draws from p.  Parity unpinned (statistical only)."""
-    rng = np.random.default_rng(seed)
-    return np.bincount(rng.choice(len(p), size=shots, p=p / p.sum()), minlength=len(p))
+def sample_inverse_cdf(p: np.ndarray, u: np.ndarray) -> np.ndarray:
+    """Measurement outcomes for the uniforms u in [0, 1) by inversion of the
+    cumulative distribution of p (the histogram the paper's measure(...,
+    shots) returns, section "Code style"): outcome y is the first index with
+    cumsum(p)[y] > u * sum(p), or the last bin of non-zero probability when
+    no such index exists."""
+    c = np.cumsum(np.asarray(p, dtype=np.float64))
+    idx = np.searchsorted(c, np.asarray(u, dtype=np.float64) * c[-1], side="right")
+    # u * sum(p) can round up to sum(p) itself for u just below 1: such a draw
+    # belongs to the last bin with non-zero probability
+    return np.where(idx >= len(c), np.searchsorted(c, c[-1], side="left"), idx)
+
+
+def sample_counts(p: np.ndarray, u: np.ndarray) -> np.ndarray:
+    """Histogram of the outcomes sample_inverse_cdf(p, u)."""
+    return np.bincount(sample_inverse_cdf(p, u), minlength=len(p))
 
 
 def z_diag(D: int) -> np.ndarray:

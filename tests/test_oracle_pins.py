@@ -534,3 +534,43 @@ def test_swap_mcx_bruteforce_and_adjoint(D, n, seed):
     g = grad.adjoint(c, terms)
     fd = grad.finite_diff(c, terms, np.arange(c.nparams), h=1e-5)
     assert np.abs(g - fd).max() <= 1e-8 * max(1.0, np.abs(fd).max())
+
+
+# ------------------------------------------------------------------ shots
+
+def test_sampling_inverse_cdf_exact_cases():
+    """Inverse-CDF sampling with given uniforms: a basis state gives its index
+    for every uniform; a uniform distribution over K bins with the midpoint
+    uniforms (i + 1/2) / K puts exactly one shot in each bin; a two-bin
+    distribution (1/3, 2/3) sends u < 1/3 to bin 0 and u >= 1/3 to bin 1; the
+    last bin of non-zero probability catches u -> 1 (never a zero-probability
+    bin)."""
+    D, n = 3, 3
+    psi = sim.basis_state(D, n, [2, 0, 1])
+    u = np.linspace(0, 0.999, 50)
+    assert np.all(measure.sample_inverse_cdf(measure.probs(psi), u) == sim.index_of(D, [2, 0, 1]))
+    K = 27
+    counts = measure.sample_counts(np.full(K, 1.0 / K), (np.arange(K) + 0.5) / K)
+    assert np.array_equal(counts, np.ones(K))
+    p = np.array([1 / 3, 2 / 3])
+    assert list(measure.sample_inverse_cdf(p, [0.0, 0.3333, 0.334, 0.9999999])) == [0, 0, 1, 1]
+    top = np.nextafter(1.0, 0.0)
+    assert measure.sample_inverse_cdf(np.array([0.5, 0.5, 0.0]), [top])[0] == 1
+    assert measure.sample_inverse_cdf(np.array([0.1, 0.0, 0.7, 0.2, 0.0, 0.0]), [top, 0.0999, 0.1])[0] == 3
+    assert list(measure.sample_inverse_cdf(np.array([0.1, 0.0, 0.7, 0.2, 0.0, 0.0]), [0.0999, 0.1, 0.85])) == [0, 2, 3]
+
+
+def test_sampling_matches_distribution_statistically():
+    """Many shots of a random state's marginal: the histogram agrees with the
+    probabilities (chi-square statistic below the 1e-6 tail of its
+    distribution; a statistical check of the sampling route)."""
+    from scipy.stats import chi2
+    D, n = 3, 4
+    psi = qi.random_state(D, n, 21)
+    p = measure.marginal(psi, D, n, [2, 0])
+    shots = 200000
+    u = np.random.default_rng(22).random(shots)
+    counts = measure.sample_counts(p, u)
+    assert counts.sum() == shots
+    stat = float(np.sum((counts - shots * p) ** 2 / (shots * p)))
+    assert stat < chi2.isf(1e-6, len(p) - 1)
