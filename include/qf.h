@@ -151,6 +151,27 @@ qf_status qf_apply_fused(const qf_state* s, int32_t k, int32_t q0, const void* B
 qf_status qf_probs(const qf_state* s, int32_t m, const int32_t* qudits, void* out,
                    void* stream);
 
+/* Measurement shots (section "Code style": measure with a shot count returns
+ * the histogram of outcomes).  Draw i of register b takes the uniform
+ * u[b*shots + i] and returns the first outcome y whose cumulative
+ * probability (prefix sum of the distribution qf_probs defines, taken in FP64
+ * in a fixed order) exceeds u * total, total being the register's summed
+ * probability (the state need not be normalised); a product that reaches the
+ * total (u >= 1 after rounding) gives the last outcome of non-zero
+ * probability, and a register of zero norm gives outcome 0.
+ * m, qudits: as qf_probs (m = 0 with qudits = NULL: the full register, D^n
+ * outcomes; else D^m outcomes of the listed qudits, first listed most
+ * significant).  shots >= 0 per register.
+ * u: DEVICE, batch*shots doubles in [0, 1), caller-drawn (NULL when shots = 0).
+ * counts: DEVICE, batch*(outcomes) int64, overwritten with the histogram.
+ * samples: DEVICE, batch*shots int32 outcomes, or NULL.
+ * All caller-owned.  Errors: QF_EINVAL (bad pointers or qudits), QF_ERANGE
+ * when batch*outcomes or batch*shots reaches 2^32, or samples are asked for
+ * with more than 2^31 outcomes; QF_ENOMEM when the FP64 work array
+ * (about 8 bytes per outcome and register) cannot be allocated. */
+qf_status qf_sample(const qf_state* s, int32_t m, const int32_t* qudits, int64_t shots,
+                    const double* u, int64_t* counts, int32_t* samples, void* stream);
+
 /* Expectation of a diagonal observable that is a sum of one-qudit terms,
  * <O> = sum_x |psi_x|^2 sum_t term_diag[t][x_{term_qudit[t]}]
  * (e.g. Z_0 with Z = diag(w^k), or sum_i Z_i).  term_qudit: host, nterms

@@ -70,6 +70,7 @@ _SIGS = {
     "qf_apply_swap": [_PS, _I32, _I32, _P],
     "qf_apply_mcx": [_PS, _I32, _PI32, _I32, _P],
     "qf_probs": [_PS, _I32, _PI32, _P, _P],
+    "qf_sample": [_PS, _I32, _PI32, ctypes.c_int64, _P, _P, _P, _P],
     "qf_expect": [_PS, _I32, _PI32, _PD, _PD, _P],
     "qf_expect_noalloc": [_PS, _I32, _PI32, _PD, _PD, _P],
     "qf_plan_create": [_I32, _I32, _I32, ctypes.POINTER(qf_op), _I32, _I32, ctypes.POINTER(qf_plan_opts),
@@ -240,6 +241,28 @@ def qf_probs(t, n: int, dim: int, qudits: Optional[Sequence[int]] = None, out=No
         qa, qp = _i32(qudits)
         _check(lib.qf_probs(ctypes.byref(s), m, qp, ctypes.c_void_p(out.data_ptr()), _stream(stream)))
     return out
+
+
+def qf_sample(t, n: int, dim: int, shots: int, u, qudits: Optional[Sequence[int]] = None, samples: bool = False,
+              stream=None):
+    """Histogram of shots draws per register (of the listed qudits' marginal,
+    or of the full register), drawn by the caller's uniforms u (a float64
+    device tensor of batch * shots values in [0, 1)).  Returns the int64 counts
+    (batch * outcomes) and, with samples=True, the int32 outcome of every draw."""
+    torch = _torch()
+    s = state_of(t, n, dim)
+    m = 0 if qudits is None else len(qudits)
+    outcomes = dim ** (n if m == 0 else m)
+    if shots > 0 and (u is None or not u.is_cuda or u.dtype != torch.float64 or not u.is_contiguous()
+                      or u.numel() != s.batch * shots):
+        raise QfError(QF_EINVAL, "u must be a contiguous float64 device tensor of batch * shots values")
+    counts = torch.empty(s.batch * outcomes, dtype=torch.int64, device=t.device)
+    draws = torch.empty(s.batch * shots, dtype=torch.int32, device=t.device) if samples else None
+    qa, qp = _i32(qudits) if qudits is not None else (None, None)
+    _check(lib.qf_sample(ctypes.byref(s), m, qp, int(shots), ctypes.c_void_p(u.data_ptr() if shots > 0 else 0),
+                         ctypes.c_void_p(counts.data_ptr()),
+                         ctypes.c_void_p(draws.data_ptr() if samples and shots > 0 else 0), _stream(stream)))
+    return (counts, draws) if samples else counts
 
 
 def _terms_arrays(dim: int, terms) -> tuple:

@@ -314,7 +314,7 @@ qf_status qf_probs(const qf_state* s, int32_t m, const int32_t* qudits, void* ou
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (m == 0) {
         QF_RETURN_IF(qudits != nullptr, QF_EINVAL, "m = 0 requires qudits = NULL");
-        return launch_probs_full(v, out, st);
+        return launch_probs_full(v, out, false, st);
     }
     QF_RETURN_IF(m < 0 || uint32_t(m) > v.n || m > 32, QF_EINVAL, "m = %d outside [0, min(n, 32)]", m);
     QF_RETURN_IF(qudits == nullptr, QF_EINVAL, "qudits is NULL");
@@ -325,8 +325,37 @@ qf_status qf_probs(const qf_state* s, int32_t m, const int32_t* qudits, void* ou
             QF_RETURN_IF(qudits[i] == qudits[j], QF_EINVAL, "qudit %d listed twice", qudits[i]);
         identity = identity && qudits[i] == i;
     }
-    if (identity) return launch_probs_full(v, out, st);
-    return launch_probs_marginal(v, m, qudits, out, st);
+    if (identity) return launch_probs_full(v, out, false, st);
+    return launch_probs_marginal(v, m, qudits, out, false, st);
+}
+
+qf_status qf_sample(const qf_state* s, int32_t m, const int32_t* qudits, int64_t shots, const double* u,
+                    int64_t* counts, int32_t* samples, void* stream) {
+    StateView v;
+    QF_CHECK(make_view(s, v));
+    QF_RETURN_IF(counts == nullptr, QF_EINVAL, "counts is NULL");
+    QF_RETURN_IF(shots < 0, QF_EINVAL, "shots = %lld < 0", (long long)shots);
+    QF_RETURN_IF(shots > 0 && u == nullptr, QF_EINVAL, "u is NULL");
+    QF_RETURN_IF(uint64_t(shots) * v.batch >= (1ull << 32), QF_ERANGE, "batch * shots >= 2^32");
+    if (m == 0) {
+        QF_RETURN_IF(qudits != nullptr, QF_EINVAL, "m = 0 requires qudits = NULL");
+    } else {
+        QF_RETURN_IF(m < 0 || uint32_t(m) > v.n || m > 32, QF_EINVAL, "m = %d outside [0, min(n, 32)]", m);
+        QF_RETURN_IF(qudits == nullptr, QF_EINVAL, "qudits is NULL");
+        bool identity = uint32_t(m) == v.n;
+        for (int i = 0; i < m; ++i) {
+            QF_CHECK(check_qudit(v, qudits[i], "measured"));
+            for (int j = 0; j < i; ++j)
+                QF_RETURN_IF(qudits[i] == qudits[j], QF_EINVAL, "qudit %d listed twice", qudits[i]);
+            identity = identity && qudits[i] == i;
+        }
+        if (identity) m = 0;
+    }
+    const uint64_t K = m == 0 ? uint64_t(v.N) : uint64_t(ipow(v.D, uint32_t(m)));
+    QF_RETURN_IF(samples != nullptr && K > (1ull << 31), QF_ERANGE, "%llu outcomes do not fit int32 samples",
+                 (unsigned long long)K);
+    return launch_sample(v, m, m == 0 ? nullptr : qudits, uint64_t(shots), u, counts, samples,
+                         reinterpret_cast<hipStream_t>(stream));
 }
 
 qf_status qf_expect(const qf_state* s, int32_t nterms, const int32_t* term_qudit, const double* term_diag,

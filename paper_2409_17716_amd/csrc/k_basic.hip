@@ -292,12 +292,13 @@ __global__ __launch_bounds__(kBlock) void k_diag(cplx<T>* __restrict__ psi, uint
 // Probabilities.
 // ---------------------------------------------------------------------------
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_probs_full(const cplx<T>* __restrict__ psi, T* __restrict__ out,
+// O = T (the state's precision) or double (squares taken in FP64).
+template <typename T, typename O>
+__global__ __launch_bounds__(kBlock) void k_probs_full(const cplx<T>* __restrict__ psi, O* __restrict__ out,
                                                        uint32_t total) {
     for (uint32_t x = blockIdx.x * kBlock + threadIdx.x; x < total; x += gridDim.x * kBlock) {
         const cplx<T> v = psi[x];
-        out[x] = v.re * v.re + v.im * v.im;
+        out[x] = O(v.re) * O(v.re) + O(v.im) * O(v.im);
     }
 }
 
@@ -370,15 +371,15 @@ __global__ __launch_bounds__(kBlock) void k_marg_partial(const cplx<T>* __restri
 }
 
 // One workgroup per bin: lanes sum chunks c = lane, lane + 256, ..., then a fixed tree.
-template <typename T>
+template <typename O>
 __global__ __launch_bounds__(kBlock) void k_marg_final(const double* __restrict__ partial, uint32_t chunks,
-                                                       T* __restrict__ out) {
+                                                       O* __restrict__ out) {
     __shared__ double sh[kBlock];
     const uint32_t i = blockIdx.x;
     double s = 0.0;
     for (uint32_t c = threadIdx.x; c < chunks; c += kBlock) s += partial[size_t(i) * chunks + c];
     s = block_sum(s, sh);
-    if (threadIdx.x == 0) out[i] = T(s);
+    if (threadIdx.x == 0) out[i] = O(s);
 }
 
 // ---------------------------------------------------------------------------
@@ -590,16 +591,22 @@ qf_status launch_diag(const StateView& s, int k, const int32_t* qudits, const do
     });
 }
 
-qf_status launch_probs_full(const StateView& s, void* out, hipStream_t st) {
+qf_status launch_probs_full(const StateView& s, void* out, bool f64, hipStream_t st) {
     return with_type(s.dtype, [&](auto tag) -> qf_status {
         using T = decltype(tag);
-        hipLaunchKernelGGL(k_probs_full<T>, dim3(grid_for(s.total, kBlock * 4)), dim3(kBlock), 0, st,
-                           reinterpret_cast<const cplx<T>*>(s.amps), reinterpret_cast<T*>(out), s.total);
+        const dim3 g(grid_for(s.total, kBlock * 4));
+        const auto* psi = reinterpret_cast<const cplx<T>*>(s.amps);
+        if (f64)
+            hipLaunchKernelGGL((k_probs_full<T, double>), g, dim3(kBlock), 0, st, psi,
+                               reinterpret_cast<double*>(out), s.total);
+        else
+            hipLaunchKernelGGL((k_probs_full<T, T>), g, dim3(kBlock), 0, st, psi, reinterpret_cast<T*>(out),
+                               s.total);
         return check_launch("qf_probs");
     });
 }
 
-qf_status launch_probs_marginal(const StateView& s, int m, const int32_t* qudits, void* out,
+qf_status launch_probs_marginal(const StateView& s, int m, const int32_t* qudits, void* out, bool f64,
                                 hipStream_t st) {
     MargArg a{};
     a.N = s.N;
@@ -635,8 +642,12 @@ qf_status launch_probs_marginal(const StateView& s, int m, const int32_t* qudits
                            reinterpret_cast<const cplx<T>*>(s.amps), a, partial);
         qf_status r1 = check_launch("qf_probs marginal");
         const uint32_t nb = a.bins * s.batch;
-        hipLaunchKernelGGL(k_marg_final<T>, dim3(nb), dim3(kBlock), 0, st, partial, a.chunks,
-                           reinterpret_cast<T*>(out));
+        if (f64)
+            hipLaunchKernelGGL(k_marg_final<double>, dim3(nb), dim3(kBlock), 0, st, partial, a.chunks,
+                               reinterpret_cast<double*>(out));
+        else
+            hipLaunchKernelGGL(k_marg_final<T>, dim3(nb), dim3(kBlock), 0, st, partial, a.chunks,
+                               reinterpret_cast<T*>(out));
         qf_status r2 = check_launch("qf_probs marginal final");
         QF_HIP_CHECK(hipFreeAsync(partial, st));
         return r1 != QF_OK ? r1 : r2;

@@ -1,0 +1,172 @@
+// Measurement shots (the histogram of the paper's measure(..., shots),
+// section "Code style") by inversion of the cumulative distribution:
+//   1. probabilities of the measured qudits in FP64 (full register or marginal),
+//   2. an inclusive prefix sum per register in FP64, in a fixed order
+//      (segmented block scans, recursively over the block totals),
+//   3. one lane per shot: the first bin whose cumulative sum exceeds
+//      u * total (a draw whose product rounds up to the total goes to the
+//      last bin of non-zero probability), counted with integer atomics
+//      (an exact, order-independent histogram).
+// The uniforms u are inputs: the caller draws them.
+#include "qf_internal.h"
+
+namespace qf {
+namespace {
+
+constexpr int kT = 256;         // threads per scan block
+constexpr int kPer = 4;         // elements per thread
+constexpr int kSpan = kT * kPer;  // elements per scan block
+
+// Inclusive scan of segments of length seg (a segment never shares a block with
+// another): block blk covers elements [s * seg + lb * kSpan, ...) of segment
+// s = blk / bps, lb = blk % bps.  Each thread sums its kPer elements in order,
+// the thread totals are scanned in LDS by doubling steps, and the block total
+// goes to sums[blk] (sums are laid out as [segment][bps]).
+__global__ __launch_bounds__(kT) void k_scan_block(double* __restrict__ data, uint64_t seg, uint32_t bps,
+                                                   double* __restrict__ sums) {
+    __shared__ double sh[kT];
+    const uint32_t blk = blockIdx.x;
+    const uint32_t s = blk / bps, lb = blk - s * bps;
+    const uint64_t lo = uint64_t(lb) * kSpan;
+    const uint64_t n = seg - lo < uint64_t(kSpan) ? seg - lo : uint64_t(kSpan);
+    double* d = data + s * seg + lo;
+    double v[kPer];
+    double run = 0.0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        const uint64_t e = uint64_t(threadIdx.x) * kPer + i;
+        run += e < n ? d[e] : 0.0;
+        v[i] = run;
+    }
+    sh[threadIdx.x] = run;
+    __syncthreads();
+    for (int off = 1; off < kT; off <<= 1) {
+        const double add = threadIdx.x >= uint32_t(off) ? sh[threadIdx.x - off] : 0.0;
+        __syncthreads();
+        sh[threadIdx.x] += add;
+        __syncthreads();
+    }
+    const double before = threadIdx.x > 0 ? sh[threadIdx.x - 1] : 0.0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        const uint64_t e = uint64_t(threadIdx.x) * kPer + i;
+        if (e < n) d[e] = before + v[i];
+    }
+    if (threadIdx.x == kT - 1) sums[blk] = sh[kT - 1];
+}
+
+// data[s * seg + lb * kSpan + e] += (scanned block totals)[s][lb - 1] for lb >= 1.
+__global__ __launch_bounds__(kT) void k_scan_add(double* __restrict__ data, uint64_t seg, uint32_t bps,
+                                                 const double* __restrict__ sums) {
+    const uint32_t blk = blockIdx.x;
+    const uint32_t s = blk / bps, lb = blk - s * bps;
+    if (lb == 0) return;
+    const uint64_t lo = uint64_t(lb) * kSpan;
+    const uint64_t n = seg - lo < uint64_t(kSpan) ? seg - lo : uint64_t(kSpan);
+    const double off = sums[uint64_t(s) * bps + lb - 1];
+    double* d = data + s * seg + lo;
+    for (uint64_t e = threadIdx.x; e < n; e += kT) d[e] += off;
+}
+
+__global__ __launch_bounds__(kT) void k_fill_u64(unsigned long long* __restrict__ p, uint64_t n) {
+    for (uint64_t i = uint64_t(blockIdx.x) * kT + threadIdx.x; i < n; i += uint64_t(gridDim.x) * kT) p[i] = 0ull;
+}
+
+// First index of c[0..K) with c[idx] > x, or K if none.
+__device__ inline uint32_t upper_bound(const double* c, uint32_t K, double x) {
+    uint32_t lo = 0, hi = K;
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (c[mid] > x) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+// First index of c[0..K) with c[idx] >= x.
+__device__ inline uint32_t lower_bound(const double* c, uint32_t K, double x) {
+    uint32_t lo = 0, hi = K;
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (c[mid] >= x) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kT) void k_sample(const double* __restrict__ cdf, uint32_t K, uint64_t shots,
+                                               uint64_t total, const double* __restrict__ u,
+                                               unsigned long long* __restrict__ counts,
+                                               int32_t* __restrict__ samples) {
+    for (uint64_t i = uint64_t(blockIdx.x) * kT + threadIdx.x; i < total; i += uint64_t(gridDim.x) * kT) {
+        const uint64_t b = i / shots;
+        const double* c = cdf + b * K;
+        const double sum = c[K - 1];
+        uint32_t idx = upper_bound(c, K, u[i] * sum);
+        if (idx >= K) idx = lower_bound(c, K, sum);
+        atomicAdd(counts + b * K + idx, 1ull);
+        if (samples) samples[i] = int32_t(idx);
+    }
+}
+
+uint32_t grid_of(uint64_t n) {
+    const uint64_t g = (n + kT - 1) / kT;
+    return uint32_t(g < 1 ? 1 : g > (1u << 20) ? (1u << 20) : g);
+}
+
+// In-place inclusive scan of nseg segments of length seg; ws holds the block
+// totals of every level.
+qf_status scan_segments(double* data, uint64_t seg, uint64_t nseg, double* ws, hipStream_t st) {
+    const uint32_t bps = uint32_t((seg + kSpan - 1) / kSpan);
+    const uint64_t nblk = nseg * bps;
+    if (nblk >= (1ull << 31)) return set_error(QF_ERANGE, "prefix sum grid too large");
+    hipLaunchKernelGGL(k_scan_block, dim3(uint32_t(nblk)), dim3(kT), 0, st, data, seg, bps, ws);
+    QF_CHECK(check_launch("prefix sum"));
+    if (bps > 1) {
+        QF_CHECK(scan_segments(ws, bps, nseg, ws + nblk, st));
+        hipLaunchKernelGGL(k_scan_add, dim3(uint32_t(nblk)), dim3(kT), 0, st, data, seg, bps, ws);
+        QF_CHECK(check_launch("prefix sum add"));
+    }
+    return QF_OK;
+}
+
+// Doubles of block totals all levels of scan_segments need.
+uint64_t scan_ws_doubles(uint64_t seg, uint64_t nseg) {
+    uint64_t total = 0;
+    while (true) {
+        const uint64_t bps = (seg + kSpan - 1) / kSpan;
+        total += bps * nseg;
+        if (bps <= 1) break;
+        seg = bps;
+    }
+    return total;
+}
+
+}  // namespace
+
+qf_status launch_sample(const StateView& s, int m, const int32_t* qudits, uint64_t shots, const double* u,
+                        int64_t* counts, int32_t* samples, hipStream_t st) {
+    const uint64_t K = m == 0 ? uint64_t(s.N) : uint64_t(ipow(s.D, uint32_t(m)));
+    const uint64_t bins = K * s.batch;
+    const uint64_t draws = shots * s.batch;
+    QF_RETURN_IF(bins >= (1ull << 32) || draws >= (1ull << 32), QF_ERANGE, "batch * bins or batch * shots >= 2^32");
+    const uint64_t wsd = scan_ws_doubles(K, s.batch);
+    double* cdf = nullptr;
+    QF_CHECK(dev_malloc_async(reinterpret_cast<void**>(&cdf), (bins + wsd) * sizeof(double), st, "sampling"));
+    qf_status rs = m == 0 ? launch_probs_full(s, cdf, true, st) : launch_probs_marginal(s, m, qudits, cdf, true, st);
+    if (rs == QF_OK) rs = scan_segments(cdf, K, s.batch, cdf + bins, st);
+    if (rs == QF_OK) {
+        hipLaunchKernelGGL(k_fill_u64, dim3(grid_of(bins)), dim3(kT), 0, st,
+                           reinterpret_cast<unsigned long long*>(counts), bins);
+        rs = check_launch("histogram clear");
+    }
+    if (rs == QF_OK && draws > 0) {
+        hipLaunchKernelGGL(k_sample, dim3(grid_of(draws)), dim3(kT), 0, st, cdf, uint32_t(K), shots, draws, u,
+                           reinterpret_cast<unsigned long long*>(counts), samples);
+        rs = check_launch("sampling");
+    }
+    (void)hipFreeAsync(cdf, st);
+    return rs;
+}
+
+}  // namespace qf

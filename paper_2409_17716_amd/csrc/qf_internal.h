@@ -38,9 +38,16 @@ qf_status launch_diag(const StateView& s, int k, const int32_t* qudits, const do
 qf_status launch_mcx(const StateView& s, int nctrl, const int32_t* ctrls, int tgt, bool inverse, hipStream_t st);
 // Exchange the digits of qudits a and b (a != b).
 qf_status launch_swap(const StateView& s, int a, int b, hipStream_t st);
-qf_status launch_probs_full(const StateView& s, void* out, hipStream_t st);
-qf_status launch_probs_marginal(const StateView& s, int m, const int32_t* qudits, void* out,
+// Probabilities in the state's precision, or in FP64 when f64 is set.
+qf_status launch_probs_full(const StateView& s, void* out, bool f64, hipStream_t st);
+qf_status launch_probs_marginal(const StateView& s, int m, const int32_t* qudits, void* out, bool f64,
                                 hipStream_t st);
+// Measurement shots (k_sample.hip): m = 0 samples the full register, else the
+// marginal of the m listed qudits; u holds batch * shots uniforms in [0, 1),
+// counts batch * D^m (or D^n) bins, samples (NULL or batch * shots) the drawn
+// bin of each shot.
+qf_status launch_sample(const StateView& s, int m, const int32_t* qudits, uint64_t shots, const double* u,
+                        int64_t* counts, int32_t* samples, hipStream_t st);
 // table: per active qudit D complex values (combined terms), active: qudit list
 qf_status launch_expect(const StateView& s, const std::vector<int>& active,
                         const std::vector<double>& table, double* out, hipStream_t st);

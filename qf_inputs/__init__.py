@@ -218,6 +218,22 @@ def random_state(D: int, n: int, seed: int, batch: int = 1) -> np.ndarray:
     return v.reshape(-1) if batch == 1 else v
 
 
+def uniforms(count: int, seed: int) -> np.ndarray:
+    """count seeded uniforms in [0, 1) (float64): the draws of measurement shots."""
+    return np.random.default_rng(seed).random(count)
+
+
+def sparse_state(D: int, n: int, seed: int, keep: float = 0.1) -> np.ndarray:
+    """A normalised random state with most amplitudes exactly zero (about a
+    fraction keep non-zero), so distributions have runs of empty bins."""
+    rng = np.random.default_rng(seed)
+    N = D ** n
+    v = (rng.standard_normal(N) + 1j * rng.standard_normal(N)) * (rng.random(N) < keep)
+    if not np.any(v):
+        v[int(rng.integers(N))] = 1.0
+    return v / np.linalg.norm(v)
+
+
 def random_unitary(m: int, seed: int | np.random.Generator) -> np.ndarray:
     """Haar-random m x m unitary: QR of a complex Gaussian with the phases of
     R's diagonal moved into Q."""

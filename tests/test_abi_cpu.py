@@ -217,3 +217,22 @@ def test_swap_mcx_rot_validation(qf):
             qf.Plan(3, 3, bad, 0)
     p = qf.Plan(3, 4, [("swap", 0, 3), ("mcx", (0, 1, 2), 3), ("h", 2)], 0)
     assert p.num_stages >= 2
+
+
+def test_sample_validation(qf):
+    f = qf.lib.qf_sample
+    s = _fake_state(qf)  # D = 3, n = 3
+    u, cnt, smp = ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000)
+    assert f(ctypes.byref(s), 0, None, 10, u, None, None, None) == qf.QF_EINVAL  # counts NULL
+    assert f(ctypes.byref(s), 0, None, -1, u, cnt, None, None) == qf.QF_EINVAL
+    assert f(ctypes.byref(s), 0, None, 10, None, cnt, None, None) == qf.QF_EINVAL  # u NULL
+    q = (ctypes.c_int32 * 2)(1, 1)
+    assert f(ctypes.byref(s), 0, q, 10, u, cnt, None, None) == qf.QF_EINVAL
+    assert f(ctypes.byref(s), 2, q, 10, u, cnt, None, None) == qf.QF_EINVAL  # listed twice
+    q3 = (ctypes.c_int32 * 1)(3)
+    assert f(ctypes.byref(s), 1, q3, 10, u, cnt, None, None) == qf.QF_EINVAL
+    assert f(ctypes.byref(s), 4, q, 10, u, cnt, None, None) == qf.QF_EINVAL  # m > n
+    big = qf.qf_state(0x1000, 20, 3, 1, 0)  # 3^20 outcomes > 2^31: no int32 samples
+    assert f(ctypes.byref(big), 0, None, 10, u, cnt, smp, None) == qf.QF_ERANGE
+    two = qf.qf_state(0x1000, 3, 3, 2, 0)
+    assert f(ctypes.byref(two), 0, None, 1 << 31, u, cnt, None, None) == qf.QF_ERANGE  # batch * shots
