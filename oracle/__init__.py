@@ -21,8 +21,11 @@ definitions directly (Appendix "Matrix form of the quantum gates"):
 * ``brute``   - full D^n x D^n circuit unitaries for tiny n, built from the
                 paper's sparse digit rules and Kronecker products, as an
                 independent second route.
+* ``mixed``   - registers of per-qudit dimensions (mixed radix): gates,
+                measurement and the adjoint gradient, with the readings of the
+                two-qudit gates across dimensions stated in its header.
 
 Parity status of each function is recorded in its docstring; every function
-is pinned (``tests/test_oracle_pins.py``).
+is pinned (``tests/test_oracle_pins.py``, ``tests/test_oracle_mixed.py``).
 """
-from . import gates, sim, measure, grad, brute  # noqa: F401
+from . import gates, sim, measure, grad, brute, mixed  # noqa: F401

@@ -315,6 +315,112 @@ def cr_ansatz(D: int, n: int, layers: int, seed: int) -> Circuit:
     return Circuit(D, n, ops, rng.uniform(-np.pi, np.pi, size=p), f"cr_ansatz_d{D}_n{n}_l{layers}")
 
 
+@dataclass
+class MixedCircuit:
+    """A circuit on qudits of different dimensions dims[q] (qudit 0 most
+    significant).  Descriptors as above, every level and shift taken in the
+    dimension of the qudit it acts on."""
+    dims: List[int]
+    ops: List[Op]
+    theta: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    name: str = ""
+
+    @property
+    def n(self) -> int:
+        return len(self.dims)
+
+    @property
+    def nparams(self) -> int:
+        return int(len(self.theta))
+
+    @property
+    def amps(self) -> int:
+        return int(np.prod(self.dims))
+
+
+def paper_mixed_example() -> dict:
+    """The example circuit of section "Code style": dims [2, 3, 4]; Fourier on
+    every qudit, R_x(pi/2) on qudit 0 (levels 0, 1), CNOT (CSUM) from qudit 0 to
+    qudit 2; initial state |0, 1, 3>; measure qudits [0, 1] with 1000 shots."""
+    ops = [("h", 0), ("h", 1), ("h", 2), ("rx", 0, 0, 1, 0), ("csum", 0, 2)]
+    return {"circuit": MixedCircuit([2, 3, 4], ops, np.array([np.pi / 2]), "paper_mixed_example"),
+            "digits": (0, 1, 3), "measured": [0, 1], "shots": 1000}
+
+
+def random_mixed_circuit(dims: Sequence[int], depth: int, seed: int, kinds=None) -> MixedCircuit:
+    """A random mix of gate kinds on a register of per-qudit dimensions."""
+    rng = np.random.default_rng(seed)
+    dims = [int(d) for d in dims]
+    n = len(dims)
+    kinds = kinds or ["h", "x", "clock", "rx", "ry", "rz", "csum", "cz", "cshift", "u1", "u2", "crx", "cry", "crz",
+                      "swap", "mcx"]
+    ops: List[Op] = []
+    thetas: List[float] = []
+    for _ in range(depth):
+        kind = kinds[rng.integers(len(kinds))]
+        q = int(rng.integers(n))
+        d = dims[q]
+        if kind == "h":
+            ops.append(("h", q))
+        elif kind == "x":
+            ops.append(("x", q, int(rng.integers(1, d))))
+        elif kind == "clock":
+            ops.append(("clock", q, int(rng.integers(1, d))))
+        elif kind in ("rx", "ry"):
+            j, k = sorted(rng.choice(d, size=2, replace=False).tolist())
+            ops.append((kind, q, int(j), int(k), len(thetas)))
+            thetas.append(float(rng.uniform(-np.pi, np.pi)))
+        elif kind == "rz":
+            ops.append(("rz", q, int(rng.integers(1, d)), len(thetas)))
+            thetas.append(float(rng.uniform(-np.pi, np.pi)))
+        elif kind in ("csum", "cz", "cshift") and n >= 2:
+            c, t = rng.choice(n, size=2, replace=False).tolist()
+            if kind == "cshift":
+                ops.append(("cshift", int(c), int(t), tuple(int(v) for v in rng.integers(0, dims[t], size=dims[c]))))
+            else:
+                ops.append((kind, int(c), int(t)))
+        elif kind == "u1":
+            ops.append(("u", q, 1, random_unitary(d, rng)))
+        elif kind == "u2" and n >= 2:
+            q0 = int(rng.integers(n - 1))
+            ops.append(("u", q0, 2, random_unitary(dims[q0] * dims[q0 + 1], rng)))
+        elif kind in ("crx", "cry", "crz") and n >= 2:
+            c, t = rng.choice(n, size=2, replace=False).tolist()
+            if kind == "crz":
+                ops.append(("crz", int(c), int(t), int(rng.integers(1, dims[t])), len(thetas)))
+            else:
+                j, k = sorted(rng.choice(dims[t], size=2, replace=False).tolist())
+                ops.append((kind, int(c), int(t), int(j), int(k), len(thetas)))
+            thetas.append(float(rng.uniform(-np.pi, np.pi)))
+        elif kind == "swap":
+            pairs = [(a_, b_) for a_ in range(n) for b_ in range(n) if a_ != b_ and dims[a_] == dims[b_]]
+            if pairs:
+                a_, b_ = pairs[int(rng.integers(len(pairs)))]
+                ops.append(("swap", a_, b_))
+        elif kind == "mcx" and n >= 3:
+            nc = int(rng.integers(1, min(4, n)))
+            qs = rng.choice(n, size=nc + 1, replace=False).tolist()
+            ops.append(("mcx", tuple(int(v) for v in qs[:nc]), int(qs[nc])))
+    return MixedCircuit(dims, ops, np.asarray(thetas, dtype=np.float64), f"random_mixed_{dims}_s{seed}")
+
+
+def mixed_hea(dims: Sequence[int], layers: int, seed: int) -> MixedCircuit:
+    """Ansatz on a mixed register: per layer R_x, R_y on levels (0, 1) and R_z
+    (j = 1) of every qudit, then a CSUM ring; angles ~ U[-pi, pi]."""
+    rng = np.random.default_rng(seed)
+    dims = [int(d) for d in dims]
+    n = len(dims)
+    ops: List[Op] = []
+    p = 0
+    for _ in range(layers):
+        for t in ("x", "y", "z"):
+            for q in range(n):
+                ops.append(("rz", q, 1, p) if t == "z" else ("r" + t, q, 0, 1, p))
+                p += 1
+        ops.extend(csum_ring(n))
+    return MixedCircuit(dims, ops, rng.uniform(-np.pi, np.pi, size=p), f"mixed_hea_{dims}_l{layers}")
+
+
 def grover_d3_n2_marker22() -> dict:
     """Inputs of the qutrit Grover example: two qutrits, marked basis state |2,2>."""
     return {"dim": 3, "n": 2, "marker": (2, 2)}
