@@ -57,13 +57,29 @@ typedef enum {
 
 typedef enum { QF_C64 = 0, QF_C128 = 1 } qf_dtype;
 
-/* A register (or a batch of registers) in device memory. */
+/* A register (or a batch of registers) in device memory.
+ *
+ * Uniform registers (dims = NULL): every qudit has dim levels (D).  Mixed
+ * registers (the paper's multidimensional circuits, section "Related work",
+ * Table 1, and the dim=[2,3,4] example of section "Code style"): dims lists
+ * the levels d_q of every qudit (2..16) and dim must be 0; an array whose
+ * entries are all equal describes a uniform register.  In both the basis index
+ * is x = sum_q x_q S_q with S_q = d_{q+1} ... d_{n-1} (qudit 0 most
+ * significant).  Below, d_q is the dimension of qudit q (D for a uniform
+ * register) and "outcomes" / table sizes are the products of the d_q involved.
+ * Across dimensions the two-qudit gates act as: controlled shift / CSUM
+ * x_t -> (x_t + shift[x_c]) mod d_t; controlled phase w_{d_t}^(x_c x_t);
+ * controlled rotation over the d_c control levels in the target's dimension;
+ * multi-controlled shift x_t -> (x_t + prod x_c) mod d_t; SWAP only between
+ * qudits of equal dimension.  Plans on mixed registers run the per-gate
+ * schedules (qf_plan_create_dims). */
 typedef struct qf_state {
-    void*   amps;    /* device pointer, batch * dim^n complex elements              */
+    void*   amps;    /* device pointer, batch * prod(d_q) complex elements          */
     int32_t n;       /* qudits per register                                          */
-    int32_t dim;     /* levels per qudit (D)                                         */
+    int32_t dim;     /* levels per qudit (D); 0 when dims is set                    */
     int64_t batch;   /* registers stored back to back                                */
     int32_t dtype;   /* qf_dtype                                                     */
+    const int32_t* dims; /* host, n per-qudit dimensions, or NULL (uniform)          */
 } qf_state;
 
 /* ------------------------------------------------------------------------- */
@@ -71,14 +87,15 @@ typedef struct qf_state {
 /* ------------------------------------------------------------------------- */
 
 /* psi = |j_0 j_1 ... j_{n-1}> in every register (the paper's State('j0-j1-..'),
- * section "Code style").  digits: host, batch*n values in [0, dim) (register b
- * uses digits[b*n .. b*n+n-1]); NULL means |0...0> everywhere. */
+ * section "Code style").  digits: host, batch*n values, digit k in [0, d_k)
+ * (register b uses digits[b*n .. b*n+n-1]); NULL means |0...0> everywhere. */
 qf_status qf_state_init(const qf_state* s, const int32_t* digits, void* stream);
 
 /* One-qudit gate: psi[h, :, l] <- U psi[h, :, l] with the register viewed as
  * [D^q][D][D^(n-1-q)] (a D x D matrix acting on qudit q, identity elsewhere;
  * subsections "Fourier gate", "Generalized rotation gate", "Generalized
- * phase-shift gate").  U: host, D*D complex FP64, row-major (U[a*D+b] is
+ * phase-shift gate"); on a mixed register [S_q-blocks][d_q][S_q] with a
+ * d_q x d_q matrix.  U: host, d_q*d_q complex FP64, row-major (U[a*d_q+b] is
  * <a|U|b>).  q in [0, n).  The matrix need not be unitary. */
 qf_status qf_apply_1q(const qf_state* s, int32_t q, const double* U, void* stream);
 
@@ -86,26 +103,29 @@ qf_status qf_apply_1q(const qf_state* s, int32_t q, const double* U, void* strea
  * gate" and "Generalized CNOT gate"): |.. x_c .. x_t ..> ->
  * |.. x_c .. (x_t + shift[x_c]) mod D ..>.  The generalized CNOT (CSUM) is
  * shift[c] = c; the shift gate X_s is ctrl = -1 with shift[0] = s.
- * shift: host, D entries (only shift[0] is read when ctrl = -1), any integers
- * (reduced mod D).  ctrl != tgt, both in [0, n) (ctrl may be -1).
+ * shift: host, d_ctrl entries (only shift[0] is read when ctrl = -1), any
+ * integers (reduced mod d_tgt).  ctrl != tgt, both in [0, n) (ctrl may be -1).
  * Bit-exact: amplitudes are moved, never recomputed. */
 qf_status qf_apply_ctrl(const qf_state* s, int32_t ctrl, int32_t tgt,
                         const int32_t* shift, void* stream);
 
 /* Diagonal gate on k qudits: psi_x <- phases[y] psi_x with
- * y = sum_i x_{qudits[i]} D^(k-1-i).  Covers the phase-shift (clock) gate and
+ * y = sum_i x_{qudits[i]} D^(k-1-i) (mixed: the mixed-radix number of those
+ * digits over their dimensions, first listed most significant).  Covers the
+ * phase-shift (clock) gate and
  * its powers (subsection "Generalized phase-shift gate"), R_z (subsection
  * "Generalized rotation gate", diagonal generator) and a controlled phase
  * w^(x_c x_t) built from the same phase rule.
- * qudits: host, k distinct indices in [0, n); phases: host, D^k complex FP64.
- * Limit: D^k <= 256 (complex64) or 128 (complex128). */
+ * qudits: host, k distinct indices in [0, n); phases: host, D^k (prod of the
+ * listed d_q) complex FP64.  Limit: D^k <= 256 (complex64) or 128 (complex128). */
 qf_status qf_apply_diag(const qf_state* s, int32_t k, const int32_t* qudits,
                         const double* phases, void* stream);
 
 /* The paper's differentiable controlled rotation (Appendix, subsection
  * "Controlled Rotation Gate"): sum_m |m><m|_ctrl (x) R(m theta)_tgt with
  * R = exp(-i theta S / 2) and S = S_x^{jk} (kind QF_OP_CRX), S_y^{jk}
- * (QF_OP_CRY, j < k) or the diagonal S_z^{j} (QF_OP_CRZ, 1 <= j < D, k ignored).
+ * (QF_OP_CRY, j < k) or the diagonal S_z^{j} (QF_OP_CRZ, 1 <= j < D, k ignored);
+ * m runs over the control's d_ctrl levels, the levels over the target's d_tgt.
  * ctrl != tgt, both in [0, n); theta in radians.  The x and y types read and
  * write only target levels j and k; the control's level-0 slab is untouched. */
 qf_status qf_apply_crot(const qf_state* s, int32_t kind, int32_t ctrl, int32_t tgt,
@@ -121,12 +141,12 @@ qf_status qf_apply_rot(const qf_state* s, int32_t kind, int32_t q, int32_t j, in
 
 /* SWAP of qudits a and b (subsection "Generalized SWAP Gate"): the digits of
  * a and b are exchanged, |.. x_a .. x_b ..> -> |.. x_b .. x_a ..>.  a != b, both
- * in [0, n).  Bit-exact: amplitudes are moved, never recomputed. */
+ * in [0, n), d_a = d_b.  Bit-exact: amplitudes are moved, never recomputed. */
 qf_status qf_apply_swap(const qf_state* s, int32_t a, int32_t b, void* stream);
 
 /* Multi-controlled shift (the Toffoli and multi-controlled NOT gates the paper
  * names in section "Quantum Gates", generalized like its CNOT index rule):
- * |.. x_t ..> -> |.. (x_t + prod_i x_{ctrls[i]}) mod D ..>.  For qubits this is
+ * |.. x_t ..> -> |.. (x_t + prod_i x_{ctrls[i]}) mod d_t ..>.  For qubits this is
  * the Toffoli (2 controls) / multi-controlled NOT; with one control it is CSUM.
  * ctrls: host, nctrl (1..8) distinct qudits, none equal to tgt.  Bit-exact. */
 qf_status qf_apply_mcx(const qf_state* s, int32_t nctrl, const int32_t* ctrls, int32_t tgt,
@@ -134,7 +154,8 @@ qf_status qf_apply_mcx(const qf_state* s, int32_t nctrl, const int32_t* ctrls, i
 
 /* Custom dense gate on the k adjacent qudits q0..q0+k-1 (the paper's
  * U(matrix, index), section "Grover's algorithm"): psi[h, :, l] <- B psi[h, :, l]
- * with the register viewed as [D^q0][D^k][D^(n-q0-k)].
+ * with the register viewed as [D^q0][D^k][D^(n-q0-k)] (mixed: K = d_q0 ... d_{q0+k-1}
+ * in place of D^k).
  * B: DEVICE pointer, D^k x D^k row-major in the state's precision (complex64
  * or complex128), caller-owned, read during the kernel.  complex64 blocks with
  * D^k >= 32 run on FP32 matrix cores; others on vector ALUs.  D^k <= 1024. */
@@ -144,8 +165,9 @@ qf_status qf_apply_fused(const qf_state* s, int32_t k, int32_t q0, const void* B
 /* Measurement probabilities (section "Code style": measure returns p).
  * m = 0 and qudits = NULL: full distribution p_x = |psi_x|^2, out holds
  * batch*D^n reals.  Otherwise the marginal of the listed qudits in the listed
- * order, p(y) = sum_{x : x_qudits = y} |psi_x|^2 with y = sum_i y_i D^(m-1-i);
- * out holds batch*D^m reals.  out: DEVICE, float for complex64 states, double
+ * order, p(y) = sum_{x : x_qudits = y} |psi_x|^2 with y = sum_i y_i D^(m-1-i)
+ * (mixed: the mixed-radix number of the y_i over the listed qudits' dimensions);
+ * out holds batch*D^m reals (batch * prod of the listed d_q).  out: DEVICE, float for complex64 states, double
  * for complex128.  Marginals accumulate in FP64 in a fixed order (bitwise
  * reproducible run to run). */
 qf_status qf_probs(const qf_state* s, int32_t m, const int32_t* qudits, void* out,
@@ -175,9 +197,10 @@ qf_status qf_sample(const qf_state* s, int32_t m, const int32_t* qudits, int64_t
 /* Expectation of a diagonal observable that is a sum of one-qudit terms,
  * <O> = sum_x |psi_x|^2 sum_t term_diag[t][x_{term_qudit[t]}]
  * (e.g. Z_0 with Z = diag(w^k), or sum_i Z_i).  term_qudit: host, nterms
- * indices in [0, n); term_diag: host, nterms*D complex FP64.
+ * indices in [0, n); term_diag: host, nterms*D complex FP64 (mixed: the terms'
+ * tables back to back, d_q values for a term on qudit q).
  * out: DEVICE, batch complex128 values (2 doubles each), accumulated in FP64
- * in a fixed order.  Limit: nterms*D <= 128. */
+ * in a fixed order.  Limit: the distinct qudits' tables hold <= 128 values. */
 qf_status qf_expect(const qf_state* s, int32_t nterms, const int32_t* term_qudit,
                     const double* term_diag, double* out, void* stream);
 
@@ -267,6 +290,19 @@ typedef struct qf_plan_opts {
 qf_status qf_plan_create(int32_t dim, int32_t n, int32_t dtype, const qf_op* ops,
                          int32_t nops, int32_t nparams, const qf_plan_opts* opts,
                          qf_plan** out);
+
+/* qf_plan_create for a register of per-qudit dimensions dims[0..n-1] (each
+ * 2..16; host, read during the call).  Levels, shifts, exponents and U blocks
+ * of every op are taken in the dimensions of the qudits they act on (a U on
+ * q0..q0+k-1 is (d_q0 ... d_{q0+k-1})^2 entries; a CSHIFT table has d_c
+ * entries; SWAP needs equal dimensions).  Equal entries give the uniform plan
+ * of qf_plan_create.  Mixed dimensions run the per-gate schedules: opts.fuse
+ * 1 or 2 (0 selects 2); fuse 3, checkpoints, qf_plan_bind and
+ * qf_plan_autotune return QF_EUNSUPPORTED.  States used with the plan must
+ * carry the same dims. */
+qf_status qf_plan_create_dims(const int32_t* dims, int32_t n, int32_t dtype, const qf_op* ops,
+                              int32_t nops, int32_t nparams, const qf_plan_opts* opts,
+                              qf_plan** out);
 
 /* Number of kernel passes over the state in the plan's forward schedule. */
 int32_t qf_plan_num_stages(const qf_plan* plan);

@@ -32,7 +32,7 @@ class QfError(RuntimeError):
 
 class qf_state(ctypes.Structure):
     _fields_ = [("amps", ctypes.c_void_p), ("n", ctypes.c_int32), ("dim", ctypes.c_int32),
-                ("batch", ctypes.c_int64), ("dtype", ctypes.c_int32)]
+                ("batch", ctypes.c_int64), ("dtype", ctypes.c_int32), ("dims", ctypes.POINTER(ctypes.c_int32))]
 
 
 class qf_op(ctypes.Structure):
@@ -75,6 +75,8 @@ _SIGS = {
     "qf_expect_noalloc": [_PS, _I32, _PI32, _PD, _PD, _P],
     "qf_plan_create": [_I32, _I32, _I32, ctypes.POINTER(qf_op), _I32, _I32, ctypes.POINTER(qf_plan_opts),
                        ctypes.POINTER(ctypes.c_void_p)],
+    "qf_plan_create_dims": [_PI32, _I32, _I32, ctypes.POINTER(qf_op), _I32, _I32, ctypes.POINTER(qf_plan_opts),
+                            ctypes.POINTER(ctypes.c_void_p)],
     "qf_plan_forward": [_P, _PS, _PD, _P],
     "qf_adjoint_grad": [_P, _PS, _PS, _PD, _I32, _PI32, _PD, _PD, ctypes.c_uint32, _P],
     "qf_plan_set_profiling": [_P, _I32],
@@ -141,8 +143,22 @@ def _c128(a) -> tuple:
     return a, a.ctypes.data_as(_PD)
 
 
-def state_of(t, n: int, dim: int, batch: Optional[int] = None) -> qf_state:
-    """qf_state describing a torch complex64/complex128 CUDA tensor of batch*dim^n amplitudes."""
+def _size(n: int, dim) -> int:
+    """Amplitudes of one register: dim^n, or the product of a list of per-qudit dimensions."""
+    if isinstance(dim, (int, np.integer)):
+        return int(dim) ** n
+    if len(dim) != n:
+        raise QfError(QF_EINVAL, f"{len(dim)} dimensions for {n} qudits")
+    return int(np.prod([int(d) for d in dim]))
+
+
+def _dim_of(dim, q: int) -> int:
+    return int(dim) if isinstance(dim, (int, np.integer)) else int(dim[q])
+
+
+def state_of(t, n: int, dim, batch: Optional[int] = None) -> qf_state:
+    """qf_state describing a torch complex64/complex128 CUDA tensor of batch
+    registers; dim is the common dimension or a list of per-qudit dimensions."""
     torch = _torch()
     if not t.is_cuda:
         raise QfError(QF_EINVAL, "state tensor must live on the GPU")
@@ -154,11 +170,16 @@ def state_of(t, n: int, dim: int, batch: Optional[int] = None) -> qf_state:
         dt = QF_C128
     else:
         raise QfError(QF_EDTYPE, f"unsupported dtype {t.dtype}")
-    N = dim ** n
+    N = _size(n, dim)
     b = t.numel() // N if batch is None else batch
     if b * N != t.numel():
-        raise QfError(QF_EINVAL, f"tensor of {t.numel()} elements is not batch * {dim}^{n}")
-    return qf_state(t.data_ptr(), n, dim, b, dt)
+        raise QfError(QF_EINVAL, f"tensor of {t.numel()} elements is not batch * {N} amplitudes")
+    if isinstance(dim, (int, np.integer)):
+        return qf_state(t.data_ptr(), n, int(dim), b, dt)
+    arr, p = _i32(dim)
+    s = qf_state(t.data_ptr(), n, 0, b, dt, p)
+    s._dims_keep = arr  # the array the dims pointer refers to
+    return s
 
 
 # ---------------------------------------------------------------------------
@@ -232,7 +253,7 @@ def qf_probs(t, n: int, dim: int, qudits: Optional[Sequence[int]] = None, out=No
     s = state_of(t, n, dim)
     rdt = torch.float32 if t.dtype == torch.complex64 else torch.float64
     m = 0 if qudits is None else len(qudits)
-    size = s.batch * (dim ** (n if m == 0 else m))
+    size = s.batch * (_size(n, dim) if m == 0 else int(np.prod([_dim_of(dim, q) for q in qudits])))
     if out is None:
         out = torch.empty(size, dtype=rdt, device=t.device)
     if qudits is None:
@@ -252,7 +273,7 @@ def qf_sample(t, n: int, dim: int, shots: int, u, qudits: Optional[Sequence[int]
     torch = _torch()
     s = state_of(t, n, dim)
     m = 0 if qudits is None else len(qudits)
-    outcomes = dim ** (n if m == 0 else m)
+    outcomes = _size(n, dim) if m == 0 else int(np.prod([_dim_of(dim, q) for q in qudits]))
     if shots > 0 and (u is None or not u.is_cuda or u.dtype != torch.float64 or not u.is_contiguous()
                       or u.numel() != s.batch * shots):
         raise QfError(QF_EINVAL, "u must be a contiguous float64 device tensor of batch * shots values")
@@ -265,16 +286,16 @@ def qf_sample(t, n: int, dim: int, shots: int, u, qudits: Optional[Sequence[int]
     return (counts, draws) if samples else counts
 
 
-def _terms_arrays(dim: int, terms) -> tuple:
-    """terms: list of (qudit, "z") or (qudit, table of dim complex values)."""
+def _terms_arrays(dim, terms) -> tuple:
+    """terms: list of (qudit, "z") or (qudit, table of d_q complex values)."""
     qs = [int(q) for q, _ in terms]
-    w = np.exp(2j * np.pi / dim)
     tabs = []
-    for _, d in terms:
+    for q, d in terms:
+        dq = _dim_of(dim, int(q))
         if isinstance(d, str):
             if d != "z":
                 raise QfError(QF_EINVAL, f"unknown term {d}")
-            tabs.append(w ** np.arange(dim))
+            tabs.append(np.exp(2j * np.pi / dq) ** np.arange(dq))
         else:
             tabs.append(np.asarray(d, dtype=np.complex128))
     return qs, np.concatenate(tabs)
@@ -364,9 +385,10 @@ def ops_to_c(ops: Sequence[tuple]):
 
 
 class Plan:
-    """A compiled circuit (qf_plan_create) for registers of n qudits of dimension dim."""
+    """A compiled circuit (qf_plan_create) for registers of n qudits of dimension
+    dim, or of per-qudit dimensions when dim is a list (qf_plan_create_dims)."""
 
-    def __init__(self, dim: int, n: int, ops: Sequence[tuple], nparams: int, dtype: str = "c64",
+    def __init__(self, dim, n: int, ops: Sequence[tuple], nparams: int, dtype: str = "c64",
                  fuse: int = 0, tile_digits: int = 0, low_digits: int = 0, ckpt_every: int = 0,
                  adj_tile_digits: int = 0, stage_kernel: int = 0, group_digits: int = 0, pipe_wgs: int = 0,
                  tile_order: int = 0, tile_search: int = 0):
@@ -376,7 +398,14 @@ class Plan:
         opts = qf_plan_opts(fuse, tile_digits, low_digits, ckpt_every, adj_tile_digits, stage_kernel, group_digits,
                             pipe_wgs, tile_order, tile_search)
         h = ctypes.c_void_p()
-        _check(lib.qf_plan_create(dim, n, self.dtype, arr, len(ops), nparams, ctypes.byref(opts), ctypes.byref(h)))
+        if isinstance(dim, (int, np.integer)):
+            _check(lib.qf_plan_create(int(dim), n, self.dtype, arr, len(ops), nparams, ctypes.byref(opts),
+                                      ctypes.byref(h)))
+        else:
+            self.dim = [int(d) for d in dim]
+            da, dp = _i32(self.dim)
+            _check(lib.qf_plan_create_dims(dp, n, self.dtype, arr, len(ops), nparams, ctypes.byref(opts),
+                                           ctypes.byref(h)))
         self._h = h
 
     @property
@@ -469,7 +498,9 @@ class Plan:
 
 
 def plan_for(circuit, dtype: str = "c64", **kw) -> Plan:
-    return Plan(circuit.dim, circuit.n, circuit.ops, circuit.nparams, dtype, **kw)
+    """Plan of a circuit description (uniform: .dim; mixed: .dims)."""
+    dim = list(circuit.dims) if hasattr(circuit, "dims") else circuit.dim
+    return Plan(dim, circuit.n, circuit.ops, circuit.nparams, dtype, **kw)
 
 
 def qf_shutdown() -> None:
@@ -477,7 +508,7 @@ def qf_shutdown() -> None:
     lib.qf_shutdown()
 
 
-def new_state(n: int, dim: int, dtype: str = "c64", batch: int = 1, device="cuda"):
+def new_state(n: int, dim, dtype: str = "c64", batch: int = 1, device="cuda"):
     torch = _torch()
     dt = torch.complex64 if dtype == "c64" else torch.complex128
-    return torch.empty(batch * dim ** n, dtype=dt, device=device)
+    return torch.empty(batch * _size(n, dim), dtype=dt, device=device)

@@ -1,5 +1,6 @@
 // C ABI of the per-gate entry points: argument validation (synchronous, before
 // any HIP call) and dispatch to the kernel launchers.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -84,24 +85,39 @@ qf_status make_view(const qf_state* s, StateView& v) {
     QF_RETURN_IF(s == nullptr, QF_EINVAL, "state is NULL");
     QF_RETURN_IF(s->amps == nullptr, QF_EINVAL, "state amplitudes pointer is NULL");
     QF_RETURN_IF(s->dtype != QF_C64 && s->dtype != QF_C128, QF_EDTYPE, "unknown dtype %d", s->dtype);
-    QF_RETURN_IF(s->dim < 2 || s->dim > kMaxDim, QF_ERANGE, "dim %d outside 2..%d", s->dim, kMaxDim);
-    QF_RETURN_IF(s->n < 1, QF_EINVAL, "n = %d < 1", s->n);
+    if (s->dims == nullptr) {
+        QF_RETURN_IF(s->dim < 2 || s->dim > kMaxDim, QF_ERANGE, "dim %d outside 2..%d", s->dim, kMaxDim);
+    } else {
+        QF_RETURN_IF(s->dim != 0, QF_EINVAL, "dim = %d must be 0 when dims is given", s->dim);
+    }
+    QF_RETURN_IF(s->n < 1 || s->n > kMaxQudits, QF_EINVAL, "n = %d outside 1..%d", s->n, kMaxQudits);
     QF_RETURN_IF(s->batch < 1, QF_EINVAL, "batch = %lld < 1", (long long)s->batch);
     uint64_t N = 1;
     for (int i = 0; i < s->n; ++i) {
-        N *= uint64_t(s->dim);
-        QF_RETURN_IF(N >= (1ull << 32), QF_ERANGE, "dim^n exceeds 2^32 amplitudes");
+        const int32_t d = s->dims ? s->dims[i] : s->dim;
+        QF_RETURN_IF(d < 2 || d > kMaxDim, QF_ERANGE, "dimension %d of qudit %d outside 2..%d", d, i, kMaxDim);
+        v.dims[i] = uint32_t(d);
+        N *= uint64_t(d);
+        QF_RETURN_IF(N >= (1ull << 32), QF_ERANGE, "the register exceeds 2^32 amplitudes");
     }
     const uint64_t total = N * uint64_t(s->batch);
-    QF_RETURN_IF(total >= (1ull << 32), QF_ERANGE, "batch * dim^n = %llu exceeds 2^32 - 1",
+    QF_RETURN_IF(total >= (1ull << 32), QF_ERANGE, "batch * amplitudes = %llu exceeds 2^32 - 1",
                  (unsigned long long)total);
     v.amps = s->amps;
     v.n = uint32_t(s->n);
-    v.D = uint32_t(s->dim);
     v.N = uint32_t(N);
     v.batch = uint32_t(s->batch);
     v.total = uint32_t(total);
     v.dtype = s->dtype;
+    v.dmin = v.dmax = v.dims[0];
+    uint32_t stride = 1;
+    for (int i = int(v.n) - 1; i >= 0; --i) {
+        v.strides[i] = stride;
+        stride *= v.dims[i];
+        v.dmin = std::min(v.dmin, v.dims[i]);
+        v.dmax = std::max(v.dmax, v.dims[i]);
+    }
+    v.D = v.dmin == v.dmax ? v.dmin : 0u;
     return QF_OK;
 }
 
@@ -117,30 +133,38 @@ static qf_status check_finite(const double* a, size_t cnt, const char* what) {
 }
 
 // Combine one-qudit diagonal terms into per-qudit tables (terms on the same
-// qudit add up).  Returns the active qudits and a [active][D] complex table.
+// qudit add up).  Returns the active qudits and their complex tables back to
+// back (d_q values for qudit q, in the order of active).
 qf_status combine_terms(const StateView& v, int32_t nterms, const int32_t* term_qudit, const double* term_diag,
                         std::vector<int>& active, std::vector<double>& table) {
     QF_RETURN_IF(nterms < 1, QF_EINVAL, "nterms = %d < 1", nterms);
     QF_RETURN_IF(term_qudit == nullptr || term_diag == nullptr, QF_EINVAL, "term arrays are NULL");
-    QF_CHECK(check_finite(term_diag, size_t(nterms) * v.D * 2, "term_diag"));
-    std::vector<int> slot(v.n, -1);
-    active.clear();
-    table.clear();
+    size_t len = 0;
     for (int t = 0; t < nterms; ++t) {
         QF_CHECK(check_qudit(v, term_qudit[t], "term"));
-        int q = term_qudit[t];
-        if (slot[q] < 0) {
-            slot[q] = int(active.size());
-            active.push_back(q);
-            table.resize(table.size() + 2 * v.D, 0.0);
-        }
-        for (uint32_t d = 0; d < v.D; ++d) {
-            table[2 * (slot[q] * v.D + d)] += term_diag[2 * (size_t(t) * v.D + d)];
-            table[2 * (slot[q] * v.D + d) + 1] += term_diag[2 * (size_t(t) * v.D + d) + 1];
-        }
+        len += v.dims[term_qudit[t]];
     }
-    QF_RETURN_IF(active.size() * v.D > 128 || active.size() > 32, QF_ERANGE,
-                 "observable spans %zu qudits x D=%u > 128 table entries", active.size(), v.D);
+    QF_CHECK(check_finite(term_diag, len * 2, "term_diag"));
+    std::vector<int> off(v.n, -1);
+    active.clear();
+    table.clear();
+    size_t src = 0;
+    for (int t = 0; t < nterms; ++t) {
+        const int q = term_qudit[t];
+        const uint32_t d = v.dims[q];
+        if (off[q] < 0) {
+            off[q] = int(table.size() / 2);
+            active.push_back(q);
+            table.resize(table.size() + 2 * d, 0.0);
+        }
+        for (uint32_t l = 0; l < d; ++l) {
+            table[2 * (off[q] + l)] += term_diag[2 * (src + l)];
+            table[2 * (off[q] + l) + 1] += term_diag[2 * (src + l) + 1];
+        }
+        src += d;
+    }
+    QF_RETURN_IF(table.size() / 2 > 128 || active.size() > 32, QF_ERANGE,
+                 "observable tables hold %zu values over %zu qudits (limit 128)", table.size() / 2, active.size());
     return QF_OK;
 }
 
@@ -166,9 +190,9 @@ qf_status qf_state_init(const qf_state* s, const int32_t* digits, void* stream) 
             uint32_t x = 0;
             for (uint32_t k = 0; k < v.n; ++k) {
                 const int32_t d = digits[size_t(b) * v.n + k];
-                QF_RETURN_IF(d < 0 || uint32_t(d) >= v.D, QF_EINVAL, "digit %d of register %u outside [0, %u)",
-                             d, b, v.D);
-                x = x * v.D + uint32_t(d);
+                QF_RETURN_IF(d < 0 || uint32_t(d) >= v.dims[k], QF_EINVAL,
+                             "digit %d of qudit %u of register %u outside [0, %u)", d, k, b, v.dims[k]);
+                x = x * v.dims[k] + uint32_t(d);
             }
             if (!idx.empty() && idx[0] != x) same = false;
             idx.push_back(x);
@@ -183,7 +207,7 @@ qf_status qf_apply_1q(const qf_state* s, int32_t q, const double* U, void* strea
     QF_CHECK(make_view(s, v));
     QF_CHECK(check_qudit(v, q, "target"));
     QF_RETURN_IF(U == nullptr, QF_EINVAL, "U is NULL");
-    QF_CHECK(check_finite(U, size_t(v.D) * v.D * 2, "U"));
+    QF_CHECK(check_finite(U, size_t(v.dims[q]) * v.dims[q] * 2, "U"));
     return launch_apply_1q(v, q, U, reinterpret_cast<hipStream_t>(stream));
 }
 
@@ -208,7 +232,9 @@ qf_status qf_apply_diag(const qf_state* s, int32_t k, const int32_t* qudits, con
         for (int j = 0; j < i; ++j)
             QF_RETURN_IF(qudits[i] == qudits[j], QF_EINVAL, "qudit %d listed twice", qudits[i]);
     }
-    QF_CHECK(check_finite(phases, size_t(ipow(v.D, k)) * 2, "phases"));
+    size_t ntab = 1;
+    for (int i = 0; i < k; ++i) ntab *= v.dims[qudits[i]];
+    QF_CHECK(check_finite(phases, ntab * 2, "phases"));
     return launch_diag(v, k, qudits, phases, reinterpret_cast<hipStream_t>(stream));
 }
 
@@ -221,14 +247,16 @@ qf_status qf_apply_crot(const qf_state* s, int32_t kind, int32_t ctrl, int32_t t
     QF_CHECK(check_qudit(v, ctrl, "control"));
     QF_CHECK(check_qudit(v, tgt, "target"));
     QF_RETURN_IF(ctrl == tgt, QF_EINVAL, "control and target are both %d", ctrl);
+    const uint32_t dt = v.dims[tgt], dc = v.dims[ctrl];
     if (kind == QF_OP_CRZ)
-        QF_RETURN_IF(j < 1 || uint32_t(j) >= v.D, QF_EINVAL, "R_z level j = %d needs 1 <= j < D", j);
+        QF_RETURN_IF(j < 1 || uint32_t(j) >= dt, QF_EINVAL, "R_z level j = %d needs 1 <= j < %u", j, dt);
     else
-        QF_RETURN_IF(!(j >= 0 && j < k && uint32_t(k) < v.D), QF_EINVAL, "levels (%d, %d) need 0 <= j < k < D", j, k);
+        QF_RETURN_IF(!(j >= 0 && j < k && uint32_t(k) < dt), QF_EINVAL, "levels (%d, %d) need 0 <= j < k < %u", j, k,
+                     dt);
     QF_RETURN_IF(!std::isfinite(theta), QF_EINVAL, "theta is not finite");
-    // table for control levels m = 0..D-1 (layout in k_crot.hip)
-    std::vector<double> tab(size_t(4) * v.D, 0.0);
-    for (uint32_t m = 0; m < v.D; ++m) {
+    // table for control levels m = 0..d_c-1 (layout in k_crot.hip)
+    std::vector<double> tab(size_t(4) * dc, 0.0);
+    for (uint32_t m = 0; m < dc; ++m) {
         if (kind == QF_OP_CRZ) {
             const double a = std::sqrt(2.0 / (double(j) * (j + 1)));
             tab[4 * m] = std::cos(-0.5 * m * theta * a);
@@ -250,6 +278,7 @@ qf_status qf_apply_swap(const qf_state* s, int32_t a, int32_t b, void* stream) {
     QF_CHECK(check_qudit(v, a, "first"));
     QF_CHECK(check_qudit(v, b, "second"));
     QF_RETURN_IF(a == b, QF_EINVAL, "SWAP of qudit %d with itself", a);
+    QF_RETURN_IF(v.dims[a] != v.dims[b], QF_EINVAL, "SWAP of qudits of dimensions %u and %u", v.dims[a], v.dims[b]);
     return launch_swap(v, a, b, reinterpret_cast<hipStream_t>(stream));
 }
 
@@ -274,13 +303,15 @@ qf_status qf_apply_rot(const qf_state* s, int32_t kind, int32_t q, int32_t j, in
     QF_RETURN_IF(kind != QF_OP_RX && kind != QF_OP_RY && kind != QF_OP_RZ, QF_EINVAL, "kind %d is not a rotation",
                  kind);
     QF_CHECK(check_qudit(v, q, "target"));
+    const uint32_t dq = v.dims[q];
     if (kind == QF_OP_RZ)
-        QF_RETURN_IF(j < 1 || uint32_t(j) >= v.D, QF_EINVAL, "R_z level j = %d needs 1 <= j < D", j);
+        QF_RETURN_IF(j < 1 || uint32_t(j) >= dq, QF_EINVAL, "R_z level j = %d needs 1 <= j < %u", j, dq);
     else
-        QF_RETURN_IF(!(j >= 0 && j < k && uint32_t(k) < v.D), QF_EINVAL, "levels (%d, %d) need 0 <= j < k < D", j, k);
+        QF_RETURN_IF(!(j >= 0 && j < k && uint32_t(k) < dq), QF_EINVAL, "levels (%d, %d) need 0 <= j < k < %u", j, k,
+                     dq);
     QF_RETURN_IF(!std::isfinite(theta), QF_EINVAL, "theta is not finite");
     // the slab kernel's table at control level m = 1 (layout in k_crot.hip)
-    std::vector<double> tab(size_t(4) * v.D, 0.0);
+    std::vector<double> tab(8, 0.0);
     if (kind == QF_OP_RZ) {
         const double a = std::sqrt(2.0 / (double(j) * (j + 1)));
         tab[4] = std::cos(-0.5 * theta * a);
@@ -301,7 +332,7 @@ qf_status qf_apply_fused(const qf_state* s, int32_t k, int32_t q0, const void* B
     QF_RETURN_IF(k < 1 || uint32_t(k) > v.n, QF_EINVAL, "k = %d outside [1, n]", k);
     QF_RETURN_IF(q0 < 0 || uint32_t(q0 + k) > v.n, QF_EINVAL, "qudits %d..%d outside [0, %u)", q0, q0 + k - 1, v.n);
     uint64_t K = 1;
-    for (int i = 0; i < k; ++i) K *= v.D;
+    for (int i = 0; i < k; ++i) K *= v.dims[q0 + i];
     QF_RETURN_IF(K > 1024, QF_ERANGE, "block size D^k = %llu > 1024", (unsigned long long)K);
     QF_RETURN_IF(B == nullptr, QF_EINVAL, "B is NULL");
     return launch_fused(v, k, q0, B, reinterpret_cast<hipStream_t>(stream));
@@ -351,7 +382,11 @@ qf_status qf_sample(const qf_state* s, int32_t m, const int32_t* qudits, int64_t
         }
         if (identity) m = 0;
     }
-    const uint64_t K = m == 0 ? uint64_t(v.N) : uint64_t(ipow(v.D, uint32_t(m)));
+    uint64_t K = v.N;
+    if (m > 0) {
+        K = 1;
+        for (int i = 0; i < m; ++i) K *= v.dims[qudits[i]];
+    }
     QF_RETURN_IF(samples != nullptr && K > (1ull << 31), QF_ERANGE, "%llu outcomes do not fit int32 samples",
                  (unsigned long long)K);
     return launch_sample(v, m, m == 0 ? nullptr : qudits, uint64_t(shots), u, counts, samples,

@@ -119,7 +119,7 @@ __global__ __launch_bounds__(kFB) void k_adj_axis(cplx<T>* __restrict__ psi, cpl
 // out[b][slot][e] = sum over the workgroups of register b: one workgroup per
 // (b, e); lanes take workgroups k = lane, lane + 256, ..., then a fixed tree.
 __global__ __launch_bounds__(256) void k_adj_reduce(const double* __restrict__ partial, uint32_t blocks_per_reg,
-                                                    uint32_t E, uint32_t nslots, uint32_t slot,
+                                                    uint32_t E, uint32_t nslots, uint32_t slot, uint32_t slot_elems,
                                                     double* __restrict__ out) {
     __shared__ double sh[2][256];
     const uint32_t b = blockIdx.x / E;
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(256) void k_adj_reduce(const double* __restrict__ p
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        double* o = out + ((size_t(b) * nslots + slot) * E + e) * 2;
+        double* o = out + ((size_t(b) * nslots + slot) * slot_elems + e) * 2;
         o[0] = sh[0][0];
         o[1] = sh[1][0];
     }
@@ -172,16 +172,16 @@ qf_status with_dim_a(uint32_t D, F&& f) {
 }  // namespace
 
 size_t adj_axis_partial_doubles(const StateView& s) {
-    const uint32_t nfib_reg = s.N / s.D;
+    const uint32_t nfib_reg = s.N / s.dmin;
     const uint32_t bpr = (nfib_reg + kFB - 1) / kFB;
-    return size_t(bpr) * s.batch * s.D * s.D * 2;
+    return size_t(bpr) * s.batch * s.dmax * s.dmax * 2;
 }
 
 qf_status launch_adj_axis(const StateView& s, void* lam, int q, const double* W, double* partial, double* mout,
-                          uint32_t nslots, uint32_t slot, hipStream_t st) {
-    const uint32_t nfib_reg = s.N / s.D;
+                          uint32_t nslots, uint32_t slot, uint32_t slot_elems, hipStream_t st) {
+    const uint32_t nfib_reg = s.N / s.dims[q];
     const uint32_t bpr = (nfib_reg + kFB - 1) / kFB;
-    const uint32_t L = ipow(s.D, s.n - 1 - q);
+    const uint32_t L = s.strides[q];
     auto body = [&](auto tag, auto dtag) -> qf_status {
         using T = decltype(tag);
         constexpr int D = decltype(dtag)::value;
@@ -196,11 +196,11 @@ qf_status launch_adj_axis(const StateView& s, void* lam, int q, const double* W,
             QF_CHECK(check_launch("adjoint axis"));
             const uint32_t E = D * D;
             hipLaunchKernelGGL(k_adj_reduce, dim3(s.batch * E), dim3(256), 0, st, partial, bpr, E, nslots, slot,
-                               mout);
+                               slot_elems, mout);
             return check_launch("adjoint reduce");
         }
     };
-    return with_dim_a(s.D, [&](auto dtag) -> qf_status {
+    return with_dim_a(s.dims[q], [&](auto dtag) -> qf_status {
         if (s.dtype == QF_C64) return body(float{}, dtag);
         return body(double{}, dtag);
     });

@@ -3,7 +3,8 @@
 // diagonal expectation values.
 //
 // A register of n qudits is viewed, for a gate on qudit q, as [H][D][L] with
-// H = batch * D^q and L = D^(n-1-q) (the decimal index puts qudit 0 first).
+// D = d_q, L = S_q (the product of the dimensions after q) and H the rest
+// (the decimal index puts qudit 0 first; qudits may differ in dimension).
 // A "fibre" is the D amplitudes psi[h, :, l].
 //  * L >= 64: one fibre per lane, lanes take consecutive l, so each of the D
 //    loads of a wavefront is one contiguous 64-element run (coalesced).
@@ -48,19 +49,22 @@ struct OpMat {
     }
 };
 
-// x_t -> x_t + shift[x_c] mod D; the control digit is read from the global
-// index of the fibre (any element of the fibre has the same x_c).
+// x_t -> x_t + shift[x_c] mod D (D = d_t); the control digit is read from
+// the global index of the fibre (any element of the fibre has the same x_c).
 template <typename T, int D>
 struct OpShift {
-    int32_t shift[D];  // already reduced to [0, D)
-    FastDiv strideC;   // x_c = (index / D^(n-1-c)) mod D
+    int32_t shift[kMaxDim];  // per control level, already reduced to [0, D)
+    FastDiv strideC;         // x_c = (index / S_c) mod d_c
+    FastDiv divDc;
+    uint32_t dc;
     int32_t has_ctrl;
     __device__ int amount(uint32_t gidx) const {
         if (!has_ctrl) return shift[0];
-        const uint32_t c = strideC.div(gidx) % D;
+        const uint32_t qv = strideC.div(gidx);
+        const uint32_t c = qv - divDc.div(qv) * dc;
         int s = shift[0];
 #pragma unroll
-        for (int a = 1; a < D; ++a) s = (c == uint32_t(a)) ? shift[a] : s;
+        for (int a = 1; a < kMaxDim; ++a) s = (c == uint32_t(a)) ? shift[a] : s;
         return s;
     }
     __device__ bool skip(uint32_t gidx) const { return amount(gidx) == 0; }
@@ -91,11 +95,15 @@ constexpr int kMaxMcxCtrl = 8;
 template <typename T, int D>
 struct OpShiftMulti {
     FastDiv strideC[kMaxMcxCtrl];
+    FastDiv divDc[kMaxMcxCtrl];  // the controls' dimensions
     int32_t nctrl;
     int32_t inverse;
     __device__ int amount(uint32_t gidx) const {
         uint32_t prod = 1;
-        for (int i = 0; i < nctrl; ++i) prod = (prod * (strideC[i].div(gidx) % D)) % D;
+        for (int i = 0; i < nctrl; ++i) {
+            const uint32_t qv = strideC[i].div(gidx);
+            prod = (prod * (qv - divDc[i].div(qv) * divDc[i].d)) % D;
+        }
         return inverse ? int((D - prod) % D) : int(prod);
     }
     __device__ bool skip(uint32_t gidx) const { return amount(gidx) == 0; }
@@ -163,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_axis_narrow(cplx<T>* __restrict__ ps
 template <typename T, int D, class Op>
 qf_status run_axis(const StateView& s, int q, const Op& op, hipStream_t st, const char* what) {
     auto* psi = reinterpret_cast<cplx<T>*>(s.amps);
-    const uint32_t L = ipow(D, s.n - 1 - q);
+    const uint32_t L = s.strides[q];
     if (L >= 64) {
         const uint32_t nfib = s.total / D;
         const uint32_t grid = (nfib + kBlock - 1) / kBlock;
@@ -265,8 +273,7 @@ template <typename T>
 struct DiagArg {
     static constexpr int kMax = kDiagBytes / int(sizeof(cplx<T>));
     FastDiv stride[8];
-    FastDiv divD;
-    uint32_t D;
+    FastDiv divd[8];  // dimensions of the listed qudits
     uint32_t k;
     uint32_t ntab;
     cplx<T> table[kMax];
@@ -282,7 +289,8 @@ __global__ __launch_bounds__(kBlock) void k_diag(cplx<T>* __restrict__ psi, uint
         uint32_t y = 0;
         for (uint32_t i = 0; i < a.k; ++i) {
             const uint32_t qv = a.stride[i].div(x);
-            y = y * a.D + (qv - a.divD.div(qv) * a.D);
+            const uint32_t d = a.divd[i].d;
+            y = y * d + (qv - a.divd[i].div(qv) * d);
         }
         psi[x] = cmul(psi[x], tab[y]);
     }
@@ -318,19 +326,19 @@ __device__ inline double block_sum(double v, double* sh) {
 constexpr int kMaxMarg = 32;
 
 struct MargArg {
-    uint32_t N;           // D^n
-    uint32_t Z;           // elements per bin = D^(n-m)
+    uint32_t N;           // amplitudes per register
+    uint32_t Z;           // elements per bin = N / bins
     uint32_t R;           // trailing contiguous run (digits below every measured qudit)
     FastDiv divR;
-    FastDiv divD;
-    uint32_t D;
     uint32_t m;           // measured qudits
     uint32_t u;           // other (non-trailing, unmeasured) qudits
-    uint32_t bins;        // D^m
+    uint32_t bins;        // product of the measured qudits' dimensions
     uint32_t chunk;       // elements of one bin summed by one workgroup
     uint32_t chunks;      // workgroups per bin
     uint32_t mstride[kMaxMarg];  // strides of measured qudits, listed order
+    FastDiv mdiv[kMaxMarg];      // their dimensions
     uint32_t ostride[kMaxMarg];  // strides of the other qudits, most significant first
+    FastDiv odiv[kMaxMarg];      // their dimensions
 };
 
 template <typename T>
@@ -346,8 +354,8 @@ __global__ __launch_bounds__(kBlock) void k_marg_partial(const cplx<T>* __restri
     {
         uint32_t yy = y;
         for (int i = int(a.m) - 1; i >= 0; --i) {
-            const uint32_t q = a.divD.div(yy);
-            base += (yy - q * a.D) * a.mstride[i];
+            const uint32_t q = a.mdiv[i].div(yy);
+            base += (yy - q * a.mdiv[i].d) * a.mstride[i];
             yy = q;
         }
     }
@@ -359,8 +367,8 @@ __global__ __launch_bounds__(kBlock) void k_marg_partial(const cplx<T>* __restri
         const uint32_t zl = z - zh * a.R;
         uint32_t off = 0;
         for (int j = int(a.u) - 1; j >= 0; --j) {
-            const uint32_t q = a.divD.div(zh);
-            off += (zh - q * a.D) * a.ostride[j];
+            const uint32_t q = a.odiv[j].div(zh);
+            off += (zh - q * a.odiv[j].d) * a.ostride[j];
             zh = q;
         }
         const cplx<T> v = psi[base + off + zl];
@@ -391,10 +399,11 @@ constexpr int kMaxTable = 128;
 
 struct ObsArg {
     uint32_t nact;
-    uint32_t D;
-    FastDiv divD;
+    uint32_t ntab;                 // table entries (sum of the active qudits' dimensions)
     FastDiv stride[kMaxActive];
-    double table[2 * kMaxTable];  // [active][D] complex, interleaved
+    FastDiv divd[kMaxActive];      // dimensions of the active qudits
+    uint32_t off[kMaxActive];      // first table entry of each active qudit
+    double table[2 * kMaxTable];   // complex, interleaved, active qudits back to back
 };
 
 __device__ inline void obs_value(const ObsArg& a, const double* tab, uint32_t x, double& fr, double& fi) {
@@ -402,9 +411,9 @@ __device__ inline void obs_value(const ObsArg& a, const double* tab, uint32_t x,
     fi = 0.0;
     for (uint32_t t = 0; t < a.nact; ++t) {
         const uint32_t qv = a.stride[t].div(x);
-        const uint32_t d = qv - a.divD.div(qv) * a.D;
-        fr += tab[2 * (t * a.D + d)];
-        fi += tab[2 * (t * a.D + d) + 1];
+        const uint32_t d = qv - a.divd[t].div(qv) * a.divd[t].d;
+        fr += tab[2 * (a.off[t] + d)];
+        fi += tab[2 * (a.off[t] + d) + 1];
     }
 }
 
@@ -414,7 +423,7 @@ __global__ __launch_bounds__(kBlock) void k_expect_partial(const cplx<T>* __rest
                                                            double* __restrict__ partial) {
     __shared__ double tab[2 * kMaxTable];
     __shared__ double sh[kBlock];
-    for (uint32_t i = threadIdx.x; i < 2 * a.nact * a.D; i += kBlock) tab[i] = a.table[i];
+    for (uint32_t i = threadIdx.x; i < 2 * a.ntab; i += kBlock) tab[i] = a.table[i];
     __syncthreads();
     const uint32_t b = blockIdx.x / nblk;
     const uint32_t blk = blockIdx.x - b * nblk;
@@ -461,7 +470,7 @@ __global__ __launch_bounds__(kBlock) void k_diag_observable(const cplx<T>* __res
                                                             cplx<T>* __restrict__ lam, uint32_t total,
                                                             FastDiv divN, uint32_t N, ObsArg a) {
     __shared__ double tab[2 * kMaxTable];
-    for (uint32_t i = threadIdx.x; i < 2 * a.nact * a.D; i += kBlock) tab[i] = a.table[i];
+    for (uint32_t i = threadIdx.x; i < 2 * a.ntab; i += kBlock) tab[i] = a.table[i];
     __syncthreads();
     for (uint32_t x = blockIdx.x * kBlock + threadIdx.x; x < total; x += gridDim.x * kBlock) {
         const uint32_t local = x - divN.div(x) * N;
@@ -476,10 +485,15 @@ ObsArg make_obs(const StateView& s, const std::vector<int>& active, const std::v
                 bool real_only) {
     ObsArg a{};
     a.nact = uint32_t(active.size());
-    a.D = s.D;
-    a.divD.init(s.D);
-    for (size_t t = 0; t < active.size(); ++t) a.stride[t].init(ipow(s.D, s.n - 1 - active[t]));
-    for (size_t i = 0; i < active.size() * s.D; ++i) {
+    uint32_t off = 0;
+    for (size_t t = 0; t < active.size(); ++t) {
+        a.stride[t].init(s.strides[active[t]]);
+        a.divd[t].init(s.dims[active[t]]);
+        a.off[t] = off;
+        off += s.dims[active[t]];
+    }
+    a.ntab = off;
+    for (uint32_t i = 0; i < off; ++i) {
         a.table[2 * i] = real_only ? table[i] : table[2 * i];
         a.table[2 * i + 1] = real_only ? 0.0 : table[2 * i + 1];
     }
@@ -514,7 +528,7 @@ qf_status launch_init(const StateView& s, const std::vector<uint32_t>& index, hi
 qf_status launch_apply_1q(const StateView& s, int q, const double* U, hipStream_t st) {
     return with_type(s.dtype, [&](auto tag) -> qf_status {
         using T = decltype(tag);
-        return with_dim(s.D, [&](auto dtag) -> qf_status {
+        return with_dim(s.dims[q], [&](auto dtag) -> qf_status {
             constexpr int D = decltype(dtag)::value;
             if constexpr (sizeof(MatArg<T, D>) > 2048) {
                 return set_error(QF_ERANGE, "dim %d too large for a complex128 kernel-argument matrix", D);
@@ -530,16 +544,18 @@ qf_status launch_apply_1q(const StateView& s, int q, const double* U, hipStream_
 qf_status launch_ctrl(const StateView& s, int ctrl, int tgt, const int32_t* shift, hipStream_t st) {
     return with_type(s.dtype, [&](auto tag) -> qf_status {
         using T = decltype(tag);
-        return with_dim(s.D, [&](auto dtag) -> qf_status {
+        return with_dim(s.dims[tgt], [&](auto dtag) -> qf_status {
             constexpr int D = decltype(dtag)::value;
             OpShift<T, D> op;
-            const int nsh = ctrl < 0 ? 1 : D;
-            for (int i = 0; i < D; ++i) {
+            const int nsh = ctrl < 0 ? 1 : int(s.dims[ctrl]);
+            for (int i = 0; i < kMaxDim; ++i) {
                 const int v = i < nsh ? shift[i] : 0;
                 op.shift[i] = ((v % D) + D) % D;
             }
             op.has_ctrl = ctrl >= 0;
-            op.strideC = FastDiv(ctrl >= 0 ? ipow(D, s.n - 1 - ctrl) : 1u);
+            op.strideC = FastDiv(ctrl >= 0 ? s.strides[ctrl] : 1u);
+            op.dc = ctrl >= 0 ? s.dims[ctrl] : 1u;
+            op.divDc = FastDiv(op.dc);
             return run_axis<T, D>(s, tgt, op, st, "qf_apply_ctrl");
         });
     });
@@ -549,12 +565,15 @@ qf_status launch_mcx(const StateView& s, int nctrl, const int32_t* ctrls, int tg
     if (nctrl < 1 || nctrl > kMaxMcxCtrl) return set_error(QF_ERANGE, "%d controls outside 1..%d", nctrl, kMaxMcxCtrl);
     return with_type(s.dtype, [&](auto tag) -> qf_status {
         using T = decltype(tag);
-        return with_dim(s.D, [&](auto dtag) -> qf_status {
+        return with_dim(s.dims[tgt], [&](auto dtag) -> qf_status {
             constexpr int D = decltype(dtag)::value;
             OpShiftMulti<T, D> op;
             op.nctrl = nctrl;
             op.inverse = inverse ? 1 : 0;
-            for (int i = 0; i < kMaxMcxCtrl; ++i) op.strideC[i] = FastDiv(i < nctrl ? ipow(D, s.n - 1 - ctrls[i]) : 1u);
+            for (int i = 0; i < kMaxMcxCtrl; ++i) {
+                op.strideC[i] = FastDiv(i < nctrl ? s.strides[ctrls[i]] : 1u);
+                op.divDc[i] = FastDiv(i < nctrl ? s.dims[ctrls[i]] : 1u);
+            }
             return run_axis<T, D>(s, tgt, op, st, "multi-controlled shift");
         });
     });
@@ -562,11 +581,11 @@ qf_status launch_mcx(const StateView& s, int nctrl, const int32_t* ctrls, int tg
 
 qf_status launch_swap(const StateView& s, int a, int b, hipStream_t st) {
     if (a > b) std::swap(a, b);  // a: the more significant qudit
-    const uint32_t Sa = ipow(s.D, s.n - 1 - uint32_t(a)), Sb = ipow(s.D, s.n - 1 - uint32_t(b));
+    const uint32_t Sa = s.strides[a], Sb = s.strides[b], D = s.dims[a];  // d_a = d_b
     return with_type(s.dtype, [&](auto tag) -> qf_status {
         using T = decltype(tag);
         hipLaunchKernelGGL(k_swap<T>, dim3(grid_for(s.total, kBlock * 4)), dim3(kBlock), 0, st,
-                           reinterpret_cast<cplx<T>*>(s.amps), s.total, FastDiv(Sa), FastDiv(Sb), s.D, FastDiv(s.D),
+                           reinterpret_cast<cplx<T>*>(s.amps), s.total, FastDiv(Sa), FastDiv(Sb), D, FastDiv(D),
                            Sa - Sb);
         return check_launch("swap");
     });
@@ -577,13 +596,15 @@ qf_status launch_diag(const StateView& s, int k, const int32_t* qudits, const do
     return with_type(s.dtype, [&](auto tag) -> qf_status {
         using T = decltype(tag);
         DiagArg<T> a{};
-        a.D = s.D;
         a.k = uint32_t(k);
-        a.ntab = ipow(s.D, k);
+        a.ntab = 1;
+        for (int i = 0; i < k; ++i) a.ntab *= s.dims[qudits[i]];
         if (a.ntab > uint32_t(DiagArg<T>::kMax))
             return set_error(QF_ERANGE, "D^k = %u exceeds %d table entries", a.ntab, DiagArg<T>::kMax);
-        a.divD.init(s.D);
-        for (int i = 0; i < k; ++i) a.stride[i].init(ipow(s.D, s.n - 1 - qudits[i]));
+        for (int i = 0; i < k; ++i) {
+            a.stride[i].init(s.strides[qudits[i]]);
+            a.divd[i].init(s.dims[qudits[i]]);
+        }
         for (uint32_t i = 0; i < a.ntab; ++i) a.table[i] = cmake<T>(T(phases[2 * i]), T(phases[2 * i + 1]));
         hipLaunchKernelGGL(k_diag<T>, dim3(grid_for(s.total, kBlock * 4)), dim3(kBlock), 0, st,
                            reinterpret_cast<cplx<T>*>(s.amps), s.total, a);
@@ -610,24 +631,26 @@ qf_status launch_probs_marginal(const StateView& s, int m, const int32_t* qudits
                                 hipStream_t st) {
     MargArg a{};
     a.N = s.N;
-    a.D = s.D;
-    a.divD.init(s.D);
     a.m = uint32_t(m);
-    a.bins = ipow(s.D, m);
-    a.Z = ipow(s.D, s.n - m);
+    a.bins = 1;
     int maxp = -1;
     std::vector<bool> meas(s.n, false);
     for (int i = 0; i < m; ++i) {
         meas[qudits[i]] = true;
         maxp = qudits[i] > maxp ? qudits[i] : maxp;
-        a.mstride[i] = ipow(s.D, s.n - 1 - qudits[i]);
+        a.mstride[i] = s.strides[qudits[i]];
+        a.mdiv[i].init(s.dims[qudits[i]]);
+        a.bins *= s.dims[qudits[i]];
     }
-    const uint32_t r = s.n - 1 - uint32_t(maxp);
-    a.R = ipow(s.D, r);
+    a.Z = s.N / a.bins;
+    a.R = s.strides[maxp];
     a.divR.init(a.R);
     uint32_t u = 0;
     for (int p = 0; p < maxp; ++p)
-        if (!meas[p]) a.ostride[u++] = ipow(s.D, s.n - 1 - p);
+        if (!meas[p]) {
+            a.ostride[u] = s.strides[p];
+            a.odiv[u++].init(s.dims[p]);
+        }
     a.u = u;
     a.chunk = kBlock * 16;
     a.chunks = (a.Z + a.chunk - 1) / a.chunk;

@@ -3,9 +3,9 @@
 // without a control the plain two-level rotation as a slab sweep (the memory
 // form of the paper's sparse rotation, subsection "Generalized rotation gate").
 //
-// The register is viewed as [H][D][L] for the target t (L = D^(n-1-t)); a
-// fibre is the D amplitudes psi[h, :, l], and its control digit m is read from
-// its index.  The x- and y-type rotations mix only target levels j and k, so a
+// The register is viewed as [H][D][L] for the target t (D = d_t, L = S_t, the
+// product of the dimensions after t); a fibre is the D amplitudes
+// psi[h, :, l], and its control digit m (0 <= m < d_c) is read from its index.  The x- and y-type rotations mix only target levels j and k, so a
 // lane reads and writes just those two amplitudes of its fibre (2/D of the
 // state); the z type scales levels 0..j.  Fibres at control level 0 are left
 // alone.  Consecutive lanes take consecutive l, so for L >= 64 every access of
@@ -32,8 +32,10 @@ struct CrGeom {
     uint32_t L;          // stride of the target qudit
     FastDiv divL;
     FastDiv cstride;     // stride of the control qudit
-    uint32_t nfib;       // fibres per register, D^(n-1)
-    uint32_t N;          // D^n
+    FastDiv divDc;       // dimension of the control qudit
+    uint32_t ntab;       // table entries: 2 per control level
+    uint32_t nfib;       // fibres per register, N / d_t
+    uint32_t N;          // amplitudes per register
     uint32_t bpr;        // workgroups per register
     int32_t kind;        // 0 = x, 1 = y, 2 = z
     int32_t j, k;        // levels (z: j)
@@ -45,11 +47,17 @@ struct CrTab {
     cplx<T> t[2 * kMaxDim];
 };
 
-template <typename T, int D>
+template <typename T>
 __device__ __forceinline__ void load_tab(const CrTab<T>& harg, const cplx<T>* __restrict__ dtab, size_t tab_stride,
-                                         uint32_t b, cplx<T>* tab) {
-    if (threadIdx.x < 2 * D) tab[threadIdx.x] = dtab ? dtab[size_t(b) * tab_stride + threadIdx.x] : harg.t[threadIdx.x];
+                                         uint32_t b, uint32_t ntab, cplx<T>* tab) {
+    if (threadIdx.x < ntab) tab[threadIdx.x] = dtab ? dtab[size_t(b) * tab_stride + threadIdx.x] : harg.t[threadIdx.x];
     __syncthreads();
+}
+
+__device__ __forceinline__ uint32_t ctrl_level(const CrGeom& g, uint32_t local) {
+    if (!g.has_ctrl) return 1u;
+    const uint32_t qv = g.cstride.div(local);
+    return qv - g.divDc.div(qv) * g.divDc.d;
 }
 
 // Applies the table's rotation for control level m to the fibre at base.
@@ -77,14 +85,14 @@ __device__ __forceinline__ void rotate(cplx<T>* __restrict__ psi, const CrGeom& 
 template <typename T, int D>
 __global__ __launch_bounds__(kCB) void k_crot(cplx<T>* __restrict__ psi, CrGeom g, CrTab<T> harg,
                                               const cplx<T>* __restrict__ dtab, size_t tab_stride) {
-    __shared__ cplx<T> tab[2 * D];
+    __shared__ cplx<T> tab[2 * kMaxDim];
     const uint32_t b = blockIdx.x / g.bpr;
-    load_tab<T, D>(harg, dtab, tab_stride, b, tab);
+    load_tab<T>(harg, dtab, tab_stride, b, g.ntab, tab);
     const uint32_t f = (blockIdx.x - b * g.bpr) * kCB + threadIdx.x;
     if (f >= g.nfib) return;
     const uint32_t h = g.divL.div(f);
     const uint32_t local = h * (uint32_t(D) * g.L) + (f - h * g.L);
-    const uint32_t m = g.has_ctrl ? g.cstride.div(local) % D : 1u;
+    const uint32_t m = ctrl_level(g, local);
     if (m == 0) return;
     rotate<T, D>(psi + size_t(b) * g.N, g, local, tab, m);
 }
@@ -104,16 +112,16 @@ template <typename T, int D>
 __global__ __launch_bounds__(kCB) void k_crot_adj(cplx<T>* __restrict__ psi, cplx<T>* __restrict__ lam, CrGeom g,
                                                   CrTab<T> harg, const cplx<T>* __restrict__ dtab, size_t tab_stride,
                                                   double* __restrict__ partial) {
-    __shared__ cplx<T> tab[2 * D];
+    __shared__ cplx<T> tab[2 * kMaxDim];
     __shared__ double sh[kCB];
     const uint32_t b = blockIdx.x / g.bpr;
-    load_tab<T, D>(harg, dtab, tab_stride, b, tab);
+    load_tab<T>(harg, dtab, tab_stride, b, g.ntab, tab);
     const uint32_t f = (blockIdx.x - b * g.bpr) * kCB + threadIdx.x;
     double acc = 0.0;
     if (f < g.nfib) {
         const uint32_t h = g.divL.div(f);
         const uint32_t local = h * (uint32_t(D) * g.L) + (f - h * g.L);
-        const uint32_t m = g.has_ctrl ? g.cstride.div(local) % D : 1u;
+        const uint32_t m = ctrl_level(g, local);
         if (m != 0) {
             cplx<T>* p = psi + size_t(b) * g.N;
             cplx<T>* l = lam + size_t(b) * g.N;
@@ -179,10 +187,12 @@ qf_status with_dim_c(uint32_t D, F&& f) {
 CrGeom make_geom(const StateView& s, const CrotArgs& a) {
     CrGeom g{};
     g.has_ctrl = a.ctrl >= 0 ? 1 : 0;
-    g.L = ipow(s.D, s.n - 1 - uint32_t(a.tgt));
+    g.L = s.strides[a.tgt];
     g.divL.init(g.L);
-    g.cstride.init(a.ctrl >= 0 ? ipow(s.D, s.n - 1 - uint32_t(a.ctrl)) : 1u);
-    g.nfib = s.N / s.D;
+    g.cstride.init(a.ctrl >= 0 ? s.strides[a.ctrl] : 1u);
+    g.divDc.init(a.ctrl >= 0 ? s.dims[a.ctrl] : 2u);
+    g.ntab = 2 * g.divDc.d;
+    g.nfib = s.N / s.dims[a.tgt];
     g.N = s.N;
     g.bpr = (g.nfib + kCB - 1) / kCB;
     g.kind = a.kind;
@@ -193,32 +203,32 @@ CrGeom make_geom(const StateView& s, const CrotArgs& a) {
 }
 
 template <typename T>
-CrTab<T> host_tab(const double* htab, uint32_t D) {
+CrTab<T> host_tab(const double* htab, uint32_t ntab) {
     CrTab<T> t{};
     if (htab)
-        for (uint32_t i = 0; i < 2 * D; ++i) t.t[i] = cmake<T>(T(htab[2 * i]), T(htab[2 * i + 1]));
+        for (uint32_t i = 0; i < ntab; ++i) t.t[i] = cmake<T>(T(htab[2 * i]), T(htab[2 * i + 1]));
     return t;
 }
 
 }  // namespace
 
 size_t crot_partial_doubles(const StateView& s) {
-    const uint32_t nfib = s.N / s.D;
+    const uint32_t nfib = s.N / s.dmin;
     return size_t((nfib + kCB - 1) / kCB) * s.batch;
 }
 
 qf_status launch_crot(const StateView& s, const CrotArgs& a, const void* dtab, size_t tab_stride, const double* htab,
                       hipStream_t st) {
     const CrGeom g = make_geom(s, a);
-    return with_dim_c(s.D, [&](auto dtag) -> qf_status {
+    return with_dim_c(s.dims[a.tgt], [&](auto dtag) -> qf_status {
         constexpr int D = decltype(dtag)::value;
         if (s.dtype == QF_C64)
             hipLaunchKernelGGL((k_crot<float, D>), dim3(g.bpr * s.batch), dim3(kCB), 0, st,
-                               reinterpret_cast<cplx<float>*>(s.amps), g, host_tab<float>(htab, s.D),
+                               reinterpret_cast<cplx<float>*>(s.amps), g, host_tab<float>(htab, g.ntab),
                                reinterpret_cast<const cplx<float>*>(dtab), tab_stride);
         else
             hipLaunchKernelGGL((k_crot<double, D>), dim3(g.bpr * s.batch), dim3(kCB), 0, st,
-                               reinterpret_cast<cplx<double>*>(s.amps), g, host_tab<double>(htab, s.D),
+                               reinterpret_cast<cplx<double>*>(s.amps), g, host_tab<double>(htab, g.ntab),
                                reinterpret_cast<const cplx<double>*>(dtab), tab_stride);
         return check_launch("controlled rotation");
     });
@@ -227,17 +237,17 @@ qf_status launch_crot(const StateView& s, const CrotArgs& a, const void* dtab, s
 qf_status launch_crot_adj(const StateView& s, void* lam, const CrotArgs& a, const void* dtab, size_t tab_stride,
                           const double* htab, double* partial, double* out, uint32_t ostride, hipStream_t st) {
     const CrGeom g = make_geom(s, a);
-    return with_dim_c(s.D, [&](auto dtag) -> qf_status {
+    return with_dim_c(s.dims[a.tgt], [&](auto dtag) -> qf_status {
         constexpr int D = decltype(dtag)::value;
         if (s.dtype == QF_C64)
             hipLaunchKernelGGL((k_crot_adj<float, D>), dim3(g.bpr * s.batch), dim3(kCB), 0, st,
                                reinterpret_cast<cplx<float>*>(s.amps), reinterpret_cast<cplx<float>*>(lam), g,
-                               host_tab<float>(htab, s.D), reinterpret_cast<const cplx<float>*>(dtab), tab_stride,
+                               host_tab<float>(htab, g.ntab), reinterpret_cast<const cplx<float>*>(dtab), tab_stride,
                                partial);
         else
             hipLaunchKernelGGL((k_crot_adj<double, D>), dim3(g.bpr * s.batch), dim3(kCB), 0, st,
                                reinterpret_cast<cplx<double>*>(s.amps), reinterpret_cast<cplx<double>*>(lam), g,
-                               host_tab<double>(htab, s.D), reinterpret_cast<const cplx<double>*>(dtab), tab_stride,
+                               host_tab<double>(htab, g.ntab), reinterpret_cast<const cplx<double>*>(dtab), tab_stride,
                                partial);
         QF_CHECK(check_launch("controlled rotation adjoint"));
         hipLaunchKernelGGL(k_crot_reduce, dim3(s.batch), dim3(kCB), 0, st, partial, g.bpr, out, ostride);

@@ -272,10 +272,10 @@ qf_status launch_mfma_regs(const StateView& s, const FusedGeom& g, const void* B
 }  // namespace
 
 qf_status launch_fused(const StateView& s, int k, int q0, const void* B, hipStream_t st, bool real) {
-    const uint32_t K = ipow(s.D, k);
+    const uint32_t K = span(s, q0, k);
     FusedGeom g{};
     g.K = K;
-    g.L = ipow(s.D, s.n - q0 - k);
+    g.L = s.strides[q0 + k - 1];
     g.nfib = s.total / K;
     const size_t esz = s.dtype == QF_C64 ? 8 : 16;
     uint32_t nt = 64;

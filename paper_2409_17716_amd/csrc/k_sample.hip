@@ -146,7 +146,11 @@ uint64_t scan_ws_doubles(uint64_t seg, uint64_t nseg) {
 
 qf_status launch_sample(const StateView& s, int m, const int32_t* qudits, uint64_t shots, const double* u,
                         int64_t* counts, int32_t* samples, hipStream_t st) {
-    const uint64_t K = m == 0 ? uint64_t(s.N) : uint64_t(ipow(s.D, uint32_t(m)));
+    uint64_t K = s.N;
+    if (m > 0) {
+        K = 1;
+        for (int i = 0; i < m; ++i) K *= s.dims[qudits[i]];
+    }
     const uint64_t bins = K * s.batch;
     const uint64_t draws = shots * s.batch;
     QF_RETURN_IF(bins >= (1ull << 32) || draws >= (1ull << 32), QF_ERANGE, "batch * bins or batch * shots >= 2^32");

@@ -29,7 +29,7 @@ qf_status combine_terms(const StateView& v, int32_t nterms, const int32_t* term_
                         std::vector<int>& active, std::vector<double>& table);
 size_t adj_axis_partial_doubles(const StateView& s);
 qf_status launch_adj_axis(const StateView& s, void* lam, int q, const double* W, double* partial, double* mout,
-                          uint32_t nslots, uint32_t slot, hipStream_t st);
+                          uint32_t nslots, uint32_t slot, uint32_t slot_elems, hipStream_t st);
 
 using cd = std::complex<double>;
 using Mat = std::vector<cd>;  // row-major D x D
@@ -95,15 +95,15 @@ static qf_op slab_op(const qf_op& o) {
     return t;
 }
 
-// Table of a controlled rotation for control levels m = 0..D-1 (2 D complex
-// entries, interleaved FP64; layout in k_crot.hip): x, y types
+// Table of a controlled rotation for control levels m = 0..nlev-1 (2 nlev
+// complex entries, interleaved FP64; layout in k_crot.hip): x, y types
 // (cos(m t / 2), sin(m t / 2)) at 2m; z type exp(-i m t a / 2) (levels below
 // j) at 2m and exp(+i m t a j / 2) (level j) at 2m + 1, a = sqrt(2/(j(j+1))).
 // The inverse is R(-m t).
-static void crot_table(const qf_op& o, int D, const double* theta, bool inverse, std::vector<double>& out) {
-    out.assign(size_t(4) * D, 0.0);
+static void crot_table(const qf_op& o, int nlev, const double* theta, bool inverse, std::vector<double>& out) {
+    out.assign(size_t(4) * nlev, 0.0);
     const double t = theta[o.param] * (inverse ? -1.0 : 1.0);
-    for (int m = 0; m < D; ++m) {
+    for (int m = 0; m < nlev; ++m) {
         if (o.kind == QF_OP_CRZ) {
             const double a = std::sqrt(2.0 / (double(o.j) * (o.j + 1)));
             out[4 * m] = std::cos(-0.5 * m * t * a);
@@ -293,7 +293,8 @@ struct ProfRec {
 }  // namespace qf
 
 struct qf_plan {
-    int D = 0, n = 0, dtype = 0, nparams = 0;
+    int D = 0, n = 0, dtype = 0, nparams = 0;  // D = 0: the qudits' dimensions differ
+    std::vector<int> dims;            // per-qudit dimensions (all D for a uniform register)
     int group = 1;                    // register-round group size
     qf_plan_opts opts{};
     std::vector<qf::Gate> gates;
@@ -344,6 +345,7 @@ struct qf_plan {
     // Exchanges everything, including the ownership of device buffers and events.
     void swap_with(qf_plan& o) {
         std::swap(D, o.D);
+        dims.swap(o.dims);
         std::swap(n, o.n);
         std::swap(dtype, o.dtype);
         std::swap(nparams, o.nparams);
@@ -409,7 +411,8 @@ static const char* kFamilies[] = {"stage", "stage_adj", "fused", "axis", "ctrl",
                                   "crot", "crot_adj"};
 enum Family { F_STAGE, F_STAGE_ADJ, F_FUSED, F_AXIS, F_CTRL, F_DIAG, F_ADJ_AXIS, F_CKPT, F_CROT, F_CROT_ADJ, F_COUNT };
 
-static qf_status validate_op(const qf_op& o, int D, int n, int nparams) {
+static qf_status validate_op(const qf_op& o, const std::vector<int>& dims, int nparams) {
+    const int n = int(dims.size());
     auto qok = [&](int q) { return q >= 0 && q < n; };
     switch (o.kind) {
         case QF_OP_H:
@@ -424,13 +427,14 @@ static qf_status validate_op(const qf_op& o, int D, int n, int nparams) {
         case QF_OP_RX:
         case QF_OP_RY:
             QF_RETURN_IF(!qok(o.q0), QF_EINVAL, "rotation qudit %d outside [0, %d)", o.q0, n);
-            QF_RETURN_IF(!(o.j >= 0 && o.j < o.k && o.k < D), QF_EINVAL, "levels (%d, %d) need 0 <= j < k < D", o.j,
-                         o.k);
+            QF_RETURN_IF(!(o.j >= 0 && o.j < o.k && o.k < dims[o.q0]), QF_EINVAL,
+                         "levels (%d, %d) need 0 <= j < k < %d", o.j, o.k, dims[o.q0]);
             QF_RETURN_IF(o.param < 0 || o.param >= nparams, QF_EINVAL, "param %d outside [0, %d)", o.param, nparams);
             break;
         case QF_OP_RZ:
             QF_RETURN_IF(!qok(o.q0), QF_EINVAL, "rotation qudit %d outside [0, %d)", o.q0, n);
-            QF_RETURN_IF(!(o.j >= 1 && o.j < D), QF_EINVAL, "R_z level j = %d needs 1 <= j < D", o.j);
+            QF_RETURN_IF(!(o.j >= 1 && o.j < dims[o.q0]), QF_EINVAL, "R_z level j = %d needs 1 <= j < %d", o.j,
+                         dims[o.q0]);
             QF_RETURN_IF(o.param < 0 || o.param >= nparams, QF_EINVAL, "param %d outside [0, %d)", o.param, nparams);
             break;
         case QF_OP_CSUM:
@@ -445,14 +449,17 @@ static qf_status validate_op(const qf_op& o, int D, int n, int nparams) {
             QF_RETURN_IF(!qok(o.q0) || !qok(o.q1) || o.q0 == o.q1, QF_EINVAL, "controlled rotation on (%d, %d)", o.q0,
                          o.q1);
             if (o.kind == QF_OP_CRZ)
-                QF_RETURN_IF(!(o.j >= 1 && o.j < D), QF_EINVAL, "R_z level j = %d needs 1 <= j < D", o.j);
+                QF_RETURN_IF(!(o.j >= 1 && o.j < dims[o.q1]), QF_EINVAL, "R_z level j = %d needs 1 <= j < %d", o.j,
+                             dims[o.q1]);
             else
-                QF_RETURN_IF(!(o.j >= 0 && o.j < o.k && o.k < D), QF_EINVAL, "levels (%d, %d) need 0 <= j < k < D",
-                             o.j, o.k);
+                QF_RETURN_IF(!(o.j >= 0 && o.j < o.k && o.k < dims[o.q1]), QF_EINVAL,
+                             "levels (%d, %d) need 0 <= j < k < %d", o.j, o.k, dims[o.q1]);
             QF_RETURN_IF(o.param < 0 || o.param >= nparams, QF_EINVAL, "param %d outside [0, %d)", o.param, nparams);
             break;
         case QF_OP_SWAP:
             QF_RETURN_IF(!qok(o.q0) || !qok(o.q1) || o.q0 == o.q1, QF_EINVAL, "SWAP of (%d, %d)", o.q0, o.q1);
+            QF_RETURN_IF(dims[o.q0] != dims[o.q1], QF_EINVAL, "SWAP of qudits of dimensions %d and %d", dims[o.q0],
+                         dims[o.q1]);
             break;
         case QF_OP_MCX:
             QF_RETURN_IF(!qok(o.q1), QF_EINVAL, "MCX target %d outside [0, %d)", o.q1, n);
@@ -466,7 +473,11 @@ static qf_status validate_op(const qf_op& o, int D, int n, int nparams) {
         case QF_OP_U:
             QF_RETURN_IF(o.q1 < 1 || o.q0 < 0 || o.q0 + o.q1 > n, QF_EINVAL, "U on qudits %d..%d", o.q0,
                          o.q0 + o.q1 - 1);
-            QF_RETURN_IF(ipow(D, o.q1) > 1024, QF_ERANGE, "U block D^k > 1024");
+            {
+                uint64_t K = 1;
+                for (int q = o.q0; q < o.q0 + o.q1; ++q) K *= uint64_t(dims[q]);
+                QF_RETURN_IF(K > 1024, QF_ERANGE, "U block of %llu > 1024 levels", (unsigned long long)K);
+            }
             QF_RETURN_IF(o.mat == nullptr, QF_EINVAL, "U matrix is NULL");
             break;
         default:
@@ -491,12 +502,14 @@ static int shift_of(const qf_op& o, int c, int D) {
     return ((v % D) + D) % D;
 }
 
-static void cz_table(int D, bool inverse, Mat& out) {
+// Controlled phase w_t^(x_c x_t) over (x_c, x_t), w_t = exp(2 pi i / d_t): the
+// clock gate of the target raised to the control digit.
+static void cz_table(int dc, int dt, bool inverse, Mat& out) {
     const double pi = 3.14159265358979323846;
-    out.assign(size_t(D) * D, cd(0, 0));
-    for (int a = 0; a < D; ++a)
-        for (int b = 0; b < D; ++b)
-            out[size_t(a) * D + b] = std::polar(1.0, 2 * pi * double((a * b) % D) / D * (inverse ? -1.0 : 1.0));
+    out.assign(size_t(dc) * dt, cd(0, 0));
+    for (int a = 0; a < dc; ++a)
+        for (int b = 0; b < dt; ++b)
+            out[size_t(a) * dt + b] = std::polar(1.0, 2 * pi * double((a * b) % dt) / dt * (inverse ? -1.0 : 1.0));
 }
 
 // ---- per-gate schedule ----
@@ -588,9 +601,14 @@ static void build_steps(qf_plan* p) {
     }
 }
 
+// Number of control levels of a controlled rotation's table (2 for a lone
+// rotation run as a slab: m = 0 unused, m = 1 the rotation).
+static int ctrl_levels(const qf_plan* p, const qf_op& o) { return o.q0 >= 0 ? p->dims[o.q0] : 2; }
+
 static Mat step_matrix(const qf_plan* p, const Step& s, const double* theta) {
-    Mat U = identity(p->D);
-    for (int gi : s.gates) U = matmul(gate_matrix(p->gates[gi].op, p->D, theta), U, p->D);
+    const int d = p->dims[s.q];
+    Mat U = identity(d);
+    for (int gi : s.gates) U = matmul(gate_matrix(p->gates[gi].op, d, theta), U, d);
     return U;
 }
 
@@ -601,27 +619,28 @@ static qf_status run_step(const qf_plan* p, const Step& s, const StateView& v, c
             if (s.slab) {
                 const qf_op so = slab_op(p->gates[s.gates[0]].op);
                 std::vector<double> tab;
-                crot_table(so, p->D, theta, inverse, tab);
+                crot_table(so, ctrl_levels(p, so), theta, inverse, tab);
                 return launch_crot(v, crot_args(so), nullptr, 0, tab.data(), st);
             }
             Mat U = step_matrix(p, s, theta);
-            if (inverse) U = dagger(U, p->D);
+            if (inverse) U = dagger(U, p->dims[s.q]);
             std::vector<double> buf;
             to_interleaved(U, buf);
             return launch_apply_1q(v, s.q, buf.data(), st);
         }
         case ST_CTRL: {
-            int32_t sh[kMaxDim];
+            int32_t sh[kMaxDim] = {};
             const qf_op& o = p->gates[s.gates[0]].op;
-            for (int c = 0; c < p->D; ++c) {
-                const int v0 = shift_of(o, c, p->D);
-                sh[c] = inverse ? (p->D - v0) % p->D : v0;
+            const int dt = p->dims[s.q], nc = s.q2 >= 0 ? p->dims[s.q2] : 1;
+            for (int c = 0; c < nc; ++c) {
+                const int v0 = shift_of(o, c, dt);
+                sh[c] = inverse ? (dt - v0) % dt : v0;
             }
             return launch_ctrl(v, s.q2, s.q, sh, st);
         }
         case ST_DIAG: {
             Mat t;
-            cz_table(p->D, inverse, t);
+            cz_table(p->dims[s.q], p->dims[s.q2], inverse, t);
             std::vector<double> buf;
             to_interleaved(t, buf);
             const int32_t qs[2] = {s.q, s.q2};
@@ -634,7 +653,7 @@ static qf_status run_step(const qf_plan* p, const Step& s, const StateView& v, c
         case ST_CROT: {
             const qf_op& o = p->gates[s.gates[0]].op;
             std::vector<double> tab;
-            crot_table(o, p->D, theta, inverse, tab);
+            crot_table(o, ctrl_levels(p, o), theta, inverse, tab);
             return launch_crot(v, crot_args(o), nullptr, 0, tab.data(), st);
         }
         case ST_PERM:
@@ -1440,7 +1459,7 @@ static qf_status upload_mats(const qf_plan* p, PassList& L, const double* theta,
             } else if (h.type == SOP_PHASE) {
                 for (size_t j = 0; j < h.g.size(); ++j) {
                     Mat t;
-                    cz_table(D, h.g[j].inv, t);
+                    cz_table(D, D, h.g[j].inv, t);
                     if (p->dtype == QF_C64)
                         put_mat<float>(L.hmats, ps.mat_off + so.ptab[j], t);
                     else
@@ -1590,6 +1609,9 @@ static qf_status check_plan_state(const qf_plan* p, const qf_state* s, StateView
     QF_RETURN_IF(int(v.D) != p->D || int(v.n) != p->n || v.dtype != p->dtype, QF_EINVAL,
                  "state (dim %u, n %u, dtype %d) does not match the plan (dim %d, n %d, dtype %d)", v.D, v.n, v.dtype,
                  p->D, p->n, p->dtype);
+    for (int q = 0; q < p->n; ++q)
+        QF_RETURN_IF(int(v.dims[q]) != p->dims[q], QF_EINVAL, "qudit %d has dimension %u in the state, %d in the plan",
+                     q, v.dims[q], p->dims[q]);
     return QF_OK;
 }
 
@@ -1598,7 +1620,7 @@ static qf_status check_plan_state(const qf_plan* p, const qf_state* s, StateView
 // after gate i (forward order), M = sum_f psi_f lam_f^dagger after the run.
 static void add_group_grad(const qf_plan* p, const std::vector<int>& fwd_gates, const double* theta,
                            const double* M, double* grad) {
-    const int D = p->D;
+    const int D = p->dims[p->gates[fwd_gates[0]].op.q0];
     const int m = int(fwd_gates.size());
     std::vector<Mat> suffix(m + 1);
     suffix[m] = identity(D);
@@ -1625,8 +1647,8 @@ static qf_status check_norm_env(const StateView& v, hipStream_t st) {
     const double tol = std::atof(e);
     if (!(tol > 0.0)) return QF_OK;
     std::vector<int> active{0};
-    std::vector<double> table(2 * v.D, 0.0);
-    for (uint32_t d = 0; d < v.D; ++d) table[2 * d] = 1.0;
+    std::vector<double> table(2 * v.dims[0], 0.0);
+    for (uint32_t d = 0; d < v.dims[0]; ++d) table[2 * d] = 1.0;
     double* out = nullptr;
     QF_CHECK(dev_malloc_async(reinterpret_cast<void**>(&out), size_t(v.batch) * 2 * sizeof(double), st, "norm check"));
     qf_status rs = launch_expect(v, active, table, out, st);
@@ -1650,36 +1672,54 @@ using namespace qf;
 
 extern "C" {
 
-qf_status qf_plan_create(int32_t dim, int32_t n, int32_t dtype, const qf_op* ops, int32_t nops, int32_t nparams,
-                         const qf_plan_opts* opts, qf_plan** out) {
+}  // extern "C"
+
+// Plan creation for per-qudit dimensions; dim = the common dimension, or 0
+// when they differ (then only the per-gate schedules exist).
+static qf_status create_plan(const std::vector<int>& dims, int32_t dtype, const qf_op* ops, int32_t nops,
+                             int32_t nparams, const qf_plan_opts* opts, qf_plan** out) {
     QF_RETURN_IF(out == nullptr, QF_EINVAL, "out is NULL");
     *out = nullptr;
-    QF_RETURN_IF(dim < 2 || dim > kMaxDim, QF_ERANGE, "dim %d outside 2..%d", dim, kMaxDim);
+    const int n = int(dims.size());
     QF_RETURN_IF(n < 1 || n > 32, QF_EINVAL, "n = %d outside 1..32", n);
+    int dim = dims[0];
+    for (int d : dims) {
+        QF_RETURN_IF(d < 2 || d > kMaxDim, QF_ERANGE, "dim %d outside 2..%d", d, kMaxDim);
+        if (d != dim) dim = 0;
+    }
+    const bool mixed = dim == 0;
     QF_RETURN_IF(dtype != QF_C64 && dtype != QF_C128, QF_EDTYPE, "unknown dtype %d", dtype);
     QF_RETURN_IF(nops < 0 || (nops > 0 && ops == nullptr), QF_EINVAL, "bad op list");
     QF_RETURN_IF(nparams < 0, QF_EINVAL, "nparams < 0");
     {
         uint64_t N = 1;
-        for (int i = 0; i < n; ++i) N *= uint64_t(dim);
-        QF_RETURN_IF(N >= (1ull << 32), QF_ERANGE, "dim^n exceeds 2^32 amplitudes");
+        for (int d : dims) N *= uint64_t(d);
+        QF_RETURN_IF(N >= (1ull << 32), QF_ERANGE, "the register exceeds 2^32 amplitudes");
     }
     for (int i = 0; i < nops; ++i) {
-        qf_status st = validate_op(ops[i], dim, n, nparams);
+        qf_status st = validate_op(ops[i], dims, nparams);
         if (st != QF_OK) return set_error(st, "op %d: %s", i, qf_last_error());
     }
     std::unique_ptr<qf_plan> p(new (std::nothrow) qf_plan);
     QF_RETURN_IF(!p, QF_ENOMEM, "plan allocation failed");
     p->D = dim;
+    p->dims = dims;
     p->n = n;
     p->dtype = dtype;
     p->nparams = nparams;
     if (opts) p->opts = *opts;
     QF_RETURN_IF(p->opts.fuse < 0 || p->opts.fuse > 3, QF_EINVAL, "fuse = %d outside 0..3", p->opts.fuse);
-    QF_RETURN_IF(p->opts.group_digits < 0 || p->opts.group_digits > max_group_size(uint32_t(dim)), QF_EINVAL,
-                 "group_digits = %d outside 0..%d for dim %d", p->opts.group_digits, max_group_size(uint32_t(dim)),
-                 dim);
-    p->group = p->opts.group_digits > 0 ? p->opts.group_digits : default_group(dim, dtype);
+    if (mixed) {
+        // mixed dimensions: the per-gate schedules only
+        if (p->opts.fuse == 0) p->opts.fuse = 2;
+        QF_RETURN_IF(p->opts.fuse == 3, QF_EUNSUPPORTED, "fuse = 3 needs qudits of one dimension");
+        QF_RETURN_IF(p->opts.ckpt_every != 0, QF_EUNSUPPORTED, "checkpoints need qudits of one dimension");
+    }
+    const int gdim = mixed ? 2 : dim;  // register-round group sizes are a stage option
+    QF_RETURN_IF(p->opts.group_digits < 0 || p->opts.group_digits > max_group_size(uint32_t(gdim)), QF_EINVAL,
+                 "group_digits = %d outside 0..%d for dim %d", p->opts.group_digits, max_group_size(uint32_t(gdim)),
+                 gdim);
+    p->group = p->opts.group_digits > 0 ? p->opts.group_digits : default_group(gdim, dtype);
     QF_RETURN_IF(p->opts.tile_digits < 0 || p->opts.tile_digits > kMaxTileDims || p->opts.adj_tile_digits < 0 ||
                      p->opts.adj_tile_digits > kMaxTileDims || p->opts.low_digits < 0 || p->opts.ckpt_every < 0 ||
                      p->opts.stage_kernel < 0 || p->opts.stage_kernel > 2 || p->opts.pipe_wgs < 0 ||
@@ -1692,7 +1732,8 @@ qf_status qf_plan_create(int32_t dim, int32_t n, int32_t dtype, const qf_op* ops
         g.op = ops[i];
         g.op.mat = nullptr;
         if (ops[i].kind == QF_OP_U) {
-            const size_t K = ipow(dim, ops[i].q1);
+            size_t K = 1;
+            for (int q = ops[i].q0; q < ops[i].q0 + ops[i].q1; ++q) K *= size_t(dims[q]);
             g.mat.resize(K * K);
             g.real = true;
             for (size_t e = 0; e < K * K; ++e) {
@@ -1773,6 +1814,23 @@ qf_status qf_plan_create(int32_t dim, int32_t n, int32_t dtype, const qf_op* ops
     return QF_OK;
 }
 
+extern "C" {
+
+qf_status qf_plan_create(int32_t dim, int32_t n, int32_t dtype, const qf_op* ops, int32_t nops, int32_t nparams,
+                         const qf_plan_opts* opts, qf_plan** out) {
+    if (out) *out = nullptr;
+    QF_RETURN_IF(n < 1 || n > 32, QF_EINVAL, "n = %d outside 1..32", n);
+    return create_plan(std::vector<int>(size_t(n), dim), dtype, ops, nops, nparams, opts, out);
+}
+
+qf_status qf_plan_create_dims(const int32_t* dims, int32_t n, int32_t dtype, const qf_op* ops, int32_t nops,
+                              int32_t nparams, const qf_plan_opts* opts, qf_plan** out) {
+    if (out) *out = nullptr;
+    QF_RETURN_IF(dims == nullptr, QF_EINVAL, "dims is NULL");
+    QF_RETURN_IF(n < 1 || n > 32, QF_EINVAL, "n = %d outside 1..32", n);
+    return create_plan(std::vector<int>(dims, dims + n), dtype, ops, nops, nparams, opts, out);
+}
+
 int32_t qf_plan_num_stages(const qf_plan* plan) {
     if (!plan) return -1;
     return !staged(plan) ? int32_t(plan->steps.size()) : int32_t(plan->fwd.passes.size());
@@ -1849,11 +1907,11 @@ qf_status qf_adjoint_grad(qf_plan* plan, const qf_state* psi, const qf_state* la
     std::vector<int> active;
     std::vector<double> table;
     if (!seed) QF_CHECK(combine_terms(v, nterms, term_qudit, term_diag, active, table));
-    std::vector<double> table_re(active.size() * v.D);
+    std::vector<double> table_re(table.size() / 2);
     for (size_t i = 0; i < table_re.size(); ++i) table_re[i] = table[2 * i];
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const int D = plan->D;
-    const size_t E = size_t(D) * D;
+    const size_t E = size_t(v.dmax) * v.dmax;  // M entries per slot (the largest qudit's D x D)
     const bool stg = staged(plan);
     const int nslots = stg ? plan->rev.nslots : plan->nslots;
     if (stg) QF_CHECK(check_ckpt_source(plan, v));
@@ -1922,22 +1980,23 @@ qf_status qf_adjoint_grad(qf_plan* plan, const qf_state* psi, const qf_state* la
             if (s.type == ST_AXIS && s.slab) {
                 const qf_op so = slab_op(plan->gates[s.gates[0]].op);
                 std::vector<double> tab;
-                crot_table(so, D, theta, true, tab);
+                crot_table(so, ctrl_levels(plan, so), theta, true, tab);
                 rs = launch_crot_adj(v, lam->amps, crot_args(so), nullptr, 0, tab.data(), partial, crout + s.cr_slot,
                                      uint32_t(ncr), st);
             } else if (s.type == ST_AXIS && s.has_param) {
-                Mat W = dagger(step_matrix(plan, s, theta), D);
+                Mat W = dagger(step_matrix(plan, s, theta), plan->dims[s.q]);
                 std::vector<double> buf;
                 to_interleaved(W, buf);
                 hipEvent_t a;
                 rs = prof_begin(plan, st, &a);
                 if (rs == QF_OK)
-                    rs = launch_adj_axis(v, lam->amps, s.q, buf.data(), partial, mdev, plan->nslots, s.slot, st);
+                    rs = launch_adj_axis(v, lam->amps, s.q, buf.data(), partial, mdev, plan->nslots, s.slot,
+                                         uint32_t(E), st);
                 if (rs == QF_OK) rs = prof_end(plan, st, a, F_ADJ_AXIS, 4.0 * state_bytes(v));
             } else if (s.type == ST_CROT) {
                 const qf_op& o = plan->gates[s.gates[0]].op;
                 std::vector<double> tab;
-                crot_table(o, D, theta, true, tab);
+                crot_table(o, ctrl_levels(plan, o), theta, true, tab);
                 rs = launch_crot_adj(v, lam->amps, crot_args(o), nullptr, 0, tab.data(), partial, crout + s.cr_slot,
                                      uint32_t(ncr), st);
             } else {
@@ -2089,6 +2148,7 @@ qf_status qf_plan_autotune(qf_plan* plan, const qf_state* s, const double* theta
     StateView v;
     QF_CHECK(check_plan_state(plan, s, v));
     QF_RETURN_IF(plan->nparams > 0 && theta == nullptr, QF_EINVAL, "theta is NULL");
+    QF_RETURN_IF(plan->D == 0, QF_EUNSUPPORTED, "autotuning needs qudits of one dimension");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const uint64_t key = plan_key(plan, v.batch);
     std::vector<qf_op> ops;
@@ -2301,25 +2361,12 @@ qf_status qf_plan_bind(qf_plan* plan, int64_t batch) {
     size_t pd = 1;
     for (const Pass& ps : plan->rev.passes)
         if (ps.tile) pd = std::max(pd, size_t(ps.nslots) * ps.geom.ntiles * size_t(batch) * E * 2);
-    if (plan->rev.ncr > 0) {
-        StateView vb{};
-        vb.n = plan->n;
-        vb.D = D;
-        vb.N = uint32_t(N);
-        vb.batch = uint32_t(batch);
-        pd = std::max(pd, crot_partial_doubles(vb));
-    }
+    if (plan->rev.ncr > 0) pd = std::max(pd, crot_partial_doubles(uniform_view(D, plan->n, batch, plan->dtype)));
     step(dev_alloc(reinterpret_cast<void**>(&plan->w_partial), pd * sizeof(double)));
     step(dev_alloc(reinterpret_cast<void**>(&plan->w_m),
                    size_t(batch) * std::max(plan->rev.nslots, 1) * E * 2 * sizeof(double)));
     step(dev_alloc(reinterpret_cast<void**>(&plan->w_contrib), size_t(batch) * std::max(nc, 1) * sizeof(double)));
-    StateView v{};
-    v.n = plan->n;
-    v.D = D;
-    v.N = uint32_t(N);
-    v.batch = uint32_t(batch);
-    v.total = uint32_t(N * uint64_t(batch));
-    v.dtype = plan->dtype;
+    StateView v = uniform_view(D, plan->n, batch, plan->dtype);
     step(dev_alloc(reinterpret_cast<void**>(&plan->w_expect), expect_ws_doubles(v) * sizeof(double)));
     if (rs == QF_OK && plan->seg_end.size() > 1) step(ensure_ckpt(plan, v));
     if (rs != QF_OK) {

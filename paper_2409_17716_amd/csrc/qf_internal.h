@@ -10,21 +10,53 @@
 namespace qf {
 
 constexpr int kMaxDim = 16;
+constexpr int kMaxQudits = 32;
 
-// A validated view of a qf_state.
+// A validated view of a qf_state.  Per-qudit dimensions and strides are
+// filled for every register; D is the common dimension, or 0 when the qudits'
+// dimensions differ (launchers that need one D then fail with an error).
 struct StateView {
     void* amps;
     uint32_t n;
     uint32_t D;
-    uint32_t N;       // D^n
+    uint32_t N;       // prod of the dimensions
     uint32_t batch;
     uint32_t total;   // batch * N  (< 2^32)
     int dtype;        // QF_C64 / QF_C128
+    uint32_t dims[kMaxQudits];     // d_q
+    uint32_t strides[kMaxQudits];  // S_q = d_{q+1} ... d_{n-1}
+    uint32_t dmin, dmax;
 };
 
 inline uint32_t ipow(uint32_t b, uint32_t e) {
     uint32_t r = 1;
     while (e--) r *= b;
+    return r;
+}
+
+// A view of a uniform register of batch registers with no amplitudes, for
+// sizing work arrays (D^n * batch < 2^32 is the caller's to check).
+inline StateView uniform_view(uint32_t D, uint32_t n, uint32_t batch, int dtype) {
+    StateView v{};
+    v.n = n;
+    v.D = v.dmin = v.dmax = D;
+    v.N = ipow(D, n);
+    v.batch = batch;
+    v.total = v.N * batch;
+    v.dtype = dtype;
+    uint32_t stride = 1;
+    for (int i = int(n) - 1; i >= 0; --i) {
+        v.dims[i] = D;
+        v.strides[i] = stride;
+        stride *= D;
+    }
+    return v;
+}
+
+// d_q0 * ... * d_{q0+k-1}
+inline uint32_t span(const StateView& s, int q0, int k) {
+    uint32_t r = 1;
+    for (int i = q0; i < q0 + k; ++i) r *= s.dims[i];
     return r;
 }
 

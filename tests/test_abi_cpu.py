@@ -236,3 +236,38 @@ def test_sample_validation(qf):
     assert f(ctypes.byref(big), 0, None, 10, u, cnt, smp, None) == qf.QF_ERANGE
     two = qf.qf_state(0x1000, 3, 3, 2, 0)
     assert f(ctypes.byref(two), 0, None, 1 << 31, u, cnt, None, None) == qf.QF_ERANGE  # batch * shots
+
+
+def test_mixed_dimension_validation(qf):
+    lib = qf.lib
+    d3 = (ctypes.c_int32 * 3)(2, 3, 4)
+    s = qf.qf_state(0x1000, 3, 0, 1, 0, d3)
+    bad_dim = qf.qf_state(0x1000, 3, 3, 1, 0, d3)  # dim must be 0 with dims
+    U = np.eye(4, dtype=np.complex128).view(np.float64)
+    pU = U.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert lib.qf_apply_1q(ctypes.byref(bad_dim), 0, pU, None) == qf.QF_EINVAL
+    d_bad = (ctypes.c_int32 * 3)(2, 17, 4)
+    assert lib.qf_apply_1q(ctypes.byref(qf.qf_state(0x1000, 3, 0, 1, 0, d_bad)), 0, pU, None) == qf.QF_ERANGE
+    assert lib.qf_apply_swap(ctypes.byref(s), 0, 2, None) == qf.QF_EINVAL  # dimensions 2 and 4
+    f = lib.qf_apply_crot
+    assert f(ctypes.byref(s), qf.QF_OP_CRX, 2, 0, 0, 2, 0.5, None) == qf.QF_EINVAL  # level 2 of a qubit target
+    assert f(ctypes.byref(s), qf.QF_OP_CRZ, 0, 1, 3, 0, 0.5, None) == qf.QF_EINVAL  # j = 3 on a qutrit
+    assert lib.qf_apply_rot(ctypes.byref(s), qf.QF_OP_RY, 1, 1, 3, 0.5, None) == qf.QF_EINVAL
+    dg = (ctypes.c_int32 * 3)(1, 2, 4)  # digit 4 on the d = 4 qudit
+    assert lib.qf_state_init(ctypes.byref(s), dg, None) == qf.QF_EINVAL
+    # plans: mixed registers run the per-gate schedules
+    ops = [("h", 0), ("rx", 2, 1, 3, 0), ("csum", 0, 2), ("crz", 2, 1, 2, 1), ("cz", 1, 0)]
+    p = qf.Plan([2, 3, 4], 3, ops, 2)
+    assert p.num_stages == 5
+    for kw in ({"fuse": 3}, {"ckpt_every": 2}):
+        with pytest.raises(qf.QfError) as e:
+            qf.Plan([2, 3, 4], 3, ops, 2, **kw)
+        assert e.value.status == qf.QF_EUNSUPPORTED
+    for bad in ([("rx", 0, 0, 2, 0)], [("rz", 1, 3, 0)], [("swap", 0, 1)], [("crx", 0, 1, 1, 3, 0)]):
+        with pytest.raises(qf.QfError):
+            qf.Plan([2, 3, 4], 3, bad, 1)
+    assert qf.Plan([3, 3, 3], 3, [("h", 0), ("csum", 0, 1)], 0).num_stages >= 1  # equal dims: uniform plan
+    th = np.zeros(2)
+    o = qf.qf_plan_opts()
+    assert lib.qf_plan_autotune(p._h, ctypes.byref(s), th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                ctypes.byref(o), None) == qf.QF_EUNSUPPORTED
