@@ -168,24 +168,37 @@ def write_traffic(fetch_dir: str, write_dir: str, rdreq_dir: str | None = None, 
 def batched_measurement(steps: int) -> dict:
     """Ragged batch of 1024 circuits (768 qutrit, n ~ U{6..10}; 256 ququart,
     n ~ U{5..8}; depth-6 ansatz, own angles): init + forward + <sum Z_i> + adjoint
-    gradient of every circuit, as one HIP graph replay per step, against the same
-    circuits looped one at a time through the per-circuit path."""
+    gradient of every circuit, as one HIP graph replay per step.  Two set-ups:
+    default schedules on one stream, and the autotuned schedules (forward +
+    adjoint timed in the device-parameter mode at each group's batch) with one
+    stream per group; both against the same circuits looped one at a time
+    through the per-circuit path."""
     import numpy as np
     import torch
 
     import qf_inputs as qi
     from paper_2409_17716_amd.batched import PlainLoop, RaggedBatch
     circ = qi.config4()
-    rb = RaggedBatch(circ)
-    rb.capture()
-    for _ in range(2):
-        rb.replay()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        rb.replay()
-    torch.cuda.synchronize()
-    tb = (time.perf_counter() - t0) / steps
+
+    def run(**kw):
+        t0 = time.perf_counter()
+        rb = RaggedBatch(circ, **kw)
+        setup = time.perf_counter() - t0
+        rb.capture()
+        for _ in range(2):
+            rb.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            rb.replay()
+        torch.cuda.synchronize()
+        return rb, (time.perf_counter() - t0) / steps, setup
+
+    rb0, t_default, _ = run(tune=False, streams=False)
+    g_default = rb0.gradients()
+    del rb0
+    torch.cuda.empty_cache()
+    rb, tb, setup = run(tune=True, streams=True)
     pl = PlainLoop(circ)
     pl.step()
     torch.cuda.synchronize()
@@ -196,12 +209,17 @@ def batched_measurement(steps: int) -> dict:
     gb = rb.gradients()
     rel = max(float(np.abs(gb[i] - pl.grads[i]).max() / max(1e-12, np.abs(pl.grads[i]).max()))
               for i in range(len(circ)))
+    rel0 = max(float(np.abs(g_default[i] - pl.grads[i]).max() / max(1e-12, np.abs(pl.grads[i]).max()))
+               for i in range(len(circ)))
     return {"workload": "1024 circuits: 768 qutrit (n ~ U{6..10}) + 256 ququart (n ~ U{5..8}), depth-6 ansatz, "
                         "complex64; forward + Re<sum Z_i> + adjoint gradient per circuit",
             "circuits": len(circ), "amplitudes": int(sum(c.dim ** c.n for c in circ)), "groups": len(rb.groups),
             "batched_ms_per_step": round(tb * 1e3, 3), "batched_circuits_per_s": len(circ) / tb,
+            "batched_setup": "autotuned schedules, one stream per group", "tune_and_build_s": round(setup, 2),
+            "default_single_stream_ms_per_step": round(t_default * 1e3, 3),
             "plain_ms_per_step": round(tp * 1e3, 2), "plain_circuits_per_s": len(circ) / tp,
-            "speedup": tp / tb, "max_rel_grad_diff_vs_plain": rel}
+            "speedup": tp / tb, "max_rel_grad_diff_vs_plain": rel, "default_max_rel_grad_diff_vs_plain": rel0,
+            "schedules": rb.schedules()}
 
 
 def _cpu_model() -> str:

@@ -385,15 +385,29 @@ qf_status qf_adjoint_grad_dev(qf_plan* plan, const qf_state* psi, const qf_state
                               const int32_t* term_qudit, const double* term_diag,
                               double* grad, double* loss, uint32_t flags, void* stream);
 
+/* Autotuner flags. */
+#define QF_TUNE_ADJOINT 1u  /* time a forward pass plus an adjoint gradient (of <Z_0>) */
+#define QF_TUNE_BOUND   2u  /* only schedules the device-parameter mode accepts (stage  */
+                            /* plans), each timed bound to the state's batch with one    */
+                            /* angle vector shared by every register                     */
+
 /* Autotuner: times candidate schedules of this plan's circuit on the caller's
- * state s (stage tiles of the default size +-1 qudit with every register group
- * size, the one-sweep-per-op stage kernel, two-qudit dense blocks, per-qudit
- * runs), each as two forward passes timed with HIP events on `stream`, then
- * rebuilds the plan with the fastest options (written to *chosen if not NULL).
- * The winner is cached per (D, n, dtype, batch, gate structure) for the life of
- * the process.  s is overwritten (it holds the result of a forward pass).
- * Synchronises `stream`. */
-qf_status qf_plan_autotune(qf_plan* plan, const qf_state* s, const double* theta,
+ * state s (stage tiles of the default size +-1 qudit with every register-group
+ * size: group 1 applies each qudit's run of one-qudit gates as a D x D matrix,
+ * group 2 the runs of two qudits as one D^2 x D^2 block; the one-sweep-per-op
+ * and pipelined stage kernels; without QF_TUNE_BOUND also two-qudit dense
+ * blocks (fuse 3) and per-qudit-run sweeps (fuse 2)), each as two steps timed
+ * with HIP events on `stream` after one warm-up step, then rebuilds the plan
+ * with the fastest options (written to *chosen if not NULL; the rebuilt plan
+ * is not bound).  A step is a forward pass, plus the adjoint gradient with
+ * QF_TUNE_ADJOINT (a scratch adjoint state of the state's size is allocated
+ * for the call).  The winner is cached per (device architecture, D, n, dtype,
+ * batch, gate structure, flags) for the life of the process; with
+ * QF_TUNE_CACHE=<file> it is also appended to that file, and the file's
+ * entries are read on the first call, so later processes skip the timing.
+ * s is overwritten.  Synchronises `stream`.  Mixed-dimension plans:
+ * QF_EUNSUPPORTED. */
+qf_status qf_plan_autotune(qf_plan* plan, const qf_state* s, const double* theta, uint32_t flags,
                            qf_plan_opts* chosen, void* stream);
 
 void qf_plan_destroy(qf_plan* plan);
@@ -408,7 +422,8 @@ const char* qf_last_error(void);
 /* Library version as major*10000 + minor*100 + patch. */
 int32_t qf_version(void);
 
-/* Releases library-wide state: the autotuner's cache of chosen options.  Plans
+/* Releases library-wide state: the autotuner's in-memory cache of chosen
+ * options (a QF_TUNE_CACHE file is kept and read again on demand).  Plans
  * stay valid (each owns its buffers until qf_plan_destroy).  Safe to call more
  * than once; the library re-creates the state on demand. */
 void qf_shutdown(void);
@@ -417,7 +432,8 @@ void qf_shutdown(void);
  *   QF_LOG=1               planner and autotuner choices on stderr;
  *   QF_CHECK_NORM=<tol>    after every qf_plan_forward, synchronise and fail
  *                          with QF_ERANGE if | |psi| - 1 | > tol for a register;
- *   QF_TEST_FAIL_ALLOC=1   every allocation fails with QF_ENOMEM (tests). */
+ *   QF_TEST_FAIL_ALLOC=1   every allocation fails with QF_ENOMEM (tests);
+ *   QF_TUNE_CACHE=<file>   the autotuner's persistent cache of chosen options. */
 
 #ifdef __cplusplus
 }

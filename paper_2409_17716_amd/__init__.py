@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(_PKG, "libqf.so")
 QF_OK, QF_EINVAL, QF_EDTYPE, QF_ERANGE, QF_ENOMEM, QF_EHIP, QF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 QF_C64, QF_C128 = 0, 1
 QF_SEED = 1  # adjoint flag: lam holds torch's gradient of the output state
+QF_TUNE_ADJOINT = 1  # autotuner flag: time forward + adjoint gradient
+QF_TUNE_BOUND = 2  # autotuner flag: device-parameter schedules only, timed bound
 (QF_OP_H, QF_OP_X, QF_OP_CLOCK, QF_OP_RX, QF_OP_RY, QF_OP_RZ, QF_OP_CSUM, QF_OP_CSHIFT, QF_OP_CZ,
  QF_OP_U, QF_OP_CRX, QF_OP_CRY, QF_OP_CRZ, QF_OP_SWAP, QF_OP_MCX) = range(15)
 
@@ -80,7 +82,7 @@ _SIGS = {
     "qf_plan_forward": [_P, _PS, _PD, _P],
     "qf_adjoint_grad": [_P, _PS, _PS, _PD, _I32, _PI32, _PD, _PD, ctypes.c_uint32, _P],
     "qf_plan_set_profiling": [_P, _I32],
-    "qf_plan_autotune": [_P, _PS, _PD, ctypes.POINTER(qf_plan_opts), _P],
+    "qf_plan_autotune": [_P, _PS, _PD, ctypes.c_uint32, ctypes.POINTER(qf_plan_opts), _P],
     "qf_plan_bind": [_P, ctypes.c_int64],
     "qf_plan_forward_dev": [_P, _PS, _P, ctypes.c_int64, _P],
     "qf_adjoint_grad_dev": [_P, _PS, _PS, _P, ctypes.c_int64, _I32, _PI32, _PD, _P, _P, ctypes.c_uint32, _P],
@@ -416,13 +418,17 @@ class Plan:
     def num_adjoint_stages(self) -> int:
         return lib.qf_plan_num_adjoint_stages(self._h)
 
-    def autotune(self, t, theta, stream=None) -> dict:
-        """qf_plan_autotune on state t (overwritten); returns the chosen options."""
+    def autotune(self, t, theta, adjoint: bool = False, bound: bool = False, stream=None) -> dict:
+        """qf_plan_autotune on state t (overwritten); returns the chosen options.
+        adjoint: time forward + adjoint gradient; bound: only device-parameter
+        schedules, timed bound to t's batch (the plan is left unbound)."""
         s = state_of(t, self.n, self.dim)
         th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
         o = qf_plan_opts()
-        _check(lib.qf_plan_autotune(self._h, ctypes.byref(s), th.ctypes.data_as(_PD), ctypes.byref(o),
+        flags = (QF_TUNE_ADJOINT if adjoint else 0) | (QF_TUNE_BOUND if bound else 0)
+        _check(lib.qf_plan_autotune(self._h, ctypes.byref(s), th.ctypes.data_as(_PD), flags, ctypes.byref(o),
                                     _stream(stream)))
+        self.bound = 0
         return {f: getattr(o, f) for f, _ in qf_plan_opts._fields_}
 
     # ---- device-parameter mode (graph-capturable) ----

@@ -5,7 +5,13 @@ stage plan over a batch of registers, with each register's angles (and clock
 exponents) in a device array.  One training step (init, forward, <O> and the
 adjoint gradient of every circuit) is then a fixed sequence of kernel launches
 with no host work, captured once in a HIP graph and replayed per step; new
-angles are written into the device arrays between replays.
+angles are written into the device arrays between replays.  Each group's
+launches go to a stream of their own (forked from and joined back into the
+capturing stream), so the graph holds one independent chain per group and the
+groups' small launches overlap on the GPU.  With tune=True the autotuner picks
+every group's schedule (tile size, register-group size: per-qudit D x D
+matrices or two-qudit D^2 x D^2 blocks, stage kernel) by timing forward plus
+adjoint in the device-parameter mode at the group's batch.
 
 ``plain_step`` runs the same circuits one at a time through the ordinary
 per-circuit path (host-built matrices, host gradient) for comparison.
@@ -59,13 +65,15 @@ class _Group:
     grad: object = None            # device float64 [batch, nrot + nclock]
     loss: object = None            # device float64 [batch, 2]
     terms: list = field(default_factory=list)
+    options: dict = field(default_factory=dict)  # the schedule options the plan was built with
+    stream: object = None
 
 
 class RaggedBatch:
     """A ragged batch of circuits (uneven n and D) stepped as one HIP graph."""
 
     def __init__(self, circuits: Sequence, dtype: str = "c64",
-                 terms: Callable[[int], list] = default_terms):
+                 terms: Callable[[int], list] = default_terms, tune: bool = False, streams: bool = True):
         torch = _torch()
         self.circuits = list(circuits)
         self.dtype = dtype
@@ -85,7 +93,6 @@ class RaggedBatch:
             P = c0.nparams + nclock
             g = _Group(idx=idx, dim=c0.dim, n=c0.n, nrot=c0.nparams, nclock=nclock)
             g.plan = Plan(c0.dim, c0.n, ops, P, dtype)
-            g.plan.bind(len(idx))
             th = np.zeros((len(idx), P))
             for r, ci in enumerate(idx):
                 c = self.circuits[ci]
@@ -94,6 +101,11 @@ class RaggedBatch:
             g.theta = torch.tensor(th, dtype=torch.float64, device="cuda")
             g.psi = new_state(g.n, g.dim, dtype, batch=len(idx))
             g.lam = new_state(g.n, g.dim, dtype, batch=len(idx))
+            if tune:
+                qf_state_init(g.psi, g.n, g.dim, None)
+                g.options = g.plan.autotune(g.psi, th[0], adjoint=True, bound=True)
+            g.plan.bind(len(idx))
+            g.stream = torch.cuda.Stream() if streams else None
             g.grad = torch.zeros((len(idx), P), dtype=torch.float64, device="cuda")
             g.loss = torch.zeros((len(idx), 2), dtype=torch.float64, device="cuda")
             g.terms = terms(g.n)
@@ -104,13 +116,35 @@ class RaggedBatch:
     def amplitudes(self) -> int:
         return sum(c.dim ** c.n for c in self.circuits)
 
+    def _group_step(self, g: _Group) -> None:
+        P = g.nrot + g.nclock
+        qf_state_init(g.psi, g.n, g.dim, None)
+        g.plan.forward_dev(g.psi, g.theta, P)
+        g.plan.adjoint_grad_dev(g.psi, g.lam, g.theta, P, g.terms, g.grad, g.loss)
+
     def step(self) -> None:
-        """Enqueue one training step of every circuit on the current stream."""
+        """Enqueue one training step of every circuit: each group on its own
+        stream, forked from and joined back into the current stream."""
+        torch = _torch()
+        cur = torch.cuda.current_stream()
         for g in self.groups:
-            P = g.nrot + g.nclock
-            qf_state_init(g.psi, g.n, g.dim, None)
-            g.plan.forward_dev(g.psi, g.theta, P)
-            g.plan.adjoint_grad_dev(g.psi, g.lam, g.theta, P, g.terms, g.grad, g.loss)
+            if g.stream is None:
+                self._group_step(g)
+                continue
+            g.stream.wait_stream(cur)
+            with torch.cuda.stream(g.stream):
+                self._group_step(g)
+        for g in self.groups:
+            if g.stream is not None:
+                cur.wait_stream(g.stream)
+
+    def schedules(self) -> List[dict]:
+        """Per group: D, n, batch and the schedule options its plan was built with
+        (those the autotuner chose when tune=True)."""
+        keep = ("fuse", "tile_digits", "group_digits", "stage_kernel", "pipe_wgs")
+        return [{"D": g.dim, "n": g.n, "batch": len(g.idx), "stages": g.plan.num_stages,
+                 "adjoint_stages": g.plan.num_adjoint_stages, **{k: g.options.get(k, 0) for k in keep}}
+                for g in self.groups]
 
     def capture(self) -> None:
         """Capture step() in a HIP graph (after one eager warm-up step)."""

@@ -18,6 +18,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "qf_internal.h"
@@ -2132,29 +2133,155 @@ static uint64_t plan_key(const qf_plan* p, uint32_t batch) {
     return h;
 }
 
+// Chosen options per (device architecture, circuit structure, batch, flags):
+// kept for the life of the process and, when QF_TUNE_CACHE names a file,
+// read from it once and appended to after every new choice.
 struct TuneCache {
     std::vector<std::pair<uint64_t, qf_plan_opts>> entries;
+    bool loaded = false;
 };
 static TuneCache g_tune;
+static std::mutex g_tune_mu;
+
+static constexpr int kOptFields = 10;
+
+static void opts_to_array(const qf_plan_opts& o, int32_t* a) {
+    const int32_t v[kOptFields] = {o.fuse, o.tile_digits, o.low_digits, o.ckpt_every, o.adj_tile_digits,
+                                   o.stage_kernel, o.group_digits, o.pipe_wgs, o.tile_order, o.tile_search};
+    std::memcpy(a, v, sizeof(v));
+}
+
+static qf_plan_opts opts_from_array(const int32_t* a) {
+    qf_plan_opts o{};
+    o.fuse = a[0];
+    o.tile_digits = a[1];
+    o.low_digits = a[2];
+    o.ckpt_every = a[3];
+    o.adj_tile_digits = a[4];
+    o.stage_kernel = a[5];
+    o.group_digits = a[6];
+    o.pipe_wgs = a[7];
+    o.tile_order = a[8];
+    o.tile_search = a[9];
+    return o;
+}
+
+// File format: one choice per line, "<key as 16 hex digits> <10 option values>".
+static void tune_cache_load() {
+    if (g_tune.loaded) return;
+    g_tune.loaded = true;
+    const char* path = std::getenv("QF_TUNE_CACHE");
+    if (path == nullptr || path[0] == '\0') return;
+    FILE* f = std::fopen(path, "r");
+    if (f == nullptr) return;
+    char line[512];
+    size_t n = 0;
+    while (std::fgets(line, sizeof(line), f)) {
+        unsigned long long key = 0;
+        int32_t a[kOptFields];
+        if (std::sscanf(line, "%llx %d %d %d %d %d %d %d %d %d %d", &key, &a[0], &a[1], &a[2], &a[3], &a[4], &a[5],
+                        &a[6], &a[7], &a[8], &a[9]) == 1 + kOptFields) {
+            g_tune.entries.push_back({uint64_t(key), opts_from_array(a)});
+            ++n;
+        }
+    }
+    std::fclose(f);
+    log_msg("autotune cache %s: %zu entries", path, n);
+}
+
+static void tune_cache_store(uint64_t key, const qf_plan_opts& o) {
+    g_tune.entries.push_back({key, o});
+    const char* path = std::getenv("QF_TUNE_CACHE");
+    if (path == nullptr || path[0] == '\0') return;
+    FILE* f = std::fopen(path, "a");
+    if (f == nullptr) {
+        log_msg("autotune cache %s: cannot append", path);
+        return;
+    }
+    int32_t a[kOptFields];
+    opts_to_array(o, a);
+    std::fprintf(f, "%016llx %d %d %d %d %d %d %d %d %d %d\n", (unsigned long long)key, a[0], a[1], a[2], a[3], a[4],
+                 a[5], a[6], a[7], a[8], a[9]);
+    std::fclose(f);
+}
+
+// FNV-1a of the current device's architecture name (e.g. "gfx950:sramecc+:xnack-").
+static qf_status arch_hash(uint64_t* out) {
+    int dev = 0;
+    QF_HIP_CHECK(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    QF_HIP_CHECK(hipGetDeviceProperties(&prop, dev));
+    uint64_t h = 1469598103934665603ull;
+    for (const char* c = prop.gcnArchName; *c; ++c) {
+        h ^= uint64_t(uint8_t(*c));
+        h *= 1099511628211ull;
+    }
+    *out = h;
+    return QF_OK;
+}
+
+// Device buffers and observable used to time candidates.
+struct TuneBench {
+    const qf_state* s = nullptr;
+    qf_state sl{};                  // adjoint state (scratch of the state's size)
+    const double* theta = nullptr;  // host
+    double* theta_dev = nullptr;    // bound mode: shared by every register (stride 0)
+    double* grad_dev = nullptr;
+    double* loss_dev = nullptr;
+    std::vector<double> grad_host;
+    int32_t term_q = 0;
+    std::vector<double> term_tab;   // Z on qudit 0
+    uint32_t flags = 0;
+    hipStream_t st = nullptr;
+};
+
+static qf_status tune_step(qf_plan* tp, TuneBench& b) {
+    const bool bound = (b.flags & QF_TUNE_BOUND) != 0, adj = (b.flags & QF_TUNE_ADJOINT) != 0;
+    void* stream = reinterpret_cast<void*>(b.st);
+    if (bound) {
+        QF_CHECK(qf_plan_forward_dev(tp, b.s, b.theta_dev, 0, stream));
+        if (adj)
+            QF_CHECK(qf_adjoint_grad_dev(tp, b.s, &b.sl, b.theta_dev, 0, 1, &b.term_q, b.term_tab.data(), b.grad_dev,
+                                         b.loss_dev, 0, stream));
+        return QF_OK;
+    }
+    QF_CHECK(qf_plan_forward(tp, b.s, b.theta, stream));
+    if (adj)
+        QF_CHECK(qf_adjoint_grad(tp, b.s, &b.sl, b.theta, 1, &b.term_q, b.term_tab.data(), b.grad_host.data(), 0,
+                                 stream));
+    return QF_OK;
+}
 
 }  // namespace qf
 
-extern "C" void qf_shutdown(void) { std::vector<std::pair<uint64_t, qf_plan_opts>>().swap(qf::g_tune.entries); }
+extern "C" void qf_shutdown(void) {
+    std::lock_guard<std::mutex> lock(qf::g_tune_mu);
+    std::vector<std::pair<uint64_t, qf_plan_opts>>().swap(qf::g_tune.entries);
+    qf::g_tune.loaded = false;
+}
 
 extern "C" {
 
-qf_status qf_plan_autotune(qf_plan* plan, const qf_state* s, const double* theta, qf_plan_opts* chosen,
-                           void* stream) {
+qf_status qf_plan_autotune(qf_plan* plan, const qf_state* s, const double* theta, uint32_t flags,
+                           qf_plan_opts* chosen, void* stream) {
     StateView v;
     QF_CHECK(check_plan_state(plan, s, v));
     QF_RETURN_IF(plan->nparams > 0 && theta == nullptr, QF_EINVAL, "theta is NULL");
+    QF_RETURN_IF((flags & ~uint32_t(QF_TUNE_ADJOINT | QF_TUNE_BOUND)) != 0, QF_EINVAL, "unknown flags 0x%x", flags);
     QF_RETURN_IF(plan->D == 0, QF_EUNSUPPORTED, "autotuning needs qudits of one dimension");
+    QF_CHECK(check_finite_theta(theta, plan->nparams));
+    const bool bound = (flags & QF_TUNE_BOUND) != 0;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const uint64_t key = plan_key(plan, v.batch);
+    uint64_t key = plan_key(plan, v.batch), ah = 0;
+    QF_CHECK(arch_hash(&ah));
+    key = (key ^ ah) * 1099511628211ull;
+    key = (key ^ uint64_t(flags)) * 1099511628211ull;
     std::vector<qf_op> ops;
     std::vector<std::vector<double>> mats;
     plan_ops(plan, ops, mats);
     qf_plan_opts best = plan->opts;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    tune_cache_load();
     bool cached = false;
     for (const auto& e : g_tune.entries)
         if (e.first == key) {
@@ -2162,8 +2289,11 @@ qf_status qf_plan_autotune(qf_plan* plan, const qf_state* s, const double* theta
             cached = true;
         }
     if (!cached) {
-        // candidates: stage plans over tile sizes and register groups, pair blocks,
-        // and the per-gate-run schedule
+        // candidates: stage plans over tile sizes and register-group sizes (group
+        // 1 applies each qudit's run as a D x D matrix, group 2 the runs of two
+        // qudits as one D^2 x D^2 block), the one-sweep-per-op and pipelined
+        // stage kernels; without QF_TUNE_BOUND also the two-qudit dense blocks
+        // (fuse 3) and the per-qudit-run sweeps (fuse 2)
         std::vector<qf_plan_opts> cand;
         int k0, r0;
         tile_shape(plan->D, plan->n, plan->dtype, 0, 0, false, k0, r0);
@@ -2195,48 +2325,86 @@ qf_status qf_plan_autotune(qf_plan* plan, const qf_state* s, const double* theta
                     cand.push_back(q);
                 }
         }
-        if (plan->D * plan->D >= 16) {
+        if (!bound && plan->D * plan->D >= 16) {
             qf_plan_opts o = plan->opts;
             o.fuse = 3;
             o.tile_digits = 0;
             o.group_digits = 0;
             cand.push_back(o);
         }
-        {
+        if (!bound) {
             qf_plan_opts o = plan->opts;
             o.fuse = 2;
             cand.push_back(o);
         }
-        hipEvent_t e0, e1;
-        QF_HIP_CHECK(hipEventCreate(&e0));
-        QF_HIP_CHECK(hipEventCreate(&e1));
+        TuneBench b;
+        b.s = s;
+        b.theta = theta;
+        b.flags = flags;
+        b.st = st;
+        b.term_tab.assign(2 * size_t(plan->D), 0.0);
+        for (int d = 0; d < plan->D; ++d) {
+            b.term_tab[2 * d] = std::cos(2 * 3.14159265358979323846 * d / plan->D);
+            b.term_tab[2 * d + 1] = std::sin(2 * 3.14159265358979323846 * d / plan->D);
+        }
+        b.grad_host.assign(size_t(v.batch) * std::max(plan->nparams, 1), 0.0);
+        b.sl = *s;
+        b.sl.amps = nullptr;
+        qf_status rs = QF_OK;
+        if (flags & QF_TUNE_ADJOINT) rs = dev_malloc(&b.sl.amps, state_bytes(v), "autotune adjoint state");
+        if (rs == QF_OK && bound) {
+            rs = dev_malloc(reinterpret_cast<void**>(&b.theta_dev), sizeof(double) * std::max(plan->nparams, 1),
+                            "autotune angles");
+            if (rs == QF_OK)
+                rs = dev_malloc(reinterpret_cast<void**>(&b.grad_dev),
+                                sizeof(double) * v.batch * std::max(plan->nparams, 1), "autotune gradients");
+            if (rs == QF_OK)
+                rs = dev_malloc(reinterpret_cast<void**>(&b.loss_dev), sizeof(double) * 2 * v.batch, "autotune loss");
+            if (rs == QF_OK && plan->nparams > 0 &&
+                hipMemcpy(b.theta_dev, theta, sizeof(double) * plan->nparams, hipMemcpyHostToDevice) != hipSuccess)
+                rs = set_error(QF_EHIP, "autotune: copy of the angles failed");
+        }
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (rs == QF_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+            rs = set_error(QF_EHIP, "autotune: event creation failed");
         float best_ms = 1e30f;
-        for (const qf_plan_opts& o : cand) {
+        size_t timed = 0;
+        for (size_t ci = 0; ci < cand.size() && rs == QF_OK; ++ci) {
+            const qf_plan_opts& o = cand[ci];
             qf_plan* tp = nullptr;
             if (qf_plan_create(plan->D, plan->n, plan->dtype, ops.data(), int32_t(ops.size()), plan->nparams, &o,
                                &tp) != QF_OK)
                 continue;  // e.g. a tile beyond the LDS size
-            qf_status rs = qf_plan_forward(tp, s, theta, stream);
-            if (rs == QF_OK) rs = hipEventRecord(e0, st) == hipSuccess ? QF_OK : QF_EHIP;
-            for (int rep = 0; rep < 2 && rs == QF_OK; ++rep) rs = qf_plan_forward(tp, s, theta, stream);
-            if (rs == QF_OK) rs = hipEventRecord(e1, st) == hipSuccess ? QF_OK : QF_EHIP;
+            qf_status cs = bound ? qf_plan_bind(tp, v.batch) : QF_OK;
+            if (cs == QF_OK) cs = tune_step(tp, b);  // warm-up
+            if (cs == QF_OK) cs = hipEventRecord(e0, st) == hipSuccess ? QF_OK : QF_EHIP;
+            for (int rep = 0; rep < 2 && cs == QF_OK; ++rep) cs = tune_step(tp, b);
+            if (cs == QF_OK) cs = hipEventRecord(e1, st) == hipSuccess ? QF_OK : QF_EHIP;
             float ms = 0.f;
-            if (rs == QF_OK && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
-                ms < best_ms) {
-                best_ms = ms;
-                best = o;
+            if (cs == QF_OK && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
+                ++timed;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = o;
+                }
             }
             qf_plan_destroy(tp);
+            if (cs == QF_EHIP) rs = cs;  // a failing HIP call ends the search
         }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        QF_RETURN_IF(best_ms >= 1e30f, QF_EHIP, "no autotuning candidate ran");
-        log_msg("autotune D=%d n=%d batch %u: %zu candidates, chose fuse %d tile %d group %d kernel %d (%.3f ms for "
-                "two forwards)", plan->D, plan->n, v.batch, cand.size(), best.fuse, best.tile_digits, best.group_digits,
-                best.stage_kernel, double(best_ms));
-        g_tune.entries.push_back({key, best});
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipStreamSynchronize(st);
+        for (void* q : {b.sl.amps, static_cast<void*>(b.theta_dev), static_cast<void*>(b.grad_dev),
+                        static_cast<void*>(b.loss_dev)})
+            if (q) (void)hipFree(q);
+        if (rs != QF_OK) return rs;
+        QF_RETURN_IF(timed == 0, QF_EHIP, "no autotuning candidate ran");
+        log_msg("autotune D=%d n=%d batch %u flags %u: %zu of %zu candidates timed, chose fuse %d tile %d group %d "
+                "kernel %d pipe %d (%.3f ms for two steps)", plan->D, plan->n, v.batch, flags, timed, cand.size(),
+                best.fuse, best.tile_digits, best.group_digits, best.stage_kernel, best.pipe_wgs, double(best_ms));
+        tune_cache_store(key, best);
     }
-    // rebuild this plan with the chosen options
+    // rebuild this plan with the chosen options (unbound)
     qf_plan* np = nullptr;
     QF_CHECK(qf_plan_create(plan->D, plan->n, plan->dtype, ops.data(), int32_t(ops.size()), plan->nparams, &best, &np));
     plan->swap_with(*np);

@@ -269,5 +269,9 @@ def test_mixed_dimension_validation(qf):
     assert qf.Plan([3, 3, 3], 3, [("h", 0), ("csum", 0, 1)], 0).num_stages >= 1  # equal dims: uniform plan
     th = np.zeros(2)
     o = qf.qf_plan_opts()
-    assert lib.qf_plan_autotune(p._h, ctypes.byref(s), th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+    assert lib.qf_plan_autotune(p._h, ctypes.byref(s), th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0,
                                 ctypes.byref(o), None) == qf.QF_EUNSUPPORTED
+    u = qf.Plan(3, 3, [("h", 0), ("rx", 1, 0, 1, 0)], 1)
+    su = qf.qf_state(0x1000, 3, 3, 1, 0)
+    assert lib.qf_plan_autotune(u._h, ctypes.byref(su), th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 4,
+                                ctypes.byref(o), None) == qf.QF_EINVAL  # unknown flag

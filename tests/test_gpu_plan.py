@@ -201,6 +201,62 @@ def test_autotune_keeps_parity(qf):
     assert _grad_close(g, ref, 1e-4, "c64")
 
 
+@pytest.mark.parametrize("adjoint,bound", [(True, False), (True, True), (False, True)])
+def test_autotune_flags_keep_parity(qf, adjoint, bound):
+    """Tuning on forward + adjoint, and on device-parameter schedules only
+    (timed bound to the batch): the rebuilt plan matches the oracle in both
+    modes, and bound tuning chooses a stage plan."""
+    import torch
+    c = qi.config2(n=7, layers=2)
+    terms = qi.zsum_terms(c.n)
+    p = qf.plan_for(c, "c64")
+    scratch = qf.new_state(c.n, c.dim, "c64", batch=3)
+    qf.qf_state_init(scratch, c.n, c.dim, None)
+    chosen = p.autotune(scratch, c.theta, adjoint=adjoint, bound=bound)
+    if bound:
+        assert chosen["fuse"] == 0
+    want = sim.run(c)
+    ref = grad.adjoint(c, terms)
+    t = qf.new_state(c.n, c.dim, "c64")
+    qf.qf_state_init(t, c.n, c.dim, None)
+    p.forward(t, c.theta)
+    assert maxabs(to_np(t), want) <= 2e-5
+    lam = qf.new_state(c.n, c.dim, "c64")
+    assert _grad_close(p.adjoint_grad(t, lam, c.theta, terms), ref, 1e-4, "c64")
+    if bound:
+        p.bind(3)
+        th = torch.tensor(np.tile(c.theta, (3, 1)), dtype=torch.float64, device="cuda")
+        psi = qf.new_state(c.n, c.dim, "c64", batch=3)
+        lam = qf.new_state(c.n, c.dim, "c64", batch=3)
+        g = torch.zeros((3, c.nparams), dtype=torch.float64, device="cuda")
+        qf.qf_state_init(psi, c.n, c.dim, None)
+        p.forward_dev(psi, th, c.nparams)
+        p.adjoint_grad_dev(psi, lam, th, c.nparams, terms, g)
+        for b in range(3):
+            assert _grad_close(g.cpu().numpy()[b], ref, 1e-4, "c64")
+
+
+def test_autotune_persistent_cache(qf, tmp_path, monkeypatch):
+    """QF_TUNE_CACHE: the first tuning appends its choice to the file; after the
+    in-memory cache is dropped, a new plan of the same circuit takes the choice
+    from the file without timing again."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("QF_TUNE_CACHE", str(path))
+    qf.qf_shutdown()
+    c = qi.config2(n=6, layers=2)
+    t = qf.new_state(c.n, c.dim, "c64")
+    qf.qf_state_init(t, c.n, c.dim, None)
+    first = qf.plan_for(c, "c64").autotune(t, c.theta, adjoint=True)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1 and len(lines[0].split()) == 11
+    qf.qf_shutdown()
+    again = qf.plan_for(c, "c64").autotune(t, c.theta, adjoint=True)
+    assert again == first
+    assert len(path.read_text().splitlines()) == 1
+    monkeypatch.delenv("QF_TUNE_CACHE")
+    qf.qf_shutdown()
+
+
 @pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("kernel", [0, 1, 2])
 def test_tile_order(qf, order, kernel):
