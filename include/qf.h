@@ -397,7 +397,9 @@ qf_status qf_adjoint_grad_dev(qf_plan* plan, const qf_state* psi, const qf_state
  * group 2 the runs of two qudits as one D^2 x D^2 block; the one-sweep-per-op
  * and pipelined stage kernels; without QF_TUNE_BOUND also two-qudit dense
  * blocks (fuse 3) and per-qudit-run sweeps (fuse 2)), each as two steps timed
- * with HIP events on `stream` after one warm-up step, then rebuilds the plan
+ * with HIP events on `stream` after one warm-up step; with QF_TUNE_ADJOINT a
+ * second round then varies the adjoint tile of the best stage plan (from one
+ * qudit below its default up to the whole register).  It then rebuilds the plan
  * with the fastest options (written to *chosen if not NULL; the rebuilt plan
  * is not bound).  A step is a forward pass, plus the adjoint gradient with
  * QF_TUNE_ADJOINT (a scratch adjoint state of the state's size is allocated

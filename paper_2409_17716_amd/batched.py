@@ -5,10 +5,16 @@ stage plan over a batch of registers, with each register's angles (and clock
 exponents) in a device array.  One training step (init, forward, <O> and the
 adjoint gradient of every circuit) is then a fixed sequence of kernel launches
 with no host work, captured once in a HIP graph and replayed per step; new
-angles are written into the device arrays between replays.  Each group's
-launches go to a stream of their own (forked from and joined back into the
-capturing stream), so the graph holds one independent chain per group and the
-groups' small launches overlap on the GPU.  With tune=True the autotuner picks
+angles are written into the device arrays between replays.  The groups are
+spread over a few streams (forked from and joined back into the capturing
+stream) by longest-processing-time-first on their algorithmic bytes per step,
+so the graph holds that many independent chains of about equal length (with
+split=True a group with more than 1/streams of the amplitudes is first split
+into batch chunks, each with its own plan; measured slower on the 1024-circuit
+batch, whose largest group does not limit the step once the GPU is full) and the
+groups' small launches overlap on the GPU (HIP maps streams onto a handful of
+hardware queues, 4 by default, so more streams than that would share queues
+unevenly).  With tune=True the autotuner picks
 every group's schedule (tile size, register-group size: per-qudit D x D
 matrices or two-qudit D^2 x D^2 blocks, stage kernel) by timing forward plus
 adjoint in the device-parameter mode at the group's batch.
@@ -66,22 +72,32 @@ class _Group:
     loss: object = None            # device float64 [batch, 2]
     terms: list = field(default_factory=list)
     options: dict = field(default_factory=dict)  # the schedule options the plan was built with
-    stream: object = None
+    chain: int = 0                 # index of the stream the group's launches go to
 
 
 class RaggedBatch:
     """A ragged batch of circuits (uneven n and D) stepped as one HIP graph."""
 
     def __init__(self, circuits: Sequence, dtype: str = "c64",
-                 terms: Callable[[int], list] = default_terms, tune: bool = False, streams: bool = True):
+                 terms: Callable[[int], list] = default_terms, tune: bool = False, streams: int = 4,
+                 split: bool = False):
         torch = _torch()
         self.circuits = list(circuits)
         self.dtype = dtype
         groups: Dict[Tuple, List[int]] = {}
         for i, c in enumerate(self.circuits):
             groups.setdefault(_layout(c), []).append(i)
-        self.groups: List[_Group] = []
+        # a group holding more than a share of the amplitudes is split into
+        # batch chunks, so that the chains can be balanced
+        share = sum(c.dim ** c.n for c in self.circuits) / max(1, int(streams))
+        chunks = []
         for key, idx in sorted(groups.items(), key=lambda kv: (kv[0][0], kv[0][1])):
+            amps = len(idx) * self.circuits[idx[0]].dim ** self.circuits[idx[0]].n
+            parts = min(len(idx), max(1, int(np.ceil(amps / share)))) if streams and split else 1
+            for p in range(parts):
+                chunks.append((key, idx[p * len(idx) // parts:(p + 1) * len(idx) // parts]))
+        self.groups: List[_Group] = []
+        for key, idx in chunks:
             c0 = self.circuits[idx[0]]
             ops, nclock = [], 0
             for op in c0.ops:
@@ -105,12 +121,26 @@ class RaggedBatch:
                 qf_state_init(g.psi, g.n, g.dim, None)
                 g.options = g.plan.autotune(g.psi, th[0], adjoint=True, bound=True)
             g.plan.bind(len(idx))
-            g.stream = torch.cuda.Stream() if streams else None
             g.grad = torch.zeros((len(idx), P), dtype=torch.float64, device="cuda")
             g.loss = torch.zeros((len(idx), 2), dtype=torch.float64, device="cuda")
             g.terms = terms(g.n)
             self.groups.append(g)
+        # longest processing time first: each group, heaviest first, joins the
+        # chain with the least work so far
+        self.streams = [torch.cuda.Stream() for _ in range(min(int(streams), len(self.groups)))]
+        load = [0.0] * max(1, len(self.streams))
+        for g in sorted(self.groups, key=self.group_bytes, reverse=True):
+            g.chain = int(np.argmin(load))
+            load[g.chain] += self.group_bytes(g)
+        self.chain_bytes = load
         self.graph = None
+
+    @staticmethod
+    def group_bytes(g: _Group) -> float:
+        """Algorithmic HBM bytes of one step of a group: each forward pass reads
+        and writes the batch's states once, each adjoint pass psi and lam."""
+        state = g.psi.numel() * g.psi.element_size()
+        return state * (2 * g.plan.num_stages + 4 * g.plan.num_adjoint_stages)
 
     @property
     def amplitudes(self) -> int:
@@ -123,27 +153,30 @@ class RaggedBatch:
         g.plan.adjoint_grad_dev(g.psi, g.lam, g.theta, P, g.terms, g.grad, g.loss)
 
     def step(self) -> None:
-        """Enqueue one training step of every circuit: each group on its own
-        stream, forked from and joined back into the current stream."""
+        """Enqueue one training step of every circuit: each chain of groups on
+        its stream, forked from and joined back into the current stream."""
         torch = _torch()
         cur = torch.cuda.current_stream()
-        for g in self.groups:
-            if g.stream is None:
+        if not self.streams:
+            for g in self.groups:
                 self._group_step(g)
-                continue
-            g.stream.wait_stream(cur)
-            with torch.cuda.stream(g.stream):
-                self._group_step(g)
-        for g in self.groups:
-            if g.stream is not None:
-                cur.wait_stream(g.stream)
+            return
+        for si, s in enumerate(self.streams):
+            s.wait_stream(cur)
+            with torch.cuda.stream(s):
+                for g in self.groups:
+                    if g.chain == si:
+                        self._group_step(g)
+        for s in self.streams:
+            cur.wait_stream(s)
 
     def schedules(self) -> List[dict]:
         """Per group: D, n, batch and the schedule options its plan was built with
         (those the autotuner chose when tune=True)."""
-        keep = ("fuse", "tile_digits", "group_digits", "stage_kernel", "pipe_wgs")
+        keep = ("fuse", "tile_digits", "adj_tile_digits", "group_digits", "stage_kernel", "pipe_wgs")
         return [{"D": g.dim, "n": g.n, "batch": len(g.idx), "stages": g.plan.num_stages,
-                 "adjoint_stages": g.plan.num_adjoint_stages, **{k: g.options.get(k, 0) for k in keep}}
+                 "adjoint_stages": g.plan.num_adjoint_stages, "stream": g.chain,
+                 "step_bytes": int(self.group_bytes(g)), **{k: g.options.get(k, 0) for k in keep}}
                 for g in self.groups]
 
     def capture(self) -> None:

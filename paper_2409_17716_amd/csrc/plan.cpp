@@ -2368,28 +2368,51 @@ qf_status qf_plan_autotune(qf_plan* plan, const qf_state* s, const double* theta
         if (rs == QF_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
             rs = set_error(QF_EHIP, "autotune: event creation failed");
         float best_ms = 1e30f;
-        size_t timed = 0;
-        for (size_t ci = 0; ci < cand.size() && rs == QF_OK; ++ci) {
-            const qf_plan_opts& o = cand[ci];
+        size_t timed = 0, ntried = 0;
+        // times one candidate (two steps after a warm-up step); < 0: it did not run
+        auto time_opts = [&](const qf_plan_opts& o) -> float {
+            ++ntried;
             qf_plan* tp = nullptr;
             if (qf_plan_create(plan->D, plan->n, plan->dtype, ops.data(), int32_t(ops.size()), plan->nparams, &o,
                                &tp) != QF_OK)
-                continue;  // e.g. a tile beyond the LDS size
+                return -1.f;  // e.g. a tile beyond the LDS size
             qf_status cs = bound ? qf_plan_bind(tp, v.batch) : QF_OK;
             if (cs == QF_OK) cs = tune_step(tp, b);  // warm-up
             if (cs == QF_OK) cs = hipEventRecord(e0, st) == hipSuccess ? QF_OK : QF_EHIP;
             for (int rep = 0; rep < 2 && cs == QF_OK; ++rep) cs = tune_step(tp, b);
             if (cs == QF_OK) cs = hipEventRecord(e1, st) == hipSuccess ? QF_OK : QF_EHIP;
-            float ms = 0.f;
-            if (cs == QF_OK && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
+            float ms = -1.f;
+            if (cs == QF_OK && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
                 ++timed;
-                if (ms < best_ms) {
+            else
+                ms = -1.f;
+            qf_plan_destroy(tp);
+            if (cs == QF_EHIP) rs = cs;  // a failing HIP call ends the search
+            return ms;
+        };
+        for (size_t ci = 0; ci < cand.size() && rs == QF_OK; ++ci) {
+            const float ms = time_opts(cand[ci]);
+            if (ms >= 0.f && ms < best_ms) {
+                best_ms = ms;
+                best = cand[ci];
+            }
+        }
+        // second phase when the adjoint is timed: the adjoint tile of the best
+        // stage plan, from one qudit below its default up to the whole register
+        if (rs == QF_OK && (flags & QF_TUNE_ADJOINT) && best.fuse == 0 && best_ms < 1e30f) {
+            int ka, ra;
+            tile_shape(plan->D, plan->n, plan->dtype, best.adj_tile_digits, best.low_digits, true, ka, ra);
+            const qf_plan_opts base = best;
+            for (int k = std::max(1, ka - 1); k <= plan->n && rs == QF_OK; ++k) {
+                if (k == ka) continue;
+                qf_plan_opts o = base;
+                o.adj_tile_digits = k;
+                const float ms = time_opts(o);
+                if (ms >= 0.f && ms < best_ms) {
                     best_ms = ms;
                     best = o;
                 }
             }
-            qf_plan_destroy(tp);
-            if (cs == QF_EHIP) rs = cs;  // a failing HIP call ends the search
         }
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
@@ -2400,8 +2423,9 @@ qf_status qf_plan_autotune(qf_plan* plan, const qf_state* s, const double* theta
         if (rs != QF_OK) return rs;
         QF_RETURN_IF(timed == 0, QF_EHIP, "no autotuning candidate ran");
         log_msg("autotune D=%d n=%d batch %u flags %u: %zu of %zu candidates timed, chose fuse %d tile %d group %d "
-                "kernel %d pipe %d (%.3f ms for two steps)", plan->D, plan->n, v.batch, flags, timed, cand.size(),
-                best.fuse, best.tile_digits, best.group_digits, best.stage_kernel, best.pipe_wgs, double(best_ms));
+                "kernel %d pipe %d adjoint tile %d (%.3f ms for two steps)", plan->D, plan->n, v.batch, flags, timed,
+                ntried, best.fuse, best.tile_digits, best.group_digits, best.stage_kernel, best.pipe_wgs,
+                best.adj_tile_digits, double(best_ms));
         tune_cache_store(key, best);
     }
     // rebuild this plan with the chosen options (unbound)

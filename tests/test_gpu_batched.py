@@ -72,8 +72,9 @@ def test_bound_mode_per_register_theta_and_checkpoints(qf, kernel):
         assert _close(gg[b], grad.adjoint(c, terms, theta=thetas[b]))
 
 
-@pytest.mark.parametrize("tune,streams", [(False, False), (False, True), (True, True)])
-def test_ragged_batch_graph_replays(qf, tune, streams):
+@pytest.mark.parametrize("tune,streams,split", [(False, 0, False), (False, 4, False), (True, 4, False),
+                                                (False, 16, False), (False, 3, True)])
+def test_ragged_batch_graph_replays(qf, tune, streams, split):
     """Ragged batch (D=3 and D=4 registers of uneven n) captured in one graph,
     on one stream or one stream per group, with default or autotuned
     schedules: every replay, with eager work and new angles between replays,
@@ -82,7 +83,7 @@ def test_ragged_batch_graph_replays(qf, tune, streams):
     from paper_2409_17716_amd.batched import PlainLoop, RaggedBatch
     circuits = qi.config4(count_d3=5, count_d4=3, layers=2)
     circuits = [c for c in circuits if c.n <= 7]
-    rb = RaggedBatch(circuits, tune=tune, streams=streams)
+    rb = RaggedBatch(circuits, tune=tune, streams=streams, split=split)
     for sch in rb.schedules():
         assert sch["fuse"] == 0 and sch["stages"] >= 1
     rb.capture()
