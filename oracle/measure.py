@@ -33,8 +33,9 @@ def sample_inverse_cdf(p: np.ndarray, u: np.ndarray) -> np.ndarray:
     no such index exists."""
     c = np.cumsum(np.asarray(p, dtype=np.float64))
     idx = np.searchsorted(c, np.asarray(u, dtype=np.float64) * c[-1], side="right")
-    # u * sum(p) can round up to sum(p) itself for u just below 1: such a draw
-    # belongs to the last bin with non-zero probability
+    # a product u * sum(p) that reaches sum(p) has no bin above it: u = 1, a
+    # subnormal sum (the product then rounds up to it), or a zero sum.  Such a
+    # draw belongs to the last bin with non-zero probability (bin 0 for a zero sum)
     return np.where(idx >= len(c), np.searchsorted(c, c[-1], side="left"), idx)
 
 

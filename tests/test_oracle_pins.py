@@ -560,6 +560,21 @@ def test_sampling_inverse_cdf_exact_cases():
     assert list(measure.sample_inverse_cdf(np.array([0.1, 0.0, 0.7, 0.2, 0.0, 0.0]), [0.0999, 0.1, 0.85])) == [0, 2, 3]
 
 
+def test_sampling_rule_when_the_draw_reaches_the_total():
+    """For a normal total, u * total < total for every u < 1 (round to
+    nearest), so the search always finds a bin.  The product reaches the total
+    for u = 1, for a subnormal total (the product rounds up: 5e-324 * u with
+    u = 1 - 2^-53 is 5e-324), and for a zero total; the draw then goes to the
+    last bin of non-zero probability, never to a trailing empty bin, and a
+    zero state gives bin 0."""
+    top = np.nextafter(1.0, 0.0)
+    assert top * 5e-324 == 5e-324
+    sub = np.array([5e-324, 5e-324, 0.0, 0.0])
+    assert list(measure.sample_inverse_cdf(sub, [0.0, top])) == [0, 1]
+    assert measure.sample_inverse_cdf(np.array([0.25, 0.75, 0.0]), [1.0])[0] == 1
+    assert list(measure.sample_inverse_cdf(np.zeros(5), [0.0, 0.5, top])) == [0, 0, 0]
+
+
 def test_sampling_matches_distribution_statistically():
     """Many shots of a random state's marginal: the histogram agrees with the
     probabilities (chi-square statistic below the 1e-6 tail of its
