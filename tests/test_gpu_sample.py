@@ -115,6 +115,24 @@ def test_zero_shots_and_zero_state(qf):
     assert np.all(c[:, 0] == 100) and c[:, 1:].sum() == 0 and int(s.abs().sum().item()) == 0
 
 
+def test_draws_that_reach_the_total(qf):
+    """A register whose probabilities are subnormal (amplitudes ~2e-162 in
+    complex128): u just below 1 rounds up to the total and goes to the last
+    outcome of non-zero probability, as does u = 1; the oracle agrees."""
+    import torch
+    D, n = 3, 3
+    psi = np.zeros(D ** n, dtype=np.complex128)
+    psi[[4, 11]] = 2.3e-162
+    t = to_dev(psi, "c128")
+    top = np.nextafter(1.0, 0.0)
+    u = np.array([0.0, 0.3, top, 1.0])
+    c, smp = qf.qf_sample(t, n, D, len(u), torch.from_numpy(u).cuda(), samples=True)
+    got = smp.cpu().numpy()
+    want = measure.sample_inverse_cdf(measure.probs(psi), u)
+    assert list(got) == list(want)
+    assert got[0] == 4 and got[2] == 11 and got[3] == 11  # never a trailing empty outcome
+
+
 def test_full_size_marginal_and_register(qf):
     """The 3^16 register in complex64: 10^5 shots of the full distribution and
     of a two-qudit marginal."""
