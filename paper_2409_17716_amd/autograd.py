@@ -18,6 +18,11 @@ rotation's derivative Im<lam|S|psi> on the way (adjoint method, Jones & Gacon,
 arXiv:2009.02823), so no per-gate state is stored; a plan with checkpoints
 keeps one state every ``ckpt_every`` gates.  Nothing synchronises the host.
 
+Registers of per-qudit dimensions (a circuit with ``dims``) have no bound
+plans; their DeviceCircuit runs the host-angle calls instead (``qf_plan_forward``
+and ``qf_adjoint_grad``, the same kernels with the angles copied to the host,
+which synchronises), with one angle vector shared by every register.
+
 The final state lives in the DeviceCircuit, so a backward pass finds it only if
 no later forward pass of the same DeviceCircuit overwrote it (and the reverse
 walk consumes it).  Otherwise the backward pass first runs the forward pass
@@ -42,24 +47,34 @@ def _torch():
 class DeviceCircuit:
     """A circuit bound to device buffers for ``batch`` registers of n qudits.
 
-    ``circuit``: any object with ``dim``, ``n``, ``ops`` (gate descriptors) and
-    ``nparams``; or pass ``dim``, ``n``, ``ops``, ``nparams`` directly.
+    ``circuit``: any object with ``dim`` (or per-qudit ``dims``), ``n``, ``ops``
+    (gate descriptors) and ``nparams``; or pass ``dim`` (an int or a list of
+    per-qudit dimensions), ``n``, ``ops``, ``nparams`` directly.
     ``digits``: initial basis state (n digits, or batch x n), default |0...0>.
     Extra keyword arguments are plan options (``ckpt_every``, ``tile_digits`` ...).
     """
 
-    def __init__(self, circuit=None, *, dim: Optional[int] = None, n: Optional[int] = None,
+    def __init__(self, circuit=None, *, dim=None, n: Optional[int] = None,
                  ops: Optional[Sequence[tuple]] = None, nparams: Optional[int] = None, dtype: str = "c64",
                  batch: int = 1, digits=None, **plan_opts):
         torch = _torch()
         if circuit is not None:
-            dim, n, ops, nparams = circuit.dim, circuit.n, circuit.ops, circuit.nparams
+            dim = list(circuit.dims) if hasattr(circuit, "dims") else circuit.dim
+            n, ops, nparams = circuit.n, circuit.ops, circuit.nparams
         if dim is None or n is None or ops is None or nparams is None:
             raise QfError(QF_EINVAL, "DeviceCircuit needs a circuit or dim, n, ops and nparams")
-        self.dim, self.n, self.nparams, self.batch, self.dtype = int(dim), int(n), int(nparams), int(batch), dtype
+        if not isinstance(dim, (int, np.integer)):
+            dim = [int(d) for d in dim]
+            if len(set(dim)) == 1:
+                dim = dim[0]
+        self.dim = dim if isinstance(dim, list) else int(dim)
+        self.n, self.nparams, self.batch, self.dtype = int(n), int(nparams), int(batch), dtype
         self.digits = None if digits is None else np.asarray(digits, dtype=np.int32)
         self.plan = Plan(self.dim, self.n, ops, self.nparams, dtype, **plan_opts)
-        self.plan.bind(self.batch)
+        # mixed dimensions: host-angle calls (no bound plans for them)
+        self.host = isinstance(self.dim, list)
+        if not self.host:
+            self.plan.bind(self.batch)
         self.psi = new_state(self.n, self.dim, dtype, self.batch)
         self.lam = new_state(self.n, self.dim, dtype, self.batch)
         self.grad = torch.zeros((self.batch, max(1, self.nparams)), dtype=torch.float64, device="cuda")
@@ -80,15 +95,30 @@ class DeviceCircuit:
                 raise QfError(QF_EINVAL, f"theta has {th.numel()} angles, the circuit {self.nparams}")
             return th, 0
         if th.dim() == 2 and th.shape == (self.batch, self.nparams):
+            if self.host:
+                raise QfError(QF_EINVAL, "per-register angles need qudits of one dimension")
             return th, self.nparams
         raise QfError(QF_EINVAL, f"theta must have shape ({self.nparams},) or ({self.batch}, {self.nparams})")
 
     def _forward(self, th, stride: int) -> int:
         qf_state_init(self.psi, self.n, self.dim, self.digits)
-        self.plan.forward_dev(self.psi, th, stride)
+        if self.host:
+            self.plan.forward(self.psi, th.cpu().numpy())
+        else:
+            self.plan.forward_dev(self.psi, th, stride)
         self._gen += 1
         self._held = self._gen
         return self._gen
+
+    def _adjoint(self, th, stride: int, terms, seed: bool = False) -> None:
+        """Gradient of every register into self.grad (the reverse walk consumes self.psi)."""
+        torch = _torch()
+        if self.host:
+            g = self.plan.adjoint_grad(self.psi, self.lam, th.cpu().numpy(), terms, seed=seed)
+            g = torch.from_numpy(np.ascontiguousarray(np.asarray(g).reshape(self.batch, -1)))
+            self.grad[:, :self.nparams].copy_(g)
+        else:
+            self.plan.adjoint_grad_dev(self.psi, self.lam, th, stride, terms, self.grad, seed=seed)
 
     def _final_state_for(self, th, stride: int, gen: int) -> None:
         """Make self.psi hold the final state of forward pass ``gen`` (re-running
@@ -114,8 +144,8 @@ class DeviceCircuit:
         return _Expectation.apply(theta, self, list(terms))
 
     def state(self, theta):
-        """The final state (a copy owned by the caller; shape (D^n,) for one
-        register, (batch, D^n) otherwise), differentiable in theta."""
+        """The final state (a copy owned by the caller; shape (N,) for one
+        register of N amplitudes, (batch, N) otherwise), differentiable in theta."""
         return _State.apply(theta, self)
 
 
@@ -140,7 +170,7 @@ class _Expectation(_function_base()):
         dc = ctx.dc
         th, stride = dc._angles(theta)
         dc._final_state_for(th, stride, ctx.gen)
-        dc.plan.adjoint_grad_dev(dc.psi, dc.lam, th, stride, ctx.terms, dc.grad)
+        dc._adjoint(th, stride, ctx.terms)
         return dc._param_grad(theta, gout), None, None
 
 
@@ -161,5 +191,5 @@ class _State(_function_base()):
         th, stride = dc._angles(theta)
         dc._final_state_for(th, stride, ctx.gen)
         dc.lam.copy_(g.reshape(-1))
-        dc.plan.adjoint_grad_dev(dc.psi, dc.lam, th, stride, None, dc.grad, seed=True)
+        dc._adjoint(th, stride, None, seed=True)
         return dc._param_grad(theta), None

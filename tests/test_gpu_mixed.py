@@ -269,3 +269,32 @@ def test_large_mixed_register(qf):
         lam = qf.new_state(c.n, c.dims, "c64")
         g = p.adjoint_grad(t, lam, c.theta, terms)
         assert _grad_close(g, ref, 1e-4, "c64"), np.abs(g - ref).max()
+
+
+def test_autograd_on_mixed_registers(qf):
+    """loss.backward() through the torch.autograd.Functions on a mixed register
+    (host-angle calls): the expectation over two registers and the paper's
+    state loss sum |t - psi|, against the mixed oracle's adjoint."""
+    import torch
+    from paper_2409_17716_amd.autograd import DeviceCircuit
+    c = qi.random_mixed_circuit([2, 3, 4, 3], 80, 7, kinds=["h", "rx", "ry", "rz", "csum", "cz", "crx", "cry",
+                                                             "crz", "mcx"])
+    terms = [(q, "z") for q in range(c.n)]
+    dc = DeviceCircuit(c, dtype="c128", batch=2)
+    assert dc.host
+    th = torch.tensor(c.theta, dtype=torch.float64, device="cuda", requires_grad=True)
+    L = dc.expectation(th, terms).sum()
+    L.backward()
+    assert abs(L.item() - 2 * mixed.loss(c, terms)) <= 1e-12
+    assert _grad_close(th.grad.cpu().numpy(), 2 * mixed.adjoint(c, terms), 1e-9, "c128")
+    target = _state(c.dims, 9)
+    dc2 = DeviceCircuit(c, dtype="c128")
+    th2 = torch.tensor(c.theta, dtype=torch.float64, device="cuda", requires_grad=True)
+    psi = dc2.state(th2)
+    loss = (torch.tensor(target, device="cuda") - psi).abs().sum()
+    loss.backward()
+    want = mixed.run(c)
+    r = target - want
+    ref = mixed.adjoint_seeded(c, -r / (2 * np.abs(r)))
+    assert abs(loss.item() - np.abs(r).sum()) <= 1e-10
+    assert _grad_close(th2.grad.cpu().numpy(), ref, 1e-9, "c128")
