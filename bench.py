@@ -16,9 +16,11 @@ recorded around each of its launches on the launch stream during the timed
 steps; its algorithmic traffic is one read and one write of the state per
 launch.  cpu_baseline times the FP64 oracle on a bounded sample of the same
 workload (the circuit's mix of rotations, clock gates and CSUM) on one host
-core and on several at once.  Extra records: the ragged 1024-circuit batch
-(graph replay vs the plain per-circuit loop) and two gradient legs (D=5 n=10
-forward + adjoint; D=10 n=8 forward + checkpointed adjoint).
+core and on several at once.  Extra records: one D x D gate on every qudit of
+the same register through the single-qudit sweep kernels (each launch's HBM
+fraction), the ragged 1024-circuit batch (graph replay vs the plain
+per-circuit loop) and two gradient legs (D=5 n=10 forward + adjoint; D=10 n=8
+forward + checkpointed adjoint).
 """
 from __future__ import annotations
 
@@ -221,6 +223,30 @@ def batched_measurement(steps: int) -> dict:
             "plain_ms_per_step": round(tp * 1e3, 2), "plain_circuits_per_s": len(circ) / tp,
             "speedup": tp / tb, "max_rel_grad_diff_vs_plain": rel, "default_max_rel_grad_diff_vs_plain": rel0,
             "schedules": rb.schedules()}
+
+
+def sweep_measurement(psi, n: int, D: int) -> dict:
+    """One Haar-random D x D gate on every qudit of the bench register through
+    qf_apply_1q (the single-qudit sweep kernels), each launch timed with HIP
+    events on the current stream after a warm-up launch; algorithmic traffic
+    2 N b per launch (one read and one write of the state)."""
+    import numpy as np
+
+    import paper_2409_17716_amd as qf
+    import qf_inputs as qi
+    N = D ** n
+    nbytes = 2 * N * psi.element_size()
+    rng = np.random.default_rng(11)
+    per = []
+    for q in range(n):
+        U = qi.random_unitary(D, rng)
+        qf.qf_apply_1q(psi, n, D, q, U)
+        ms = _event_time(lambda: qf.qf_apply_1q(psi, n, D, q, U), 3)
+        per.append(nbytes / (ms * 1e-3) / 1e9)
+    fr = [g / HBM_PEAK_GBS for g in per]
+    return {"kernel": "k_axis_wide / k_axis_narrow (qf_apply_1q)", "bytes_per_launch": nbytes,
+            "per_qudit_GBps": [round(g, 1) for g in per], "frac_mean": round(sum(fr) / len(fr), 4),
+            "frac_min": round(min(fr), 4), "frac_max": round(max(fr), 4), "peak": HBM_PEAK_GBS, "unit": "GB/s"}
 
 
 def _cpu_model() -> str:
@@ -505,14 +531,16 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64",
+        "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "qutrit HEA, D=3, n=16 (3^16 amplitudes, complex64), depth 10, batch 1: "
                                "init + 1280 gates + full probabilities + <Z_0>",
                    "dim": D, "n": n, "layers": 10, "gates": len(c.ops), "amplitudes": N, "batch": 1,
-                   "forward_passes": plan.num_stages},
+                   "forward_passes": plan.num_stages,
+                   "state": "complex64 (FP32 arithmetic, FP64 reductions)"},
         "roofline": roofline,
         "z0": [float(ev[0]), float(ev[1])],
+        "sweeps": sweep_measurement(psi, n, D),
     }
     if not a.no_batched:
         out["batched"] = batched_measurement(max(1, a.steps // 2))
