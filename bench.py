@@ -48,13 +48,16 @@ def _args():
     ap.add_argument("--no-batched", action="store_true", help="skip the ragged-batch measurement")
     ap.add_argument("--pmc-workload", action="store_true",
                     help="run only the counter workload: two plain copies of the state size, then one step")
-    ap.add_argument("--profile-workload", choices=["stage", "axis", "fused", "adjoint", "batched"],
+    ap.add_argument("--profile-workload", choices=["stage", "axis", "fused", "adjoint", "batched", "next"],
                     help="run only a short workload for rocprofv3 (kernel traces and counters), printing its "
                          "own HIP-event timings: stage = --pmc-workload; axis = one random unitary on each of "
                          "the 16 qudits of the 3^16 state; fused = dense blocks K = 100 (real, D=10 n=8) and "
                          "K = 49 (complex, D=7 n=9); adjoint = the D=5 n=10 forward + adjoint gradient; "
-                         "batched = one graph replay of the 1024-circuit batch")
+                         "batched = one graph replay of the 1024-circuit batch; next = the controlled-rotation, "
+                         "slab, SWAP, MCX, shots and mixed-register kernels")
     ap.add_argument("--no-legs", action="store_true", help="skip the D=5 n=10 and D=10 n=8 gradient legs")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the controlled-rotation, slab, SWAP, MCX, shots and mixed-register record")
     ap.add_argument("--write-traffic", nargs="+", metavar="DIR",
                     help="turn rocprofv3 --pmc runs of --profile-workload stage (FETCH_SIZE, WRITE_SIZE, and "
                          "optionally the read- and write-request counters) into profiles/stage_d3_n16_traffic.json")
@@ -249,6 +252,83 @@ def sweep_measurement(psi, n: int, D: int) -> dict:
             "frac_min": round(min(fr), 4), "frac_max": round(max(fr), 4), "peak": HBM_PEAK_GBS, "unit": "GB/s"}
 
 
+def next_rows_measurement() -> dict:
+    """The kernels of the controlled rotation, the slab rotation, SWAP, MCX and
+    shots on the 3^16 complex64 register, and one-qudit sweeps plus a plan on a
+    mixed register of dims [2, 3, 4, 5] x 4 (120^4 = 207.4M amplitudes), each
+    timed with HIP events (warm-up, then 5 launches) against its algorithmic
+    bytes: the amplitudes the operation must read and write (a gate reads and
+    writes only the amplitudes it changes; shots read the state and write the
+    histogram).  Where the changed amplitudes are spread over every 128-byte
+    line of a region (a stride-1 target or control), line_bytes counts those
+    lines, the least traffic such an access pattern can cause."""
+    import numpy as np
+    import torch
+
+    import paper_2409_17716_amd as qf
+    import qf_inputs as qi
+    D, n = 3, 16
+    N, b = D ** n, 8
+    psi = qf.new_state(n, D, "c64")
+    qf.qf_state_init(psi, n, D, None)
+    for q in range(n):
+        qf.qf_apply_1q(psi, n, D, q, qi.random_unitary(D, q))
+    rec = {"register": "3^16 complex64 (344.4 MB)"}
+
+    def measure(name, fn, nbytes, line_bytes=None, reps=5):
+        fn()
+        ms = _event_time(fn, reps)
+        gbps = nbytes / (ms * 1e-3) / 1e9
+        rec[name] = {"us": round(ms * 1e3, 2), "algorithmic_bytes": int(nbytes), "GBps": round(gbps, 1),
+                     "frac": round(gbps / HBM_PEAK_GBS, 4)}
+        if line_bytes is not None:
+            rec[name]["line_bytes"] = int(line_bytes)
+            rec[name]["line_frac"] = round(line_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+
+    moved = 2 * b * N  # read and write of every amplitude
+    # controlled rotation: fibres at control levels 1..D-1, x/y types touch 2 of D levels, z type j + 1
+    measure("crx_c0_t15", lambda: qf.qf_apply_crot(psi, n, D, "crx", 0, 15, 0, 1, 0.3), moved * (D - 1) / D * 2 / D,
+            moved * (D - 1) / D)
+    measure("cry_c15_t0", lambda: qf.qf_apply_crot(psi, n, D, "cry", 15, 0, 1, 2, 0.3), moved * (D - 1) / D * 2 / D,
+            moved * 2 / D)
+    measure("crz_c4_t9", lambda: qf.qf_apply_crot(psi, n, D, "crz", 4, 9, 1, 0, 0.3), moved * (D - 1) / D * 2 / D)
+    measure("slab_rx_q0", lambda: qf.qf_apply_rot(psi, n, D, "rx", 0, 0, 2, 0.3), moved * 2 / D)
+    measure("slab_ry_q15", lambda: qf.qf_apply_rot(psi, n, D, "ry", 15, 0, 1, 0.3), moved * 2 / D, moved)
+    measure("swap_0_15", lambda: qf.qf_apply_swap(psi, n, D, 0, 15), moved * (D - 1) / D, moved)
+    measure("swap_7_8", lambda: qf.qf_apply_swap(psi, n, D, 7, 8), moved * (D - 1) / D)
+    # x_15 += x_0 x_1 mod 3 moves the fibres whose two control digits are both non-zero
+    measure("mcx_c01_t15", lambda: qf.qf_apply_mcx(psi, n, D, [0, 1], 15), moved * ((D - 1) / D) ** 2)
+    shots = 1 << 20
+    u = torch.from_numpy(qi.uniforms(shots, 1)).cuda()
+    measure("shots_full_2^20", lambda: qf.qf_sample(psi, n, D, shots, u), N * b + 8 * N)
+    measure("shots_marginal_q0q15_2^20", lambda: qf.qf_sample(psi, n, D, shots, u, qudits=[0, 15]), N * b + 8 * 9)
+    del psi, u
+    torch.cuda.empty_cache()
+    dims = [2, 3, 4, 5] * 4
+    nm = len(dims)
+    Nm = int(np.prod(dims))
+    x = qf.new_state(nm, dims, "c64")
+    qf.qf_state_init(x, nm, dims, None)
+    fr = []
+    for q in range(nm):
+        U = qi.random_unitary(dims[q], q)
+        qf.qf_apply_1q(x, nm, dims, q, U)
+        ms = _event_time(lambda: qf.qf_apply_1q(x, nm, dims, q, U), 3)
+        fr.append(2 * b * Nm / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+    c = qi.mixed_hea(dims, 1, 5)
+    p = qf.plan_for(c, "c64")
+    qf.qf_state_init(x, nm, dims, None)
+    p.forward(x, c.theta)
+    ms = _event_time(lambda: p.forward(x, c.theta), 2)
+    rec["mixed"] = {"dims": "[2,3,4,5] x 4", "amplitudes": Nm, "sweep_frac_per_qudit": [round(f, 4) for f in fr],
+                    "sweep_frac_mean": round(float(np.mean(fr)), 4), "sweep_frac_min": round(float(min(fr)), 4),
+                    "plan": f"mixed ansatz, 1 layer ({len(c.ops)} gates), per-qudit runs", "plan_ms": round(ms, 3),
+                    "plan_steps": p.num_stages, "plan_amp_updates_per_s": len(c.ops) * Nm / (ms * 1e-3)}
+    del x
+    torch.cuda.empty_cache()
+    return rec
+
+
 def _cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -440,6 +520,8 @@ def profile_workload(kind: str) -> int:
         prof = p.read_profile()
         rec["families"] = {k: {"launches": v[0], "ms": round(v[1], 3),
                                "GBps": round(v[2] / (v[1] * 1e-3) / 1e9, 1)} for k, v in prof.items()}
+    elif kind == "next":
+        rec.update(next_rows_measurement())
     elif kind == "batched":
         from paper_2409_17716_amd.batched import RaggedBatch
         rb = RaggedBatch(qi.config4(), tune=True)
@@ -546,6 +628,8 @@ def main() -> int:
         out["batched"] = batched_measurement(max(1, a.steps // 2))
     if not a.no_legs:
         out["legs"] = gradient_legs()
+    if not a.no_next:
+        out["next_rows"] = next_rows_measurement()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c)
     print(json.dumps(out), flush=True)

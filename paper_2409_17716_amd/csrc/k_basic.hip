@@ -148,14 +148,18 @@ __global__ __launch_bounds__(kBlock) void k_axis_narrow(cplx<T>* __restrict__ ps
     const uint32_t E = rows * uint32_t(D) * L;  // <= kBlock * D
     const uint32_t start = blockIdx.x * E;
     const uint32_t cnt = min(E, total - start);
+    const uint32_t nf = cnt / D;
+    const uint32_t r = threadIdx.x / L;
+    const uint32_t l = threadIdx.x - r * L;
+    const uint32_t off = r * uint32_t(D) * L + l;
+    // a block none of whose fibres changes (a permutation whose controls
+    // select shift 0 here) is neither read nor written
+    const bool act = threadIdx.x < nf && !op.skip(start + off);
+    if (!__syncthreads_or(act)) return;
     for (uint32_t i = threadIdx.x; i < cnt; i += kBlock) tile[i] = psi[start + i];
     __syncthreads();
-    const uint32_t nf = cnt / D;
     if (threadIdx.x < nf) {
-        const uint32_t r = threadIdx.x / L;
-        const uint32_t l = threadIdx.x - r * L;
-        const uint32_t off = r * uint32_t(D) * L + l;
-        if (!op.skip(start + off)) {
+        if (act) {
             cplx<T> v[D];
 #pragma unroll
             for (int d = 0; d < D; ++d) v[d] = tile[off + uint32_t(d) * L];
@@ -221,23 +225,72 @@ qf_status with_type(int dtype, F&& f) {
 }
 
 // ---------------------------------------------------------------------------
-// SWAP of two qudits: amplitude x (digits x_a < x_b) trades places with the
-// amplitude whose a and b digits are exchanged, x' = x + (x_b - x_a)(S_a - S_b)
-// for strides S_a > S_b; each pair is moved once, by the lane of its x_a < x_b
-// member.  Consecutive lanes touch consecutive x and x'.
+// SWAP of two qudits a, b of one dimension D (strides S_a > S_b): lane r owns
+// the D x D block {x0 + i S_a + j S_b} of one setting of the other digits and
+// exchanges entries (i, j) and (j, i) for i < j (the diagonal stays).  The
+// other digits split as x0 = hi (D S_a) + mid (D S_b) + lo, lo < S_b, and
+// consecutive lanes take consecutive lo, so for S_b >= 64 every load and
+// store of a wavefront is one contiguous run; both members of a pair are read
+// and written by the same lane.
 // ---------------------------------------------------------------------------
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_swap(cplx<T>* __restrict__ psi, uint32_t total, FastDiv sa, FastDiv sb,
-                                                 uint32_t D, FastDiv divD, uint32_t delta_unit) {
-    for (uint32_t x = blockIdx.x * kBlock + threadIdx.x; x < total; x += gridDim.x * kBlock) {
-        const uint32_t qa = sa.div(x), qb = sb.div(x);
-        const uint32_t xa = qa - divD.div(qa) * D, xb = qb - divD.div(qb) * D;
-        if (xa < xb) {
-            const uint32_t y = x + (xb - xa) * delta_unit;
-            const cplx<T> u = psi[x], v = psi[y];
-            psi[x] = v;
-            psi[y] = u;
+// Pair e of the strictly upper triangle of a D x D block, row by row.
+template <int D>
+__host__ __device__ constexpr int pair_row(int e) {
+    int i = 0;
+    while (e >= D - 1 - i) {
+        e -= D - 1 - i;
+        ++i;
+    }
+    return i;
+}
+template <int D>
+__host__ __device__ constexpr int pair_col(int e) {
+    int i = 0;
+    while (e >= D - 1 - i) {
+        e -= D - 1 - i;
+        ++i;
+    }
+    return i + 1 + e;
+}
+
+// Exchanges pairs E, E + 1, ... of a block: each pair's two loads are issued
+// before the later pairs' (recursion), its stores after them, so every load
+// of the block is in flight at once with no private array.
+template <typename T, int D, int E>
+__device__ __forceinline__ void swap_pairs(cplx<T>* __restrict__ psi, uint32_t x0, uint32_t Sa, uint32_t Sb) {
+    if constexpr (E < D * (D - 1) / 2) {
+        constexpr uint32_t ia = uint32_t(pair_row<D>(E)), ib = uint32_t(pair_col<D>(E));
+        const cplx<T> v = psi[x0 + ia * Sa + ib * Sb];
+        const cplx<T> w = psi[x0 + ib * Sa + ia * Sb];
+        swap_pairs<T, D, E + 1>(psi, x0, Sa, Sb);
+        psi[x0 + ia * Sa + ib * Sb] = w;
+        psi[x0 + ib * Sa + ia * Sb] = v;
+    }
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(kBlock) void k_swap(cplx<T>* __restrict__ psi, uint32_t nblk, FastDiv divSb, FastDiv divM,
+                                                 uint32_t Sa, uint32_t Sb) {
+    for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < nblk; r += gridDim.x * kBlock) {
+        const uint32_t t = divSb.div(r);
+        const uint32_t lo = r - t * Sb;
+        const uint32_t hi = divM.div(t);
+        const uint32_t mid = t - hi * divM.d;
+        const uint32_t x0 = hi * (uint32_t(D) * Sa) + mid * (uint32_t(D) * Sb) + lo;
+        // all pairs' loads in flight where that stays in registers (measured:
+        // complex128 blocks beyond D = 3 go to scratch)
+        if constexpr ((sizeof(T) == 4 && D <= 6) || D <= 3) {
+            swap_pairs<T, D, 0>(psi, x0, Sa, Sb);
+        } else {
+            // larger D: one pair at a time
+            for (uint32_t ia = 0; ia + 1 < uint32_t(D); ++ia)
+                for (uint32_t ib = ia + 1; ib < uint32_t(D); ++ib) {
+                    const cplx<T> v = psi[x0 + ia * Sa + ib * Sb];
+                    const cplx<T> w = psi[x0 + ib * Sa + ia * Sb];
+                    psi[x0 + ia * Sa + ib * Sb] = w;
+                    psi[x0 + ib * Sa + ia * Sb] = v;
+                }
         }
     }
 }
@@ -581,13 +634,17 @@ qf_status launch_mcx(const StateView& s, int nctrl, const int32_t* ctrls, int tg
 
 qf_status launch_swap(const StateView& s, int a, int b, hipStream_t st) {
     if (a > b) std::swap(a, b);  // a: the more significant qudit
-    const uint32_t Sa = s.strides[a], Sb = s.strides[b], D = s.dims[a];  // d_a = d_b
+    const uint32_t Sa = s.strides[a], Sb = s.strides[b], Dq = s.dims[a];  // d_a = d_b
+    const uint32_t nblk = s.total / (Dq * Dq);
+    const uint32_t M = Sa / (Sb * Dq);  // settings of the digits between b and a
     return with_type(s.dtype, [&](auto tag) -> qf_status {
         using T = decltype(tag);
-        hipLaunchKernelGGL(k_swap<T>, dim3(grid_for(s.total, kBlock * 4)), dim3(kBlock), 0, st,
-                           reinterpret_cast<cplx<T>*>(s.amps), s.total, FastDiv(Sa), FastDiv(Sb), D, FastDiv(D),
-                           Sa - Sb);
-        return check_launch("swap");
+        return with_dim(Dq, [&](auto dtag) -> qf_status {
+            constexpr int D = decltype(dtag)::value;
+            hipLaunchKernelGGL((k_swap<T, D>), dim3(grid_for(nblk, kBlock)), dim3(kBlock), 0, st,
+                               reinterpret_cast<cplx<T>*>(s.amps), nblk, FastDiv(Sb), FastDiv(M), Sa, Sb);
+            return check_launch("swap");
+        });
     });
 }
 

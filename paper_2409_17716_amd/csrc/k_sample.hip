@@ -4,10 +4,15 @@
 //   2. an inclusive prefix sum per register in FP64, in a fixed order
 //      (segmented block scans, recursively over the block totals),
 //   3. one lane per shot: the first bin whose cumulative sum exceeds
-//      u * total (a draw whose product rounds up to the total goes to the
-//      last bin of non-zero probability), counted with integer atomics
-//      (an exact, order-independent histogram).
+//      u * total (a draw whose product reaches the total goes to the last
+//      bin of non-zero probability), counted with integer atomics (an exact,
+//      order-independent histogram); up to 4096 outcomes per register the
+//      counts first go to a workgroup histogram in LDS, flushed once per
+//      workgroup, so that many shots on few outcomes do not serialise on a
+//      few global counters.
 // The uniforms u are inputs: the caller draws them.
+#include <algorithm>
+
 #include "qf_internal.h"
 
 namespace qf {
@@ -109,6 +114,32 @@ __global__ __launch_bounds__(kT) void k_sample(const double* __restrict__ cdf, u
     }
 }
 
+constexpr uint32_t kLdsBins = 4096;  // 32 KB of 64-bit counters
+
+// Workgroup (blockIdx.x % bpr) of register b = blockIdx.x / bpr draws shots
+// i = that index, + bpr * kT, ... of the register into an LDS histogram.
+__global__ __launch_bounds__(kT) void k_sample_lds(const double* __restrict__ cdf, uint32_t K, uint64_t shots,
+                                                   uint32_t bpr, const double* __restrict__ u,
+                                                   unsigned long long* __restrict__ counts,
+                                                   int32_t* __restrict__ samples) {
+    __shared__ unsigned long long h[kLdsBins];
+    for (uint32_t i = threadIdx.x; i < K; i += kT) h[i] = 0ull;
+    __syncthreads();
+    const uint32_t b = blockIdx.x / bpr, w = blockIdx.x - b * bpr;
+    const double* c = cdf + uint64_t(b) * K;
+    const double sum = c[K - 1];
+    for (uint64_t i = uint64_t(w) * kT + threadIdx.x; i < shots; i += uint64_t(bpr) * kT) {
+        const uint64_t d = uint64_t(b) * shots + i;
+        uint32_t idx = upper_bound(c, K, u[d] * sum);
+        if (idx >= K) idx = lower_bound(c, K, sum);
+        atomicAdd(h + idx, 1ull);
+        if (samples) samples[d] = int32_t(idx);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < K; i += kT)
+        if (h[i]) atomicAdd(counts + uint64_t(b) * K + i, h[i]);
+}
+
 uint32_t grid_of(uint64_t n) {
     const uint64_t g = (n + kT - 1) / kT;
     return uint32_t(g < 1 ? 1 : g > (1u << 20) ? (1u << 20) : g);
@@ -165,8 +196,17 @@ qf_status launch_sample(const StateView& s, int m, const int32_t* qudits, uint64
         rs = check_launch("histogram clear");
     }
     if (rs == QF_OK && draws > 0) {
-        hipLaunchKernelGGL(k_sample, dim3(grid_of(draws)), dim3(kT), 0, st, cdf, uint32_t(K), shots, draws, u,
-                           reinterpret_cast<unsigned long long*>(counts), samples);
+        if (K <= kLdsBins) {
+            // about 16 shots per lane, at most 1024 workgroups in all
+            uint64_t bpr = (shots + 16 * kT - 1) / (16 * kT);
+            const uint64_t cap = std::max<uint64_t>(1, 1024 / s.batch);
+            bpr = std::min(bpr, cap);
+            hipLaunchKernelGGL(k_sample_lds, dim3(uint32_t(bpr * s.batch)), dim3(kT), 0, st, cdf, uint32_t(K), shots,
+                               uint32_t(bpr), u, reinterpret_cast<unsigned long long*>(counts), samples);
+        } else {
+            hipLaunchKernelGGL(k_sample, dim3(grid_of(draws)), dim3(kT), 0, st, cdf, uint32_t(K), shots, draws, u,
+                               reinterpret_cast<unsigned long long*>(counts), samples);
+        }
         rs = check_launch("sampling");
     }
     (void)hipFreeAsync(cdf, st);
