@@ -298,6 +298,12 @@ def next_rows_measurement() -> dict:
     measure("swap_7_8", lambda: qf.qf_apply_swap(psi, n, D, 7, 8), moved * (D - 1) / D)
     # x_15 += x_0 x_1 mod 3 moves the fibres whose two control digits are both non-zero
     measure("mcx_c01_t15", lambda: qf.qf_apply_mcx(psi, n, D, [0, 1], 15), moved * ((D - 1) / D) ** 2)
+    pf = torch.empty(N, dtype=torch.float32, device="cuda")
+    pm = torch.empty(9, dtype=torch.float32, device="cuda")
+    measure("probs_full", lambda: qf.qf_probs(psi, n, D, out=pf), N * b + 4 * N)
+    measure("probs_marginal_q0q15", lambda: qf.qf_probs(psi, n, D, qudits=[0, 15], out=pm), N * b)
+    p27 = torch.empty(27, dtype=torch.float32, device="cuda")
+    measure("probs_marginal_q3q7q11", lambda: qf.qf_probs(psi, n, D, qudits=[3, 7, 11], out=p27), N * b)
     shots = 1 << 20
     u = torch.from_numpy(qi.uniforms(shots, 1)).cuda()
     measure("shots_full_2^20", lambda: qf.qf_sample(psi, n, D, shots, u), N * b + 8 * N)

@@ -443,6 +443,73 @@ __global__ __launch_bounds__(kBlock) void k_marg_final(const double* __restrict_
     if (threadIdx.x == 0) out[i] = O(s);
 }
 
+// Marginals of at most 32 outcomes, streamed: workgroup w of register b reads
+// elements [w * per_wg, (w + 1) * per_wg) in memory order (coalesced), each
+// lane adds |psi_x|^2 in FP64 to its register copy of bin y(x) (a predicated
+// add into every bin, so the bins stay in registers), then every bin is summed
+// over the wavefront by a fixed xor-butterfly and over the wavefronts in a
+// fixed order: one partial per (workgroup, bin), bitwise reproducible.
+struct MargSmall {
+    uint32_t N;
+    uint32_t m;
+    uint32_t bins;
+    uint32_t per_wg;
+    uint32_t wpr;                  // workgroups per register
+    FastDiv stride[kMaxMarg];      // strides of the measured qudits, listed order
+    FastDiv dim[kMaxMarg];         // their dimensions
+};
+
+template <typename T, int NB>
+__global__ __launch_bounds__(kBlock) void k_marg_stream(const cplx<T>* __restrict__ psi, MargSmall a,
+                                                        double* __restrict__ partial) {
+    __shared__ double sh[kBlock / 64][NB];
+    const uint32_t b = blockIdx.x / a.wpr, w = blockIdx.x - b * a.wpr;
+    const cplx<T>* reg = psi + size_t(b) * a.N;
+    const uint32_t x0 = w * a.per_wg;
+    const uint32_t x1 = min(a.N, x0 + a.per_wg);
+    double acc[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[j] = 0.0;
+    for (uint32_t x = x0 + threadIdx.x; x < x1; x += kBlock) {
+        const cplx<T> v = reg[x];
+        const double p = double(v.re) * double(v.re) + double(v.im) * double(v.im);
+        uint32_t y = 0;
+        for (uint32_t i = 0; i < a.m; ++i) {
+            const uint32_t qv = a.stride[i].div(x);
+            const uint32_t d = a.dim[i].d;
+            y = y * d + (qv - a.dim[i].div(qv) * d);
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[j] += (y == uint32_t(j)) ? p : 0.0;
+    }
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        double v = acc[j];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) sh[wave][j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < a.bins) {
+        double t = 0.0;
+        for (uint32_t wv = 0; wv < blockDim.x / 64; ++wv) t += sh[wv][threadIdx.x];
+        partial[size_t(blockIdx.x) * a.bins + threadIdx.x] = t;
+    }
+}
+
+// out[b * bins + y] = sum over the register's workgroups of partial (fixed order).
+template <typename O>
+__global__ __launch_bounds__(kBlock) void k_marg_stream_final(const double* __restrict__ partial, uint32_t wpr,
+                                                              uint32_t bins, O* __restrict__ out) {
+    __shared__ double sh[kBlock];
+    const uint32_t b = blockIdx.x / bins, y = blockIdx.x - b * bins;
+    double s = 0.0;
+    for (uint32_t w = threadIdx.x; w < wpr; w += kBlock) s += partial[(size_t(b) * wpr + w) * bins + y];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = O(s);
+}
+
 // ---------------------------------------------------------------------------
 // Diagonal expectation values and the Hermitian part of a diagonal observable.
 // ---------------------------------------------------------------------------
@@ -684,8 +751,51 @@ qf_status launch_probs_full(const StateView& s, void* out, bool f64, hipStream_t
     });
 }
 
+template <int NB>
+qf_status launch_marg_stream(const StateView& s, const MargSmall& a, void* out, bool f64, hipStream_t st) {
+    const uint64_t nwg = uint64_t(a.wpr) * s.batch;
+    if (nwg >= (1ull << 31)) return set_error(QF_ERANGE, "marginal grid too large");
+    return with_type(s.dtype, [&](auto tag) -> qf_status {
+        using T = decltype(tag);
+        double* partial = nullptr;
+        QF_CHECK(dev_malloc_async(reinterpret_cast<void**>(&partial), nwg * a.bins * sizeof(double), st,
+                                  "marginal partial sums"));
+        hipLaunchKernelGGL((k_marg_stream<T, NB>), dim3(uint32_t(nwg)), dim3(kBlock), 0, st,
+                           reinterpret_cast<const cplx<T>*>(s.amps), a, partial);
+        qf_status r1 = check_launch("qf_probs marginal (streamed)");
+        const uint32_t nout = a.bins * s.batch;
+        if (f64)
+            hipLaunchKernelGGL(k_marg_stream_final<double>, dim3(nout), dim3(kBlock), 0, st, partial, a.wpr, a.bins,
+                               reinterpret_cast<double*>(out));
+        else
+            hipLaunchKernelGGL(k_marg_stream_final<T>, dim3(nout), dim3(kBlock), 0, st, partial, a.wpr, a.bins,
+                               reinterpret_cast<T*>(out));
+        qf_status r2 = check_launch("qf_probs marginal final (streamed)");
+        QF_HIP_CHECK(hipFreeAsync(partial, st));
+        return r1 != QF_OK ? r1 : r2;
+    });
+}
+
 qf_status launch_probs_marginal(const StateView& s, int m, const int32_t* qudits, void* out, bool f64,
                                 hipStream_t st) {
+    uint32_t nbins = 1;
+    for (int i = 0; i < m; ++i) nbins *= s.dims[qudits[i]];
+    if (nbins <= 32) {
+        MargSmall a{};
+        a.N = s.N;
+        a.m = uint32_t(m);
+        a.bins = nbins;
+        a.per_wg = kBlock * 32;
+        a.wpr = (s.N + a.per_wg - 1) / a.per_wg;
+        for (int i = 0; i < m; ++i) {
+            a.stride[i].init(s.strides[qudits[i]]);
+            a.dim[i].init(s.dims[qudits[i]]);
+        }
+        if (nbins <= 4) return launch_marg_stream<4>(s, a, out, f64, st);
+        if (nbins <= 8) return launch_marg_stream<8>(s, a, out, f64, st);
+        if (nbins <= 16) return launch_marg_stream<16>(s, a, out, f64, st);
+        return launch_marg_stream<32>(s, a, out, f64, st);
+    }
     MargArg a{};
     a.N = s.N;
     a.m = uint32_t(m);
