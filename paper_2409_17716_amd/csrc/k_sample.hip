@@ -12,6 +12,7 @@
 //      few global counters.
 // The uniforms u are inputs: the caller draws them.
 #include <algorithm>
+#include <type_traits>
 
 #include "qf_internal.h"
 
@@ -27,20 +28,34 @@ constexpr int kSpan = kT * kPer;  // elements per scan block
 // s = blk / bps, lb = blk % bps.  Each thread sums its kPer elements in order,
 // the thread totals are scanned in LDS by doubling steps, and the block total
 // goes to sums[blk] (sums are laid out as [segment][bps]).
-__global__ __launch_bounds__(kT) void k_scan_block(double* __restrict__ data, uint64_t seg, uint32_t bps,
-                                                   double* __restrict__ sums) {
+// Src = double: scan data in place; Src = cplx<float> / cplx<double>: the
+// values are |psi_x|^2 of the state src (taken in FP64), written scanned to data.
+template <typename Src>
+__device__ inline double scan_value(const Src* p, uint64_t e) {
+    if constexpr (std::is_same<Src, double>::value) {
+        return p[e];
+    } else {
+        const Src v = p[e];
+        return double(v.re) * double(v.re) + double(v.im) * double(v.im);
+    }
+}
+
+template <typename Src>
+__global__ __launch_bounds__(kT) void k_scan_block(const Src* __restrict__ src, double* __restrict__ data,
+                                                   uint64_t seg, uint32_t bps, double* __restrict__ sums) {
     __shared__ double sh[kT];
     const uint32_t blk = blockIdx.x;
     const uint32_t s = blk / bps, lb = blk - s * bps;
     const uint64_t lo = uint64_t(lb) * kSpan;
     const uint64_t n = seg - lo < uint64_t(kSpan) ? seg - lo : uint64_t(kSpan);
+    const Src* q = src + s * seg + lo;
     double* d = data + s * seg + lo;
     double v[kPer];
     double run = 0.0;
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
         const uint64_t e = uint64_t(threadIdx.x) * kPer + i;
-        run += e < n ? d[e] : 0.0;
+        run += e < n ? scan_value(q, e) : 0.0;
         v[i] = run;
     }
     sh[threadIdx.x] = run;
@@ -147,11 +162,19 @@ uint32_t grid_of(uint64_t n) {
 
 // In-place inclusive scan of nseg segments of length seg; ws holds the block
 // totals of every level.
-qf_status scan_segments(double* data, uint64_t seg, uint64_t nseg, double* ws, hipStream_t st) {
+// The first level may read its values from src (|psi|^2 of a state) instead
+// of data.
+template <typename Src = double>
+qf_status scan_segments(double* data, uint64_t seg, uint64_t nseg, double* ws, hipStream_t st,
+                        const Src* src = nullptr) {
     const uint32_t bps = uint32_t((seg + kSpan - 1) / kSpan);
     const uint64_t nblk = nseg * bps;
     if (nblk >= (1ull << 31)) return set_error(QF_ERANGE, "prefix sum grid too large");
-    hipLaunchKernelGGL(k_scan_block, dim3(uint32_t(nblk)), dim3(kT), 0, st, data, seg, bps, ws);
+    if constexpr (std::is_same<Src, double>::value)
+        hipLaunchKernelGGL(k_scan_block<double>, dim3(uint32_t(nblk)), dim3(kT), 0, st, src ? src : data, data, seg,
+                           bps, ws);
+    else
+        hipLaunchKernelGGL(k_scan_block<Src>, dim3(uint32_t(nblk)), dim3(kT), 0, st, src, data, seg, bps, ws);
     QF_CHECK(check_launch("prefix sum"));
     if (bps > 1) {
         QF_CHECK(scan_segments(ws, bps, nseg, ws + nblk, st));
@@ -188,8 +211,17 @@ qf_status launch_sample(const StateView& s, int m, const int32_t* qudits, uint64
     const uint64_t wsd = scan_ws_doubles(K, s.batch);
     double* cdf = nullptr;
     QF_CHECK(dev_malloc_async(reinterpret_cast<void**>(&cdf), (bins + wsd) * sizeof(double), st, "sampling"));
-    qf_status rs = m == 0 ? launch_probs_full(s, cdf, true, st) : launch_probs_marginal(s, m, qudits, cdf, true, st);
-    if (rs == QF_OK) rs = scan_segments(cdf, K, s.batch, cdf + bins, st);
+    qf_status rs = QF_OK;
+    if (m == 0) {
+        // the full register: |psi|^2 is taken inside the first scan level
+        if (s.dtype == QF_C64)
+            rs = scan_segments(cdf, K, s.batch, cdf + bins, st, reinterpret_cast<const cplx<float>*>(s.amps));
+        else
+            rs = scan_segments(cdf, K, s.batch, cdf + bins, st, reinterpret_cast<const cplx<double>*>(s.amps));
+    } else {
+        rs = launch_probs_marginal(s, m, qudits, cdf, true, st);
+        if (rs == QF_OK) rs = scan_segments(cdf, K, s.batch, cdf + bins, st);
+    }
     if (rs == QF_OK) {
         hipLaunchKernelGGL(k_fill_u64, dim3(grid_of(bins)), dim3(kT), 0, st,
                            reinterpret_cast<unsigned long long*>(counts), bins);
