@@ -228,11 +228,18 @@ def batched_measurement(steps: int) -> dict:
             "schedules": rb.schedules()}
 
 
+def _median_launch_ms(fn, reps: int = 5, per: int = 3) -> float:
+    """Milliseconds per launch of fn(): the median over reps trials, each timing
+    per back-to-back launches with HIP events on the current stream (a stray
+    stall of the host or the GPU affects one trial)."""
+    return sorted(_event_time(fn, per) for _ in range(reps))[reps // 2]
+
+
 def sweep_measurement(psi, n: int, D: int) -> dict:
     """One Haar-random D x D gate on every qudit of the bench register through
-    qf_apply_1q (the single-qudit sweep kernels), each launch timed with HIP
-    events on the current stream after a warm-up launch; algorithmic traffic
-    2 N b per launch (one read and one write of the state)."""
+    qf_apply_1q (the single-qudit sweep kernels), each qudit's launch time the
+    median of 5 trials of 3 back-to-back launches (HIP events) after a warm-up;
+    algorithmic traffic 2 N b per launch (one read and one write of the state)."""
     import numpy as np
 
     import paper_2409_17716_amd as qf
@@ -244,7 +251,7 @@ def sweep_measurement(psi, n: int, D: int) -> dict:
     for q in range(n):
         U = qi.random_unitary(D, rng)
         qf.qf_apply_1q(psi, n, D, q, U)
-        ms = _event_time(lambda: qf.qf_apply_1q(psi, n, D, q, U), 3)
+        ms = _median_launch_ms(lambda: qf.qf_apply_1q(psi, n, D, q, U))
         per.append(nbytes / (ms * 1e-3) / 1e9)
     fr = [g / HBM_PEAK_GBS for g in per]
     return {"kernel": "k_axis_wide / k_axis_narrow (qf_apply_1q)", "bytes_per_launch": nbytes,
@@ -256,7 +263,7 @@ def next_rows_measurement() -> dict:
     """The kernels of the controlled rotation, the slab rotation, SWAP, MCX and
     shots on the 3^16 complex64 register, and one-qudit sweeps plus a plan on a
     mixed register of dims [2, 3, 4, 5] x 4 (120^4 = 207.4M amplitudes), each
-    timed with HIP events (warm-up, then 5 launches) against its algorithmic
+    timed with HIP events (warm-up, then the median of 5 trials of 3 launches) against its algorithmic
     bytes: the amplitudes the operation must read and write (a gate reads and
     writes only the amplitudes it changes; shots read the state and write the
     histogram).  Where the changed amplitudes are spread over every 128-byte
@@ -277,7 +284,7 @@ def next_rows_measurement() -> dict:
 
     def measure(name, fn, nbytes, line_bytes=None, reps=5):
         fn()
-        ms = _event_time(fn, reps)
+        ms = _median_launch_ms(fn, reps)
         gbps = nbytes / (ms * 1e-3) / 1e9
         rec[name] = {"us": round(ms * 1e3, 2), "algorithmic_bytes": int(nbytes), "GBps": round(gbps, 1),
                      "frac": round(gbps / HBM_PEAK_GBS, 4)}
@@ -319,7 +326,7 @@ def next_rows_measurement() -> dict:
     for q in range(nm):
         U = qi.random_unitary(dims[q], q)
         qf.qf_apply_1q(x, nm, dims, q, U)
-        ms = _event_time(lambda: qf.qf_apply_1q(x, nm, dims, q, U), 3)
+        ms = _median_launch_ms(lambda: qf.qf_apply_1q(x, nm, dims, q, U))
         fr.append(2 * b * Nm / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
     c = qi.mixed_hea(dims, 1, 5)
     p = qf.plan_for(c, "c64")
