@@ -309,6 +309,9 @@ def next_rows_measurement() -> dict:
     pm = torch.empty(9, dtype=torch.float32, device="cuda")
     measure("probs_full", lambda: qf.qf_probs(psi, n, D, out=pf), N * b + 4 * N)
     measure("probs_marginal_q0q15", lambda: qf.qf_probs(psi, n, D, qudits=[0, 15], out=pm), N * b)
+    zb = torch.empty(2, dtype=torch.float64, device="cuda")
+    measure("expect_z0", lambda: qf.qf_expect(psi, n, D, qi.z0_terms(), out=zb), N * b)
+    measure("expect_sum_z", lambda: qf.qf_expect(psi, n, D, qi.zsum_terms(n), out=zb), N * b)
     p27 = torch.empty(27, dtype=torch.float32, device="cuda")
     measure("probs_marginal_q3q7q11", lambda: qf.qf_probs(psi, n, D, qudits=[3, 7, 11], out=p27), N * b)
     shots = 1 << 20

@@ -209,8 +209,11 @@ qf_status qf_expect(const qf_state* s, int32_t nterms, const int32_t* term_qudit
  * same kernels and summation order (bitwise the same result), with the
  * partial sums in a library-owned device array of 4 MiB per GPU, held until
  * the process ends, instead of a stream-ordered allocation.  Calls no
- * allocating routine.  Limit: batch * ceil(D^n / 4096) <= 262144 (one register
- * of up to 2^30 amplitudes); beyond it QF_ERANGE.  Every call on a GPU shares
+ * allocating routine.  Limit: batch * (chunks per register) <= 262144 partial
+ * sums, a register splitting into chunks of its smallest qudit stride of at
+ * least 4096 amplitudes (one chunk if it has none); so batch * ceil(N / 4096)
+ * <= 262144 always fits (one register of up to 2^30 amplitudes).  Beyond the
+ * limit QF_ERANGE.  Every call on a GPU shares
  * that GPU's array: calls that overlap on one GPU (other streams, other
  * threads) race, so the caller must order them. */
 qf_status qf_expect_noalloc(const qf_state* s, int32_t nterms, const int32_t* term_qudit,

@@ -443,20 +443,29 @@ __global__ __launch_bounds__(kBlock) void k_marg_final(const double* __restrict_
     if (threadIdx.x == 0) out[i] = O(s);
 }
 
-// Marginals of at most 16 outcomes, streamed: workgroup w of register b reads
-// elements [w * per_wg, (w + 1) * per_wg) in memory order (coalesced), each
-// lane adds |psi_x|^2 in FP64 to its register copy of bin y(x) (a predicated
-// add into every bin, so the bins stay in registers), then every bin is summed
-// over the wavefront by a fixed xor-butterfly and over the wavefronts in a
-// fixed order: one partial per (workgroup, bin), bitwise reproducible.
+// Marginals streamed in memory order.  A workgroup reads one chunk of
+// per_wg elements, per_wg the stride of some qudit, so the digits of every
+// qudit of at least that stride are constant over the chunk: the measured
+// ones among them ("high") give the chunk one bin offset y_hi.  The other
+// measured qudits ("low", at most 16 digit combinations c) vary inside it;
+// each lane adds |psi_x|^2 in FP64 to its register copy of combination c(x)
+// (a predicated add into every combination, so they stay in registers).  Each
+// combination is summed over the wavefront by a fixed xor-butterfly and over
+// the wavefronts in a fixed order; the workgroup writes one partial per bin
+// (y_hi + y_lo(c), zero for the bins it does not reach): bitwise reproducible.
 struct MargSmall {
     uint32_t N;
     uint32_t m;
-    uint32_t bins;
+    uint32_t bins;                 // all outcomes (<= 256)
     uint32_t per_wg;
     uint32_t wpr;                  // workgroups per register
-    FastDiv stride[kMaxMarg];      // strides of the measured qudits, listed order
-    FastDiv dim[kMaxMarg];         // their dimensions
+    uint32_t nlow;                 // low measured qudits
+    uint32_t ncomb;                // their digit combinations (<= 16)
+    FastDiv stride[kMaxMarg];      // measured qudits, listed order
+    FastDiv dim[kMaxMarg];
+    uint32_t radix[kMaxMarg];      // bin weight of each measured qudit
+    uint32_t low[kMaxMarg];        // indices (into the measured list) of the low qudits, listed order
+    uint32_t ylo[16];              // bin offset of each combination
 };
 
 template <typename T, int NB>
@@ -467,20 +476,32 @@ __global__ __launch_bounds__(kBlock) void k_marg_stream(const cplx<T>* __restric
     const cplx<T>* reg = psi + size_t(b) * a.N;
     const uint32_t x0 = w * a.per_wg;
     const uint32_t x1 = min(a.N, x0 + a.per_wg);
+    uint32_t yhi = 0;  // the high qudits' part of the bin, from the chunk's first index
+    for (uint32_t i = 0; i < a.m; ++i) {
+        const uint32_t qv = a.stride[i].div(x0);
+        yhi += (qv - a.dim[i].div(qv) * a.dim[i].d) * a.radix[i];
+    }
+    for (uint32_t j = 0; j < a.nlow; ++j) {
+        const uint32_t i = a.low[j];
+        const uint32_t qv = a.stride[i].div(x0);
+        yhi -= (qv - a.dim[i].div(qv) * a.dim[i].d) * a.radix[i];
+    }
     double acc[NB];
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[j] = 0.0;
+#pragma unroll 8
     for (uint32_t x = x0 + threadIdx.x; x < x1; x += kBlock) {
         const cplx<T> v = reg[x];
         const double p = double(v.re) * double(v.re) + double(v.im) * double(v.im);
-        uint32_t y = 0;
-        for (uint32_t i = 0; i < a.m; ++i) {
+        uint32_t c = 0;
+        for (uint32_t j = 0; j < a.nlow; ++j) {
+            const uint32_t i = a.low[j];
             const uint32_t qv = a.stride[i].div(x);
             const uint32_t d = a.dim[i].d;
-            y = y * d + (qv - a.dim[i].div(qv) * d);
+            c = c * d + (qv - a.dim[i].div(qv) * d);
         }
 #pragma unroll
-        for (int j = 0; j < NB; ++j) acc[j] += (y == uint32_t(j)) ? p : 0.0;
+        for (int j = 0; j < NB; ++j) acc[j] += (c == uint32_t(j)) ? p : 0.0;
     }
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -491,10 +512,12 @@ __global__ __launch_bounds__(kBlock) void k_marg_stream(const cplx<T>* __restric
         if (lane == 0) sh[wave][j] = v;
     }
     __syncthreads();
-    if (threadIdx.x < a.bins) {
+    for (uint32_t y = threadIdx.x; y < a.bins; y += kBlock) {
         double t = 0.0;
-        for (uint32_t wv = 0; wv < blockDim.x / 64; ++wv) t += sh[wv][threadIdx.x];
-        partial[size_t(blockIdx.x) * a.bins + threadIdx.x] = t;
+        for (uint32_t c = 0; c < a.ncomb; ++c)
+            if (yhi + a.ylo[c] == y)
+                for (uint32_t wv = 0; wv < blockDim.x / 64; ++wv) t += sh[wv][c];
+        partial[size_t(blockIdx.x) * a.bins + y] = t;
     }
 }
 
@@ -523,6 +546,8 @@ struct ObsArg {
     FastDiv stride[kMaxActive];
     FastDiv divd[kMaxActive];      // dimensions of the active qudits
     uint32_t off[kMaxActive];      // first table entry of each active qudit
+    uint32_t nlow;                 // expectation chunks: terms whose digit varies inside a chunk
+    uint32_t low[kMaxActive];      // their indices (the others are constant over a chunk)
     double table[2 * kMaxTable];   // complex, interleaved, active qudits back to back
 };
 
@@ -537,6 +562,10 @@ __device__ inline void obs_value(const ObsArg& a, const double* tab, uint32_t x,
     }
 }
 
+// A workgroup sums one chunk of a register, chunk = a qudit stride, so the
+// terms on qudits of at least that stride are constant over the chunk (taken
+// once from its first index); per element only the other ("low") terms are
+// looked up.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_expect_partial(const cplx<T>* __restrict__ psi, uint32_t N,
                                                            uint32_t chunk, uint32_t nblk, ObsArg a,
@@ -550,12 +579,28 @@ __global__ __launch_bounds__(kBlock) void k_expect_partial(const cplx<T>* __rest
     const uint32_t x0 = blk * chunk;
     const uint32_t x1 = min(N, x0 + chunk);
     const cplx<T>* reg = psi + size_t(b) * N;
+    // the chunk-constant part of f (all terms at x0 minus the low ones, which are
+    // at digit 0 there since the chunk starts at a multiple of their period)
+    double hr, hi;
+    obs_value(a, tab, x0, hr, hi);
+    for (uint32_t j = 0; j < a.nlow; ++j) {
+        const uint32_t t = a.low[j];
+        hr -= tab[2 * a.off[t]];
+        hi -= tab[2 * a.off[t] + 1];
+    }
     double ar = 0.0, ai = 0.0;
+#pragma unroll 4
     for (uint32_t x = x0 + threadIdx.x; x < x1; x += kBlock) {
         const cplx<T> v = reg[x];
         const double p = double(v.re) * double(v.re) + double(v.im) * double(v.im);
-        double fr, fi;
-        obs_value(a, tab, x, fr, fi);
+        double fr = hr, fi = hi;
+        for (uint32_t j = 0; j < a.nlow; ++j) {
+            const uint32_t t = a.low[j];
+            const uint32_t qv = a.stride[t].div(x);
+            const uint32_t d = qv - a.divd[t].div(qv) * a.divd[t].d;
+            fr += tab[2 * (a.off[t] + d)];
+            fi += tab[2 * (a.off[t] + d) + 1];
+        }
         ar += p * fr;
         ai += p * fi;
     }
@@ -780,22 +825,49 @@ qf_status launch_probs_marginal(const StateView& s, int m, const int32_t* qudits
                                 hipStream_t st) {
     uint32_t nbins = 1;
     for (int i = 0; i < m; ++i) nbins *= s.dims[qudits[i]];
-    // streamed up to 16 outcomes (measured: 9 outcomes of 3^16 202 -> 140 us;
-    // with 27 its predicated FP64 adds make it slower than the gather below)
-    if (nbins <= 16) {
+    // streamed when the measured qudits below the chunk stride have at most 16
+    // digit combinations and there are at most 256 outcomes; gathered otherwise
+    if (nbins <= 256) {
         MargSmall a{};
         a.N = s.N;
         a.m = uint32_t(m);
         a.bins = nbins;
-        a.per_wg = kBlock * 32;
-        a.wpr = (s.N + a.per_wg - 1) / a.per_wg;
+        // chunk: the largest qudit stride <= 16384 (the register if smaller)
+        a.per_wg = s.N;
+        if (s.N > 16384) {
+            a.per_wg = 1;
+            for (int q = int(s.n) - 1; q >= 0 && s.strides[q] <= 16384; --q) a.per_wg = s.strides[q];
+        }
+        a.wpr = s.N / a.per_wg;
+        uint32_t radix = 1, ncomb = 1;
+        for (int i = m - 1; i >= 0; --i) {
+            a.radix[i] = radix;
+            radix *= s.dims[qudits[i]];
+        }
         for (int i = 0; i < m; ++i) {
             a.stride[i].init(s.strides[qudits[i]]);
             a.dim[i].init(s.dims[qudits[i]]);
+            if (s.strides[qudits[i]] < a.per_wg) {
+                a.low[a.nlow++] = uint32_t(i);
+                ncomb *= s.dims[qudits[i]];
+            }
         }
-        if (nbins <= 4) return launch_marg_stream<4>(s, a, out, f64, st);
-        if (nbins <= 8) return launch_marg_stream<8>(s, a, out, f64, st);
-        return launch_marg_stream<16>(s, a, out, f64, st);
+        if (ncomb <= 16) {
+            a.ncomb = ncomb;
+            // bin offset of combination c: its low digits, last low qudit fastest
+            for (uint32_t c = 0; c < ncomb; ++c) {
+                uint32_t cc = c, y = 0;
+                for (int j = int(a.nlow) - 1; j >= 0; --j) {
+                    const uint32_t i = a.low[j], d = s.dims[qudits[i]];
+                    y += (cc % d) * a.radix[i];
+                    cc /= d;
+                }
+                a.ylo[c] = y;
+            }
+            if (ncomb <= 4) return launch_marg_stream<4>(s, a, out, f64, st);
+            if (ncomb <= 8) return launch_marg_stream<8>(s, a, out, f64, st);
+            return launch_marg_stream<16>(s, a, out, f64, st);
+        }
     }
     MargArg a{};
     a.N = s.N;
@@ -845,8 +917,26 @@ qf_status launch_probs_marginal(const StateView& s, int m, const int32_t* qudits
     });
 }
 
+// Expectation chunk: the smallest qudit stride of at least 4096 amplitudes (the
+// register if there is none), so a register has at most ceil(N / 4096) chunks.
+static uint32_t expect_chunk(const StateView& s) {
+    uint32_t c = s.N;
+    for (int q = int(s.n) - 1; q >= 0; --q)
+        if (s.strides[q] >= 4096) {
+            c = s.strides[q];
+            break;
+        }
+    return c;
+}
+
+static void set_low_terms(ObsArg& a, const StateView& s, const std::vector<int>& active, uint32_t chunk) {
+    a.nlow = 0;
+    for (size_t t = 0; t < active.size(); ++t)
+        if (s.strides[active[t]] < chunk) a.low[a.nlow++] = uint32_t(t);
+}
+
 size_t expect_ws_doubles(const StateView& s) {
-    const uint32_t chunk = kBlock * 16;
+    const uint32_t chunk = expect_chunk(s);
     const uint32_t nblk = (s.N + chunk - 1) / chunk;
     return size_t(nblk) * s.batch * 2;
 }
@@ -854,7 +944,8 @@ size_t expect_ws_doubles(const StateView& s) {
 qf_status launch_expect_ws(const StateView& s, const std::vector<int>& active, const std::vector<double>& table,
                            double* out, double* partial, hipStream_t st) {
     ObsArg a = make_obs(s, active, table, false);
-    const uint32_t chunk = kBlock * 16;
+    const uint32_t chunk = expect_chunk(s);
+    set_low_terms(a, s, active, chunk);
     const uint32_t nblk = (s.N + chunk - 1) / chunk;
     const uint64_t nblocks = uint64_t(nblk) * s.batch;
     if (nblocks >= (1ull << 31)) return set_error(QF_ERANGE, "expectation grid too large");
@@ -871,7 +962,8 @@ qf_status launch_expect_ws(const StateView& s, const std::vector<int>& active, c
 qf_status launch_expect(const StateView& s, const std::vector<int>& active, const std::vector<double>& table,
                         double* out, hipStream_t st) {
     ObsArg a = make_obs(s, active, table, false);
-    const uint32_t chunk = kBlock * 16;
+    const uint32_t chunk = expect_chunk(s);
+    set_low_terms(a, s, active, chunk);
     const uint32_t nblk = (s.N + chunk - 1) / chunk;
     const uint64_t nblocks = uint64_t(nblk) * s.batch;
     if (nblocks >= (1ull << 31)) return set_error(QF_ERANGE, "expectation grid too large");
@@ -923,7 +1015,7 @@ qf_status launch_expect_noalloc(const StateView& s, const std::vector<int>& acti
     const size_t need = expect_ws_doubles(s);
     if (need > kScratchDoubles)
         return set_error(QF_ERANGE, "qf_expect_noalloc: %zu partial sums exceed the %zu of the library's scratch "
-                         "array (batch * ceil(D^n / 4096) must be <= %zu)", need / 2, kScratchDoubles / 2,
+                         "array (batch * chunks per register must be <= %zu)", need / 2, kScratchDoubles / 2,
                          kScratchDoubles / 2);
     double* ws = nullptr;
     QF_CHECK(scratch_address(&ws));
