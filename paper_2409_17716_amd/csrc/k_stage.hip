@@ -624,6 +624,33 @@ __device__ __forceinline__ void load_addrs(uint32_t (&a)[cpow(D, M)], uint32_t t
     for (int i = 0; i < DM; ++i) a[i] = tb + od[rdigit<D, M, 0>(i)] + rest_offset<D, M>(i, rd.gls);
 }
 
+// Digits of sub-tile u over the k - M other tile qudits, least significant
+// first, one byte each; the first 8 digits.
+struct SubDigits {
+    uint32_t w[2];
+};
+
+// pre2 on the load addresses (after pre0 and pre1): its target is one of the
+// lane's own digits x_t, so register i loads from x_t - s(d_ctrl(i)), an
+// offset per value of the control digit.  The amplitudes come from other
+// lanes' sub-tiles (see run_round).
+template <int D, int M>
+__device__ __forceinline__ void add_pre2(uint32_t (&a)[cpow(D, M)], const RoundDesc& rd, const SubDigits& dg) {
+    constexpr int DM = cpow(D, M);
+    const int b = rd.pre2_byte;
+    const uint32_t xt = (((b >> 2) != 0 ? dg.w[1] : dg.w[0]) >> (8 * (b & 3))) & 0xffu;
+    uint32_t o2[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) o2[d] = (add_mod<D>(xt, neg_mod<D>(uint32_t(rd.pre2_shifts[d]))) - xt) * rd.pre2_ls;
+    if (rd.pre2_cpos == 0) {
+#pragma unroll
+        for (int i = 0; i < DM; ++i) a[i] += o2[rdigit<D, M, 0>(i)];
+    } else {
+#pragma unroll
+        for (int i = 0; i < DM; ++i) a[i] += o2[rdigit<D, M, 1>(i)];
+    }
+}
+
 template <int D, int M>
 __device__ __forceinline__ void store_addrs(uint32_t (&a)[cpow(D, M)], uint32_t tb, const RoundDesc& rd,
                                             uint32_t gidx0) {
@@ -672,12 +699,6 @@ __device__ __forceinline__ void round_ops(cplx<T> (&v)[cpow(D, M)], const RoundD
         }
     }
 }
-
-// Digits of sub-tile u over the k - M other tile qudits, least significant
-// first, one byte each; the first 8 digits.
-struct SubDigits {
-    uint32_t w[2];
-};
 
 template <int D>
 __device__ __forceinline__ SubDigits sub_digits(uint32_t u, int nother) {
@@ -833,6 +854,36 @@ __device__ __forceinline__ void run_round(cplx<T>* const (&t)[NT], const StageGe
     // U shapes: the matrices of position 0 (or the one U) and position 1
     const cplx<T>* U0 = mats + rd.mat0;
     const cplx<T>* U1 = mats + rd.mat1;
+    if constexpr (NT == 1 && M == 2) {
+        if (rd.pre2 >= 0) {
+            // a pair round with pre2 (forward lists, one sub-tile per lane):
+            // its loads read other lanes' sub-tiles, so every lane loads and
+            // multiplies before any lane stores
+            const bool act = threadIdx.x < nsub;
+            cplx<T> v[DM];
+            uint32_t tb = 0, gidx0 = 0;
+            if (act) {
+                tb = sub_base<D>(dig0, rd);
+                gidx0 = rd.need_gidx ? global_index(g, offhi, base, tb) : 0u;
+                uint32_t al[DM];
+                load_addrs<D, M>(al, tb, rd, gidx0);
+                add_pre2<D, M>(al, rd, dig0);
+#pragma unroll
+                for (int i = 0; i < DM; ++i) v[i] = t[0][al[i]];
+                r_u<T, D, M, 0, false>(v, U0);
+                asm volatile("" ::: "memory");
+                r_u<T, D, M, 1, false>(v, U1);
+            }
+            __syncthreads();
+            if (act) {
+                uint32_t as[DM];
+                store_addrs<D, M>(as, tb, rd, gidx0);
+#pragma unroll
+                for (int i = 0; i < DM; ++i) t[0][as[i]] = v[i];
+            }
+            return;
+        }
+    }
     for (uint32_t u = threadIdx.x; u < nsub; u += blockDim.x) {
         const uint32_t tb = sub_base<D>(u == threadIdx.x ? dig0 : sub_digits<D>(u, rd.nother), rd);
         const uint32_t gidx0 = rd.need_gidx ? global_index(g, offhi, base, tb) : 0u;

@@ -1050,8 +1050,12 @@ static Mat group_matrix(const qf_plan* p, const std::vector<GRef>& g, const doub
 // single leading SHIFT whose control is a tile qudit is taken as pre1), takes
 // consecutive in-place ops (U, PHASE) while the U targets fit in a group of M
 // tile qudits, and may end with one SHIFT folded into its stores (post: target
-// on position 0, control on position 1, outside the group or none).  The group
-// is padded with unused tile qudits.  Adjoint lists: a U that owns an M slot
+// on position 0, control on position 1, outside the group or none).  In
+// forward lists with groups of 2 and at most 256 sub-tiles, U on a, then
+// SHIFT x_t += s(x_c), then U on c (a, c, t different, t outside the group)
+// is taken as one round: U on a commutes with the SHIFT, which moves before it
+// and into the loads (pre2), and the two U make a pair.  The group is padded
+// with unused tile qudits.  Adjoint lists: a U that owns an M slot
 // opens its round (no SHIFT before it in the round).
 static void build_rounds(const qf_plan* p, Pass& ps, PassList& L, const std::vector<int>& dim_of, size_t& moff,
                          bool adjoint) {
@@ -1066,11 +1070,14 @@ static void build_rounds(const qf_plan* p, Pass& ps, PassList& L, const std::vec
     auto has = [](const std::vector<int>& v, int d) { return std::find(v.begin(), v.end(), d) != v.end(); };
     auto ctrl_dim = [&](const HOp& h) { return h.ctrl >= 0 ? dim_of[h.ctrl] : -1; };  // -1: none or outside
     auto slotted = [&](size_t j) { return adjoint && ps.ops[j].type == SOP_U && L.hops[ps.op_off + j].slot >= 0; };
+    // pre2 rounds (forward lists, groups of 2): the kernel keeps one sub-tile
+    // per lane of its 256-lane workgroup across a barrier
+    const bool pre2_ok = !adjoint && M == 2 && ipow(D, k - M) <= 256;
     size_t i = 0;
     while (i < nops) {
         std::vector<int> front;  // fixed group positions 0, 1, ...
         std::vector<int> rest;   // other group qudits (U targets)
-        int pre0 = -1, pre1 = -1, post = -1;
+        int pre0 = -1, pre1 = -1, pre2 = -1, post = -1;
         size_t j = i;
         if (ps.ops[j].type == SOP_SHIFT) {
             const int t = dim_of[ps.ops[j].q], c = ctrl_dim(ps.ops[j]);
@@ -1127,8 +1134,25 @@ static void build_rounds(const qf_plan* p, Pass& ps, PassList& L, const std::vec
                 ipe = j + 1;
                 continue;
             }
-            // a SHIFT after the in-place ops: post if it fits
             const int t = dim_of[h.q], c = ctrl_dim(h);
+            // U on a, SHIFT c -> t, U on c: the SHIFT becomes pre2 and the U a pair
+            if (pre2_ok && nin == 1 && pre2 < 0 && c >= 0 && j + 1 < nops && ps.ops[ip0].type == SOP_U) {
+                const HOp& nx = ps.ops[j + 1];
+                const int a = dim_of[ps.ops[ip0].q];
+                const std::vector<int> m = members();
+                const bool pair = nx.type == SOP_U && dim_of[nx.q] == c && !slotted(j + 1) && !is_real_u(ip0) &&
+                                  !is_real_u(j + 1);
+                const bool fits = has(m, c) || int(m.size()) < M;
+                const int lane_ctrl = pre0 >= 0 ? ctrl_dim(ps.ops[size_t(pre0)]) : -2;
+                if (pair && fits && a != c && a != t && c != t && !has(m, t) && lane_ctrl != t && lane_ctrl != c) {
+                    if (!has(m, c)) rest.push_back(c);
+                    pre2 = int(j);
+                    ++j;         // the loop's ++j passes the second U
+                    ipe = j + 1;
+                    continue;
+                }
+            }
+            // a SHIFT after the in-place ops: post if it fits
             if (front.empty()) {
                 std::vector<int> r2, r1;
                 for (int d : rest) {
@@ -1227,8 +1251,27 @@ static void build_rounds(const qf_plan* p, Pass& ps, PassList& L, const std::vec
             if (rd.nops == 1 && L.hops[ps.op_off + ip0].type == SOP_PHASE) rd.kind = RK_PHASE;
             if (allu && rd.nops == 2 && posmask == 3 && !anyreal && M >= 2) rd.kind = RK_U01;
         }
-        if (rd.kind == RK_U0 || rd.kind == RK_U0_REAL || rd.kind == RK_U1 || rd.kind == RK_U1_REAL ||
-            rd.kind == RK_U01) {
+        rd.pre2 = pre2;
+        if (pre2 >= 0) {
+            // ops: U, the pre2 SHIFT, U
+            const StageOp& ua = L.hops[ps.op_off + ip0];
+            const StageOp& ub = L.hops[ps.op_off + ip0 + 2];
+            const StageOp& sh = L.hops[ps.op_off + size_t(pre2)];
+            const HOp& h = ps.ops[size_t(pre2)];
+            rd.kind = RK_U01;
+            rd.mat0 = ua.gpos == 0 ? ua.mat : ub.mat;
+            rd.mat1 = ua.gpos == 0 ? ub.mat : ua.mat;
+            rd.pre2_cpos = gpos_of_qudit(h.ctrl);
+            const int t = dim_of[h.q];
+            int ot = 0;  // t's index among the other tile qudits (ols order)
+            for (int d = 0; d < t; ++d)
+                if (!has(grp, d)) ++ot;
+            rd.pre2_byte = rd.nother - 1 - ot;
+            rd.pre2_ls = ipow(D, k - 1 - t);
+            for (int c = 0; c < 16; ++c) rd.pre2_shifts[c] = sh.shifts[c];
+        }
+        if (pre2 < 0 && (rd.kind == RK_U0 || rd.kind == RK_U0_REAL || rd.kind == RK_U1 || rd.kind == RK_U1_REAL ||
+                         rd.kind == RK_U01)) {
             const StageOp& a = L.hops[ps.op_off + ip0];
             rd.mat0 = rd.mat1 = a.mat;
             if (rd.kind == RK_U01) {
@@ -1810,6 +1853,15 @@ static qf_status create_plan(const std::vector<int>& dims, int32_t dtype, const 
         log_msg("plan D=%d n=%d %s: %d gates, tile %d qudits (%d low), group %d: %zu forward passes; adjoint tile %d "
                 "(%d low): %zu passes, %d M slots", dim, n, dtype == QF_C64 ? "c64" : "c128", nops, k, r, p->group,
                 p->fwd.passes.size(), ka, ra, p->rev.passes.size(), p->rev.nslots);
+        // forward register rounds by shape and the permutations folded into their addresses
+        int kinds[8] = {0, 0, 0, 0, 0, 0, 0, 0}, nperm = 0;
+        for (const RoundDesc& rd : p->fwd.hrounds) {
+            if (rd.kind >= 0 && rd.kind < 8) ++kinds[rd.kind];
+            nperm += (rd.pre0 >= 0) + (rd.pre1 >= 0) + (rd.pre2 >= 0) + (rd.post >= 0);
+        }
+        log_msg("plan rounds (forward): %zu (generic %d, none %d, U0 %d, U0 real %d, U01 %d, U1 %d, U1 real %d, "
+                "phase %d), %d folded permutations", p->fwd.hrounds.size(), kinds[0], kinds[1], kinds[2], kinds[3],
+                kinds[4], kinds[5], kinds[6], kinds[7], nperm);
     }
     *out = p.release();
     return QF_OK;
