@@ -615,7 +615,7 @@ def main() -> int:
     traffic = _traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_stage_rounds<float, 3, 2>", "launches_per_step": launches // a.steps,
+                "kernel": "k_stage_rounds_w8<float, 3, 2>", "launches_per_step": launches // a.steps,
                 "avg_launch_us": round(avg_ms * 1e3, 2), "bytes_per_launch": per_launch}
     ev = z0.cpu().numpy()
     out = {

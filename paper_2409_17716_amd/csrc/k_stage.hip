@@ -631,9 +631,9 @@ struct SubDigits {
 };
 
 // pre2 on the load addresses (after pre0 and pre1): its target is one of the
-// lane's own digits x_t, so register i loads from x_t - s(d_ctrl(i)), an
-// offset per value of the control digit.  The amplitudes come from other
-// lanes' sub-tiles (see run_round).
+// lane's own digits x_t and its control is group position 1, so register i
+// loads from x_t - s(d_1(i)), an offset per value of that digit.  The
+// amplitudes come from other lanes' sub-tiles (see run_round).
 template <int D, int M>
 __device__ __forceinline__ void add_pre2(uint32_t (&a)[cpow(D, M)], const RoundDesc& rd, const SubDigits& dg) {
     constexpr int DM = cpow(D, M);
@@ -642,13 +642,8 @@ __device__ __forceinline__ void add_pre2(uint32_t (&a)[cpow(D, M)], const RoundD
     uint32_t o2[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) o2[d] = (add_mod<D>(xt, neg_mod<D>(uint32_t(rd.pre2_shifts[d]))) - xt) * rd.pre2_ls;
-    if (rd.pre2_cpos == 0) {
 #pragma unroll
-        for (int i = 0; i < DM; ++i) a[i] += o2[rdigit<D, M, 0>(i)];
-    } else {
-#pragma unroll
-        for (int i = 0; i < DM; ++i) a[i] += o2[rdigit<D, M, 1>(i)];
-    }
+    for (int i = 0; i < DM; ++i) a[i] += o2[rdigit<D, M, 1>(i)];
 }
 
 template <int D, int M>
@@ -989,9 +984,7 @@ __global__ __launch_bounds__(kSB) void k_stage_rounds(cplx<T>* __restrict__ psi,
 // instantiations holds 106 scalar registers, which caps a SIMD at 7 waves
 // (800 scalar registers each); this one is held to 78 at the price of at
 // most 64 bytes of spill per lane (measured 2% faster for D = 10 in
-// complex64; no change for D = 3 groups of 2, whose rounds are bound by the
-// latency of their LDS and scalar-load round trips, so those keep the default
-// build).
+// complex64, and 4% for D = 3 groups of 2, whose pair rounds need no spill).
 template <typename T, int D, int M>
 __global__ __launch_bounds__(kSB) __attribute__((amdgpu_waves_per_eu(8))) void k_stage_rounds_w8(
     cplx<T>* __restrict__ psi, StageGeom g, const RoundDesc* __restrict__ rounds, int nrounds,
@@ -1003,7 +996,7 @@ __global__ __launch_bounds__(kSB) __attribute__((amdgpu_waves_per_eu(8))) void k
 // the 8-wave build spills at most 64 bytes per lane.
 template <typename T, int D, int M>
 constexpr bool rounds_w8() {
-    if constexpr (sizeof(T) == 4) return M == 2 ? D == 2 : (M == 1 && D >= 5 && D <= 11);
+    if constexpr (sizeof(T) == 4) return M == 2 ? (D == 2 || D == 3) : (M == 1 && D >= 5 && D <= 11);
     else return M == 2 ? D == 2 : (M == 1 && D >= 3 && D <= 5);
 }
 

@@ -1052,9 +1052,9 @@ static Mat group_matrix(const qf_plan* p, const std::vector<GRef>& g, const doub
 // tile qudits, and may end with one SHIFT folded into its stores (post: target
 // on position 0, control on position 1, outside the group or none).  In
 // forward lists with groups of 2 and at most 256 sub-tiles, U on a, then
-// SHIFT x_t += s(x_c), then U on c (a, c, t different, t outside the group)
-// is taken as one round: U on a commutes with the SHIFT, which moves before it
-// and into the loads (pre2), and the two U make a pair.  The group is padded
+// SHIFT x_t += s(x_c), then U on c (a, c, t different, t outside the group, c
+// on group position 1) is taken as one round: U on a commutes with the SHIFT,
+// which moves before it and into the loads (pre2), and the two U make a pair.  The group is padded
 // with unused tile qudits.  Adjoint lists: a U that owns an M slot
 // opens its round (no SHIFT before it in the round).
 static void build_rounds(const qf_plan* p, Pass& ps, PassList& L, const std::vector<int>& dim_of, size_t& moff,
@@ -1142,7 +1142,9 @@ static void build_rounds(const qf_plan* p, Pass& ps, PassList& L, const std::vec
                 const std::vector<int> m = members();
                 const bool pair = nx.type == SOP_U && dim_of[nx.q] == c && !slotted(j + 1) && !is_real_u(ip0) &&
                                   !is_real_u(j + 1);
-                const bool fits = has(m, c) || int(m.size()) < M;
+                // the control lands on group position 1 (the kernel reads it there)
+                const int cpos = has(m, c) ? int(std::find(m.begin(), m.end(), c) - m.begin()) : int(m.size());
+                const bool fits = cpos == 1;
                 const int lane_ctrl = pre0 >= 0 ? ctrl_dim(ps.ops[size_t(pre0)]) : -2;
                 if (pair && fits && a != c && a != t && c != t && !has(m, t) && lane_ctrl != t && lane_ctrl != c) {
                     if (!has(m, c)) rest.push_back(c);
@@ -1261,7 +1263,6 @@ static void build_rounds(const qf_plan* p, Pass& ps, PassList& L, const std::vec
             rd.kind = RK_U01;
             rd.mat0 = ua.gpos == 0 ? ua.mat : ub.mat;
             rd.mat1 = ua.gpos == 0 ? ub.mat : ua.mat;
-            rd.pre2_cpos = gpos_of_qudit(h.ctrl);
             const int t = dim_of[h.q];
             int ot = 0;  // t's index among the other tile qudits (ols order)
             for (int d = 0; d < t; ++d)

@@ -198,10 +198,9 @@ struct RoundDesc {
     int32_t mat0, mat1;             // U shapes: matrix offset of the U on position 0 (or the one U), position 1
     PermDesc perm[3];               // the pre0, pre1 and post permutations (where present)
     // pre2 (groups of 2): a permutation after pre0 and pre1 whose target t is a
-    // tile qudit outside the group and whose control is on group position
-    // pre2_cpos; the lane's digit x_t loads from x_t - pre2_shifts[d_ctrl]
+    // tile qudit outside the group and whose control is group position 1; the
+    // lane's digit x_t loads from x_t - pre2_shifts[d_1]
     int32_t pre2;                   // its op, -1 = none
-    int32_t pre2_cpos;
     int32_t pre2_byte;              // byte of the sub-tile digits (sub_digits) that holds x_t
     uint32_t pre2_ls;               // LDS stride of t
     int32_t pre2_shifts[16];
