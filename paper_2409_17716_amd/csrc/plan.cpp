@@ -809,6 +809,13 @@ static void tile_shape(int D, int n, int dtype, int tile_opt, int low_opt, bool 
 
 static void make_geom(int D, int n, int k, int r, const std::vector<int>& T, StageGeom& g) {
     g = StageGeom{};
+    std::vector<bool> in(n, false);
+    for (int q : T) in[q] = true;
+    // the tile's HBM runs: the longest stretch of lowest qudits it holds (at
+    // least the r it was planned with), shorter than the 256-lane workgroup
+    // (longer runs take fewer, fuller memory requests; the LDS layout does not
+    // depend on r)
+    while (r < k && in[size_t(n - 1 - r)] && ipow(D, r + 1) < 256u) ++r;
     g.k = k;
     g.r = r;
     g.TE = ipow(D, k);
@@ -818,8 +825,6 @@ static void make_geom(int D, int n, int k, int r, const std::vector<int>& T, Sta
     g.N = ipow(D, n);
     g.nout = n - k;
     g.divR.init(g.R);
-    std::vector<bool> in(n, false);
-    for (int q : T) in[q] = true;
     int h = 0;
     for (int q : T)
         if (q < n - r) g.hi_stride[h++] = ipow(D, n - 1 - q);
