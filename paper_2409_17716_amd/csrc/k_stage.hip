@@ -525,12 +525,13 @@ __device__ __forceinline__ void r_phase(cplx<T> (&v)[cpow(D, M)], const StageOp&
     }
 }
 
-// LDS offset of register i over group positions 1 .. M-1.
+// LDS byte offset of register i over group positions 1 .. M-1 (glsb: the
+// group's byte strides; uniform, so this is scalar work).
 template <int D, int M>
-__device__ __forceinline__ uint32_t rest_offset(int i, const uint32_t* gls) {
+__device__ __forceinline__ uint32_t rest_offset(int i, const uint32_t* glsb) {
     uint32_t o = 0;
 #pragma unroll
-    for (int j = 1; j < M; ++j) o += uint32_t((i / cpow(D, M - 1 - j)) % D) * gls[j];
+    for (int j = 1; j < M; ++j) o += uint32_t((i / cpow(D, M - 1 - j)) % D) * glsb[j];
     return o;
 }
 
@@ -541,13 +542,46 @@ __device__ __forceinline__ uint32_t add_mod(uint32_t d, uint32_t s) {
     return t >= uint32_t(D) ? t - uint32_t(D) : t;
 }
 
-// LDS offset of register i over group positions 2 .. M-1.
+// LDS byte offset of register i over group positions 2 .. M-1.
 template <int D, int M>
-__device__ __forceinline__ uint32_t rest2_offset(int i, const uint32_t* gls) {
+__device__ __forceinline__ uint32_t rest2_offset(int i, const uint32_t* glsb) {
     uint32_t o = 0;
 #pragma unroll
-    for (int j = 2; j < M; ++j) o += uint32_t((i / cpow(D, M - 1 - j)) % D) * gls[j];
+    for (int j = 2; j < M; ++j) o += uint32_t((i / cpow(D, M - 1 - j)) % D) * glsb[j];
     return o;
+}
+
+// LDS access by 32-bit LDS byte address: a tile's base is added once to a
+// sub-tile's base address, not once per access.
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<float> {
+    typedef float type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Vec2<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+    return uint32_t(uintptr_t((const __attribute__((address_space(3))) unsigned char*)p));
+}
+
+template <typename T>
+__device__ __forceinline__ cplx<T> lds_ld(uint32_t a) {
+    typedef typename Vec2<T>::type V;
+    const V x = *(const __attribute__((address_space(3))) V*)uintptr_t(a);
+    return cmake<T>(x.x, x.y);
+}
+
+template <typename T>
+__device__ __forceinline__ void lds_st(uint32_t a, cplx<T> v) {
+    typedef typename Vec2<T>::type V;
+    V x;
+    x.x = v.re;
+    x.y = v.im;
+    *(__attribute__((address_space(3))) V*)uintptr_t(a) = x;
 }
 
 // Shift of a permutation op whose control is not a group qudit: one value per
@@ -580,29 +614,32 @@ __device__ __forceinline__ uint32_t neg_mod(uint32_t s) {
 //   post  target position 0, control position 1, per lane or none.
 // pre0 then pre1 act before the in-place ops: register (d0, d1) loads the
 // amplitude they bring there, from (d0 - s0, d1 - s1(d0)).  post acts after
-// them: register (d0, d1) stores to (d0 + s(d1), d1).
+// them: register (d0, d1) stores to (d0 + s(d1), d1).  Addresses are LDS byte
+// addresses (tbb: the sub-tile's register 0).
 template <int D, int M>
-__device__ __forceinline__ void load_addrs(uint32_t (&a)[cpow(D, M)], uint32_t tb, const RoundDesc& rd,
+__device__ __forceinline__ void load_addrs(uint32_t (&a)[cpow(D, M)], uint32_t tbb, const RoundDesc& rd,
                                            uint32_t gidx0) {
     constexpr int DM = cpow(D, M);
+    const uint32_t g0 = rd.glsb[0];
     if constexpr (M >= 2) {
         if (rd.pre1 >= 0) {
             uint32_t od[D];
             const uint32_t s0 = rd.pre0 >= 0 ? neg_mod<D>(lane_shift<D>(rd.perm[0], gidx0)) : 0u;
 #pragma unroll
-            for (int d = 0; d < D; ++d) od[d] = __umul24(add_mod<D>(uint32_t(d), s0), rd.gls[0]);
+            for (int d = 0; d < D; ++d) od[d] = tbb + __umul24(add_mod<D>(uint32_t(d), s0), g0);
+            const uint32_t g1 = rd.glsb[1];
 #pragma unroll
             for (int i = 0; i < DM; ++i) {
                 const int d0 = rdigit<D, M, 0>(i);
                 const uint32_t e1 = add_mod<D>(uint32_t(rdigit<D, M, 1>(i)), neg_mod<D>(uint32_t(rd.perm[1].shifts[d0])));
-                a[i] = tb + od[d0] + e1 * rd.gls[1] + rest2_offset<D, M>(i, rd.gls);
+                a[i] = od[d0] + (e1 * g1 + rest2_offset<D, M>(i, rd.glsb));
             }
             return;
         }
     }
     if (rd.pre0 < 0) {
 #pragma unroll
-        for (int i = 0; i < DM; ++i) a[i] = tb + uint32_t(rdigit<D, M, 0>(i)) * rd.gls[0] + rest_offset<D, M>(i, rd.gls);
+        for (int i = 0; i < DM; ++i) a[i] = tbb + (uint32_t(rdigit<D, M, 0>(i)) * g0 + rest_offset<D, M>(i, rd.glsb));
         return;
     }
     const PermDesc& P = rd.perm[0];
@@ -611,7 +648,7 @@ __device__ __forceinline__ void load_addrs(uint32_t (&a)[cpow(D, M)], uint32_t t
 #pragma unroll
             for (int i = 0; i < DM; ++i) {
                 const uint32_t s = neg_mod<D>(uint32_t(P.shifts[rdigit<D, M, 1>(i)]));
-                a[i] = tb + add_mod<D>(uint32_t(rdigit<D, M, 0>(i)), s) * rd.gls[0] + rest_offset<D, M>(i, rd.gls);
+                a[i] = tbb + (add_mod<D>(uint32_t(rdigit<D, M, 0>(i)), s) * g0 + rest_offset<D, M>(i, rd.glsb));
             }
             return;
         }
@@ -619,9 +656,9 @@ __device__ __forceinline__ void load_addrs(uint32_t (&a)[cpow(D, M)], uint32_t t
     const uint32_t s = neg_mod<D>(lane_shift<D>(P, gidx0));
     uint32_t od[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d) od[d] = __umul24(add_mod<D>(uint32_t(d), s), rd.gls[0]);
+    for (int d = 0; d < D; ++d) od[d] = tbb + __umul24(add_mod<D>(uint32_t(d), s), g0);
 #pragma unroll
-    for (int i = 0; i < DM; ++i) a[i] = tb + od[rdigit<D, M, 0>(i)] + rest_offset<D, M>(i, rd.gls);
+    for (int i = 0; i < DM; ++i) a[i] = od[rdigit<D, M, 0>(i)] + rest_offset<D, M>(i, rd.glsb);
 }
 
 // Digits of sub-tile u over the k - M other tile qudits, least significant
@@ -639,20 +676,22 @@ __device__ __forceinline__ void add_pre2(uint32_t (&a)[cpow(D, M)], const RoundD
     constexpr int DM = cpow(D, M);
     const int b = rd.pre2_byte;
     const uint32_t xt = (((b >> 2) != 0 ? dg.w[1] : dg.w[0]) >> (8 * (b & 3))) & 0xffu;
+    const uint32_t ls = rd.pre2_lsb;
     uint32_t o2[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d) o2[d] = (add_mod<D>(xt, neg_mod<D>(uint32_t(rd.pre2_shifts[d]))) - xt) * rd.pre2_ls;
+    for (int d = 0; d < D; ++d) o2[d] = (add_mod<D>(xt, neg_mod<D>(uint32_t(rd.pre2_shifts[d]))) - xt) * ls;
 #pragma unroll
     for (int i = 0; i < DM; ++i) a[i] += o2[rdigit<D, M, 1>(i)];
 }
 
 template <int D, int M>
-__device__ __forceinline__ void store_addrs(uint32_t (&a)[cpow(D, M)], uint32_t tb, const RoundDesc& rd,
+__device__ __forceinline__ void store_addrs(uint32_t (&a)[cpow(D, M)], uint32_t tbb, const RoundDesc& rd,
                                             uint32_t gidx0) {
     constexpr int DM = cpow(D, M);
+    const uint32_t g0 = rd.glsb[0];
     if (rd.post < 0) {
 #pragma unroll
-        for (int i = 0; i < DM; ++i) a[i] = tb + uint32_t(rdigit<D, M, 0>(i)) * rd.gls[0] + rest_offset<D, M>(i, rd.gls);
+        for (int i = 0; i < DM; ++i) a[i] = tbb + (uint32_t(rdigit<D, M, 0>(i)) * g0 + rest_offset<D, M>(i, rd.glsb));
         return;
     }
     const PermDesc& P = rd.perm[2];
@@ -661,7 +700,7 @@ __device__ __forceinline__ void store_addrs(uint32_t (&a)[cpow(D, M)], uint32_t 
 #pragma unroll
             for (int i = 0; i < DM; ++i) {
                 const uint32_t s = uint32_t(P.shifts[rdigit<D, M, 1>(i)]);
-                a[i] = tb + add_mod<D>(uint32_t(rdigit<D, M, 0>(i)), s) * rd.gls[0] + rest_offset<D, M>(i, rd.gls);
+                a[i] = tbb + (add_mod<D>(uint32_t(rdigit<D, M, 0>(i)), s) * g0 + rest_offset<D, M>(i, rd.glsb));
             }
             return;
         }
@@ -669,9 +708,9 @@ __device__ __forceinline__ void store_addrs(uint32_t (&a)[cpow(D, M)], uint32_t 
     const uint32_t s = lane_shift<D>(P, gidx0);
     uint32_t od[D];
 #pragma unroll
-    for (int d = 0; d < D; ++d) od[d] = __umul24(add_mod<D>(uint32_t(d), s), rd.gls[0]);
+    for (int d = 0; d < D; ++d) od[d] = tbb + __umul24(add_mod<D>(uint32_t(d), s), g0);
 #pragma unroll
-    for (int i = 0; i < DM; ++i) a[i] = tb + od[rdigit<D, M, 0>(i)] + rest_offset<D, M>(i, rd.gls);
+    for (int i = 0; i < DM; ++i) a[i] = od[rdigit<D, M, 0>(i)] + rest_offset<D, M>(i, rd.glsb);
 }
 
 template <typename T, int D, int M>
@@ -839,12 +878,19 @@ __device__ __forceinline__ void run_round(cplx<T>* const (&t)[NT], const StageGe
                                           const cplx<T>* __restrict__ mats, const SubDigits& dig0,
                                           const MArgs& ma = MArgs{}) {
     constexpr int DM = cpow(D, M);
+    constexpr uint32_t ESZ = uint32_t(sizeof(cplx<T>));
     MAcc<T, D> macc;
     if constexpr (MACC) {
 #pragma unroll
         for (int e = 0; e < D * D; ++e) macc.re[e] = macc.im[e] = T(0);
     }
     const uint32_t nsub = g.TE / DM;
+    // LDS byte addresses: tile 0's base goes into each sub-tile base; the
+    // other tile is a uniform distance away
+    const uint32_t lb0 = lds_addr(t[0]);
+    uint32_t dt[NT];
+#pragma unroll
+    for (int x = 0; x < NT; ++x) dt[x] = x == 0 ? 0u : lds_addr(t[x]) - lb0;
     const int kind = rd.kind;
     // U shapes: the matrices of position 0 (or the one U) and position 1
     const cplx<T>* U0 = mats + rd.mat0;
@@ -861,10 +907,10 @@ __device__ __forceinline__ void run_round(cplx<T>* const (&t)[NT], const StageGe
                 tb = sub_base<D>(dig0, rd);
                 gidx0 = rd.need_gidx ? global_index(g, offhi, base, tb) : 0u;
                 uint32_t al[DM];
-                load_addrs<D, M>(al, tb, rd, gidx0);
+                load_addrs<D, M>(al, lb0 + tb * ESZ, rd, gidx0);
                 add_pre2<D, M>(al, rd, dig0);
 #pragma unroll
-                for (int i = 0; i < DM; ++i) v[i] = t[0][al[i]];
+                for (int i = 0; i < DM; ++i) v[i] = lds_ld<T>(al[i]);
                 r_u<T, D, M, 0, false>(v, U0);
                 asm volatile("" ::: "memory");
                 r_u<T, D, M, 1, false>(v, U1);
@@ -872,9 +918,9 @@ __device__ __forceinline__ void run_round(cplx<T>* const (&t)[NT], const StageGe
             __syncthreads();
             if (act) {
                 uint32_t as[DM];
-                store_addrs<D, M>(as, tb, rd, gidx0);
+                store_addrs<D, M>(as, lb0 + tb * ESZ, rd, gidx0);
 #pragma unroll
-                for (int i = 0; i < DM; ++i) t[0][as[i]] = v[i];
+                for (int i = 0; i < DM; ++i) lds_st<T>(as[i], v[i]);
             }
             return;
         }
@@ -883,18 +929,18 @@ __device__ __forceinline__ void run_round(cplx<T>* const (&t)[NT], const StageGe
         const uint32_t tb = sub_base<D>(u == threadIdx.x ? dig0 : sub_digits<D>(u, rd.nother), rd);
         const uint32_t gidx0 = rd.need_gidx ? global_index(g, offhi, base, tb) : 0u;
         uint32_t al[DM];
-        load_addrs<D, M>(al, tb, rd, gidx0);
+        load_addrs<D, M>(al, lb0 + tb * ESZ, rd, gidx0);
         // the tiles one after the other (one sub-tile live at a time)
 #pragma unroll
         for (int x = 0; x < NT; ++x) {
             cplx<T> v[DM];
 #pragma unroll
-            for (int i = 0; i < DM; ++i) v[i] = t[x][al[i]];
+            for (int i = 0; i < DM; ++i) v[i] = lds_ld<T>(al[i] + dt[x]);
             if constexpr (MACC && NT == 2) {
                 if (x == 0 && ma.mslot >= 0) {
                     cplx<T> w[DM];
 #pragma unroll
-                    for (int i = 0; i < DM; ++i) w[i] = t[1][al[i]];
+                    for (int i = 0; i < DM; ++i) w[i] = lds_ld<T>(al[i] + dt[1]);
                     if (ma.mpos == 0) {
                         macc_add<T, D, M, 0>(macc, v, w);
                     } else {
@@ -905,9 +951,9 @@ __device__ __forceinline__ void run_round(cplx<T>* const (&t)[NT], const StageGe
             // each shape stores from its own branch
             auto store = [&]() {
                 uint32_t as[DM];
-                store_addrs<D, M>(as, tb, rd, gidx0);
+                store_addrs<D, M>(as, lb0 + tb * ESZ, rd, gidx0);
 #pragma unroll
-                for (int i = 0; i < DM; ++i) t[x][as[i]] = v[i];
+                for (int i = 0; i < DM; ++i) lds_st<T>(as[i] + dt[x], v[i]);
             };
             if (kind == RK_U0) {
                 r_u<T, D, M, 0, false>(v, U0);

@@ -1203,7 +1203,11 @@ static void build_rounds(const qf_plan* p, Pass& ps, PassList& L, const std::vec
         rd.pre0 = pre0;
         rd.pre1 = pre1;
         rd.post = post;
-        for (int g = 0; g < M; ++g) rd.gls[g] = ipow(D, k - 1 - grp[g]);
+        const uint32_t esz = p->dtype == QF_C64 ? 8u : 16u;
+        for (int g = 0; g < M; ++g) {
+            rd.gls[g] = ipow(D, k - 1 - grp[g]);
+            rd.glsb[g] = rd.gls[g] * esz;
+        }
         rd.nother = k - M;
         int o = 0;
         for (int d = 0; d < k; ++d)
@@ -1273,7 +1277,7 @@ static void build_rounds(const qf_plan* p, Pass& ps, PassList& L, const std::vec
             for (int d = 0; d < t; ++d)
                 if (!has(grp, d)) ++ot;
             rd.pre2_byte = rd.nother - 1 - ot;
-            rd.pre2_ls = ipow(D, k - 1 - t);
+            rd.pre2_lsb = ipow(D, k - 1 - t) * esz;
             for (int c = 0; c < 16; ++c) rd.pre2_shifts[c] = sh.shifts[c];
         }
         if (pre2 < 0 && (rd.kind == RK_U0 || rd.kind == RK_U0_REAL || rd.kind == RK_U1 || rd.kind == RK_U1_REAL ||

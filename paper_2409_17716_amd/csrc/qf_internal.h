@@ -190,6 +190,7 @@ struct RoundDesc {
     int32_t pre0, pre1, post;       // permutation ops, -1 = none
     int32_t need_gidx;              // some op reads a digit from the global index
     uint32_t gls[kMaxGroup];        // LDS strides of the group qudits, register digit 0 first
+    uint32_t glsb[kMaxGroup];       // the same in bytes (amplitudes of the plan's dtype)
     int32_t nother;                 // k - M
     uint32_t ols[kMaxTileDims];     // LDS strides of the other tile qudits, most significant first
     uint32_t spair[4];              // the last 8 of ols, least significant first, two 16-bit halves per word
@@ -202,7 +203,7 @@ struct RoundDesc {
     // lane's digit x_t loads from x_t - pre2_shifts[d_1]
     int32_t pre2;                   // its op, -1 = none
     int32_t pre2_byte;              // byte of the sub-tile digits (sub_digits) that holds x_t
-    uint32_t pre2_ls;               // LDS stride of t
+    uint32_t pre2_lsb;              // LDS stride of t in bytes
     int32_t pre2_shifts[16];
     int32_t mslot, mpos;            // adjoint: M slot and group position of the U that opens the round, -1 = none
 };
