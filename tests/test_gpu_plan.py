@@ -49,22 +49,24 @@ def test_plan_forward_matches_oracle(qf, name, make, dt, fuse, kernel):
 
 
 PAIR_SHIFT = [
-    ("config2_n10", lambda: qi.config2(n=10, layers=3)),
-    ("config2_n11", lambda: qi.config2(n=11, layers=2)),
-    ("hea_d4_n8", lambda: qi.hea(4, 8, 2, 31)),
-    ("hea_d3_n10_chain", lambda: qi.hea(3, 10, 3, 32, entangler="chain")),
+    ("config2_n10", lambda: qi.config2(n=10, layers=3), "c64"),
+    ("config2_n11", lambda: qi.config2(n=11, layers=2), "c64"),
+    ("hea_d4_n8", lambda: qi.hea(4, 8, 2, 31), "c64"),
+    ("hea_d3_n10_chain", lambda: qi.hea(3, 10, 3, 32, entangler="chain"), "c64"),
+    ("hea_d3_n10_c128", lambda: qi.hea(3, 10, 2, 35), "c128"),
+    ("hea_d4_n7_c128", lambda: qi.hea(4, 7, 2, 36), "c128"),
 ]
 
 
-@pytest.mark.parametrize("name,make", PAIR_SHIFT, ids=[c[0] for c in PAIR_SHIFT])
+@pytest.mark.parametrize("name,make,dt", PAIR_SHIFT, ids=[c[0] for c in PAIR_SHIFT])
 @pytest.mark.parametrize("kernel", [0, 2])
-def test_pair_rounds_with_shift_before(qf, name, make, kernel):
+def test_pair_rounds_with_shift_before(qf, name, make, dt, kernel):
     """Registers large enough that a tile spans several wavefronts: rounds that
     take U on a, the CSUM a+1 -> a+2 and U on a+1 read the CSUM's target from
     other lanes' sub-tiles (the round's loads all precede its stores)."""
     c = make()
-    _, t = run_gpu(qf, c, "c64", stage_kernel=kernel)
-    assert maxabs(to_np(t), sim.run(c)) <= TOL["c64"], name
+    _, t = run_gpu(qf, c, dt, stage_kernel=kernel)
+    assert maxabs(to_np(t), sim.run(c)) <= TOL[dt], name
 
 
 TILES = [(3, 1), (3, 2), (4, 2), (5, 3), (2, 1)]
