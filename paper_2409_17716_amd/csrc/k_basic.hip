@@ -539,6 +539,8 @@ __global__ __launch_bounds__(kBlock) void k_marg_stream_final(const double* __re
 
 constexpr int kMaxActive = 32;
 constexpr int kMaxTable = 128;
+// Row table of the expectation kernel (doubles, complex): chunk / lane span entries.
+constexpr int kMaxExpectRows = 512;
 
 struct ObsArg {
     uint32_t nact;
@@ -548,6 +550,9 @@ struct ObsArg {
     uint32_t off[kMaxActive];      // first table entry of each active qudit
     uint32_t nlow;                 // expectation chunks: terms whose digit varies inside a chunk
     uint32_t low[kMaxActive];      // their indices (the others are constant over a chunk)
+    uint32_t span;                 // expectation lanes: a qudit stride L <= kBlock (digits below it per lane)
+    uint32_t nrow;                 // chunk / L rows, whose other low digits are tabled per workgroup
+    uint32_t rows_table;           // 1: the row table is used (nrow <= kMaxExpectRows)
     double table[2 * kMaxTable];   // complex, interleaved, active qudits back to back
 };
 
@@ -566,12 +571,22 @@ __device__ inline void obs_value(const ObsArg& a, const double* tab, uint32_t x,
 // terms on qudits of at least that stride are constant over the chunk (taken
 // once from its first index); per element only the other ("low") terms are
 // looked up.
+// Expectation partial sums, one workgroup per chunk (a qudit stride).  The
+// digits of qudits at or above the chunk size are constant over the chunk
+// (taken once); the others vary.  Lanes walk the chunk in steps of
+// T = L floor(kBlock / L), L a qudit stride: lane tid = r L + l visits
+// x = x0 + tid + T j, whose digits below L are those of l (summed once per
+// lane) and whose digits between L and the chunk size are those of row
+// m = r + (T / L) j (summed once per workgroup into an LDS table).  Where that
+// table would be too large, or no term varies inside the chunk, every element
+// takes its varying digits itself.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_expect_partial(const cplx<T>* __restrict__ psi, uint32_t N,
                                                            uint32_t chunk, uint32_t nblk, ObsArg a,
                                                            double* __restrict__ partial) {
     __shared__ double tab[2 * kMaxTable];
     __shared__ double sh[kBlock];
+    __shared__ double rowf[2 * kMaxExpectRows];
     for (uint32_t i = threadIdx.x; i < 2 * a.ntab; i += kBlock) tab[i] = a.table[i];
     __syncthreads();
     const uint32_t b = blockIdx.x / nblk;
@@ -589,20 +604,60 @@ __global__ __launch_bounds__(kBlock) void k_expect_partial(const cplx<T>* __rest
         hi -= tab[2 * a.off[t] + 1];
     }
     double ar = 0.0, ai = 0.0;
-#pragma unroll 4
-    for (uint32_t x = x0 + threadIdx.x; x < x1; x += kBlock) {
-        const cplx<T> v = reg[x];
-        const double p = double(v.re) * double(v.re) + double(v.im) * double(v.im);
-        double fr = hr, fi = hi;
+    if (a.rows_table) {
+        const uint32_t L = a.span, R = kBlock / L, TL = R * L;
+        const uint32_t r = threadIdx.x / L, l = threadIdx.x - r * L;
+        // rows: the low terms at or above L, at x = m L
+        for (uint32_t m = threadIdx.x; m < a.nrow; m += kBlock) {
+            double fr = 0.0, fi = 0.0;
+            for (uint32_t j = 0; j < a.nlow; ++j) {
+                const uint32_t t = a.low[j];
+                if (a.stride[t].d < L) continue;
+                const uint32_t qv = a.stride[t].div(m * L);
+                const uint32_t d = qv - a.divd[t].div(qv) * a.divd[t].d;
+                fr += tab[2 * (a.off[t] + d)];
+                fi += tab[2 * (a.off[t] + d) + 1];
+            }
+            rowf[2 * m] = fr;
+            rowf[2 * m + 1] = fi;
+        }
+        // this lane: the low terms below L, at x = l
+        double cr = hr, ci = hi;
         for (uint32_t j = 0; j < a.nlow; ++j) {
             const uint32_t t = a.low[j];
-            const uint32_t qv = a.stride[t].div(x);
+            if (a.stride[t].d >= L) continue;
+            const uint32_t qv = a.stride[t].div(l);
             const uint32_t d = qv - a.divd[t].div(qv) * a.divd[t].d;
-            fr += tab[2 * (a.off[t] + d)];
-            fi += tab[2 * (a.off[t] + d) + 1];
+            cr += tab[2 * (a.off[t] + d)];
+            ci += tab[2 * (a.off[t] + d) + 1];
         }
-        ar += p * fr;
-        ai += p * fi;
+        __syncthreads();
+        if (threadIdx.x < TL) {
+            uint32_t m = r;
+#pragma unroll 4
+            for (uint32_t x = x0 + threadIdx.x; x < x1; x += TL, m += R) {
+                const cplx<T> v = reg[x];
+                const double p = double(v.re) * double(v.re) + double(v.im) * double(v.im);
+                ar += p * (cr + rowf[2 * m]);
+                ai += p * (ci + rowf[2 * m + 1]);
+            }
+        }
+    } else {
+#pragma unroll 4
+        for (uint32_t x = x0 + threadIdx.x; x < x1; x += kBlock) {
+            const cplx<T> v = reg[x];
+            const double p = double(v.re) * double(v.re) + double(v.im) * double(v.im);
+            double fr = hr, fi = hi;
+            for (uint32_t j = 0; j < a.nlow; ++j) {
+                const uint32_t t = a.low[j];
+                const uint32_t qv = a.stride[t].div(x);
+                const uint32_t d = qv - a.divd[t].div(qv) * a.divd[t].d;
+                fr += tab[2 * (a.off[t] + d)];
+                fi += tab[2 * (a.off[t] + d) + 1];
+            }
+            ar += p * fr;
+            ai += p * fi;
+        }
     }
     const double sr = block_sum(ar, sh);
     const double si = block_sum(ai, sh);
@@ -933,6 +988,14 @@ static void set_low_terms(ObsArg& a, const StateView& s, const std::vector<int>&
     a.nlow = 0;
     for (size_t t = 0; t < active.size(); ++t)
         if (s.strides[active[t]] < chunk) a.low[a.nlow++] = uint32_t(t);
+    // lanes span the largest qudit stride of at most kBlock amplitudes (and of
+    // at most the chunk); the chunk is a multiple of it
+    a.span = 1;
+    for (int q = int(s.n) - 1; q >= 0; --q)
+        if (s.strides[q] <= uint32_t(kBlock) && s.strides[q] <= chunk) a.span = s.strides[q];
+    a.nrow = chunk / a.span;
+    // (without low terms the plain loop has no per-element digit work)
+    a.rows_table = a.nlow > 0 && a.nrow <= uint32_t(kMaxExpectRows) ? 1u : 0u;
 }
 
 size_t expect_ws_doubles(const StateView& s) {
