@@ -2,7 +2,10 @@
 // section "Code style") by inversion of the cumulative distribution:
 //   1. probabilities of the measured qudits in FP64 (full register or marginal),
 //   2. an inclusive prefix sum per register in FP64, in a fixed order
-//      (segmented block scans, recursively over the block totals),
+//      (segmented block scans, recursively over the block totals; above 4096
+//      outcomes the block offsets are not added to the elements: a search
+//      finds the block on an array of block ends, then the element, adding
+//      its block's offset as it compares),
 //   3. one lane per shot: the first bin whose cumulative sum exceeds
 //      u * total (a draw whose product reaches the total goes to the last
 //      bin of non-zero probability), counted with integer atomics (an exact,
@@ -114,16 +117,61 @@ __device__ inline uint32_t lower_bound(const double* c, uint32_t K, double x) {
     return lo;
 }
 
-__global__ __launch_bounds__(kT) void k_sample(const double* __restrict__ cdf, uint32_t K, uint64_t shots,
-                                               uint64_t total, const double* __restrict__ u,
-                                               unsigned long long* __restrict__ counts,
-                                               int32_t* __restrict__ samples) {
+// Registers scanned without the last offset pass (more than kLdsBins outcomes):
+// the cumulative sum at x in scan block lb is off(lb) + local(x), off(lb) the
+// scanned block totals before lb (the same FP64 sum the offset pass forms).
+// ends[lb] = off(lb) + local(last element of lb), a short array the first
+// search runs on.
+__global__ __launch_bounds__(kT) void k_block_ends(const double* __restrict__ local, uint64_t seg, uint32_t bps,
+                                                   uint64_t nseg, const double* __restrict__ sums,
+                                                   double* __restrict__ ends) {
+    for (uint64_t i = uint64_t(blockIdx.x) * kT + threadIdx.x; i < nseg * bps; i += uint64_t(gridDim.x) * kT) {
+        const uint64_t s = i / bps, lb = i - s * bps;
+        const uint64_t last = std::min<uint64_t>(seg, (lb + 1) * kSpan) - 1;
+        const double off = lb > 0 ? sums[i - 1] : 0.0;
+        ends[i] = off + local[s * seg + last];
+    }
+}
+
+// First j of c[0..n) with off + c[j] > x (n if none); with GE, >= x.
+template <bool GE>
+__device__ inline uint32_t bound_off(const double* c, uint32_t n, double off, double x) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        const double v = off + c[mid];
+        if (GE ? v >= x : v > x) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+// One lane per shot on block-local sums: the block first (on ends), then the
+// element; counts with 64-bit integer atomics.
+__global__ __launch_bounds__(kT) void k_sample_blocks(const double* __restrict__ local, uint32_t K, uint32_t bps,
+                                                      const double* __restrict__ sums, const double* __restrict__ ends,
+                                                      uint64_t shots, uint64_t total, const double* __restrict__ u,
+                                                      unsigned long long* __restrict__ counts,
+                                                      int32_t* __restrict__ samples) {
     for (uint64_t i = uint64_t(blockIdx.x) * kT + threadIdx.x; i < total; i += uint64_t(gridDim.x) * kT) {
         const uint64_t b = i / shots;
-        const double* c = cdf + b * K;
-        const double sum = c[K - 1];
-        uint32_t idx = upper_bound(c, K, u[i] * sum);
-        if (idx >= K) idx = lower_bound(c, K, sum);
+        const double* c = local + b * K;
+        const double* e = ends + b * bps;
+        const double* so = sums + b * bps;
+        const double sum = e[bps - 1];
+        const double x = u[i] * sum;
+        uint32_t lb = upper_bound(e, bps, x);
+        uint32_t idx = K;
+        if (lb < bps) {
+            const uint32_t n = std::min<uint32_t>(kSpan, K - lb * kSpan);
+            idx = lb * kSpan + bound_off<false>(c + size_t(lb) * kSpan, n, lb > 0 ? so[lb - 1] : 0.0, x);
+        }
+        if (idx >= K) {
+            // the draw reached the total: the first element whose sum reaches it
+            lb = lower_bound(e, bps, sum);
+            const uint32_t n = std::min<uint32_t>(kSpan, K - lb * kSpan);
+            idx = lb * kSpan + bound_off<true>(c + size_t(lb) * kSpan, n, lb > 0 ? so[lb - 1] : 0.0, sum);
+        }
         atomicAdd(counts + b * K + idx, 1ull);
         if (samples) samples[i] = int32_t(idx);
     }
@@ -166,7 +214,7 @@ uint32_t grid_of(uint64_t n) {
 // of data.
 template <typename Src = double>
 qf_status scan_segments(double* data, uint64_t seg, uint64_t nseg, double* ws, hipStream_t st,
-                        const Src* src = nullptr) {
+                        const Src* src = nullptr, bool local_only = false) {
     const uint32_t bps = uint32_t((seg + kSpan - 1) / kSpan);
     const uint64_t nblk = nseg * bps;
     if (nblk >= (1ull << 31)) return set_error(QF_ERANGE, "prefix sum grid too large");
@@ -178,8 +226,11 @@ qf_status scan_segments(double* data, uint64_t seg, uint64_t nseg, double* ws, h
     QF_CHECK(check_launch("prefix sum"));
     if (bps > 1) {
         QF_CHECK(scan_segments(ws, bps, nseg, ws + nblk, st));
-        hipLaunchKernelGGL(k_scan_add, dim3(uint32_t(nblk)), dim3(kT), 0, st, data, seg, bps, ws);
-        QF_CHECK(check_launch("prefix sum add"));
+        // local_only: the block offsets stay in ws (scanned), data keeps block-local sums
+        if (!local_only) {
+            hipLaunchKernelGGL(k_scan_add, dim3(uint32_t(nblk)), dim3(kT), 0, st, data, seg, bps, ws);
+            QF_CHECK(check_launch("prefix sum add"));
+        }
     }
     return QF_OK;
 }
@@ -209,18 +260,31 @@ qf_status launch_sample(const StateView& s, int m, const int32_t* qudits, uint64
     const uint64_t draws = shots * s.batch;
     QF_RETURN_IF(bins >= (1ull << 32) || draws >= (1ull << 32), QF_ERANGE, "batch * bins or batch * shots >= 2^32");
     const uint64_t wsd = scan_ws_doubles(K, s.batch);
+    // more than kLdsBins outcomes: block-local sums and a block-end array
+    // (bps entries per register) searched first
+    const bool blocks = K > kLdsBins;
+    const uint64_t bps = (K + kSpan - 1) / kSpan;
+    const uint64_t nends = blocks ? bps * s.batch : 0;
     double* cdf = nullptr;
-    QF_CHECK(dev_malloc_async(reinterpret_cast<void**>(&cdf), (bins + wsd) * sizeof(double), st, "sampling"));
+    QF_CHECK(dev_malloc_async(reinterpret_cast<void**>(&cdf), (bins + wsd + nends) * sizeof(double), st,
+                              "sampling"));
+    double* ws = cdf + bins;
+    double* ends = ws + wsd;
     qf_status rs = QF_OK;
     if (m == 0) {
         // the full register: |psi|^2 is taken inside the first scan level
         if (s.dtype == QF_C64)
-            rs = scan_segments(cdf, K, s.batch, cdf + bins, st, reinterpret_cast<const cplx<float>*>(s.amps));
+            rs = scan_segments(cdf, K, s.batch, ws, st, reinterpret_cast<const cplx<float>*>(s.amps), blocks);
         else
-            rs = scan_segments(cdf, K, s.batch, cdf + bins, st, reinterpret_cast<const cplx<double>*>(s.amps));
+            rs = scan_segments(cdf, K, s.batch, ws, st, reinterpret_cast<const cplx<double>*>(s.amps), blocks);
     } else {
         rs = launch_probs_marginal(s, m, qudits, cdf, true, st);
-        if (rs == QF_OK) rs = scan_segments(cdf, K, s.batch, cdf + bins, st);
+        if (rs == QF_OK) rs = scan_segments<double>(cdf, K, s.batch, ws, st, nullptr, blocks);
+    }
+    if (rs == QF_OK && blocks) {
+        hipLaunchKernelGGL(k_block_ends, dim3(grid_of(nends)), dim3(kT), 0, st, cdf, K, uint32_t(bps),
+                           uint64_t(s.batch), ws, ends);
+        rs = check_launch("sampling block ends");
     }
     if (rs == QF_OK) {
         hipLaunchKernelGGL(k_fill_u64, dim3(grid_of(bins)), dim3(kT), 0, st,
@@ -236,7 +300,8 @@ qf_status launch_sample(const StateView& s, int m, const int32_t* qudits, uint64
             hipLaunchKernelGGL(k_sample_lds, dim3(uint32_t(bpr * s.batch)), dim3(kT), 0, st, cdf, uint32_t(K), shots,
                                uint32_t(bpr), u, reinterpret_cast<unsigned long long*>(counts), samples);
         } else {
-            hipLaunchKernelGGL(k_sample, dim3(grid_of(draws)), dim3(kT), 0, st, cdf, uint32_t(K), shots, draws, u,
+            hipLaunchKernelGGL(k_sample_blocks, dim3(grid_of(draws)), dim3(kT), 0, st, cdf, uint32_t(K),
+                               uint32_t(bps), ws, ends, shots, draws, u,
                                reinterpret_cast<unsigned long long*>(counts), samples);
         }
         rs = check_launch("sampling");
