@@ -208,13 +208,43 @@ __global__ __launch_bounds__(kBlock) void k_fused_mfma_regs(cplx<float>* __restr
         const uint32_t f0 = tile * NTM;
         const uint32_t nt = min(uint32_t(NTM), g.nfib - f0);
         __syncthreads();
-        for (uint32_t e = threadIdx.x; e < uint32_t(Kp * NTM); e += kBlock) {
-            const uint32_t b = e / NTM;
-            const uint32_t i = e - b * NTM;
-            cplx<float> v = cmake<float>(0.f, 0.f);
-            if (b < g.K && i < nt) v = psi[fibre_base(g, f0 + i) + b * g.L];
-            xr[b * RS + i] = v.re;
-            xi[b * RS + i] = v.im;
+        // X[b][i] goes to position (i % 16) * 4 + i / 16 of LDS row b, so that a
+        // lane's four column blocks are one 16-byte read
+        if (g.L == 1) {
+            // nt whole fibres of K contiguous amplitudes: consecutive lanes take
+            // consecutive amplitudes
+            const uint32_t cnt = g.K * nt;
+            const cplx<float>* src = psi + size_t(f0) * g.K;
+            for (uint32_t e = threadIdx.x; e < cnt; e += kBlock) {
+                const uint32_t i = g.divK.div(e);
+                const uint32_t b = e - i * g.K;
+                const cplx<float> v = src[e];
+                const uint32_t pos = b * RS + (i & 15u) * 4 + (i >> 4);
+                xr[pos] = v.re;
+                xi[pos] = v.im;
+            }
+            // zero the padding: rows past K, columns past nt
+            for (uint32_t e = threadIdx.x; e < uint32_t(Kp * NTM); e += kBlock) {
+                const uint32_t b = e / NTM, i = e - b * NTM;
+                if (b >= g.K || i >= nt) {
+                    const uint32_t pos = b * RS + (i & 15u) * 4 + (i >> 4);
+                    xr[pos] = 0.f;
+                    xi[pos] = 0.f;
+                }
+            }
+        } else {
+            // a lane keeps one fibre (its base computed once) and takes every
+            // fourth row; consecutive lanes take consecutive fibres
+            const uint32_t i = threadIdx.x & (NTM - 1);
+            const bool have = i < nt;
+            const uint32_t fb = have ? fibre_base(g, f0 + i) : 0u;
+            const uint32_t col = (i & 15u) * 4 + (i >> 4);
+            for (uint32_t b = threadIdx.x / NTM; b < uint32_t(Kp); b += kBlock / NTM) {
+                cplx<float> v = cmake<float>(0.f, 0.f);
+                if (have && b < g.K) v = psi[fb + b * g.L];
+                xr[b * RS + col] = v.re;
+                xi[b * RS + col] = v.im;
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -229,12 +259,12 @@ __global__ __launch_bounds__(kBlock) void k_fused_mfma_regs(cplx<float>* __restr
             }
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
-                const float* xrr = xr + (ks * 4 + lk) * RS + lr;
-                const float* xir = xi + (ks * 4 + lk) * RS + lr;
+                const f32x4 br4 = *reinterpret_cast<const f32x4*>(xr + (ks * 4 + lk) * RS + lr * 4);
+                const f32x4 bi4 = *reinterpret_cast<const f32x4*>(xi + (ks * 4 + lk) * RS + lr * 4);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const float br = xrr[j * 16];
-                    const float bi = xir[j * 16];
+                    const float br = br4[j];
+                    const float bi = bi4[j];
                     cr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(are[q][ks], br, cr[j], 0, 0, 0);
                     ci[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(are[q][ks], bi, ci[j], 0, 0, 0);
                     if (!real) {
