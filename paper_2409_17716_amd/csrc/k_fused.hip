@@ -176,21 +176,28 @@ __global__ __launch_bounds__(kBlock) void k_fused_mfma(cplx<float>* __restrict__
 // Persistent variant for Kp = 16 * NRB <= 128: wave w owns row blocks w and
 // w + 4 and keeps their B fragments for every k step in registers, then loops
 // over fibre tiles (grid-stride), so B is read once per workgroup.
-template <int NRB>
+// Template: NJ column blocks of 16 fibres per tile (NT = 16 NJ fibres; fewer
+// make the LDS tile smaller, so more workgroups share a CU and one's staging
+// overlaps another's products); REAL: the block's imaginary parts are zero,
+// so their fragments are not held.
+template <int NRB, int NJ, bool REAL>
 __global__ __launch_bounds__(kBlock) void k_fused_mfma_regs(cplx<float>* __restrict__ psi,
-                                                            const cplx<float>* __restrict__ B, FusedGeom g,
-                                                            int real) {
+                                                            const cplx<float>* __restrict__ B, FusedGeom g) {
     constexpr int Kp = 16 * NRB;
     constexpr int KS = Kp / 4;
     constexpr int RPW = (NRB + 3) / 4;  // row blocks per wave
+    constexpr int NTR = 16 * NJ;        // fibres per tile
+    constexpr int RSR = NTR + 4;        // LDS row stride (floats)
+    typedef float fNJ __attribute__((ext_vector_type(NJ)));
     extern __shared__ unsigned char smem[];
     float* xr = reinterpret_cast<float*>(smem);
-    float* xi = xr + size_t(Kp) * RS;
+    float* xi = xr + size_t(Kp) * RSR;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int lr = lane & 15;
     const int lk = lane >> 4;
-    float are[RPW][KS], aim[RPW][KS];
+    float are[RPW][KS];
+    float aim[REAL ? 1 : RPW][REAL ? 1 : KS];
 #pragma unroll
     for (int q = 0; q < RPW; ++q) {
         const uint32_t arow = uint32_t((wave + 4 * q) * 16 + lr);
@@ -200,16 +207,16 @@ __global__ __launch_bounds__(kBlock) void k_fused_mfma_regs(cplx<float>* __restr
             cplx<float> a = cmake<float>(0.f, 0.f);
             if (wave + 4 * q < NRB && arow < g.K && acol < g.K) a = B[arow * g.K + acol];
             are[q][ks] = a.re;
-            aim[q][ks] = a.im;
+            if constexpr (!REAL) aim[q][ks] = a.im;
         }
     }
-    const uint32_t ntiles = (g.nfib + NTM - 1) / NTM;
+    const uint32_t ntiles = (g.nfib + NTR - 1) / NTR;
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint32_t f0 = tile * NTM;
-        const uint32_t nt = min(uint32_t(NTM), g.nfib - f0);
+        const uint32_t f0 = tile * NTR;
+        const uint32_t nt = min(uint32_t(NTR), g.nfib - f0);
         __syncthreads();
-        // X[b][i] goes to position (i % 16) * 4 + i / 16 of LDS row b, so that a
-        // lane's four column blocks are one 16-byte read
+        // X[b][i] goes to position (i % 16) NJ + i / 16 of LDS row b, so that a
+        // lane's NJ column blocks are one read
         if (g.L == 1) {
             // nt whole fibres of K contiguous amplitudes: consecutive lanes take
             // consecutive amplitudes
@@ -219,31 +226,31 @@ __global__ __launch_bounds__(kBlock) void k_fused_mfma_regs(cplx<float>* __restr
                 const uint32_t i = g.divK.div(e);
                 const uint32_t b = e - i * g.K;
                 const cplx<float> v = src[e];
-                const uint32_t pos = b * RS + (i & 15u) * 4 + (i >> 4);
+                const uint32_t pos = b * RSR + (i & 15u) * NJ + (i >> 4);
                 xr[pos] = v.re;
                 xi[pos] = v.im;
             }
             // zero the padding: rows past K, columns past nt
-            for (uint32_t e = threadIdx.x; e < uint32_t(Kp * NTM); e += kBlock) {
-                const uint32_t b = e / NTM, i = e - b * NTM;
+            for (uint32_t e = threadIdx.x; e < uint32_t(Kp * NTR); e += kBlock) {
+                const uint32_t b = e / NTR, i = e - b * NTR;
                 if (b >= g.K || i >= nt) {
-                    const uint32_t pos = b * RS + (i & 15u) * 4 + (i >> 4);
+                    const uint32_t pos = b * RSR + (i & 15u) * NJ + (i >> 4);
                     xr[pos] = 0.f;
                     xi[pos] = 0.f;
                 }
             }
         } else {
             // a lane keeps one fibre (its base computed once) and takes every
-            // fourth row; consecutive lanes take consecutive fibres
-            const uint32_t i = threadIdx.x & (NTM - 1);
+            // (kBlock / NT)-th row; consecutive lanes take consecutive fibres
+            const uint32_t i = threadIdx.x & (NTR - 1);
             const bool have = i < nt;
             const uint32_t fb = have ? fibre_base(g, f0 + i) : 0u;
-            const uint32_t col = (i & 15u) * 4 + (i >> 4);
-            for (uint32_t b = threadIdx.x / NTM; b < uint32_t(Kp); b += kBlock / NTM) {
+            const uint32_t col = (i & 15u) * NJ + (i >> 4);
+            for (uint32_t b = threadIdx.x / NTR; b < uint32_t(Kp); b += kBlock / NTR) {
                 cplx<float> v = cmake<float>(0.f, 0.f);
                 if (have && b < g.K) v = psi[fb + b * g.L];
-                xr[b * RS + col] = v.re;
-                xi[b * RS + col] = v.im;
+                xr[b * RSR + col] = v.re;
+                xi[b * RSR + col] = v.im;
             }
         }
         __syncthreads();
@@ -251,30 +258,30 @@ __global__ __launch_bounds__(kBlock) void k_fused_mfma_regs(cplx<float>* __restr
         for (int q = 0; q < RPW; ++q) {
             const int rb = wave + 4 * q;
             if (rb >= NRB) continue;
-            f32x4 cr[4], ci[4];
+            f32x4 cr[NJ], ci[NJ];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < NJ; ++j) {
                 cr[j] = f32x4{0.f, 0.f, 0.f, 0.f};
                 ci[j] = f32x4{0.f, 0.f, 0.f, 0.f};
             }
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
-                const f32x4 br4 = *reinterpret_cast<const f32x4*>(xr + (ks * 4 + lk) * RS + lr * 4);
-                const f32x4 bi4 = *reinterpret_cast<const f32x4*>(xi + (ks * 4 + lk) * RS + lr * 4);
+                const fNJ brv = *reinterpret_cast<const fNJ*>(xr + (ks * 4 + lk) * RSR + lr * NJ);
+                const fNJ biv = *reinterpret_cast<const fNJ*>(xi + (ks * 4 + lk) * RSR + lr * NJ);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float br = br4[j];
-                    const float bi = bi4[j];
+                for (int j = 0; j < NJ; ++j) {
+                    const float br = brv[j];
+                    const float bi = biv[j];
                     cr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(are[q][ks], br, cr[j], 0, 0, 0);
                     ci[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(are[q][ks], bi, ci[j], 0, 0, 0);
-                    if (!real) {
+                    if constexpr (!REAL) {
                         cr[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(-aim[q][ks], bi, cr[j], 0, 0, 0);
                         ci[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(aim[q][ks], br, ci[j], 0, 0, 0);
                     }
                 }
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < NJ; ++j) {
                 const uint32_t col = uint32_t(j * 16 + lr);
                 if (col >= nt) continue;
                 const uint32_t base = fibre_base(g, f0 + col);
@@ -288,15 +295,22 @@ __global__ __launch_bounds__(kBlock) void k_fused_mfma_regs(cplx<float>* __restr
     }
 }
 
-template <int NRB>
-qf_status launch_mfma_regs(const StateView& s, const FusedGeom& g, const void* B, bool real, hipStream_t st) {
-    const size_t lds = size_t(2) * (16 * NRB) * RS * sizeof(float);
-    const uint32_t ntiles = (g.nfib + NTM - 1) / NTM;
-    const uint32_t grid = ntiles < 2048 ? ntiles : 2048;
-    hipLaunchKernelGGL(k_fused_mfma_regs<NRB>, dim3(grid), dim3(kBlock), lds, st,
-                       reinterpret_cast<cplx<float>*>(s.amps), reinterpret_cast<const cplx<float>*>(B), g,
-                       real ? 1 : 0);
+template <int NRB, int NJ, bool REAL>
+qf_status launch_mfma_regs(const StateView& s, const FusedGeom& g, const void* B, hipStream_t st) {
+    constexpr int NTR = 16 * NJ;
+    const size_t lds = size_t(2) * (16 * NRB) * (NTR + 4) * sizeof(float);
+    const uint32_t ntiles = (g.nfib + NTR - 1) / NTR;
+    const uint32_t grid = ntiles < 4096 ? ntiles : 4096;
+    hipLaunchKernelGGL((k_fused_mfma_regs<NRB, NJ, REAL>), dim3(grid), dim3(kBlock), lds, st,
+                       reinterpret_cast<cplx<float>*>(s.amps), reinterpret_cast<const cplx<float>*>(B), g);
     return check_launch("qf_apply_fused (matrix cores, persistent)");
+}
+
+// Real blocks: tiles of 32 fibres; complex blocks (twice the products per
+// operand read): 16 (both measured best on the D = 10 and D = 7 pair blocks).
+template <int NRB>
+qf_status launch_mfma_regs_any(const StateView& s, const FusedGeom& g, const void* B, bool real, hipStream_t st) {
+    return real ? launch_mfma_regs<NRB, 2, true>(s, g, B, st) : launch_mfma_regs<NRB, 1, false>(s, g, B, st);
 }
 
 }  // namespace
@@ -316,13 +330,13 @@ qf_status launch_fused(const StateView& s, int k, int q0, const void* B, hipStre
     g.divNT.init(nt);
     if (s.dtype == QF_C64 && K >= 32 && K <= 128) {
         switch ((K + 15) / 16) {
-            case 2: return launch_mfma_regs<2>(s, g, B, real, st);
-            case 3: return launch_mfma_regs<3>(s, g, B, real, st);
-            case 4: return launch_mfma_regs<4>(s, g, B, real, st);
-            case 5: return launch_mfma_regs<5>(s, g, B, real, st);
-            case 6: return launch_mfma_regs<6>(s, g, B, real, st);
-            case 7: return launch_mfma_regs<7>(s, g, B, real, st);
-            case 8: return launch_mfma_regs<8>(s, g, B, real, st);
+            case 2: return launch_mfma_regs_any<2>(s, g, B, real, st);
+            case 3: return launch_mfma_regs_any<3>(s, g, B, real, st);
+            case 4: return launch_mfma_regs_any<4>(s, g, B, real, st);
+            case 5: return launch_mfma_regs_any<5>(s, g, B, real, st);
+            case 6: return launch_mfma_regs_any<6>(s, g, B, real, st);
+            case 7: return launch_mfma_regs_any<7>(s, g, B, real, st);
+            case 8: return launch_mfma_regs_any<8>(s, g, B, real, st);
         }
     }
     if (s.dtype == QF_C64 && K >= 32 && K <= 256) {
