@@ -126,6 +126,25 @@ def test_diagonals_controlled_rotations_and_blocks(qf, dims, dt):
             assert maxabs(to_np(x), mixed.apply_block(psi, dims, q0, k, rounded(B, dt))) <= 4 * TOL[dt], (q0, k)
 
 
+# Registers whose expectation chunks span many rows of the lanes' span (span
+# 18, chunk 36,864: 2,048 rows, so every element takes its varying digits
+# itself) or a few (span 120, chunk 5,760: 48 rows in the workgroup's table).
+WIDE = [[2, 16, 2, 2, 2, 16, 3, 3, 2], [2, 3, 16, 4, 5, 3, 2]]
+
+
+@pytest.mark.parametrize("dims", WIDE, ids=str)
+def test_expectation_chunk_rows(qf, dims):
+    n, dt = len(dims), "c128"
+    psi = _state(dims, 7, batch=2)
+    x = to_dev(psi, dt)
+    rows = _rows(psi, 2)
+    terms = [(q, "z") for q in range(n)] + [(2, np.arange(dims[2]) * 0.25 - 0.5j)]
+    got = to_np(qf.qf_expect(x, n, dims, terms)).reshape(2, 2)
+    for b in range(2):
+        w = mixed.expect_diag(rows[b], dims, terms)
+        assert abs(got[b, 0] - w.real) <= 1e-12 and abs(got[b, 1] - w.imag) <= 1e-12, (b, got[b], w)
+
+
 @pytest.mark.parametrize("dims", DIMS, ids=str)
 def test_measurement(qf, dims):
     """Probabilities, marginals in any order, expectation of the Z sum and of a
