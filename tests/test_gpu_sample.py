@@ -133,6 +133,23 @@ def test_draws_that_reach_the_total(qf):
     assert got[0] == 4 and got[2] == 11 and got[3] == 11  # never a trailing empty outcome
 
 
+def test_draws_that_reach_the_total_many_outcomes(qf):
+    """The same rule with 3^9 outcomes (the search over scan-block ends, then
+    inside one block) and the non-zero outcomes in different scan blocks."""
+    import torch
+    D, n = 3, 9
+    psi = np.zeros(D ** n, dtype=np.complex128)
+    psi[[4, 5000, 15000]] = 2.3e-162
+    t = to_dev(psi, "c128")
+    top = np.nextafter(1.0, 0.0)
+    u = np.array([0.0, 0.3, 0.6, top, 1.0])
+    c, smp = qf.qf_sample(t, n, D, len(u), torch.from_numpy(u).cuda(), samples=True)
+    got = smp.cpu().numpy()
+    want = measure.sample_inverse_cdf(measure.probs(psi), u)
+    assert list(got) == list(want)
+    assert got[0] == 4 and got[3] == 15000 and got[4] == 15000
+
+
 def test_full_size_marginal_and_register(qf):
     """The 3^16 register in complex64: 10^5 shots of the full distribution and
     of a two-qudit marginal."""
