@@ -269,15 +269,66 @@ __device__ __forceinline__ void swap_pairs(cplx<T>* __restrict__ psi, uint32_t x
     }
 }
 
+// The same for two blocks at once (the second only where has1): both blocks'
+// loads are in flight before the first store.
+template <typename T, int D, int E>
+__device__ __forceinline__ void swap_pairs2(cplx<T>* __restrict__ psi, uint32_t x0, uint32_t x1, bool has1,
+                                            uint32_t Sa, uint32_t Sb) {
+    if constexpr (E < D * (D - 1) / 2) {
+        constexpr uint32_t ia = uint32_t(pair_row<D>(E)), ib = uint32_t(pair_col<D>(E));
+        const uint32_t oab = ia * Sa + ib * Sb, oba = ib * Sa + ia * Sb;
+        const cplx<T> v0 = psi[x0 + oab];
+        const cplx<T> w0 = psi[x0 + oba];
+        cplx<T> v1 = cmake<T>(0, 0), w1 = cmake<T>(0, 0);
+        if (has1) {
+            v1 = psi[x1 + oab];
+            w1 = psi[x1 + oba];
+        }
+        swap_pairs2<T, D, E + 1>(psi, x0, x1, has1, Sa, Sb);
+        psi[x0 + oab] = w0;
+        psi[x0 + oba] = v0;
+        if (has1) {
+            psi[x1 + oab] = w1;
+            psi[x1 + oba] = v1;
+        }
+    }
+}
+
+// Blocks a lane exchanges per loop trip in k_swap: two for small blocks whose
+// lower qudit has a stride of at least a wavefront (every load of a wavefront
+// then reads one run, and it keeps twice the loads in flight); one otherwise
+// (measured with the stride-1 qudit: two blocks per lane, each access spread
+// over 24-byte steps, were 10% slower).
 template <typename T, int D>
+constexpr bool swap_two_blocks_ok() {
+    return sizeof(T) == 4 && D <= 4;
+}
+
+template <typename T, int D>
+__device__ __forceinline__ uint32_t swap_block_base(uint32_t r, const FastDiv& divSb, const FastDiv& divM, uint32_t Sa,
+                                                    uint32_t Sb) {
+    const uint32_t t = divSb.div(r);
+    const uint32_t lo = r - t * Sb;
+    const uint32_t hi = divM.div(t);
+    const uint32_t mid = t - hi * divM.d;
+    return hi * (uint32_t(D) * Sa) + mid * (uint32_t(D) * Sb) + lo;
+}
+
+template <typename T, int D, int BPL>
 __global__ __launch_bounds__(kBlock) void k_swap(cplx<T>* __restrict__ psi, uint32_t nblk, FastDiv divSb, FastDiv divM,
                                                  uint32_t Sa, uint32_t Sb) {
+    if constexpr (BPL == 2) {
+        for (uint32_t r = blockIdx.x * (2 * kBlock) + threadIdx.x; r < nblk; r += gridDim.x * (2 * kBlock)) {
+            const uint32_t r1 = r + kBlock;
+            const bool has1 = r1 < nblk;
+            const uint32_t x0 = swap_block_base<T, D>(r, divSb, divM, Sa, Sb);
+            const uint32_t x1 = has1 ? swap_block_base<T, D>(r1, divSb, divM, Sa, Sb) : 0u;
+            swap_pairs2<T, D, 0>(psi, x0, x1, has1, Sa, Sb);
+        }
+        return;
+    }
     for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < nblk; r += gridDim.x * kBlock) {
-        const uint32_t t = divSb.div(r);
-        const uint32_t lo = r - t * Sb;
-        const uint32_t hi = divM.div(t);
-        const uint32_t mid = t - hi * divM.d;
-        const uint32_t x0 = hi * (uint32_t(D) * Sa) + mid * (uint32_t(D) * Sb) + lo;
+        const uint32_t x0 = swap_block_base<T, D>(r, divSb, divM, Sa, Sb);
         // all pairs' loads in flight where that stays in registers (measured:
         // complex128 blocks beyond D = 3 go to scratch)
         if constexpr ((sizeof(T) == 4 && D <= 6) || D <= 3) {
@@ -808,7 +859,14 @@ qf_status launch_swap(const StateView& s, int a, int b, hipStream_t st) {
         using T = decltype(tag);
         return with_dim(Dq, [&](auto dtag) -> qf_status {
             constexpr int D = decltype(dtag)::value;
-            hipLaunchKernelGGL((k_swap<T, D>), dim3(grid_for(nblk, kBlock)), dim3(kBlock), 0, st,
+            if constexpr (swap_two_blocks_ok<T, D>()) {
+                if (Sb >= 64) {
+                    hipLaunchKernelGGL((k_swap<T, D, 2>), dim3(grid_for(nblk, kBlock * 2)), dim3(kBlock), 0, st,
+                                       reinterpret_cast<cplx<T>*>(s.amps), nblk, FastDiv(Sb), FastDiv(M), Sa, Sb);
+                    return check_launch("swap");
+                }
+            }
+            hipLaunchKernelGGL((k_swap<T, D, 1>), dim3(grid_for(nblk, kBlock)), dim3(kBlock), 0, st,
                                reinterpret_cast<cplx<T>*>(s.amps), nblk, FastDiv(Sb), FastDiv(M), Sa, Sb);
             return check_launch("swap");
         });

@@ -9,7 +9,10 @@
 // lane reads and writes just those two amplitudes of its fibre (2/D of the
 // state); the z type scales levels 0..j.  Fibres at control level 0 are left
 // alone.  Consecutive lanes take consecutive l, so for L >= 64 every access of
-// a wavefront is one contiguous run.
+// a wavefront is one contiguous run.  The forward kernel gives each lane
+// kFPL fibres, kCB apart, and issues all their loads before the first store:
+// with one fibre a wavefront keeps only 1 KB of loads in flight when the two
+// levels are contiguous slabs, too little to cover the HBM latency.
 //
 // Per control level m the kernels read a two-entry table: x, y types
 // (cos(m theta / 2), sin(m theta / 2)) in one complex entry (the inverse
@@ -26,6 +29,7 @@ namespace qf {
 namespace {
 
 constexpr int kCB = 256;
+constexpr int kFPL = 4;  // fibres per lane in the forward kernel
 
 struct CrGeom {
     int32_t has_ctrl;    // 0: plain rotation, every fibre uses table entry 1
@@ -36,7 +40,8 @@ struct CrGeom {
     uint32_t ntab;       // table entries: 2 per control level
     uint32_t nfib;       // fibres per register, N / d_t
     uint32_t N;          // amplitudes per register
-    uint32_t bpr;        // workgroups per register
+    uint32_t bpr;        // workgroups per register (one fibre per lane: the adjoint)
+    uint32_t bprf;       // workgroups per register of the forward kernel (kFPL fibres per lane)
     int32_t kind;        // 0 = x, 1 = y, 2 = z
     int32_t j, k;        // levels (z: j)
     double alpha;        // z: sqrt(2 / (j (j + 1)))
@@ -60,6 +65,21 @@ __device__ __forceinline__ uint32_t ctrl_level(const CrGeom& g, uint32_t local) 
     return qv - g.divDc.div(qv) * g.divDc.d;
 }
 
+// The x- or y-type rotation of levels (j, k) with cs = (cos, sin) of half the
+// angle, on the pair (a, b) = (psi_j, psi_k).
+template <typename T>
+__device__ __forceinline__ void rot_pair(int kind, cplx<T> cs, cplx<T>& a, cplx<T>& b) {
+    const T c = cs.re, s = cs.im;
+    const cplx<T> x = a, y = b;
+    if (kind == 0) {  // [[c, -i s], [-i s, c]]
+        a = cmake<T>(c * x.re + s * y.im, c * x.im - s * y.re);
+        b = cmake<T>(c * y.re + s * x.im, c * y.im - s * x.re);
+    } else {          // [[c, -s], [s, c]]
+        a = cmake<T>(c * x.re - s * y.re, c * x.im - s * y.im);
+        b = cmake<T>(s * x.re + c * y.re, s * x.im + c * y.im);
+    }
+}
+
 // Applies the table's rotation for control level m to the fibre at base.
 template <typename T, int D>
 __device__ __forceinline__ void rotate(cplx<T>* __restrict__ psi, const CrGeom& g, uint32_t base, const cplx<T>* tab,
@@ -70,31 +90,57 @@ __device__ __forceinline__ void rotate(cplx<T>* __restrict__ psi, const CrGeom& 
         psi[base + uint32_t(g.j) * g.L] = cmul(psi[base + uint32_t(g.j) * g.L], p2);
         return;
     }
-    const T c = tab[2 * m].re, s = tab[2 * m].im;
     const uint32_t ia = base + uint32_t(g.j) * g.L, ib = base + uint32_t(g.k) * g.L;
-    const cplx<T> a = psi[ia], b = psi[ib];
-    if (g.kind == 0) {  // [[c, -i s], [-i s, c]]
-        psi[ia] = cmake<T>(c * a.re + s * b.im, c * a.im - s * b.re);
-        psi[ib] = cmake<T>(c * b.re + s * a.im, c * b.im - s * a.re);
-    } else {            // [[c, -s], [s, c]]
-        psi[ia] = cmake<T>(c * a.re - s * b.re, c * a.im - s * b.im);
-        psi[ib] = cmake<T>(s * a.re + c * b.re, s * a.im + c * b.im);
-    }
+    cplx<T> a = psi[ia], b = psi[ib];
+    rot_pair<T>(g.kind, tab[2 * m], a, b);
+    psi[ia] = a;
+    psi[ib] = b;
 }
 
 template <typename T, int D>
 __global__ __launch_bounds__(kCB) void k_crot(cplx<T>* __restrict__ psi, CrGeom g, CrTab<T> harg,
                                               const cplx<T>* __restrict__ dtab, size_t tab_stride) {
     __shared__ cplx<T> tab[2 * kMaxDim];
-    const uint32_t b = blockIdx.x / g.bpr;
+    const uint32_t b = blockIdx.x / g.bprf;
     load_tab<T>(harg, dtab, tab_stride, b, g.ntab, tab);
-    const uint32_t f = (blockIdx.x - b * g.bpr) * kCB + threadIdx.x;
-    if (f >= g.nfib) return;
-    const uint32_t h = g.divL.div(f);
-    const uint32_t local = h * (uint32_t(D) * g.L) + (f - h * g.L);
-    const uint32_t m = ctrl_level(g, local);
-    if (m == 0) return;
-    rotate<T, D>(psi + size_t(b) * g.N, g, local, tab, m);
+    const uint32_t f0 = (blockIdx.x - b * g.bprf) * (kCB * kFPL) + threadIdx.x;
+    cplx<T>* const p = psi + size_t(b) * g.N;
+    uint32_t loc[kFPL], lev[kFPL];  // fibre base and control level (0: left alone)
+#pragma unroll
+    for (int i = 0; i < kFPL; ++i) {
+        const uint32_t f = f0 + uint32_t(i) * kCB;
+        loc[i] = 0;
+        lev[i] = 0;
+        if (f < g.nfib) {
+            const uint32_t h = g.divL.div(f);
+            loc[i] = h * (uint32_t(D) * g.L) + (f - h * g.L);
+            lev[i] = ctrl_level(g, loc[i]);
+        }
+    }
+    if (g.kind == 2) {
+#pragma unroll
+        for (int i = 0; i < kFPL; ++i)
+            if (lev[i] != 0) rotate<T, D>(p, g, loc[i], tab, lev[i]);
+        return;
+    }
+    const uint32_t oj = uint32_t(g.j) * g.L, ok = uint32_t(g.k) * g.L;
+    cplx<T> va[kFPL], vb[kFPL];
+#pragma unroll
+    for (int i = 0; i < kFPL; ++i) {
+        va[i] = cmake<T>(0, 0);
+        vb[i] = cmake<T>(0, 0);
+        if (lev[i] != 0) {
+            va[i] = p[loc[i] + oj];
+            vb[i] = p[loc[i] + ok];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kFPL; ++i) {
+        if (lev[i] == 0) continue;
+        rot_pair<T>(g.kind, tab[2 * lev[i]], va[i], vb[i]);
+        p[loc[i] + oj] = va[i];
+        p[loc[i] + ok] = vb[i];
+    }
 }
 
 // Deterministic workgroup sum (fixed tree).
@@ -195,6 +241,7 @@ CrGeom make_geom(const StateView& s, const CrotArgs& a) {
     g.nfib = s.N / s.dims[a.tgt];
     g.N = s.N;
     g.bpr = (g.nfib + kCB - 1) / kCB;
+    g.bprf = (g.nfib + kCB * kFPL - 1) / (kCB * kFPL);
     g.kind = a.kind;
     g.j = a.j;
     g.k = a.k;
@@ -223,11 +270,11 @@ qf_status launch_crot(const StateView& s, const CrotArgs& a, const void* dtab, s
     return with_dim_c(s.dims[a.tgt], [&](auto dtag) -> qf_status {
         constexpr int D = decltype(dtag)::value;
         if (s.dtype == QF_C64)
-            hipLaunchKernelGGL((k_crot<float, D>), dim3(g.bpr * s.batch), dim3(kCB), 0, st,
+            hipLaunchKernelGGL((k_crot<float, D>), dim3(g.bprf * s.batch), dim3(kCB), 0, st,
                                reinterpret_cast<cplx<float>*>(s.amps), g, host_tab<float>(htab, g.ntab),
                                reinterpret_cast<const cplx<float>*>(dtab), tab_stride);
         else
-            hipLaunchKernelGGL((k_crot<double, D>), dim3(g.bpr * s.batch), dim3(kCB), 0, st,
+            hipLaunchKernelGGL((k_crot<double, D>), dim3(g.bprf * s.batch), dim3(kCB), 0, st,
                                reinterpret_cast<cplx<double>*>(s.amps), g, host_tab<double>(htab, g.ntab),
                                reinterpret_cast<const cplx<double>*>(dtab), tab_stride);
         return check_launch("controlled rotation");

@@ -22,7 +22,8 @@ def _grad_close(g, ref, rel, dtype="c64"):
     return np.all(np.abs(g - ref) <= rel * np.maximum(np.abs(ref), floor))
 
 
-@pytest.mark.parametrize("D,n,dt", [(3, 7, "c64"), (2, 11, "c128"), (5, 4, "c64"), (10, 3, "c128")])
+@pytest.mark.parametrize("D,n,dt", [(3, 7, "c64"), (2, 11, "c128"), (5, 4, "c64"), (10, 3, "c128"), (2, 10, "c64"),
+                                    (4, 6, "c64")])
 def test_swap_every_pair_bit_exact(qf, D, n, dt):
     psi = rounded(qi.random_state(D, n, 3, batch=2).reshape(-1), dt)
     for a in range(n):
