@@ -29,8 +29,11 @@ constexpr int kSpan = kT * kPer;  // elements per scan block
 // Inclusive scan of segments of length seg (a segment never shares a block with
 // another): block blk covers elements [s * seg + lb * kSpan, ...) of segment
 // s = blk / bps, lb = blk % bps.  Each thread sums its kPer elements in order,
-// the thread totals are scanned in LDS by doubling steps, and the block total
-// goes to sums[blk] (sums are laid out as [segment][bps]).
+// the thread totals are scanned within each wavefront by lane shifts (six
+// doubling steps), the four wavefront totals are added in order through LDS
+// (one barrier), and the block total goes to sums[blk] (sums are laid out as
+// [segment][bps]).  Full blocks whose source and destination are 16-byte
+// aligned move their elements with 16-byte loads and stores.
 // Src = double: scan data in place; Src = cplx<float> / cplx<double>: the
 // values are |psi_x|^2 of the state src (taken in FP64), written scanned to data.
 template <typename Src>
@@ -43,39 +46,90 @@ __device__ inline double scan_value(const Src* p, uint64_t e) {
     }
 }
 
+__device__ inline double sq2(float a, float b) { return double(a) * double(a) + double(b) * double(b); }
+
+// A thread's kPer values of a full block, 16 bytes per load where the element
+// is narrower than that.
+template <typename Src>
+__device__ inline void scan_values_vec(const Src* q, double (&x)[kPer]) {
+    static_assert(kPer % 2 == 0, "pairs of elements per 16-byte load");
+    if constexpr (std::is_same<Src, double>::value) {
+        const double2* p = reinterpret_cast<const double2*>(q);
+#pragma unroll
+        for (int i = 0; i < kPer / 2; ++i) {
+            const double2 a = p[i];
+            x[2 * i] = a.x;
+            x[2 * i + 1] = a.y;
+        }
+    } else if constexpr (sizeof(Src) == 8) {
+        const float4* p = reinterpret_cast<const float4*>(q);
+#pragma unroll
+        for (int i = 0; i < kPer / 2; ++i) {
+            const float4 a = p[i];
+            x[2 * i] = sq2(a.x, a.y);
+            x[2 * i + 1] = sq2(a.z, a.w);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) x[i] = scan_value(q, uint64_t(i));
+    }
+}
+
 template <typename Src>
 __global__ __launch_bounds__(kT) void k_scan_block(const Src* __restrict__ src, double* __restrict__ data,
                                                    uint64_t seg, uint32_t bps, double* __restrict__ sums) {
-    __shared__ double sh[kT];
+    constexpr int kW = kT / 64;
+    __shared__ double wt[kW];
     const uint32_t blk = blockIdx.x;
     const uint32_t s = blk / bps, lb = blk - s * bps;
     const uint64_t lo = uint64_t(lb) * kSpan;
     const uint64_t n = seg - lo < uint64_t(kSpan) ? seg - lo : uint64_t(kSpan);
     const Src* q = src + s * seg + lo;
     double* d = data + s * seg + lo;
+    const bool vec = n == uint64_t(kSpan) &&
+                     ((reinterpret_cast<uintptr_t>(q) | reinterpret_cast<uintptr_t>(d)) & 15u) == 0;
     double v[kPer];
+    if (vec) {
+        scan_values_vec<Src>(q + size_t(threadIdx.x) * kPer, v);
+    } else {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const uint64_t e = uint64_t(threadIdx.x) * kPer + i;
+            v[i] = e < n ? scan_value(q, e) : 0.0;
+        }
+    }
     double run = 0.0;
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
-        const uint64_t e = uint64_t(threadIdx.x) * kPer + i;
-        run += e < n ? scan_value(q, e) : 0.0;
+        run += v[i];
         v[i] = run;
     }
-    sh[threadIdx.x] = run;
-    __syncthreads();
-    for (int off = 1; off < kT; off <<= 1) {
-        const double add = threadIdx.x >= uint32_t(off) ? sh[threadIdx.x - off] : 0.0;
-        __syncthreads();
-        sh[threadIdx.x] += add;
-        __syncthreads();
-    }
-    const double before = threadIdx.x > 0 ? sh[threadIdx.x - 1] : 0.0;
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    double incl = run;
 #pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-        const uint64_t e = uint64_t(threadIdx.x) * kPer + i;
-        if (e < n) d[e] = before + v[i];
+    for (int off = 1; off < 64; off <<= 1) {
+        const double y = __shfl_up(incl, off, 64);
+        if (lane >= uint32_t(off)) incl += y;
     }
-    if (threadIdx.x == kT - 1) sums[blk] = sh[kT - 1];
+    double excl = __shfl_up(incl, 1, 64);
+    if (lane == 0) excl = 0.0;
+    if (lane == 63) wt[wv] = incl;
+    __syncthreads();
+    double wpre = 0.0;
+    for (uint32_t w = 0; w < wv; ++w) wpre += wt[w];
+    const double before = wpre + excl;
+    if (vec) {
+        double2* p = reinterpret_cast<double2*>(d + size_t(threadIdx.x) * kPer);
+#pragma unroll
+        for (int i = 0; i < kPer / 2; ++i) p[i] = make_double2(before + v[2 * i], before + v[2 * i + 1]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const uint64_t e = uint64_t(threadIdx.x) * kPer + i;
+            if (e < n) d[e] = before + v[i];
+        }
+    }
+    if (threadIdx.x == kT - 1) sums[blk] = wpre + incl;
 }
 
 // data[s * seg + lb * kSpan + e] += (scanned block totals)[s][lb - 1] for lb >= 1.
