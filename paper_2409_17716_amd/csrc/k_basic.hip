@@ -408,7 +408,19 @@ __global__ __launch_bounds__(kBlock) void k_diag(cplx<T>* __restrict__ psi, uint
 template <typename T, typename O>
 __global__ __launch_bounds__(kBlock) void k_probs_full(const cplx<T>* __restrict__ psi, O* __restrict__ out,
                                                        uint32_t total) {
-    for (uint32_t x = blockIdx.x * kBlock + threadIdx.x; x < total; x += gridDim.x * kBlock) {
+    // four grid strides per trip, loads first, 64-bit indices (a 32-bit index
+    // plus the grid stride could wrap for totals near 2^32); measured at the
+    // same speed as one element per trip on 3^16 (91-92 us)
+    const uint64_t st = uint64_t(gridDim.x) * kBlock;
+    uint64_t x = uint64_t(blockIdx.x) * kBlock + threadIdx.x;
+    for (; x + 3 * st < total; x += 4 * st) {
+        cplx<T> v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = psi[x + uint64_t(i) * st];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) out[x + uint64_t(i) * st] = O(v[i].re) * O(v[i].re) + O(v[i].im) * O(v[i].im);
+    }
+    for (; x < total; x += st) {
         const cplx<T> v = psi[x];
         out[x] = O(v.re) * O(v.re) + O(v.im) * O(v.im);
     }
