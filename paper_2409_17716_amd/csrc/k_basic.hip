@@ -426,15 +426,19 @@ __global__ __launch_bounds__(kBlock) void k_probs_full(const cplx<T>* __restrict
     }
 }
 
-// Deterministic workgroup sum of one double per lane (fixed tree order).
+// Deterministic workgroup sum of one double per lane (fixed order; a
+// workgroup of kBlock lanes): an xor butterfly inside each wavefront (partners
+// add the same two values, so every lane ends with the same total), then the
+// wavefront totals in wavefront order through LDS (sh holds kBlock / 64).
 __device__ inline double block_sum(double v, double* sh) {
-    sh[threadIdx.x] = v;
+    constexpr int kWaves = kBlock / 64;
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    if ((threadIdx.x & 63u) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if (int(threadIdx.x) < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-        __syncthreads();
-    }
-    const double r = sh[0];
+    double r = sh[0];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) r += sh[w];
     __syncthreads();
     return r;
 }
@@ -590,9 +594,30 @@ __global__ __launch_bounds__(kBlock) void k_marg_stream_final(const double* __re
                                                               uint32_t bins, O* __restrict__ out) {
     __shared__ double sh[kBlock];
     const uint32_t b = blockIdx.x / bins, y = blockIdx.x - b * bins;
-    double s = 0.0;
-    for (uint32_t w = threadIdx.x; w < wpr; w += kBlock) s += partial[(size_t(b) * wpr + w) * bins + y];
-    s = block_sum(s, sh);
+    // kAcc accumulators per lane (independent loads in flight), met in a fixed tree
+    constexpr int kAcc = 8;
+    const double* p = partial + size_t(b) * wpr * bins + y;
+    double acc[kAcc];
+#pragma unroll
+    for (int j = 0; j < kAcc; ++j) acc[j] = 0.0;
+    uint32_t w = threadIdx.x;
+    for (; uint64_t(w) + uint64_t(kAcc - 1) * kBlock < wpr; w += kAcc * kBlock) {
+        double v[kAcc];
+#pragma unroll
+        for (int j = 0; j < kAcc; ++j) v[j] = p[size_t(w + uint32_t(j) * kBlock) * bins];
+#pragma unroll
+        for (int j = 0; j < kAcc; ++j) acc[j] += v[j];
+    }
+#pragma unroll
+    for (int j = 0; j < kAcc - 1; ++j) {
+        const uint64_t wj = uint64_t(w) + uint64_t(j) * kBlock;
+        if (wj < wpr) acc[j] += p[size_t(wj) * bins];
+    }
+#pragma unroll
+    for (int h = kAcc / 2; h > 0; h >>= 1)
+#pragma unroll
+        for (int j = 0; j < h; ++j) acc[j] += acc[j + h];
+    double s = block_sum(acc[0], sh);
     if (threadIdx.x == 0) out[blockIdx.x] = O(s);
 }
 
@@ -730,16 +755,49 @@ __global__ __launch_bounds__(kBlock) void k_expect_partial(const cplx<T>* __rest
     }
 }
 
-// One workgroup per register: lanes sum partials c = lane, lane + 256, ..., then a fixed tree.
+// One workgroup per register; a fixed summation order, so the result is bitwise reproducible.
 __global__ __launch_bounds__(kBlock) void k_expect_final(const double* __restrict__ partial, uint32_t nblk,
                                                          double* __restrict__ out) {
+    // Lane t takes the partials t, t + kBlock, ... into kAcc accumulators (the
+    // j-th of each group of kAcc strides into the j-th), so kAcc independent
+    // 16-byte loads are in flight per trip instead of one dependent chain; the
+    // accumulators meet in a fixed pairwise tree, then the workgroup tree.
+    constexpr int kAcc = 8;
     __shared__ double sh[kBlock];
     const uint32_t b = blockIdx.x;
-    double sr = 0.0, si = 0.0;
-    for (uint32_t c = threadIdx.x; c < nblk; c += kBlock) {
-        sr += partial[2 * (size_t(b) * nblk + c)];
-        si += partial[2 * (size_t(b) * nblk + c) + 1];
+    const double2* p = reinterpret_cast<const double2*>(partial) + size_t(b) * nblk;
+    double ar[kAcc], ai[kAcc];
+#pragma unroll
+    for (int j = 0; j < kAcc; ++j) ar[j] = ai[j] = 0.0;
+    uint32_t c = threadIdx.x;
+    for (; uint64_t(c) + uint64_t(kAcc - 1) * kBlock < nblk; c += kAcc * kBlock) {
+        double2 v[kAcc];
+#pragma unroll
+        for (int j = 0; j < kAcc; ++j) v[j] = p[c + uint32_t(j) * kBlock];
+#pragma unroll
+        for (int j = 0; j < kAcc; ++j) {
+            ar[j] += v[j].x;
+            ai[j] += v[j].y;
+        }
     }
+    // fewer than kAcc strides remain
+#pragma unroll
+    for (int j = 0; j < kAcc - 1; ++j) {
+        const uint64_t cj = uint64_t(c) + uint64_t(j) * kBlock;
+        if (cj < nblk) {
+            const double2 v = p[cj];
+            ar[j] += v.x;
+            ai[j] += v.y;
+        }
+    }
+#pragma unroll
+    for (int w = kAcc / 2; w > 0; w >>= 1)
+#pragma unroll
+        for (int j = 0; j < w; ++j) {
+            ar[j] += ar[j + w];
+            ai[j] += ai[j + w];
+        }
+    double sr = ar[0], si = ai[0];
     sr = block_sum(sr, sh);
     si = block_sum(si, sh);
     if (threadIdx.x == 0) {
