@@ -24,7 +24,9 @@
  * Ownership: the caller owns every state, output and device matrix buffer.
  * Host arrays are read before the call returns and may be freed right after.
  * The library owns plan objects (freed by qf_plan_destroy) and stream-ordered
- * temporary reduction buffers (allocated and freed on `stream`).
+ * temporary reduction buffers (allocated and freed on `stream`, from the
+ * device's default pool, which keeps up to 4 GiB of freed memory for reuse
+ * until qf_shutdown).
  *
  * Errors: argument validation is synchronous and enqueues nothing on failure.
  * A failed HIP launch returns QF_EHIP.  Faults inside a kernel surface at the
@@ -428,7 +430,9 @@ const char* qf_last_error(void);
 int32_t qf_version(void);
 
 /* Releases library-wide state: the autotuner's in-memory cache of chosen
- * options (a QF_TUNE_CACHE file is kept and read again on demand).  Plans
+ * options (a QF_TUNE_CACHE file is kept and read again on demand) and the
+ * freed temporaries the devices' default stream-ordered pools keep for reuse
+ * (up to 4 GiB per device).  Plans
  * stay valid (each owns its buffers until qf_plan_destroy).  Safe to call more
  * than once; the library re-creates the state on demand. */
 void qf_shutdown(void);

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "qf_internal.h"
@@ -45,10 +46,49 @@ qf_status dev_malloc(void** p, size_t bytes, const char* what) {
     return QF_OK;
 }
 
+// The temporaries are stream-ordered allocations from each device's default
+// pool.  With the pool's default release threshold (0) every synchronisation
+// hands freed memory back to the driver, so the next call maps its pages again
+// (hundreds of microseconds for the FP64 prefix sums of a large register).
+// Freed memory up to kPoolKeepBytes per device stays in the pool instead;
+// qf_shutdown trims it.
+constexpr uint64_t kPoolKeepBytes = uint64_t(4) << 30;
+static std::mutex g_pool_mu;
+static std::vector<char> g_pool_set;
+
+static void keep_pool_memory() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) {
+        (void)hipGetLastError();
+        return;
+    }
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    if (size_t(dev) < g_pool_set.size() && g_pool_set[size_t(dev)]) return;
+    if (size_t(dev) >= g_pool_set.size()) g_pool_set.resize(size_t(dev) + 1, 0);
+    hipMemPool_t pool = nullptr;
+    uint64_t keep = kPoolKeepBytes;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) != hipSuccess ||
+        hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess) {
+        (void)hipGetLastError();  // the pool keeps its default: correct, only slower
+    }
+    g_pool_set[size_t(dev)] = 1;
+}
+
+void trim_pools() {
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    for (size_t dev = 0; dev < g_pool_set.size(); ++dev) {
+        if (!g_pool_set[dev]) continue;
+        hipMemPool_t pool = nullptr;
+        if (hipDeviceGetDefaultMemPool(&pool, int(dev)) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
+        (void)hipGetLastError();
+    }
+}
+
 qf_status dev_malloc_async(void** p, size_t bytes, hipStream_t st, const char* what) {
     *p = nullptr;
     if (env_on("QF_TEST_FAIL_ALLOC")) return set_error(QF_ENOMEM, "%s: allocation of %zu bytes refused "
                                                        "(QF_TEST_FAIL_ALLOC)", what, bytes);
+    keep_pool_memory();
     if (hipMallocAsync(p, bytes < 16 ? 16 : bytes, st) != hipSuccess) {
         (void)hipGetLastError();
         *p = nullptr;

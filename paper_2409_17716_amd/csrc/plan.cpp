@@ -2320,6 +2320,7 @@ extern "C" void qf_shutdown(void) {
     std::lock_guard<std::mutex> lock(qf::g_tune_mu);
     std::vector<std::pair<uint64_t, qf_plan_opts>>().swap(qf::g_tune.entries);
     qf::g_tune.loaded = false;
+    qf::trim_pools();
 }
 
 extern "C" {

@@ -103,6 +103,8 @@ qf_status check_launch(const char* what);
 // fail with QF_ENOMEM before calling HIP (failure injection for tests).
 qf_status dev_malloc(void** p, size_t bytes, const char* what);
 qf_status dev_malloc_async(void** p, size_t bytes, hipStream_t st, const char* what);
+// Returns the freed memory the default pools keep (every device the library used).
+void trim_pools();
 qf_status host_malloc_pinned(void** p, size_t bytes, const char* what);
 // QF_LOG set to a non-zero value: planner and autotuner choices go to stderr.
 bool log_enabled();
