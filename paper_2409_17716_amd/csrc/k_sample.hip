@@ -25,6 +25,8 @@ namespace {
 constexpr int kT = 256;         // threads per scan block
 constexpr int kPer = 4;         // elements per thread
 constexpr int kSpan = kT * kPer;  // elements per scan block
+constexpr int kSub = 32;           // elements per sub-block (the searches' middle level)
+constexpr int kMid = kSpan / kSub; // sub-blocks per scan block
 
 // Inclusive scan of segments of length seg (a segment never shares a block with
 // another): block blk covers elements [s * seg + lb * kSpan, ...) of segment
@@ -75,9 +77,13 @@ __device__ inline void scan_values_vec(const Src* q, double (&x)[kPer]) {
     }
 }
 
+// With mids (the first level of a block-local scan), the local sum at the end
+// of each kSub-element sub-block (the block's last element ending the last
+// one) also goes to mids[blk * kMid + sub-block].
 template <typename Src>
 __global__ __launch_bounds__(kT) void k_scan_block(const Src* __restrict__ src, double* __restrict__ data,
-                                                   uint64_t seg, uint32_t bps, double* __restrict__ sums) {
+                                                   uint64_t seg, uint32_t bps, double* __restrict__ sums,
+                                                   double* __restrict__ mids) {
     constexpr int kW = kT / 64;
     __shared__ double wt[kW];
     const uint32_t blk = blockIdx.x;
@@ -122,11 +128,18 @@ __global__ __launch_bounds__(kT) void k_scan_block(const Src* __restrict__ src, 
         double2* p = reinterpret_cast<double2*>(d + size_t(threadIdx.x) * kPer);
 #pragma unroll
         for (int i = 0; i < kPer / 2; ++i) p[i] = make_double2(before + v[2 * i], before + v[2 * i + 1]);
+        // a full block: sub-block t ends at element t * kSub + kSub - 1, the
+        // last of lane t * (kSub / kPer) + kSub / kPer - 1
+        if (mids && (threadIdx.x % (kSub / kPer)) == kSub / kPer - 1)
+            mids[size_t(blk) * kMid + threadIdx.x / (kSub / kPer)] = before + v[kPer - 1];
     } else {
 #pragma unroll
         for (int i = 0; i < kPer; ++i) {
             const uint64_t e = uint64_t(threadIdx.x) * kPer + i;
-            if (e < n) d[e] = before + v[i];
+            if (e < n) {
+                d[e] = before + v[i];
+                if (mids && (e % kSub == kSub - 1 || e == n - 1)) mids[size_t(blk) * kMid + e / kSub] = before + v[i];
+            }
         }
     }
     if (threadIdx.x == kT - 1) sums[blk] = wpre + incl;
@@ -231,6 +244,66 @@ __global__ __launch_bounds__(kT) void k_sample_blocks(const double* __restrict__
     }
 }
 
+// The same draws with the first search split in two: every G-th block end
+// (G = 2^gsh, at most kTop of them) sits in LDS and is searched first, then
+// the G block ends of the group found.  The first end above x lies in the
+// first group whose last end is above x, so the block (and the outcome) is the
+// one the whole-array search finds.  Workgroup (blockIdx.x % bpr) of register
+// b = blockIdx.x / bpr takes shots j = that index * kT + lane, + bpr * kT, ...
+constexpr uint32_t kTop = 2048;  // 16 KB of FP64 group ends
+
+__global__ __launch_bounds__(kT) void k_sample_blocks2(const double* __restrict__ local, uint32_t K, uint32_t bps,
+                                                       uint32_t gsh, uint32_t bpr,
+                                                       const double* __restrict__ sums,
+                                                       const double* __restrict__ ends,
+                                                       const double* __restrict__ mids, uint64_t shots,
+                                                       const double* __restrict__ u,
+                                                       unsigned long long* __restrict__ counts,
+                                                       int32_t* __restrict__ samples) {
+    __shared__ double top[kTop];
+    const uint32_t b = blockIdx.x / bpr, w = blockIdx.x - b * bpr;
+    const double* c = local + size_t(b) * K;
+    const double* e = ends + size_t(b) * bps;
+    const double* so = sums + size_t(b) * bps;
+    const uint32_t G = 1u << gsh;
+    const uint32_t ntop = (bps + G - 1) >> gsh;  // <= kTop (host check)
+    for (uint32_t t = threadIdx.x; t < ntop; t += kT) top[t] = e[min((t + 1) << gsh, bps) - 1];
+    __syncthreads();
+    const double sum = e[bps - 1];
+    for (uint64_t j = uint64_t(w) * kT + threadIdx.x; j < shots; j += uint64_t(bpr) * kT) {
+        const uint64_t i = uint64_t(b) * shots + j;
+        const double x = u[i] * sum;
+        const uint32_t t = upper_bound(top, ntop, x);
+        uint32_t lb = bps;
+        if (t < ntop) {
+            const uint32_t g0 = t << gsh;
+            lb = g0 + upper_bound(e + g0, min(G, bps - g0), x);
+        }
+        uint32_t idx = K;
+        if (lb < bps) {
+            // the sub-block on the mids (one short run), then inside it
+            const uint32_t n = std::min<uint32_t>(kSpan, K - lb * kSpan);
+            const uint32_t nsub = (n + kSub - 1) / kSub;
+            const double off = lb > 0 ? so[lb - 1] : 0.0;
+            const uint32_t sb = bound_off<false>(mids + (size_t(b) * bps + lb) * kMid, nsub, off, x);
+            idx = lb * kSpan + n;
+            if (sb < nsub) {
+                const uint32_t j0 = sb * kSub;
+                idx = lb * kSpan + j0 +
+                      bound_off<false>(c + size_t(lb) * kSpan + j0, std::min<uint32_t>(kSub, n - j0), off, x);
+            }
+        }
+        if (idx >= K) {
+            // the draw reached the total: the first element whose sum reaches it
+            lb = lower_bound(e, bps, sum);
+            const uint32_t n = std::min<uint32_t>(kSpan, K - lb * kSpan);
+            idx = lb * kSpan + bound_off<true>(c + size_t(lb) * kSpan, n, lb > 0 ? so[lb - 1] : 0.0, sum);
+        }
+        atomicAdd(counts + size_t(b) * K + idx, 1ull);
+        if (samples) samples[i] = int32_t(idx);
+    }
+}
+
 constexpr uint32_t kLdsBins = 4096;  // 32 KB of 64-bit counters
 
 // Workgroup (blockIdx.x % bpr) of register b = blockIdx.x / bpr draws shots
@@ -268,15 +341,15 @@ uint32_t grid_of(uint64_t n) {
 // of data.
 template <typename Src = double>
 qf_status scan_segments(double* data, uint64_t seg, uint64_t nseg, double* ws, hipStream_t st,
-                        const Src* src = nullptr, bool local_only = false) {
+                        const Src* src = nullptr, bool local_only = false, double* mids = nullptr) {
     const uint32_t bps = uint32_t((seg + kSpan - 1) / kSpan);
     const uint64_t nblk = nseg * bps;
     if (nblk >= (1ull << 31)) return set_error(QF_ERANGE, "prefix sum grid too large");
     if constexpr (std::is_same<Src, double>::value)
         hipLaunchKernelGGL(k_scan_block<double>, dim3(uint32_t(nblk)), dim3(kT), 0, st, src ? src : data, data, seg,
-                           bps, ws);
+                           bps, ws, mids);
     else
-        hipLaunchKernelGGL(k_scan_block<Src>, dim3(uint32_t(nblk)), dim3(kT), 0, st, src, data, seg, bps, ws);
+        hipLaunchKernelGGL(k_scan_block<Src>, dim3(uint32_t(nblk)), dim3(kT), 0, st, src, data, seg, bps, ws, mids);
     QF_CHECK(check_launch("prefix sum"));
     if (bps > 1) {
         QF_CHECK(scan_segments(ws, bps, nseg, ws + nblk, st));
@@ -319,21 +392,25 @@ qf_status launch_sample(const StateView& s, int m, const int32_t* qudits, uint64
     const bool blocks = K > kLdsBins;
     const uint64_t bps = (K + kSpan - 1) / kSpan;
     const uint64_t nends = blocks ? bps * s.batch : 0;
+    const uint64_t nmids = nends * kMid;
     double* cdf = nullptr;
-    QF_CHECK(dev_malloc_async(reinterpret_cast<void**>(&cdf), (bins + wsd + nends) * sizeof(double), st,
+    QF_CHECK(dev_malloc_async(reinterpret_cast<void**>(&cdf), (bins + wsd + nends + nmids) * sizeof(double), st,
                               "sampling"));
     double* ws = cdf + bins;
     double* ends = ws + wsd;
+    double* mids = ends + nends;
     qf_status rs = QF_OK;
     if (m == 0) {
         // the full register: |psi|^2 is taken inside the first scan level
         if (s.dtype == QF_C64)
-            rs = scan_segments(cdf, K, s.batch, ws, st, reinterpret_cast<const cplx<float>*>(s.amps), blocks);
+            rs = scan_segments(cdf, K, s.batch, ws, st, reinterpret_cast<const cplx<float>*>(s.amps), blocks,
+                               blocks ? mids : nullptr);
         else
-            rs = scan_segments(cdf, K, s.batch, ws, st, reinterpret_cast<const cplx<double>*>(s.amps), blocks);
+            rs = scan_segments(cdf, K, s.batch, ws, st, reinterpret_cast<const cplx<double>*>(s.amps), blocks,
+                               blocks ? mids : nullptr);
     } else {
         rs = launch_probs_marginal(s, m, qudits, cdf, true, st);
-        if (rs == QF_OK) rs = scan_segments<double>(cdf, K, s.batch, ws, st, nullptr, blocks);
+        if (rs == QF_OK) rs = scan_segments<double>(cdf, K, s.batch, ws, st, nullptr, blocks, blocks ? mids : nullptr);
     }
     if (rs == QF_OK && blocks) {
         hipLaunchKernelGGL(k_block_ends, dim3(grid_of(nends)), dim3(kT), 0, st, cdf, K, uint32_t(bps),
@@ -354,11 +431,24 @@ qf_status launch_sample(const StateView& s, int m, const int32_t* qudits, uint64
             hipLaunchKernelGGL(k_sample_lds, dim3(uint32_t(bpr * s.batch)), dim3(kT), 0, st, cdf, uint32_t(K), shots,
                                uint32_t(bpr), u, reinterpret_cast<unsigned long long*>(counts), samples);
         } else {
-            hipLaunchKernelGGL(k_sample_blocks, dim3(grid_of(draws)), dim3(kT), 0, st, cdf, uint32_t(K),
-                               uint32_t(bps), ws, ends, shots, draws, u,
-                               reinterpret_cast<unsigned long long*>(counts), samples);
+            // group ends in LDS: G = 2^gsh block ends per group, at most kTop groups
+            uint32_t gsh = 5;
+            while (((bps + (uint64_t(1) << gsh) - 1) >> gsh) > kTop) ++gsh;
+            // about 4 shots per lane, at most 2048 workgroups in all
+            uint64_t bpr = (shots + 4 * kT - 1) / (4 * kT);
+            bpr = std::min<uint64_t>(bpr, std::max<uint64_t>(1, 2048 / s.batch));
+            if (uint64_t(s.batch) * bpr < (1ull << 31) && gsh < 32) {
+                hipLaunchKernelGGL(k_sample_blocks2, dim3(uint32_t(bpr * s.batch)), dim3(kT), 0, st, cdf,
+                                   uint32_t(K), uint32_t(bps), gsh, uint32_t(bpr), ws, ends, mids, shots, u,
+                                   reinterpret_cast<unsigned long long*>(counts), samples);
+            } else {
+                hipLaunchKernelGGL(k_sample_blocks, dim3(grid_of(draws)), dim3(kT), 0, st, cdf, uint32_t(K),
+                                   uint32_t(bps), ws, ends, shots, draws, u,
+                                   reinterpret_cast<unsigned long long*>(counts), samples);
+            }
         }
-        rs = check_launch("sampling");
+        const qf_status rl = check_launch("sampling");
+        if (rs == QF_OK) rs = rl;
     }
     (void)hipFreeAsync(cdf, st);
     return rs;
